@@ -1,0 +1,217 @@
+"""Seeded synthetic workloads.
+
+This module holds input recipes only: parameter sets, seeded draws and the
+mesh layout of each workload.  It contains none of the pricing method's
+arithmetic and imports nothing from the rest of the package, so both the GPU
+path and the CPU oracle can be fed from it.
+
+Parameter values follow the paper's "2007 market" set (section 3.3:
+lambda = 0.15, gamma = 0.9, theta = 0.25) and its metric choice (section 7.1,
+scaled units r0 = 0.01: r and y up to 250, v up to 30, stretch 0.5), converted
+to physical units:  r in [0, 2.5] with alpha_r = 0.005 centred on the strike,
+v in [0, 30] with alpha_v = 0.5 centred on 0.5, y in [0, 0.025] with
+alpha_y = 5e-5 centred on 0.  The paper's figures and its discrete market
+curve are not available, so every curve is the parametric
+f(0,t) = level + slope (1 - exp(-decay t)).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+from typing import List, Tuple
+
+import numpy as np
+
+OUTFLOW = 0
+DIRICHLET = 1
+BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
+
+LAMBDA = 0.15
+GAMMA = 0.9
+THETA_V = 0.25
+
+R_MAX, ALPHA_R = 2.5, 0.005
+V_MAX, ALPHA_V, CENTER_V = 30.0, 0.5, 0.5
+Y_MAX, ALPHA_Y = 0.025, 5e-5
+
+
+@dataclass(frozen=True)
+class AxisSpec:
+    n: int
+    z_min: float
+    z_max: float
+    center: float
+    alpha: float
+    lo_face: int = OUTFLOW
+    hi_face: int = OUTFLOW
+
+
+@dataclass(frozen=True)
+class ModelSpec:
+    kappa: float
+    epsilon: float
+    rho: float
+    f_level: float
+    f_slope: float = 0.0
+    f_decay: float = 0.0
+    theta_v: float = THETA_V
+    lam: float = LAMBDA
+    gamma: float = GAMMA
+
+
+@dataclass(frozen=True)
+class PayoffSpec:
+    kind: int
+    expiry: float
+    pay: float
+    strike: float
+
+
+@dataclass(frozen=True)
+class SolveSpec:
+    axes: Tuple[AxisSpec, AxisSpec, AxisSpec]
+    model: ModelSpec
+    payoff: PayoffSpec
+    n_steps: int
+    r0: float
+    v0: float = 1.0
+
+    @property
+    def shape(self):
+        return (self.axes[2].n, self.axes[1].n, self.axes[0].n)
+
+    @property
+    def points(self) -> int:
+        return self.axes[0].n * self.axes[1].n * self.axes[2].n
+
+
+def default_axes(nr: int, nv: int, ny: int, center_r: float,
+                 r_min: float = 0.0, r_lo_face: int = OUTFLOW) -> Tuple[AxisSpec, AxisSpec, AxisSpec]:
+    """Default mesh: outflow at r = 0, v = 0, v = v_max, y = 0; Dirichlet at r_max, y_max."""
+    return (AxisSpec(nr, r_min, R_MAX, center_r, ALPHA_R, r_lo_face, DIRICHLET),
+            AxisSpec(nv, 0.0, V_MAX, CENTER_V, ALPHA_V, OUTFLOW, OUTFLOW),
+            AxisSpec(ny, 0.0, Y_MAX, 0.0, ALPHA_Y, OUTFLOW, DIRICHLET))
+
+
+def curve_integral(m: ModelSpec, t: float) -> float:
+    """int_0^t f(0,s) ds for the parametric curve (input recipe for strikes)."""
+    if m.f_decay == 0.0:
+        return m.f_level * t
+    return m.f_level * t + m.f_slope * (t - (1.0 - math.exp(-m.f_decay * t)) / m.f_decay)
+
+
+def atm_strike(m: ModelSpec, expiry: float, pay: float) -> float:
+    """Simple-compounded forward rate over [expiry, pay]: the at-the-money strike."""
+    ratio = math.exp(curve_integral(m, pay) - curve_integral(m, expiry))
+    return (ratio - 1.0) / (pay - expiry)
+
+
+CURVE_SLOPED = dict(f_level=0.02, f_slope=0.01, f_decay=0.5)
+
+
+def _draw_model(rng: np.random.Generator, **curve) -> ModelSpec:
+    kappa = float(rng.uniform(0.01, 0.2))
+    eps = float(rng.uniform(0.1, 0.6))
+    rho = float(rng.uniform(-0.8, 0.8))
+    return ModelSpec(kappa=kappa, epsilon=eps, rho=rho, **curve)
+
+
+def config1() -> List[SolveSpec]:
+    """32^3, 50 steps to T = 1y, flat 3 %, kappa 0.05, eps 0.3, rho -0.5: bond and ATM caplet."""
+    m = ModelSpec(kappa=0.05, epsilon=0.3, rho=-0.5, f_level=0.03)
+    k = atm_strike(m, 1.0, 2.0)
+    bond = SolveSpec(default_axes(32, 32, 32, 0.03), m, PayoffSpec(BOND, 1.0, 2.0, k), 50, m.f_level)
+    cap = SolveSpec(default_axes(32, 32, 32, k), m, PayoffSpec(CAPLET, 1.0, 2.0, k), 50, m.f_level)
+    return [bond, cap]
+
+
+def config2() -> List[SolveSpec]:
+    """128x64x64, 200 steps to 5y, sloped curve, seed 1; caplets at ATM-100bp, ATM, ATM+100bp."""
+    rng = np.random.default_rng(1)
+    m = _draw_model(rng, **CURVE_SLOPED)
+    k = atm_strike(m, 5.0, 6.0)
+    ax = default_axes(128, 64, 64, k)
+    return [SolveSpec(ax, m, PayoffSpec(CAPLET, 5.0, 6.0, k + dk), 200, m.f_level)
+            for dk in (-0.01, 0.0, 0.01)]
+
+
+def config3() -> List[SolveSpec]:
+    """256x128x128, dt = 0.025 (400 steps to 10y), seed 2; ATM caplets expiring 1..10y, paid +1y."""
+    rng = np.random.default_rng(2)
+    m = _draw_model(rng, **CURVE_SLOPED)
+    out = []
+    for T in range(1, 11):
+        k = atm_strike(m, float(T), float(T + 1))
+        out.append(SolveSpec(default_axes(256, 128, 128, k), m,
+                             PayoffSpec(CAPLET, float(T), float(T + 1), k), 40 * T, m.f_level))
+    return out
+
+
+def config4(n: int = 512, seed: int = 3) -> List[SolveSpec]:
+    """Batched calibration-style solves: per solve n_r, n_v, n_y ~ U{32,48,64,96}, N ~ U{50..200},
+    expiry ~ U{1..5}y paid +1y, strike ATM + U{-100,0,+100} bp, parameters as config 2."""
+    rng = np.random.default_rng(seed)
+    sizes = (32, 48, 64, 96)
+    out = []
+    for _ in range(n):
+        nr, nv, ny = (int(sizes[rng.integers(0, 4)]) for _ in range(3))
+        N = int(rng.integers(50, 201))
+        m = _draw_model(rng, **CURVE_SLOPED)
+        T = float(rng.integers(1, 6))
+        dk = float((-0.01, 0.0, 0.01)[rng.integers(0, 3)])
+        k = atm_strike(m, T, T + 1.0) + dk
+        out.append(SolveSpec(default_axes(nr, nv, ny, k), m, PayoffSpec(CAPLET, T, T + 1.0, k), N, m.f_level))
+    return out
+
+
+# Surrogate box (8 inputs): kappa, eps, rho, v0, curve level, curve slope, strike offset, expiry.
+SURROGATE_BOX_LO = np.array([0.01, 0.1, -0.8, 0.5, 0.01, 0.0, -0.01, 0.5])
+SURROGATE_BOX_HI = np.array([0.2, 0.6, 0.8, 1.5, 0.04, 0.02, 0.01, 5.0])
+SURROGATE_DT = 0.025
+SURROGATE_N = 64
+SURROGATE_V0 = tuple(0.5 + (1.5 - 0.5) * (q + 0.5) / 16.0 for q in range(16))
+
+
+def surrogate_solve(x: np.ndarray, n: int = SURROGATE_N) -> SolveSpec:
+    """One caplet solve from a surrogate input row (v0 is read out, not solved for)."""
+    kappa, eps, rho, v0, lvl, slope, dk, T = (float(t) for t in x)
+    m = ModelSpec(kappa=kappa, epsilon=eps, rho=rho, f_level=lvl, f_slope=slope, f_decay=0.5)
+    k = atm_strike(m, T, T + 1.0) + dk
+    N = max(1, int(round(T / SURROGATE_DT)))
+    return SolveSpec(default_axes(n, n, n, k), m, PayoffSpec(CAPLET, T, T + 1.0, k), N, lvl, v0)
+
+
+def surrogate_params(n_solves: int, seed: int) -> np.ndarray:
+    """Uniform draws in the surrogate box, one row per solve (column 3, v0, is overwritten
+    by the readout grid of SURROGATE_V0 when the training set is built)."""
+    rng = np.random.default_rng(seed)
+    return SURROGATE_BOX_LO + (SURROGATE_BOX_HI - SURROGATE_BOX_LO) * rng.random((n_solves, 8))
+
+
+def surrogate_outside(n: int, seed: int) -> np.ndarray:
+    """Rows with one coordinate pushed outside the box (fallback routing test)."""
+    rng = np.random.default_rng(seed)
+    x = surrogate_params(n, seed + 1000)
+    span = SURROGATE_BOX_HI - SURROGATE_BOX_LO
+    for r in range(n):
+        c = int(rng.integers(0, 8))
+        if rng.random() < 0.5:
+            x[r, c] = SURROGATE_BOX_LO[c] - span[c] * float(rng.uniform(0.05, 0.3))
+        else:
+            x[r, c] = SURROGATE_BOX_HI[c] + span[c] * float(rng.uniform(0.05, 0.3))
+    return x
+
+
+def gaussian_variant(s: SolveSpec, lam: float = 0.01, r_min: float = -0.5) -> SolveSpec:
+    """Deterministic-volatility limit: gamma = 0, epsilon = 0, v0 = 1, negative rates allowed
+    (both r faces Dirichlet)."""
+    m = replace(s.model, gamma=0.0, epsilon=0.0, lam=lam)
+    ax = default_axes(s.axes[0].n, s.axes[1].n, s.axes[2].n, s.axes[0].center,
+                      r_min=r_min, r_lo_face=DIRICHLET)
+    return replace(s, axes=ax, model=m, v0=1.0)
+
+
+def with_shape(s: SolveSpec, nr: int, nv: int, ny: int, n_steps: int | None = None) -> SolveSpec:
+    """Same problem on another mesh (and optionally another step count)."""
+    ax = tuple(replace(a, n=n) for a, n in zip(s.axes, (nr, nv, ny)))
+    return replace(s, axes=ax, n_steps=s.n_steps if n_steps is None else n_steps)
