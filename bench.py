@@ -1,0 +1,154 @@
+#!/usr/bin/env python3
+"""Benchmark of the Douglas-ADI HJM solver on one MI355X.
+
+One benchmark step prices the ten at-the-money caplets of the 256x128x128
+workload (expiries 1..10 years, paid one year later, dt = 0.025, so 40..400
+Douglas steps each, 2200 in total): table set-up and terminal data, every
+Douglas step (explicit predictor, r, v and y sweeps, update) and the
+readout.  The metric is grid-point ADI updates per second (one grid point
+advanced one Douglas step).  Inputs are seeded and synthetic.
+
+Prints one JSON line (the last line of stdout).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point ADI updates/s (FP64, % HBM roofline); calibration solves/s batched+surrogate vs plain"
+UNIT = "grid-point ADI updates/s"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per grid point per launch of each pass
+PASS_BYTES = {"explicit+r": 16.0, "v": 16.0, "y+update": 24.0}
+PASS_NAMES = ["explicit+r", "v", "y+update"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds: float):
+    """The oracle, as it stands, on the host cores: Douglas steps of the
+    10-year caplet grid (256x128x128) until `seconds` of work are done."""
+    import oracle as O
+    from paper_1108_1688_amd import workloads as W
+
+    spec = W.config3()[-1]
+    m = spec.model
+    axes = [O.Axis(a.n, a.z_min, a.z_max, a.center, a.alpha, a.lo_face, a.hi_face) for a in spec.axes]
+    p = O.Problem(axes, kappa=m.kappa, theta_v=m.theta_v, lam=m.lam, gamma=m.gamma, epsilon=m.epsilon,
+                  rho=m.rho, f_level=m.f_level, f_slope=m.f_slope, f_decay=m.f_decay, kind=spec.payoff.kind,
+                  expiry=spec.payoff.expiry, pay=spec.payoff.pay, strike=spec.payoff.strike,
+                  n_steps=spec.n_steps)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    O.set_threads(threads)
+    U = O.terminal(p)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        O.step(p, done, U)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or done >= spec.n_steps:
+            break
+    return {"value": spec.points * done / el, "unit": UNIT, "cores": O.get_threads(), "kind": "oracle",
+            "sample": f"{done} Douglas steps of the 256x128x128 10-year caplet grid ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the sharded design is described in DESIGN.md and is not built", flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_1108_1688_amd import hjm
+    from paper_1108_1688_amd import workloads as W
+
+    if args.tile:
+        hjm.set_line_tile(*[int(x) for x in args.tile.split(",")])
+    torch.cuda.set_device(0)
+    specs = W.config3()
+    points = specs[0].points
+    total_steps = sum(s.n_steps for s in specs)
+    nbytes = max(hjm.workspace_bytes(s) for s in specs)
+    workspaces = [torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda") for _ in specs]
+    stream = torch.cuda.current_stream()
+
+    def one_step(profile: bool):
+        grids = [hjm.Grid(s, stream=stream, workspace=ws) for s, ws in zip(specs, workspaces)]
+        for g in grids:
+            if profile:
+                g.profile(True)
+            g.step()
+        prices = [g.price() for g in grids]
+        prof = [g.profile_read() for g in grids] if profile else None
+        for g in grids:
+            g.close()
+        return prices, prof
+
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    profs = []
+    prices = None
+    for _ in range(args.steps):
+        prices, prof = one_step(True)
+        profs.extend(prof)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+    value = points * total_steps * args.steps / el
+
+    pass_ms = [0.0, 0.0, 0.0]
+    pass_n = [0, 0, 0]
+    for ms, n in profs:
+        for q in range(3):
+            pass_ms[q] += ms[q]
+            pass_n[q] += n[q]
+    passes = {}
+    for q, name in enumerate(PASS_NAMES):
+        avg_ms = pass_ms[q] / max(pass_n[q], 1)
+        gbs = PASS_BYTES[name] * points / (avg_ms * 1e-3) / 1e9
+        passes[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": pass_n[q], "GB/s": round(gbs, 1),
+                        "share": round(pass_ms[q] / max(sum(pass_ms), 1e-12), 3)}
+    dom = max(range(3), key=lambda q: pass_ms[q])
+    dname = PASS_NAMES[dom]
+    achieved = passes[dname]["GB/s"]
+    step_gbs = sum(PASS_BYTES.values()) * points / (sum(pass_ms) / max(pass_n[0], 1) * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_point": PASS_BYTES[dname], "points_per_launch": points,
+                "douglas_step_GBs": round(step_gbs, 1), "passes": passes}
+    log(f"prices (1..10y): {[round(p, 8) for p in prices]}")
+    log(f"{value / 1e9:.2f} G pt-steps/s, {ms_per_step:.2f} ms per bench step; passes {passes}")
+
+    out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "256x128x128 grid (r x v x y), 10 ATM caplets expiring 1..10y paid +1y, "
+                                  "dt=0.025 (2200 Douglas steps per bench step), seeded parameters (seed 2)",
+                      "grid": [256, 128, 128], "douglas_steps": total_steps, "line_tile": list(hjm.get_line_tile()),
+                      "parallelism": "single GPU"},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * hjm.h -- C ABI of the MI355X (gfx950) Douglas-ADI solver for the
+ * single-factor Heath-Jarrow-Morton model with stochastic volatility
+ * (Valero, Torrealba, Lacasa, Fraysse).
+ *
+ * Problem (section 3): price, at t = 0 and state (r0, v0, y = 0), a contract
+ * paying F at T on the PDE of eq. (1) in (r, v, y) with coefficients from
+ * the short-rate SDE (section 3.1) and terminal / boundary data of section
+ * 3.2, discretised on the sinh mesh of section 4.3 with the centred stencils
+ * of eq. (esquema), theta = 1/2 (Crank-Nicolson) and the Douglas ADI
+ * splitting of section 5.1.
+ *
+ * Conventions shared by every entry point:
+ *  - Grids are FP64, indexed U[(k*nv + j)*nr + i] with i along r (contiguous),
+ *    j along v and k along y.  "n" nodes per axis include both end nodes.
+ *  - Device memory and the HIP stream belong to the caller; the library only
+ *    borrows them between create and destroy and never allocates device
+ *    memory.  Opaque handles are host objects owned by the library.
+ *  - Every call returns hjm_status: HJM_OK (0) or a negative error; nothing
+ *    throws across the ABI.  hjm_last_error() returns a message for the last
+ *    failure of the calling thread.
+ *  - Handles are not thread-safe: one handle is used from one thread and one
+ *    stream at a time.
+ *  - Asynchronous calls (create, step, batch run) only enqueue work on the
+ *    stream; calls that return host values (price, prices) synchronise it.
+ */
+#ifndef HJM_H
+#define HJM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hjm_status;
+#define HJM_OK        0
+#define HJM_EINVAL   (-1)  /* invalid argument; detected on the host before any device work */
+#define HJM_ENOMEM   (-2)  /* the caller's workspace is too small */
+#define HJM_EDEVICE  (-3)  /* a HIP runtime call failed */
+#define HJM_ENUMERIC (-4)  /* a non-finite value or a non-positive pivot was met */
+#define HJM_ESTATE   (-5)  /* call out of order (e.g. price before every step ran) */
+
+/* Face types.  OUTFLOW: one-sided second-order normal first difference
+   (section 7.3), the normal second-derivative term taken as zero (section
+   3.2); allowed only where the drift points out of the domain in backward
+   time (checked: HJM_EINVAL otherwise).  DIRICHLET: the closed-form value of
+   the contract with a linear payoff (section 4.1 bond formula) is imposed.
+   Dirichlet is accepted on the r faces and on the y_max face only. */
+#define HJM_FACE_OUTFLOW   0
+#define HJM_FACE_DIRICHLET 1
+
+/* Payoffs (section 3.2): bond pays 1; caplet max(1 - Delta p(T,T_M), 0);
+   floorlet max(Delta p(T,T_M) - 1, 0); forward 1 - Delta p(T,T_M), with
+   Delta = 1 + (T_M - T) K. */
+#define HJM_BOND     0
+#define HJM_CAPLET   1
+#define HJM_FLOORLET 2
+#define HJM_FORWARD  3
+
+/* One axis of the hyperbolic mesh z = center + alpha sinh(c2 x + c1 (1-x)),
+   x in [0,1] uniform (eq. (metrica), section 4.3 / 7.1).  Requires n >= 5,
+   alpha > 0, z_min < z_max. */
+typedef struct {
+    int32_t n;
+    int32_t lo_face;
+    int32_t hi_face;
+    int32_t reserved;
+    double z_min, z_max, center, alpha;
+} hjm_axis;
+
+/* Model of section 3.1: dr = (f_t - kappa (r - f) + y) dt + sqrt(v) lambda r^gamma dW,
+   dv = theta_v (1 - v) dt + epsilon sqrt(v) dZ, dW dZ = rho dt, and the
+   initial curve f(0,t) = f_level + f_slope (1 - exp(-f_decay t)).
+   Requires kappa >= 0, theta_v >= 0, lambda >= 0, epsilon >= 0, |rho| <= 1,
+   gamma in [0,1] (gamma > 0 needs r_min >= 0), f_decay >= 0. */
+typedef struct {
+    double kappa, theta_v, lambda, gamma, epsilon, rho;
+    double f_level, f_slope, f_decay;
+} hjm_model;
+
+/* Contract: kind, expiry T > 0, payment T_M > T and strike K > 0 (caplet,
+   floorlet, forward; ignored for the bond). */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double expiry, pay, strike;
+} hjm_payoff;
+
+typedef struct hjm_grid hjm_grid;
+typedef struct hjm_batch hjm_batch;
+
+/* Bytes of device workspace hjm_grid_create needs for these axes and step
+   count: the grid U and the Douglas increment D (nr*nv*ny doubles each) plus
+   1D tables (axis coefficients, per-step curve and bond-factor scalars,
+   readout weights and a health flag).  Host only. */
+hjm_status hjm_workspace_bytes(const hjm_axis ax[3], int32_t n_steps, size_t* bytes);
+
+/* Validate the problem, lay out the caller's workspace (d_workspace, at least
+   hjm_workspace_bytes, 256-byte aligned), upload the tables and enqueue the
+   terminal data U := payoff at t = T on hip_stream (a hipStream_t; NULL is
+   the null stream).  n_steps > 0 Douglas steps of dt = T / n_steps will take
+   the solution back to t = 0.  On success *out owns a host handle. */
+hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff,
+                           int32_t n_steps, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                           hjm_grid** out);
+
+/* Enqueue k more Douglas steps (section 5.1) on the grid's stream.
+   HJM_ESTATE if that would go past n_steps. */
+hjm_status hjm_adi_step(hjm_grid* g, int32_t k);
+
+/* After all n_steps: synchronise the stream, check the health flag and the
+   grid for non-finite values (HJM_ENUMERIC), and return C(t=0; r0, v0, y=0)
+   by tensor 4-point Lagrange interpolation in the mesh coordinates on the
+   lowest y plane.  HJM_ESTATE before the last step, HJM_EINVAL if (r0, v0)
+   is outside the mesh. */
+hjm_status hjm_price(hjm_grid* g, double r0, double v0, double* out);
+
+/* Borrow the device grid U (nr*nv*ny doubles, inside the caller's workspace)
+   and the number of steps taken so far.  Writing U and then calling
+   hjm_grid_set_step restores a checkpoint. */
+hjm_status hjm_grid_solution(hjm_grid* g, double** d_U, int64_t* step);
+
+/* Declare that U holds the solution after `step` steps (0 <= step <= n_steps),
+   e.g. after copying a checkpoint into the borrowed U. */
+hjm_status hjm_grid_set_step(hjm_grid* g, int64_t step);
+
+/* Release the host handle (the caller's device memory is untouched). */
+hjm_status hjm_grid_destroy(hjm_grid* g);
+
+/* Per-pass timing.  While enabled, each pass launch of hjm_adi_step (the
+   explicit + r sweep, the v sweep, the y sweep + update) is bracketed by HIP
+   events recorded on the grid's stream. */
+hjm_status hjm_grid_profile(hjm_grid* g, int32_t enable);
+
+/* Synchronise the stream and return, per pass, the summed event-to-event
+   milliseconds and the number of launches bracketed since the previous read
+   (ms[3], launches[3]); the sums restart from zero. */
+hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[3], int64_t launches[3]);
+
+/* ---------------------------------------------------------------------- */
+/* Batched independent solves (calibration-style throughput).              */
+/* ---------------------------------------------------------------------- */
+
+/* Workspace for n solves with axes ax[s][3] and n_steps[s]. */
+hjm_status hjm_batch_workspace_bytes(int32_t n, const hjm_axis* ax, const int32_t* n_steps,
+                                     size_t* bytes);
+
+/* n independent solves: ax is n*3 axes (solve-major), model/payoff/n_steps
+   arrays of n.  Validates each like hjm_grid_create, lays out the shared
+   workspace and uploads the tables (synchronises the stream). */
+hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* model,
+                            const hjm_payoff* payoff, const int32_t* n_steps,
+                            void* d_workspace, size_t ws_bytes, void* hip_stream,
+                            hjm_batch** out);
+
+/* Enqueue a complete solve of every problem: terminal data at t = T, then
+   every Douglas step, where at step n one launch per pass covers all solves
+   with more than n steps.  use_graph != 0 captures the launches into a HIP
+   graph on the first call (the stream must not be the null stream) and
+   replays it afterwards. */
+hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph);
+
+/* After hjm_batch_run: synchronise, check health, and read out the n prices
+   at (r0[s], v0[s]) as hjm_price does. */
+hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, double* out);
+
+hjm_status hjm_batch_destroy(hjm_batch* b);
+
+/* ---------------------------------------------------------------------- */
+/* Tuning and diagnostics.                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Line-solve tile: rows per thread of the segmented tridiagonal solves
+   (8, 16 or 32) for the r, v and y sweeps.  Applies to handles created
+   afterwards in this process.  HJM_EINVAL for other values. */
+hjm_status hjm_set_line_tile(int32_t r_rows, int32_t v_rows, int32_t y_rows);
+hjm_status hjm_get_line_tile(int32_t* r_rows, int32_t* v_rows, int32_t* y_rows);
+
+const char* hjm_status_str(hjm_status s);
+const char* hjm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HJM_H */

@@ -1,0 +1,868 @@
+// Host layer of libhjm: argument validation, mesh and coefficient tables,
+// line-solve tiling, workspace layout and the C ABI of include/hjm.h.
+#include "hjm.h"
+#include "hjm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace hjm;
+
+namespace {
+
+thread_local std::string g_last_error;
+int g_rows[3] = {16, 16, 16};  // rows per thread of the r, v, y line solves
+
+hjm_status fail(hjm_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+hjm_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(HJM_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int kMaxNodes = 2048;  // per axis (S <= 256 segments of >= 8 rows)
+constexpr double kTheta = 0.5;   // Crank-Nicolson weight
+
+bool finite(double x) { return std::isfinite(x); }
+
+// ---------------------------------------------------------------------------
+// Curve and bond factors (sections 2 and 3.1).
+// ---------------------------------------------------------------------------
+struct Curve {
+    double a, b, c;
+    double f(double t) const { return c == 0.0 ? a : a + b * (1.0 - std::exp(-c * t)); }
+    double ft(double t) const { return c == 0.0 ? 0.0 : b * c * std::exp(-c * t); }
+    double integral(double t) const { return c == 0.0 ? a * t : a * t + b * (t - (1.0 - std::exp(-c * t)) / c); }
+    double P(double t) const { return std::exp(-integral(t)); }
+};
+
+double Gfun(double kappa, double s) { return kappa == 0.0 ? s : -std::expm1(-kappa * s) / kappa; }
+
+// ---------------------------------------------------------------------------
+// Mesh (eq. (metrica)).
+// ---------------------------------------------------------------------------
+struct Mesh {
+    std::vector<double> z, J, J2;
+};
+
+Mesh make_mesh(const hjm_axis& a)
+{
+    Mesh m;
+    const int n = a.n;
+    m.z.resize(n);
+    m.J.resize(n);
+    m.J2.resize(n);
+    const double c1 = std::asinh((a.z_min - a.center) / a.alpha);
+    const double c2 = std::asinh((a.z_max - a.center) / a.alpha);
+    const double dc = c2 - c1;
+    for (int q = 0; q < n; ++q) {
+        const double x = (double)q / (double)(n - 1);
+        const double s = c2 * x + c1 * (1.0 - x);
+        m.z[q] = a.center + a.alpha * std::sinh(s);
+        m.J[q] = a.alpha * std::cosh(s) * dc;
+        m.J2[q] = a.alpha * std::sinh(s) * dc * dc;
+    }
+    m.z[0] = a.z_min;
+    m.z[n - 1] = a.z_max;
+    return m;
+}
+
+double mesh_x(const hjm_axis& a, double z)
+{
+    const double c1 = std::asinh((a.z_min - a.center) / a.alpha);
+    const double c2 = std::asinh((a.z_max - a.center) / a.alpha);
+    return (std::asinh((z - a.center) / a.alpha) - c1) / (c2 - c1);
+}
+
+double rpow(double r, double g) { return g == 0.0 ? 1.0 : std::pow(r, g); }
+
+// ---------------------------------------------------------------------------
+// Validation.
+// ---------------------------------------------------------------------------
+hjm_status validate_axes(const hjm_axis ax[3])
+{
+    static const char* names[3] = {"r", "v", "y"};
+    for (int a = 0; a < 3; ++a) {
+        const hjm_axis& x = ax[a];
+        if (x.n < 5 || x.n > kMaxNodes) return fail(HJM_EINVAL, "axis %s: n=%d outside [5, %d]", names[a], x.n, kMaxNodes);
+        if (!(finite(x.z_min) && finite(x.z_max) && finite(x.center) && finite(x.alpha)))
+            return fail(HJM_EINVAL, "axis %s: non-finite geometry", names[a]);
+        if (!(x.alpha > 0.0)) return fail(HJM_EINVAL, "axis %s: alpha must be > 0", names[a]);
+        if (!(x.z_min < x.z_max)) return fail(HJM_EINVAL, "axis %s: z_min must be < z_max", names[a]);
+        for (int f : {x.lo_face, x.hi_face})
+            if (f != HJM_FACE_OUTFLOW && f != HJM_FACE_DIRICHLET)
+                return fail(HJM_EINVAL, "axis %s: unknown face type %d", names[a], f);
+    }
+    if (ax[1].lo_face != HJM_FACE_OUTFLOW || ax[1].hi_face != HJM_FACE_OUTFLOW)
+        return fail(HJM_EINVAL, "the v faces must be OUTFLOW");
+    if (ax[2].lo_face != HJM_FACE_OUTFLOW) return fail(HJM_EINVAL, "the y_min face must be OUTFLOW");
+    if (ax[1].z_min < 0.0) return fail(HJM_EINVAL, "v_min must be >= 0");
+    if (ax[2].z_min < 0.0) return fail(HJM_EINVAL, "y_min must be >= 0");
+    const double pts = (double)ax[0].n * ax[1].n * ax[2].n;
+    if (pts > 2147483647.0) return fail(HJM_EINVAL, "grid too large");
+    return HJM_OK;
+}
+
+hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_payoff* p, int32_t n_steps)
+{
+    if (!ax || !m || !p) return fail(HJM_EINVAL, "null argument");
+    hjm_status st = validate_axes(ax);
+    if (st) return st;
+    const double vals[] = {m->kappa, m->theta_v, m->lambda, m->gamma, m->epsilon, m->rho,
+                           m->f_level, m->f_slope, m->f_decay, p->expiry, p->pay, p->strike};
+    for (double v : vals)
+        if (!finite(v)) return fail(HJM_EINVAL, "non-finite model or payoff parameter");
+    if (m->kappa < 0.0) return fail(HJM_EINVAL, "kappa must be >= 0");
+    if (m->theta_v < 0.0) return fail(HJM_EINVAL, "theta_v must be >= 0");
+    if (m->lambda < 0.0) return fail(HJM_EINVAL, "lambda must be >= 0");
+    if (m->epsilon < 0.0) return fail(HJM_EINVAL, "epsilon must be >= 0");
+    if (std::fabs(m->rho) > 1.0) return fail(HJM_EINVAL, "|rho| must be <= 1");
+    if (m->gamma < 0.0 || m->gamma > 1.0) return fail(HJM_EINVAL, "gamma must be in [0, 1]");
+    if (m->gamma > 0.0 && ax[0].z_min < 0.0) return fail(HJM_EINVAL, "gamma > 0 needs r_min >= 0");
+    if (m->f_decay < 0.0) return fail(HJM_EINVAL, "f_decay must be >= 0");
+    if (p->kind < HJM_BOND || p->kind > HJM_FORWARD) return fail(HJM_EINVAL, "unknown payoff kind %d", p->kind);
+    if (!(p->expiry > 0.0)) return fail(HJM_EINVAL, "expiry must be > 0");
+    if (p->kind != HJM_BOND) {
+        if (!(p->pay > p->expiry)) return fail(HJM_EINVAL, "payment date must be after expiry");
+        if (!(p->strike > 0.0)) return fail(HJM_EINVAL, "strike must be > 0");
+    }
+    if (n_steps <= 0) return fail(HJM_EINVAL, "n_steps must be > 0");
+    // Outflow faces: the drift must point out of the domain in backward time.
+    const Curve cv{m->f_level, m->f_slope, m->f_decay};
+    const double T = p->expiry, dt = T / n_steps;
+    const double r0 = ax[0].z_min, r1 = ax[0].z_max;
+    const double v0 = ax[1].z_min, v1 = ax[1].z_max;
+    const double y0 = ax[2].z_min, y1 = ax[2].z_max;
+    for (int n = 0; n < n_steps; ++n) {
+        const double t = T - (n + 0.5) * dt;
+        const double phi = cv.ft(t) + m->kappa * cv.f(t);
+        if (ax[0].lo_face == HJM_FACE_OUTFLOW && phi - m->kappa * r0 + y0 < 0.0)
+            return fail(HJM_EINVAL, "r_min outflow face has inflowing drift at t=%g (f_t + kappa f < kappa r_min - y_min)", t);
+        if (ax[0].hi_face == HJM_FACE_OUTFLOW && phi - m->kappa * r1 + y1 > 0.0)
+            return fail(HJM_EINVAL, "r_max outflow face has inflowing drift at t=%g", t);
+    }
+    if (m->theta_v * (1.0 - v0) < 0.0) return fail(HJM_EINVAL, "v_min outflow face needs v_min <= 1");
+    if (m->theta_v * (1.0 - v1) > 0.0) return fail(HJM_EINVAL, "v_max outflow face needs v_max >= 1");
+    const double l2 = m->lambda * m->lambda;
+    if (l2 * rpow(r0, 2.0 * m->gamma) * v0 - 2.0 * m->kappa * y0 < 0.0)
+        return fail(HJM_EINVAL, "y_min outflow face has inflowing drift");
+    if (ax[2].hi_face == HJM_FACE_OUTFLOW) {
+        const double rmax = std::max(std::fabs(r0), std::fabs(r1));
+        if (l2 * rpow(rmax, 2.0 * m->gamma) * v1 - 2.0 * m->kappa * y1 > 0.0)
+            return fail(HJM_EINVAL, "y_max outflow face has inflowing drift");
+    }
+    return HJM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Line-solve tiling.
+// ---------------------------------------------------------------------------
+struct Plan {
+    int r_S, r_L, r_pitch, v_S, v_L, y_S, y_L;
+    int r_tiles, v_tiles, y_tiles;
+    size_t r_lds, v_lds, y_lds;
+};
+
+constexpr size_t kTileLdsBudget = 96 * 1024;
+
+Plan make_plan(int nr, int nv, int ny, const int rows[3])
+{
+    Plan p;
+    p.r_S = (nr + rows[0] - 1) / rows[0];
+    p.r_pitch = nr | 1;  // odd pitch: conflict-free strided LDS access
+    int L = kBlock / p.r_S;
+    const size_t per_line = (size_t)p.r_pitch * 8 + 2 * 8;
+    L = std::max(1, std::min<int>(L, (int)(kTileLdsBudget / per_line)));
+    p.r_L = L;
+    p.r_tiles = (nv * ny + L - 1) / L;
+    p.r_lds = per_line * L;
+    p.v_S = (nv + rows[1] - 1) / rows[1];
+    p.v_L = kBlock / p.v_S;
+    p.v_tiles = (nr * ny + p.v_L - 1) / p.v_L;
+    p.v_lds = (size_t)p.v_L * 2 * 8;
+    p.y_S = (ny + rows[2] - 1) / rows[2];
+    p.y_L = kBlock / p.y_S;
+    p.y_tiles = (nr * nv + p.y_L - 1) / p.y_L;
+    p.y_lds = (size_t)p.y_L * 2 * 8;
+    return p;
+}
+
+// Upper bound of the tiles of any plan (used to size task lists).
+Plan plan_bound(int nr, int nv, int ny)
+{
+    static const int options[3] = {8, 16, 32};
+    Plan b{};
+    for (int o : options) {
+        const int rows[3] = {o, o, o};
+        Plan p = make_plan(nr, nv, ny, rows);
+        b.r_tiles = std::max(b.r_tiles, p.r_tiles);
+        b.v_tiles = std::max(b.v_tiles, p.v_tiles);
+        b.y_tiles = std::max(b.y_tiles, p.y_tiles);
+    }
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout: a bump allocator over the caller's buffer.
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t at = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return at;
+    }
+};
+
+size_t table_doubles(const hjm_axis ax[3], int n_steps)
+{
+    return (size_t)kRT * ax[0].n + (size_t)kVT * ax[1].n + (size_t)kYT * ax[2].n +
+           (size_t)kStepStride * (n_steps + 1);
+}
+
+struct SolveOffsets {
+    size_t U, D, tables;
+};
+
+SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
+{
+    const size_t pts = (size_t)ax[0].n * ax[1].n * ax[2].n;
+    SolveOffsets o;
+    o.U = L.take(pts * 8);
+    o.D = L.take(pts * 8);
+    o.tables = L.take(table_doubles(ax, n_steps) * 8);
+    return o;
+}
+
+// Fill the host tables of one solve: axis coefficient rows, step table.
+void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps,
+                  std::vector<double>& out)
+{
+    const int nr = ax[0].n, nv = ax[1].n, ny = ax[2].n;
+    out.assign(table_doubles(ax, n_steps), 0.0);
+    double* rt = out.data();
+    double* vt = rt + (size_t)kRT * nr;
+    double* yt = vt + (size_t)kVT * nv;
+    double* st = yt + (size_t)kYT * ny;
+    const Mesh mr = make_mesh(ax[0]), mv = make_mesh(ax[1]), my = make_mesh(ax[2]);
+    const double lam = m.lambda, eps = m.epsilon;
+    for (int i = 0; i < nr; ++i) {
+        const double r = mr.z[i], J = mr.J[i], J2 = mr.J2[i];
+        const double rg = rpow(r, m.gamma);
+        const double zr = 0.5 * lam * lam * rg * rg;  // zeta_rr / v
+        rt[RT_R * nr + i] = r;
+        rt[RT_A * nr + i] = zr / (J * J);
+        rt[RT_B1 * nr + i] = 1.0 / J;
+        rt[RT_B2 * nr + i] = zr * J2 / (J * J * J);
+        rt[RT_X * nr + i] = lam * rg / J;
+        rt[RT_Y * nr + i] = lam * lam * rg * rg;
+    }
+    for (int j = 0; j < nv; ++j) {
+        const double v = mv.z[j], J = mv.J[j], J2 = mv.J2[j];
+        const double zv = 0.5 * eps * eps * v;
+        const double mu = m.theta_v * (1.0 - v);
+        vt[VT_V * nv + j] = v;
+        vt[VT_A * nv + j] = zv / (J * J);
+        vt[VT_B * nv + j] = mu / J - zv * J2 / (J * J * J);
+        vt[VT_M * nv + j] = mu / J;
+        vt[VT_X * nv + j] = m.rho * eps * v / J;
+    }
+    for (int k = 0; k < ny; ++k) {
+        yt[YT_Y * ny + k] = my.z[k];
+        yt[YT_I * ny + k] = 1.0 / my.J[k];
+        yt[YT_K * ny + k] = 2.0 * m.kappa * my.z[k];
+    }
+    const Curve cv{m.f_level, m.f_slope, m.f_decay};
+    const double T = p.expiry, TM = p.kind == HJM_BOND ? p.expiry : p.pay;
+    const double dt = T / n_steps;
+    const double PT = cv.P(T), PM = cv.P(TM);
+    for (int n = 0; n <= n_steps; ++n) {
+        double* e = st + (size_t)kStepStride * n;
+        const double t = T - n * dt;
+        const double th = T - (n + 0.5) * dt;
+        e[ST_PHI] = n < n_steps ? cv.ft(th) + m.kappa * cv.f(th) : 0.0;
+        const double Pt = cv.P(t), ft = cv.f(t);
+        const double GT = Gfun(m.kappa, T - t), GM = Gfun(m.kappa, TM - t);
+        e[ST_AT] = PT / Pt * std::exp(GT * ft);
+        e[ST_GT] = GT;
+        e[ST_HT] = 0.5 * GT * GT;
+        e[ST_AM] = PM / Pt * std::exp(GM * ft);
+        e[ST_GM] = GM;
+        e[ST_HM] = 0.5 * GM * GM;
+    }
+}
+
+void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps,
+               const Plan& pl, char* base, const SolveOffsets& o, int32_t* flag)
+{
+    std::memset(&d, 0, sizeof d);
+    d.nr = ax[0].n; d.nv = ax[1].n; d.ny = ax[2].n;
+    d.n_steps = n_steps;
+    d.r_lo_dir = ax[0].lo_face == HJM_FACE_DIRICHLET;
+    d.r_hi_dir = ax[0].hi_face == HJM_FACE_DIRICHLET;
+    d.y_hi_dir = ax[2].hi_face == HJM_FACE_DIRICHLET;
+    d.kind = p.kind;
+    d.r_S = pl.r_S; d.r_L = pl.r_L; d.v_S = pl.v_S; d.v_L = pl.v_L;
+    d.y_S = pl.y_S; d.y_L = pl.y_L;
+    d.r_tiles = pl.r_tiles; d.v_tiles = pl.v_tiles; d.y_tiles = pl.y_tiles;
+    d.r_pitch = pl.r_pitch;
+    d.dt = p.expiry / n_steps;
+    d.tdt = kTheta * d.dt;
+    d.kappa = m.kappa;
+    d.accrual = 1.0 + (p.pay - p.expiry) * p.strike;
+    const double hr1 = ax[0].n - 1.0, hv1 = ax[1].n - 1.0, hy1 = ax[2].n - 1.0;
+    d.ih2r = hr1 * hr1; d.i2hr = 0.5 * hr1;
+    d.ih2v = hv1 * hv1; d.i2hv = 0.5 * hv1;
+    d.i2hy = 0.5 * hy1;
+    d.i4hrhv = 0.25 * hr1 * hv1;
+    d.U = reinterpret_cast<double*>(base + o.U);
+    d.D = reinterpret_cast<double*>(base + o.D);
+    double* t = reinterpret_cast<double*>(base + o.tables);
+    d.rt = t;
+    d.vt = t + (size_t)kRT * ax[0].n;
+    d.yt = d.vt + (size_t)kVT * ax[1].n;
+    d.st = d.yt + (size_t)kYT * ax[2].n;
+    d.flag = flag;
+}
+
+// 4-point Lagrange stencil in mesh coordinates (window centred on the
+// bracketing interval, clamped to the mesh).
+void lagrange4(double x, int n, int* start, double w[4])
+{
+    const double h = 1.0 / (double)(n - 1);
+    int m = (int)std::floor(x / h);
+    m = std::max(0, std::min(m, n - 2));
+    int s = std::max(0, std::min(m - 1, n - 4));
+    for (int a = 0; a < 4; ++a) {
+        const double xa = (double)(s + a) * h;
+        double num = 1.0, den = 1.0;
+        for (int b = 0; b < 4; ++b) {
+            if (b == a) continue;
+            const double xb = (double)(s + b) * h;
+            num *= (x - xb);
+            den *= (xa - xb);
+        }
+        w[a] = num / den;
+    }
+    *start = s;
+}
+
+hjm_status make_readout(const hjm_axis ax[3], double r0, double v0, int solve, Readout* R)
+{
+    if (!(finite(r0) && finite(v0))) return fail(HJM_EINVAL, "non-finite readout point");
+    if (r0 < ax[0].z_min || r0 > ax[0].z_max) return fail(HJM_EINVAL, "r0=%g outside the mesh", r0);
+    if (v0 < ax[1].z_min || v0 > ax[1].z_max) return fail(HJM_EINVAL, "v0=%g outside the mesh", v0);
+    std::memset(R, 0, sizeof *R);
+    R->solve = solve;
+    lagrange4(mesh_x(ax[0], r0), ax[0].n, &R->i0, R->wr);
+    lagrange4(mesh_x(ax[1], v0), ax[1].n, &R->j0, R->wv);
+    return HJM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Single grid.
+// ---------------------------------------------------------------------------
+struct hjm_grid {
+    hjm_axis ax[3];
+    hjm_model model;
+    hjm_payoff payoff;
+    int n_steps = 0;
+    int64_t step = 0;
+    int rows[3];
+    Plan plan;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    SolveDesc desc;
+    SolveDesc* d_desc = nullptr;
+    Readout* d_rq = nullptr;
+    double* d_out = nullptr;
+    int32_t* d_flag = nullptr;
+    std::vector<double> tables;
+    Readout rq;            // host copy of the last readout request
+    double out_host = 0.0;
+    int32_t flag_host = 0;
+    // per-pass timing
+    bool profile = false;
+    std::vector<hipEvent_t> events;  // pool, 2 per bracketed launch
+    std::vector<int> ev_pass;        // pass of each recorded pair
+    size_t ev_used = 0;              // pairs recorded since the last read
+    ~hjm_grid()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+struct GridLayout {
+    size_t desc, rq, out, flag, total;
+    SolveOffsets s;
+};
+
+GridLayout grid_layout(const hjm_axis ax[3], int n_steps)
+{
+    Layout L;
+    GridLayout g;
+    g.desc = L.take(sizeof(SolveDesc));
+    g.rq = L.take(sizeof(Readout));
+    g.out = L.take(sizeof(double));
+    g.flag = L.take(sizeof(int32_t));
+    g.s = layout_solve(L, ax, n_steps);
+    g.total = L.off;
+    return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hjm_status_str(hjm_status s)
+{
+    switch (s) {
+    case HJM_OK: return "HJM_OK";
+    case HJM_EINVAL: return "HJM_EINVAL: invalid argument";
+    case HJM_ENOMEM: return "HJM_ENOMEM: workspace too small";
+    case HJM_EDEVICE: return "HJM_EDEVICE: HIP runtime error";
+    case HJM_ENUMERIC: return "HJM_ENUMERIC: non-finite value or non-positive pivot";
+    case HJM_ESTATE: return "HJM_ESTATE: call out of order";
+    default: return "unknown hjm_status";
+    }
+}
+
+const char* hjm_last_error(void) { return g_last_error.c_str(); }
+
+hjm_status hjm_set_line_tile(int32_t r_rows, int32_t v_rows, int32_t y_rows)
+{
+    for (int32_t v : {r_rows, v_rows, y_rows})
+        if (v != 8 && v != 16 && v != 32) return fail(HJM_EINVAL, "line tile rows must be 8, 16 or 32 (got %d)", v);
+    g_rows[0] = r_rows;
+    g_rows[1] = v_rows;
+    g_rows[2] = y_rows;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_line_tile(int32_t* r_rows, int32_t* v_rows, int32_t* y_rows)
+{
+    if (!r_rows || !v_rows || !y_rows) return fail(HJM_EINVAL, "null argument");
+    *r_rows = g_rows[0];
+    *v_rows = g_rows[1];
+    *y_rows = g_rows[2];
+    return HJM_OK;
+}
+
+hjm_status hjm_workspace_bytes(const hjm_axis ax[3], int32_t n_steps, size_t* bytes)
+{
+    if (!ax || !bytes) return fail(HJM_EINVAL, "null argument");
+    hjm_status st = validate_axes(ax);
+    if (st) return st;
+    if (n_steps <= 0) return fail(HJM_EINVAL, "n_steps must be > 0");
+    *bytes = grid_layout(ax, n_steps).total;
+    return HJM_OK;
+}
+
+hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff, int32_t n_steps,
+                           void* d_workspace, size_t ws_bytes, void* hip_stream, hjm_grid** out)
+{
+    if (!out) return fail(HJM_EINVAL, "null output handle");
+    *out = nullptr;
+    hjm_status st = validate_problem(ax, model, payoff, n_steps);
+    if (st) return st;
+    if (!d_workspace) return fail(HJM_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return fail(HJM_EINVAL, "workspace must be 256-byte aligned");
+    const GridLayout gl = grid_layout(ax, n_steps);
+    if (ws_bytes < gl.total) return fail(HJM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, gl.total);
+    hjm_grid* g = new (std::nothrow) hjm_grid;
+    if (!g) return fail(HJM_EINVAL, "host allocation failed");
+    std::memcpy(g->ax, ax, sizeof g->ax);
+    g->model = *model;
+    g->payoff = *payoff;
+    g->n_steps = n_steps;
+    std::memcpy(g->rows, g_rows, sizeof g->rows);
+    g->plan = make_plan(ax[0].n, ax[1].n, ax[2].n, g->rows);
+    g->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    g->base = reinterpret_cast<char*>(d_workspace);
+    g->d_desc = reinterpret_cast<SolveDesc*>(g->base + gl.desc);
+    g->d_rq = reinterpret_cast<Readout*>(g->base + gl.rq);
+    g->d_out = reinterpret_cast<double*>(g->base + gl.out);
+    g->d_flag = reinterpret_cast<int32_t*>(g->base + gl.flag);
+    fill_desc(g->desc, ax, *model, *payoff, n_steps, g->plan, g->base, gl.s, g->d_flag);
+    build_tables(ax, *model, *payoff, n_steps, g->tables);
+    hipError_t e;
+    if ((e = init_kernel_attributes()) ||
+        (e = hipMemcpyAsync(g->d_desc, &g->desc, sizeof(SolveDesc), hipMemcpyHostToDevice, g->stream)) ||
+        (e = hipMemcpyAsync(const_cast<double*>(g->desc.rt), g->tables.data(), g->tables.size() * 8,
+                            hipMemcpyHostToDevice, g->stream)) ||
+        (e = launch_terminal(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n * ax[2].n, g->stream)) ||
+        (e = hipStreamSynchronize(g->stream))) {
+        delete g;
+        return hip_fail(e, "hjm_grid_create");
+    }
+    *out = g;
+    return HJM_OK;
+}
+
+hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
+{
+    if (!g) return fail(HJM_EINVAL, "null grid");
+    if (k < 0) return fail(HJM_EINVAL, "negative step count");
+    if (g->step + k > g->n_steps)
+        return fail(HJM_ESTATE, "%d more steps would pass n_steps=%d (at step %lld)", k, g->n_steps, (long long)g->step);
+    const Plan& p = g->plan;
+    for (int32_t c = 0; c < k; ++c) {
+        const int n = (int)g->step;
+        for (int pass = 0; pass < 3; ++pass) {
+            hipError_t e = hipSuccess;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (g->profile) {
+                if (g->events.size() < 2 * (g->ev_used + 1)) {
+                    for (int q = 0; q < 2 && !e; ++q) {
+                        hipEvent_t ev;
+                        e = hipEventCreate(&ev);
+                        if (!e) g->events.push_back(ev);
+                    }
+                    g->ev_pass.resize(g->events.size() / 2);
+                }
+                if (e) return hip_fail(e, "hjm_adi_step (profile events)");
+                e0 = g->events[2 * g->ev_used];
+                e1 = g->events[2 * g->ev_used + 1];
+                g->ev_pass[g->ev_used] = pass;
+                if ((e = hipEventRecord(e0, g->stream))) return hip_fail(e, "hipEventRecord");
+            }
+            if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
+            else if (pass == 1) e = launch_v(g->rows[1], g->d_desc, nullptr, p.v_tiles, p.v_lds, g->stream);
+            else e = launch_yu(g->rows[2], g->d_desc, nullptr, p.y_tiles, p.y_lds, g->stream);
+            if (e) return hip_fail(e, "hjm_adi_step");
+            if (g->profile) {
+                if ((e = hipEventRecord(e1, g->stream))) return hip_fail(e, "hipEventRecord");
+                g->ev_used += 1;
+            }
+        }
+        g->step += 1;
+    }
+    return HJM_OK;
+}
+
+hjm_status hjm_price(hjm_grid* g, double r0, double v0, double* out)
+{
+    if (!g || !out) return fail(HJM_EINVAL, "null argument");
+    if (g->step != g->n_steps)
+        return fail(HJM_ESTATE, "price needs all %d steps (taken %lld)", g->n_steps, (long long)g->step);
+    hjm_status st = make_readout(g->ax, r0, v0, 0, &g->rq);
+    if (st) return st;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(g->d_rq, &g->rq, sizeof g->rq, hipMemcpyHostToDevice, g->stream)) ||
+        (e = launch_health(g->d_desc, 1, (int64_t)g->ax[0].n * g->ax[1].n * g->ax[2].n, g->stream)) ||
+        (e = launch_readout(g->d_desc, g->d_rq, 1, g->d_out, g->stream)) ||
+        (e = hipMemcpyAsync(&g->out_host, g->d_out, sizeof(double), hipMemcpyDeviceToHost, g->stream)) ||
+        (e = hipMemcpyAsync(&g->flag_host, g->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream)) ||
+        (e = hipStreamSynchronize(g->stream)))
+        return hip_fail(e, "hjm_price");
+    if (g->flag_host) return fail(HJM_ENUMERIC, "non-finite value or non-positive pivot in the solve");
+    *out = g->out_host;
+    return HJM_OK;
+}
+
+hjm_status hjm_grid_solution(hjm_grid* g, double** d_U, int64_t* step)
+{
+    if (!g || !d_U || !step) return fail(HJM_EINVAL, "null argument");
+    *d_U = g->desc.U;
+    *step = g->step;
+    return HJM_OK;
+}
+
+hjm_status hjm_grid_set_step(hjm_grid* g, int64_t step)
+{
+    if (!g) return fail(HJM_EINVAL, "null grid");
+    if (step < 0 || step > g->n_steps) return fail(HJM_EINVAL, "step %lld outside [0, %d]", (long long)step, g->n_steps);
+    g->step = step;
+    return HJM_OK;
+}
+
+hjm_status hjm_grid_destroy(hjm_grid* g)
+{
+    delete g;
+    return HJM_OK;
+}
+
+hjm_status hjm_grid_profile(hjm_grid* g, int32_t enable)
+{
+    if (!g) return fail(HJM_EINVAL, "null grid");
+    g->profile = enable != 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[3], int64_t launches[3])
+{
+    if (!g || !ms || !launches) return fail(HJM_EINVAL, "null argument");
+    for (int q = 0; q < 3; ++q) { ms[q] = 0.0; launches[q] = 0; }
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e) return hip_fail(e, "hjm_grid_profile_read");
+    for (size_t u = 0; u < g->ev_used; ++u) {
+        float t = 0.0f;
+        if ((e = hipEventElapsedTime(&t, g->events[2 * u], g->events[2 * u + 1])))
+            return hip_fail(e, "hipEventElapsedTime");
+        ms[g->ev_pass[u]] += t;
+        launches[g->ev_pass[u]] += 1;
+    }
+    g->ev_used = 0;
+    return HJM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched solves.
+// ---------------------------------------------------------------------------
+struct hjm_batch {
+    int n = 0;
+    std::vector<hjm_axis> ax;  // 3 per solve
+    std::vector<int> n_steps;
+    int rows[3];
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    SolveDesc* d_desc = nullptr;
+    int2* d_tr = nullptr;
+    int2* d_tv = nullptr;
+    int2* d_ty = nullptr;
+    Readout* d_rq = nullptr;
+    double* d_out = nullptr;
+    int32_t* d_flags = nullptr;
+    std::vector<SolveDesc> descs;
+    std::vector<std::vector<double>> tables;
+    std::vector<int2> tr, tv, ty;
+    std::vector<int> cnt_r, cnt_v, cnt_y;  // active task prefix per step
+    size_t lds_r = 0, lds_v = 0, lds_y = 0;
+    int max_steps = 0;
+    int64_t max_points = 0;
+    hipGraphExec_t graph = nullptr;
+    bool ran = false;
+    std::vector<Readout> rq;
+    std::vector<int32_t> flags_host;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t desc, tr, tv, ty, rq, out, flags, total;
+    std::vector<SolveOffsets> s;
+};
+
+BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
+{
+    Layout L;
+    BatchLayout b;
+    size_t nr_t = 0, nv_t = 0, ny_t = 0;
+    for (int s = 0; s < n; ++s) {
+        Plan pb = plan_bound(ax[3 * s].n, ax[3 * s + 1].n, ax[3 * s + 2].n);
+        nr_t += pb.r_tiles;
+        nv_t += pb.v_tiles;
+        ny_t += pb.y_tiles;
+    }
+    b.desc = L.take(sizeof(SolveDesc) * n);
+    b.tr = L.take(sizeof(int2) * nr_t);
+    b.tv = L.take(sizeof(int2) * nv_t);
+    b.ty = L.take(sizeof(int2) * ny_t);
+    b.rq = L.take(sizeof(Readout) * n);
+    b.out = L.take(sizeof(double) * n);
+    b.flags = L.take(sizeof(int32_t) * n);
+    b.s.resize(n);
+    for (int s = 0; s < n; ++s) b.s[s] = layout_solve(L, ax + 3 * s, n_steps[s]);
+    b.total = L.off;
+    return b;
+}
+
+hjm_status batch_enqueue(hjm_batch* b)
+{
+    hipError_t e;
+    if ((e = launch_terminal(b->d_desc, b->n, b->max_points, b->stream))) return hip_fail(e, "batch terminal");
+    for (int step = 0; step < b->max_steps; ++step) {
+        if ((e = launch_xr(b->rows[0], b->d_desc, b->d_tr, b->cnt_r[step], step, b->lds_r, b->stream)) ||
+            (e = launch_v(b->rows[1], b->d_desc, b->d_tv, b->cnt_v[step], b->lds_v, b->stream)) ||
+            (e = launch_yu(b->rows[2], b->d_desc, b->d_ty, b->cnt_y[step], b->lds_y, b->stream)))
+            return hip_fail(e, "batch step");
+    }
+    return HJM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hjm_status hjm_batch_workspace_bytes(int32_t n, const hjm_axis* ax, const int32_t* n_steps, size_t* bytes)
+{
+    if (n <= 0 || !ax || !n_steps || !bytes) return fail(HJM_EINVAL, "invalid batch arguments");
+    for (int s = 0; s < n; ++s) {
+        hjm_status st = validate_axes(ax + 3 * s);
+        if (st) return fail(st, "solve %d: %s", s, g_last_error.c_str());
+        if (n_steps[s] <= 0) return fail(HJM_EINVAL, "solve %d: n_steps must be > 0", s);
+    }
+    *bytes = batch_layout(n, ax, n_steps).total;
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* model, const hjm_payoff* payoff,
+                            const int32_t* n_steps, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                            hjm_batch** out)
+{
+    if (!out) return fail(HJM_EINVAL, "null output handle");
+    *out = nullptr;
+    if (n <= 0 || !ax || !model || !payoff || !n_steps) return fail(HJM_EINVAL, "invalid batch arguments");
+    for (int s = 0; s < n; ++s) {
+        hjm_status st = validate_problem(ax + 3 * s, model + s, payoff + s, n_steps[s]);
+        if (st) return fail(st, "solve %d: %s", s, g_last_error.c_str());
+    }
+    if (!d_workspace) return fail(HJM_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return fail(HJM_EINVAL, "workspace must be 256-byte aligned");
+    const BatchLayout bl = batch_layout(n, ax, n_steps);
+    if (ws_bytes < bl.total) return fail(HJM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, bl.total);
+    hjm_batch* b = new (std::nothrow) hjm_batch;
+    if (!b) return fail(HJM_EINVAL, "host allocation failed");
+    b->n = n;
+    b->ax.assign(ax, ax + 3 * n);
+    b->n_steps.assign(n_steps, n_steps + n);
+    std::memcpy(b->rows, g_rows, sizeof b->rows);
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->base = reinterpret_cast<char*>(d_workspace);
+    b->d_desc = reinterpret_cast<SolveDesc*>(b->base + bl.desc);
+    b->d_tr = reinterpret_cast<int2*>(b->base + bl.tr);
+    b->d_tv = reinterpret_cast<int2*>(b->base + bl.tv);
+    b->d_ty = reinterpret_cast<int2*>(b->base + bl.ty);
+    b->d_rq = reinterpret_cast<Readout*>(b->base + bl.rq);
+    b->d_out = reinterpret_cast<double*>(b->base + bl.out);
+    b->d_flags = reinterpret_cast<int32_t*>(b->base + bl.flags);
+    b->descs.resize(n);
+    b->tables.resize(n);
+    // Solves ordered by step count, longest first: the solves still running
+    // at step n are a prefix, so each launch covers a prefix of the task list.
+    std::vector<int> order(n);
+    for (int s = 0; s < n; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n_steps[a] > n_steps[c]; });
+    for (int s = 0; s < n; ++s) {
+        const hjm_axis* a = ax + 3 * s;
+        Plan pl = make_plan(a[0].n, a[1].n, a[2].n, b->rows);
+        fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], pl, b->base, bl.s[s], b->d_flags + s);
+        build_tables(a, model[s], payoff[s], n_steps[s], b->tables[s]);
+        b->lds_r = std::max(b->lds_r, pl.r_lds);
+        b->lds_v = std::max(b->lds_v, pl.v_lds);
+        b->lds_y = std::max(b->lds_y, pl.y_lds);
+        b->max_steps = std::max(b->max_steps, n_steps[s]);
+        b->max_points = std::max<int64_t>(b->max_points, (int64_t)a[0].n * a[1].n * a[2].n);
+    }
+    for (int s : order) {
+        const SolveDesc& d = b->descs[s];
+        for (int t = 0; t < d.r_tiles; ++t) b->tr.push_back(make_int2(s, t));
+        for (int t = 0; t < d.v_tiles; ++t) b->tv.push_back(make_int2(s, t));
+        for (int t = 0; t < d.y_tiles; ++t) b->ty.push_back(make_int2(s, t));
+    }
+    b->cnt_r.assign(b->max_steps, 0);
+    b->cnt_v.assign(b->max_steps, 0);
+    b->cnt_y.assign(b->max_steps, 0);
+    for (int s : order) {
+        const SolveDesc& d = b->descs[s];
+        for (int step = 0; step < d.n_steps; ++step) {
+            b->cnt_r[step] += d.r_tiles;
+            b->cnt_v[step] += d.v_tiles;
+            b->cnt_y[step] += d.y_tiles;
+        }
+    }
+    hipError_t e = init_kernel_attributes();
+    if (!e) e = hipMemcpyAsync(b->d_desc, b->descs.data(), sizeof(SolveDesc) * n, hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipMemcpyAsync(b->d_tr, b->tr.data(), sizeof(int2) * b->tr.size(), hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipMemcpyAsync(b->d_tv, b->tv.data(), sizeof(int2) * b->tv.size(), hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipMemcpyAsync(b->d_ty, b->ty.data(), sizeof(int2) * b->ty.size(), hipMemcpyHostToDevice, b->stream);
+    for (int s = 0; s < n && !e; ++s)
+        e = hipMemcpyAsync(const_cast<double*>(b->descs[s].rt), b->tables[s].data(), b->tables[s].size() * 8,
+                           hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipStreamSynchronize(b->stream);
+    if (e) {
+        delete b;
+        return hip_fail(e, "hjm_batch_create");
+    }
+    *out = b;
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph)
+{
+    if (!b) return fail(HJM_EINVAL, "null batch");
+    if (!use_graph) {
+        hjm_status st = batch_enqueue(b);
+        if (st) return st;
+        b->ran = true;
+        return HJM_OK;
+    }
+    if (!b->stream) return fail(HJM_EINVAL, "graph mode needs a non-null stream");
+    hipError_t e;
+    if (!b->graph) {
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)))
+            return hip_fail(e, "hipStreamBeginCapture");
+        hjm_status st = batch_enqueue(b);
+        e = hipStreamEndCapture(b->stream, &graph);
+        if (st) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e) {
+            b->graph = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+    }
+    if ((e = hipGraphLaunch(b->graph, b->stream))) return hip_fail(e, "hipGraphLaunch");
+    b->ran = true;
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, double* out)
+{
+    if (!b || !r0 || !v0 || !out) return fail(HJM_EINVAL, "null argument");
+    if (!b->ran) return fail(HJM_ESTATE, "hjm_batch_run has not been called");
+    b->rq.resize(b->n);
+    b->flags_host.assign(b->n, 0);
+    for (int s = 0; s < b->n; ++s) {
+        hjm_status st = make_readout(&b->ax[3 * s], r0[s], v0[s], s, &b->rq[s]);
+        if (st) return fail(st, "solve %d: %s", s, g_last_error.c_str());
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(b->d_rq, b->rq.data(), sizeof(Readout) * b->n, hipMemcpyHostToDevice, b->stream)) ||
+        (e = launch_health(b->d_desc, b->n, b->max_points, b->stream)) ||
+        (e = launch_readout(b->d_desc, b->d_rq, b->n, b->d_out, b->stream)) ||
+        (e = hipMemcpyAsync(out, b->d_out, sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream)) ||
+        (e = hipMemcpyAsync(b->flags_host.data(), b->d_flags, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost,
+                            b->stream)) ||
+        (e = hipStreamSynchronize(b->stream)))
+        return hip_fail(e, "hjm_batch_prices");
+    for (int s = 0; s < b->n; ++s)
+        if (b->flags_host[s]) return fail(HJM_ENUMERIC, "solve %d: non-finite value or non-positive pivot", s);
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_destroy(hjm_batch* b)
+{
+    if (b && b->graph) (void)hipGraphExecDestroy(b->graph);
+    delete b;
+    return HJM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libhjm (include/hjm.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch provides device memory (the workspace tensors) and streams.
+If libhjm.so has not been built this module raises on first use; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhjm.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5
+FACE_OUTFLOW, FACE_DIRICHLET = 0, 1
+BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
+
+
+class HjmError(RuntimeError):
+    def __init__(self, status: int, text: str, detail: str):
+        super().__init__(f"{text} ({detail})" if detail else text)
+        self.status = status
+        self.detail = detail
+
+
+class Axis(C.Structure):
+    _fields_ = [("n", C.c_int32), ("lo_face", C.c_int32), ("hi_face", C.c_int32), ("reserved", C.c_int32),
+                ("z_min", C.c_double), ("z_max", C.c_double), ("center", C.c_double), ("alpha", C.c_double)]
+
+
+class Model(C.Structure):
+    _fields_ = [("kappa", C.c_double), ("theta_v", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
+                ("epsilon", C.c_double), ("rho", C.c_double), ("f_level", C.c_double), ("f_slope", C.c_double),
+                ("f_decay", C.c_double)]
+
+
+class Payoff(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("expiry", C.c_double), ("pay", C.c_double),
+                ("strike", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhjm.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1108_1688_amd.build`")
+    l = C.CDLL(LIB_PATH)
+    st, vp, i32, i64, sz, d = C.c_int32, C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
+    P = C.POINTER
+    sig = {
+        "hjm_workspace_bytes": (st, [P(Axis), i32, P(sz)]),
+        "hjm_grid_create": (st, [P(Axis), P(Model), P(Payoff), i32, vp, sz, vp, P(vp)]),
+        "hjm_adi_step": (st, [vp, i32]),
+        "hjm_price": (st, [vp, d, d, P(d)]),
+        "hjm_grid_solution": (st, [vp, P(vp), P(i64)]),
+        "hjm_grid_set_step": (st, [vp, i64]),
+        "hjm_grid_destroy": (st, [vp]),
+        "hjm_grid_profile": (st, [vp, i32]),
+        "hjm_grid_profile_read": (st, [vp, P(d), P(i64)]),
+        "hjm_batch_workspace_bytes": (st, [i32, P(Axis), P(i32), P(sz)]),
+        "hjm_batch_create": (st, [i32, P(Axis), P(Model), P(Payoff), P(i32), vp, sz, vp, P(vp)]),
+        "hjm_batch_run": (st, [vp, i32]),
+        "hjm_batch_prices": (st, [vp, P(d), P(d), P(d)]),
+        "hjm_batch_destroy": (st, [vp]),
+        "hjm_set_line_tile": (st, [i32, i32, i32]),
+        "hjm_get_line_tile": (st, [P(i32), P(i32), P(i32)]),
+        "hjm_status_str": (C.c_char_p, [st]),
+        "hjm_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(l, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = l
+    return l
+
+
+def check(status: int) -> None:
+    if status != OK:
+        L = lib()
+        raise HjmError(status, L.hjm_status_str(status).decode(), L.hjm_last_error().decode())
+
+
+def make_axes(spec_axes) -> "C.Array":
+    arr = (Axis * 3)()
+    for a, s in zip(arr, spec_axes):
+        a.n, a.lo_face, a.hi_face = s.n, s.lo_face, s.hi_face
+        a.z_min, a.z_max, a.center, a.alpha = s.z_min, s.z_max, s.center, s.alpha
+    return arr
+
+
+def make_model(m) -> Model:
+    return Model(m.kappa, m.theta_v, m.lam, m.gamma, m.epsilon, m.rho, m.f_level, m.f_slope, m.f_decay)
+
+
+def make_payoff(p) -> Payoff:
+    return Payoff(p.kind, 0, p.expiry, p.pay, p.strike)
+
+
+def set_line_tile(r_rows: int, v_rows: int, y_rows: int) -> None:
+    """Rows per thread of the r, v, y line solves (8, 16 or 32) for handles created afterwards."""
+    check(lib().hjm_set_line_tile(r_rows, v_rows, y_rows))
+
+
+def get_line_tile():
+    r, v, y = C.c_int32(), C.c_int32(), C.c_int32()
+    check(lib().hjm_get_line_tile(C.byref(r), C.byref(v), C.byref(y)))
+    return r.value, v.value, y.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace tensor is not 256-byte aligned")
+    return ws
+
+
+def workspace_bytes(spec) -> int:
+    nbytes = C.c_size_t()
+    check(lib().hjm_workspace_bytes(make_axes(spec.axes), spec.n_steps, C.byref(nbytes)))
+    return nbytes.value
+
+
+def _stream_handle(stream) -> C.c_void_p:
+    return C.c_void_p(stream.cuda_stream if stream is not None else 0)
+
+
+class Grid:
+    """One solve: workspace in a torch tensor, work on a torch stream."""
+
+    def __init__(self, spec, stream=None, device: Optional[str] = None, workspace=None):
+        torch = _torch()
+        L = lib()
+        self.spec = spec
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ax = make_axes(spec.axes)
+        self._model = make_model(spec.model)
+        self._payoff = make_payoff(spec.payoff)
+        nbytes = C.c_size_t()
+        check(L.hjm_workspace_bytes(self._ax, spec.n_steps, C.byref(nbytes)))
+        if workspace is not None:
+            if workspace.dtype != torch.float64 or workspace.numel() * 8 < nbytes.value:
+                raise ValueError("workspace must be a float64 tensor of at least the required bytes")
+            if workspace.data_ptr() % 256:
+                raise ValueError("workspace must be 256-byte aligned")
+            self.ws = workspace
+        else:
+            self.ws = _workspace(nbytes.value, self.device)
+        h = C.c_void_p()
+        check(L.hjm_grid_create(self._ax, C.byref(self._model), C.byref(self._payoff), spec.n_steps,
+                                C.c_void_p(self.ws.data_ptr()), nbytes.value, _stream_handle(self.stream),
+                                C.byref(h)))
+        self._h = h
+
+    def step(self, k: Optional[int] = None) -> "Grid":
+        """Enqueue k Douglas steps (all remaining ones by default)."""
+        if k is None:
+            k = self.spec.n_steps - self.steps_taken
+        check(lib().hjm_adi_step(self._h, int(k)))
+        return self
+
+    def price(self, r0: Optional[float] = None, v0: Optional[float] = None) -> float:
+        out = C.c_double()
+        r0 = self.spec.r0 if r0 is None else r0
+        v0 = self.spec.v0 if v0 is None else v0
+        check(lib().hjm_price(self._h, float(r0), float(v0), C.byref(out)))
+        return out.value
+
+    @property
+    def steps_taken(self) -> int:
+        p, s = C.c_void_p(), C.c_int64()
+        check(lib().hjm_grid_solution(self._h, C.byref(p), C.byref(s)))
+        return s.value
+
+    def solution(self):
+        """The device grid U as a (ny, nv, nr) float64 view into the workspace."""
+        p, s = C.c_void_p(), C.c_int64()
+        check(lib().hjm_grid_solution(self._h, C.byref(p), C.byref(s)))
+        off = (p.value - self.ws.data_ptr()) // 8
+        npts = self.spec.points
+        return self.ws[off:off + npts].view(*self.spec.shape)
+
+    def set_step(self, step: int) -> None:
+        check(lib().hjm_grid_set_step(self._h, int(step)))
+
+    def profile(self, enable: bool = True) -> None:
+        """Bracket every pass launch with HIP events on the grid's stream."""
+        check(lib().hjm_grid_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(ms per pass, launches per pass) since the last read; passes are
+        explicit+r, v, y+update.  Synchronises the stream."""
+        ms = (C.c_double * 3)()
+        n = (C.c_int64 * 3)()
+        check(lib().hjm_grid_profile_read(self._h, ms, n))
+        return list(ms), list(n)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().hjm_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent solves advanced together (one launch per pass per step)."""
+
+    def __init__(self, specs: Sequence, stream=None, device: Optional[str] = None):
+        torch = _torch()
+        L = lib()
+        self.specs = list(specs)
+        n = len(self.specs)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ax = (Axis * (3 * n))()
+        for s, sp in enumerate(self.specs):
+            for a in range(3):
+                x, y = self._ax[3 * s + a], sp.axes[a]
+                x.n, x.lo_face, x.hi_face = y.n, y.lo_face, y.hi_face
+                x.z_min, x.z_max, x.center, x.alpha = y.z_min, y.z_max, y.center, y.alpha
+        self._models = (Model * n)(*[make_model(sp.model) for sp in self.specs])
+        self._payoffs = (Payoff * n)(*[make_payoff(sp.payoff) for sp in self.specs])
+        self._steps = (C.c_int32 * n)(*[sp.n_steps for sp in self.specs])
+        nbytes = C.c_size_t()
+        check(L.hjm_batch_workspace_bytes(n, self._ax, self._steps, C.byref(nbytes)))
+        self.ws = _workspace(nbytes.value, self.device)
+        h = C.c_void_p()
+        check(L.hjm_batch_create(n, self._ax, self._models, self._payoffs, self._steps,
+                                 C.c_void_p(self.ws.data_ptr()), nbytes.value, _stream_handle(self.stream),
+                                 C.byref(h)))
+        self._h = h
+
+    def run(self, graph: bool = False) -> "Batch":
+        check(lib().hjm_batch_run(self._h, 1 if graph else 0))
+        return self
+
+    def prices(self, r0=None, v0=None) -> np.ndarray:
+        n = len(self.specs)
+        r0 = np.array([sp.r0 for sp in self.specs] if r0 is None else r0, dtype=np.float64)
+        v0 = np.array([sp.v0 for sp in self.specs] if v0 is None else v0, dtype=np.float64)
+        out = np.empty(n)
+        dp = C.POINTER(C.c_double)
+        check(lib().hjm_batch_prices(self._h, r0.ctypes.data_as(dp), v0.ctypes.data_as(dp), out.ctypes.data_as(dp)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().hjm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bar: every readout price within 1e-12 of the oracle's relative to the readout
+scale max(|p|, R(|U|)), where R(|U|) is the same 4x4 Lagrange readout applied
+to |U| (for the caplets and bonds U > 0 near the readout point, so this is the
+plain relative bound |dp| <= 1e-12 |p|; it only differs for a readout that is
+itself a cancellation, such as the linear forward payoff at the money), and
+the whole grid within max|dU| / max|U| <= 1e-12.  Shapes span
+several tiles and segments with ragged tails; every line-tile setting is used;
+the full-size 256x128x128 grid is checked element-wise after the first steps
+in the launch configuration the benchmark times, a full 256x128x128 solve
+(the 1-year caplet) is checked end to end, and the 10-year solve through
+properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from adapt import to_oracle
+from paper_1108_1688_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+torch = pytest.importorskip("torch")
+hjm = pytest.importorskip("paper_1108_1688_amd.hjm")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    old = hjm.get_line_tile()
+    yield
+    hjm.set_line_tile(*old)
+
+
+def gpu_grid(spec, steps=None, price=True):
+    print(f"[gpu] shape={spec.shape} steps={steps} kind={spec.payoff.kind} tile={hjm.get_line_tile()}", flush=True)
+    g = hjm.Grid(spec)
+    g.step(steps)
+    p = g.price() if (price and g.steps_taken == spec.n_steps) else None
+    U = g.solution().cpu().numpy().copy()
+    g.close()
+    return U, p
+
+
+class OraclePrice(float):
+    """Oracle price carrying its readout scale R(|U|)."""
+    scale = 0.0
+
+
+def oracle_grid(spec, steps=None):
+    p = to_oracle(spec)
+    U = O.run(p, 0, spec.n_steps if steps is None else steps)
+    price = None
+    if steps in (None, spec.n_steps):
+        price = OraclePrice(O.readout(p, U, spec.r0, spec.v0))
+        price.scale = O.readout(p, np.abs(U), spec.r0, spec.v0)
+    return U, price
+
+
+def assert_grid(Ug, Uo, tol=REL):
+    assert np.isfinite(Ug).all()
+    err = np.abs(Ug - Uo).max() / np.abs(Uo).max()
+    assert err <= tol, f"grid rel err {err:.3e}"
+    return err
+
+
+def assert_price(pg, po, tol=REL):
+    scale = max(abs(po), getattr(po, "scale", 0.0))
+    assert abs(pg - po) <= tol * scale, (pg, float(po), abs(pg - po) / scale)
+    if po.__class__ is OraclePrice and po > 0 and po.scale <= abs(po) * (1 + 1e-12):
+        assert abs(pg - po) <= tol * abs(po)
+
+
+@pytest.mark.parametrize("which", [0, 1], ids=["bond", "caplet"])
+def test_config1_full_solve(which):
+    s = W.config1()[which]
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+def _sloped(shape, steps, kind=W.CAPLET, rho=-0.6, gaussian=False):
+    m = W.ModelSpec(kappa=0.08, epsilon=0.45, rho=rho, **W.CURVE_SLOPED)
+    k = W.atm_strike(m, 2.0, 3.0)
+    s = W.SolveSpec(W.default_axes(*shape, k), m, W.PayoffSpec(kind, 2.0, 3.0, k), steps, m.f_level)
+    if gaussian:
+        s = W.gaussian_variant(s)
+    return s
+
+
+SHAPES = [(5, 5, 5), (37, 29, 41), (64, 48, 33), (33, 65, 17), (100, 40, 40), (257, 9, 11)]
+TILES = [(8, 8, 8), (16, 16, 16), (32, 32, 32), (8, 16, 32)]
+
+
+@pytest.mark.parametrize("tile", TILES, ids=lambda t: "x".join(map(str, t)))
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_ragged_shapes_and_tiles(shape, tile):
+    hjm.set_line_tile(*tile)
+    s = _sloped(shape, 6)
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+@pytest.mark.parametrize("kind", [W.BOND, W.FLOORLET, W.FORWARD])
+def test_payoff_kinds(kind):
+    s = _sloped((48, 32, 24), 20, kind=kind)
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+def test_gaussian_mode_both_r_faces_dirichlet():
+    s = _sloped((40, 24, 24), 20, gaussian=True)
+    assert s.axes[0].lo_face == W.DIRICHLET and s.axes[0].z_min < 0
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+def test_outflow_r_max_face():
+    from dataclasses import replace
+    s = _sloped((40, 24, 24), 12)
+    ax = (replace(s.axes[0], hi_face=W.OUTFLOW), s.axes[1], s.axes[2])
+    s = replace(s, axes=ax)
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+def test_zero_correlation_and_zero_kappa():
+    from dataclasses import replace
+    s = _sloped((40, 24, 24), 12, rho=0.0)
+    s = replace(s, model=replace(s.model, kappa=0.0))
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+def test_config2_full_solve_atm():
+    s = W.config2()[1]
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    err = assert_grid(Ug, Uo)
+    assert_price(pg, po)
+    print(f"config2 grid rel err {err:.2e}, price {pg!r} vs {po!r}")
+
+
+def test_config3_full_size_first_steps_elementwise():
+    """256x128x128, the 10-year caplet, default tiles (the benchmark's launch
+    configuration): three Douglas steps compared on every node."""
+    s = W.config3()[-1]
+    Ug, _ = gpu_grid(s, steps=3, price=False)
+    Uo, _ = oracle_grid(s, steps=3)
+    assert_grid(Ug, Uo)
+
+
+def test_config3_one_year_caplet_full_solve():
+    s = W.config3()[0]
+    assert s.n_steps == 40 and s.shape == (128, 128, 256)
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    err = assert_grid(Ug, Uo)
+    assert_price(pg, po)
+    print(f"config3 1y grid rel err {err:.2e}, price rel err {abs(pg - po) / po:.2e}")
+
+
+def test_config3_ten_year_properties():
+    """Full 400-step solves at 256x128x128: caplet - floorlet equals the linear
+    payoff's solve (linearity), which reproduces P(0,T) - Delta P(0,T_M)."""
+    from dataclasses import replace
+    s = W.config3()[-1]
+    prices = {}
+    grids = {}
+    for kind in (W.CAPLET, W.FLOORLET, W.FORWARD):
+        sk = replace(s, payoff=replace(s.payoff, kind=kind))
+        grids[kind], prices[kind] = gpu_grid(sk)
+    lin = grids[W.FORWARD]
+    assert np.abs(grids[W.CAPLET] - grids[W.FLOORLET] - lin).max() <= 1e-12 * np.abs(lin).max()
+    p = to_oracle(s)
+    T, TM, K = s.payoff.expiry, s.payoff.pay, s.payoff.strike
+    closed = O.discount(p, T) - (1 + (TM - T) * K) * O.discount(p, TM)
+    assert abs(prices[W.FORWARD] - closed) < 2e-5
+    assert 0.0 < prices[W.CAPLET] < O.discount(p, T)
