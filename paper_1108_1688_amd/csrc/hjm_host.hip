@@ -17,7 +17,7 @@ using namespace hjm;
 namespace {
 
 thread_local std::string g_last_error;
-int g_rows[3] = {16, 16, 16};  // rows per thread of the r, v, y line solves
+int g_rows[3] = {8, 16, 16};  // rows per thread of the r, v, y line solves
 
 hjm_status fail(hjm_status code, const char* fmt, ...)
 {
@@ -173,33 +173,83 @@ hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_
 // Line-solve tiling.
 // ---------------------------------------------------------------------------
 struct Plan {
+    bool r_spike;
     int r_S, r_L, r_pitch, v_S, v_L, y_S, y_L;
     int r_tiles, v_tiles, y_tiles;
     size_t r_lds, v_lds, y_lds;
 };
 
 constexpr size_t kTileLdsBudget = 96 * 1024;
+constexpr int kLCDoubles = 16;  // per-line constants of the explicit phase
 
-Plan make_plan(int nr, int nv, int ny, const int rows[3])
+// r_spike: the r sweep uses the spike solve (reduced-system scratch per line).
+Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
 {
     Plan p;
+    p.r_spike = r_spike;
     p.r_S = (nr + rows[0] - 1) / rows[0];
-    p.r_pitch = nr | 1;  // odd pitch: conflict-free strided LDS access
+    p.r_pitch = (nr + 4) | 1;  // two zero pads per side, odd: conflict-free strided LDS access
     int L = kBlock / p.r_S;
-    const size_t per_line = (size_t)p.r_pitch * 8 + 2 * 8;
-    L = std::max(1, std::min<int>(L, (int)(kTileLdsBudget / per_line)));
+    const size_t per_line = (size_t)p.r_pitch * 8 + (size_t)kLCDoubles * 8 +
+                            (r_spike ? (size_t)p.r_S * kRed * 8 : 16);
+    const size_t fixed = (size_t)4 * p.r_pitch * 8 + (size_t)6 * nr * 8;  // halo lines + r solve table
+    L = std::max(1, std::min<int>(L, (int)((kTileLdsBudget - std::min(fixed, kTileLdsBudget / 2)) / per_line)));
+    // the explicit phase gives each thread at most rows[0] + 1 lines of its column
+    int tpl = 1;
+    while (tpl < nr) tpl <<= 1;
+    tpl = std::min(tpl, kBlock);
+    const int lpp = kBlock / tpl;
+    const int col_reps = (nr + tpl - 1) / tpl;  // columns per thread (nr > kBlock)
+    // (ceil(L / lpp) lines x col_reps columns <= rows[0] + 1 points; the tile
+    // with its 4 halo lines <= rows[0] + 8 points)
+    L = std::max(1, std::min(L, lpp * std::max(1, (rows[0] + 1) / col_reps)));
+    while (L > 1 && ((L + 4 + lpp - 1) / lpp) * col_reps > rows[0] + 8) --L;
     p.r_L = L;
     p.r_tiles = (nv * ny + L - 1) / L;
-    p.r_lds = per_line * L;
+    p.r_lds = fixed + per_line * L;
     p.v_S = (nv + rows[1] - 1) / rows[1];
     p.v_L = kBlock / p.v_S;
     p.v_tiles = (nr * ny + p.v_L - 1) / p.v_L;
-    p.v_lds = (size_t)p.v_L * 2 * 8;
+    p.v_lds = 2 * (size_t)p.v_L * 8;
     p.y_S = (ny + rows[2] - 1) / rows[2];
     p.y_L = kBlock / p.y_S;
     p.y_tiles = (nr * nv + p.y_L - 1) / p.y_L;
-    p.y_lds = (size_t)p.y_L * 2 * 8;
+    p.y_lds = 2 * (size_t)p.y_L * 8;
     return p;
+}
+
+// The spike solve is accurate when every r row is diagonally dominant, which
+// holds when the cell Courant number theta dt |b| / (2 h_r) <= 0.4 (then
+// B - |A| - |C| >= 1 - 2 * 0.4).  b = (c - kappa r) / J - v zeta_rr J2 / (v J^3)
+// is affine in c = f_t + kappa f + y and in v, so its extremes over all rows,
+// lines and steps sit at the corners of those ranges.
+bool r_spike_ok(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps)
+{
+    const Curve cv{m.f_level, m.f_slope, m.f_decay};
+    const double T = p.expiry, dt = T / n_steps, tdt = kTheta * dt;
+    double phi_lo = 1e300, phi_hi = -1e300;
+    for (int n = 0; n < n_steps; ++n) {
+        const double t = T - (n + 0.5) * dt;
+        const double phi = cv.ft(t) + m.kappa * cv.f(t);
+        phi_lo = std::min(phi_lo, phi);
+        phi_hi = std::max(phi_hi, phi);
+    }
+    const double c_lo = phi_lo + ax[2].z_min, c_hi = phi_hi + ax[2].z_max;
+    const double v_lo = ax[1].z_min, v_hi = ax[1].z_max;
+    const Mesh mr = make_mesh(ax[0]);
+    const double i2h = 0.5 * (ax[0].n - 1.0);
+    double worst = 0.0;
+    for (int i = 0; i < ax[0].n; ++i) {
+        const double r = mr.z[i], J = mr.J[i], J2 = mr.J2[i];
+        const double rg = rpow(r, m.gamma);
+        const double zr = 0.5 * m.lambda * m.lambda * rg * rg;
+        for (double c : {c_lo, c_hi})
+            for (double v : {0.0, v_lo, v_hi}) {
+                const double b = (c - m.kappa * r) / J - v * zr * J2 / (J * J * J);
+                worst = std::max(worst, tdt * std::fabs(b) * i2h);
+            }
+    }
+    return worst <= 0.4;
 }
 
 // Upper bound of the tiles of any plan (used to size task lists).
@@ -207,13 +257,14 @@ Plan plan_bound(int nr, int nv, int ny)
 {
     static const int options[3] = {8, 16, 32};
     Plan b{};
-    for (int o : options) {
-        const int rows[3] = {o, o, o};
-        Plan p = make_plan(nr, nv, ny, rows);
-        b.r_tiles = std::max(b.r_tiles, p.r_tiles);
-        b.v_tiles = std::max(b.v_tiles, p.v_tiles);
-        b.y_tiles = std::max(b.y_tiles, p.y_tiles);
-    }
+    for (int o : options)
+        for (bool sp : {true, false}) {
+            const int rows[3] = {o, o, o};
+            Plan p = make_plan(nr, nv, ny, rows, sp);
+            b.r_tiles = std::max(b.r_tiles, p.r_tiles);
+            b.v_tiles = std::max(b.v_tiles, p.v_tiles);
+            b.y_tiles = std::max(b.y_tiles, p.y_tiles);
+        }
     return b;
 }
 
@@ -232,7 +283,7 @@ struct Layout {
 
 size_t table_doubles(const hjm_axis ax[3], int n_steps)
 {
-    return (size_t)kRT * ax[0].n + (size_t)kVT * ax[1].n + (size_t)kYT * ax[2].n +
+    return (size_t)kRT * ax[0].n + (size_t)kVT * ax[1].n + (size_t)kYT * ax[2].n + (size_t)kVF * ax[1].n + kVS +
            (size_t)kStepStride * (n_steps + 1);
 }
 
@@ -259,38 +310,132 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
     double* rt = out.data();
     double* vt = rt + (size_t)kRT * nr;
     double* yt = vt + (size_t)kVT * nv;
-    double* st = yt + (size_t)kYT * ny;
+    double* vf = yt + (size_t)kYT * ny;
+    double* st = vf + (size_t)kVF * nv + kVS;
     const Mesh mr = make_mesh(ax[0]), mv = make_mesh(ax[1]), my = make_mesh(ax[2]);
     const double lam = m.lambda, eps = m.epsilon;
+    const double dt = p.expiry / n_steps, tdt = kTheta * dt;
+    const double hr1 = nr - 1.0, hv1 = nv - 1.0, hy1 = ny - 1.0;
+    const double ih2r = hr1 * hr1, i2hr = 0.5 * hr1, ih2v = hv1 * hv1, i2hv = 0.5 * hv1, i2hy = 0.5 * hy1;
+    const double i4hrhv = 0.25 * hr1 * hv1;
+    const bool r_lo_dir = ax[0].lo_face == HJM_FACE_DIRICHLET, r_hi_dir = ax[0].hi_face == HJM_FACE_DIRICHLET;
+    const bool y_hi_dir = ax[2].hi_face == HJM_FACE_DIRICHLET;
     for (int i = 0; i < nr; ++i) {
         const double r = mr.z[i], J = mr.J[i], J2 = mr.J2[i];
         const double rg = rpow(r, m.gamma);
         const double zr = 0.5 * lam * lam * rg * rg;  // zeta_rr / v
+        const double ra = zr / (J * J), rb1 = 1.0 / J, rb2 = zr * J2 / (J * J * J);
+        const bool lo = i == 0, hi = i == nr - 1;
+        const bool dir = (lo && r_lo_dir) || (hi && r_hi_dir);
+        double mlo = -1.0, mdi = 0.0, mup = 1.0, mex = 0.0;
+        double alo = ra * ih2r + rb2 * i2hr, adi = -2.0 * ra * ih2r, aup = ra * ih2r - rb2 * i2hr;
+        if (lo) { mlo = 0.0; mdi = -3.0; mup = 4.0; mex = -1.0; alo = adi = aup = 0.0; }
+        if (hi) { mlo = -4.0; mdi = 3.0; mup = 0.0; mex = 1.0; alo = adi = aup = 0.0; }
+        if (dir) { mlo = mdi = mup = mex = 0.0; alo = adi = aup = 0.0; }
         rt[RT_R * nr + i] = r;
-        rt[RT_A * nr + i] = zr / (J * J);
-        rt[RT_B1 * nr + i] = 1.0 / J;
-        rt[RT_B2 * nr + i] = zr * J2 / (J * J * J);
-        rt[RT_X * nr + i] = lam * rg / J;
+        rt[RT_P * nr + i] = rb1 * i2hr;
+        rt[RT_Q * nr + i] = -m.kappa * r * rb1 * i2hr;
+        rt[RT_MLO * nr + i] = mlo;
+        rt[RT_MDI * nr + i] = mdi;
+        rt[RT_MUP * nr + i] = mup;
+        rt[RT_MEX * nr + i] = mex;
+        rt[RT_ALO * nr + i] = alo;
+        rt[RT_ADI * nr + i] = adi;
+        rt[RT_AUP * nr + i] = aup;
+        rt[RT_RR * nr + i] = dir ? 0.0 : r;
+        rt[RT_X * nr + i] = (lo || hi) ? 0.0 : lam * rg / J;
         rt[RT_Y * nr + i] = lam * lam * rg * rg;
     }
+    std::vector<double> va(nv), vb(nv), vm(nv);  // v operator pieces, also used by the factorisation
     for (int j = 0; j < nv; ++j) {
         const double v = mv.z[j], J = mv.J[j], J2 = mv.J2[j];
         const double zv = 0.5 * eps * eps * v;
         const double mu = m.theta_v * (1.0 - v);
+        va[j] = zv / (J * J);
+        vb[j] = mu / J - zv * J2 / (J * J * J);
+        vm[j] = mu / J;
+        double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (j == 0) {
+            o[2] = -3.0 * vm[j] * i2hv; o[3] = 4.0 * vm[j] * i2hv; o[4] = -vm[j] * i2hv;
+        } else if (j == nv - 1) {
+            o[0] = vm[j] * i2hv; o[1] = -4.0 * vm[j] * i2hv; o[2] = 3.0 * vm[j] * i2hv;
+        } else {
+            o[1] = va[j] * ih2v - vb[j] * i2hv; o[2] = -2.0 * va[j] * ih2v; o[3] = va[j] * ih2v + vb[j] * i2hv;
+        }
         vt[VT_V * nv + j] = v;
-        vt[VT_A * nv + j] = zv / (J * J);
-        vt[VT_B * nv + j] = mu / J - zv * J2 / (J * J * J);
-        vt[VT_M * nv + j] = mu / J;
-        vt[VT_X * nv + j] = m.rho * eps * v / J;
+        for (int w = 0; w < 5; ++w) vt[(VT_O0 + w) * nv + j] = o[w];
+        vt[VT_X * nv + j] = (j == 0 || j == nv - 1) ? 0.0 : m.rho * eps * v / J * i4hrhv;
     }
     for (int k = 0; k < ny; ++k) {
-        yt[YT_Y * ny + k] = my.z[k];
-        yt[YT_I * ny + k] = 1.0 / my.J[k];
-        yt[YT_K * ny + k] = 2.0 * m.kappa * my.z[k];
+        const double y = my.z[k], yi = 1.0 / my.J[k];
+        const bool lo = k == 0, hi = k == ny - 1;
+        const bool dir = hi && y_hi_dir;
+        double w[5] = {0.0, -i2hy, 0.0, i2hy, 0.0};
+        double ma = 1.0, mb = 0.0, mc = -1.0, me = 0.0;
+        if (lo) { w[1] = 0.0; w[2] = -3.0 * i2hy; w[3] = 4.0 * i2hy; w[4] = -i2hy; ma = 0.0; mb = 3.0; mc = -4.0; me = 1.0; }
+        if (hi) { w[0] = i2hy; w[1] = -4.0 * i2hy; w[2] = 3.0 * i2hy; w[3] = 0.0; ma = 4.0; mb = -3.0; mc = 0.0; me = -1.0; }
+        if (dir) { for (double& x : w) x = 0.0; ma = mb = mc = me = 0.0; }
+        yt[YT_Y * ny + k] = y;
+        yt[YT_I * ny + k] = yi;
+        yt[YT_K * ny + k] = 2.0 * m.kappa * y * yi;
+        for (int q = 0; q < 5; ++q) yt[(YT_W0 + q) * ny + k] = w[q];
+        yt[YT_T1 * ny + k] = tdt * i2hy * yi;
+        yt[YT_T2 * ny + k] = -tdt * i2hy * 2.0 * m.kappa * y * yi;
+        yt[YT_MA * ny + k] = ma;
+        yt[YT_MB * ny + k] = mb;
+        yt[YT_MC * ny + k] = mc;
+        yt[YT_ME * ny + k] = me;
+    }
+    // LU factors of the v-line matrix (I - theta dt A2): rows depend on j
+    // alone, so one elimination serves every line and every step.  Same
+    // order of operations as the per-line solve: x0 eliminated from row 1,
+    // x_{n-1} from row n-2, then forward elimination over rows 1..n-2.
+    {
+        std::vector<double> A(nv), B(nv), C(nv);
+        double E0 = 0.0, El = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            const double a = va[j], b = vb[j], mf = vm[j];
+            const double ih2 = ih2v, i2h = i2hv;
+            if (j == 0) {
+                A[j] = 0.0; B[j] = 1.0 - tdt * (-3.0 * mf * i2h); C[j] = -tdt * (4.0 * mf * i2h);
+                E0 = -tdt * (-mf * i2h);
+            } else if (j == nv - 1) {
+                A[j] = -tdt * (-4.0 * mf * i2h); B[j] = 1.0 - tdt * (3.0 * mf * i2h); C[j] = 0.0;
+                El = -tdt * (mf * i2h);
+            } else {
+                A[j] = -tdt * (a * ih2 - b * i2h);
+                B[j] = 1.0 - tdt * (-2.0 * a * ih2);
+                C[j] = -tdt * (a * ih2 + b * i2h);
+            }
+        }
+        double* fs = vf + (size_t)kVF * nv;
+        fs[VS_B0] = B[0]; fs[VS_C0] = C[0]; fs[VS_E0] = E0;
+        const double f1 = A[1] / B[0];
+        fs[VS_F1] = f1;
+        fs[VS_AL] = A[nv - 1]; fs[VS_BL] = B[nv - 1]; fs[VS_EL] = El;
+        const double f2 = C[nv - 2] / B[nv - 1];
+        fs[VS_F2] = f2;
+        std::vector<double> Am(A), Bm(B), Cm(C);
+        Bm[1] = B[1] - f1 * C[0];
+        Cm[1] = C[1] - f1 * E0;
+        Am[1] = 0.0;
+        Am[nv - 2] = A[nv - 2] - f2 * El;
+        Bm[nv - 2] = B[nv - 2] - f2 * A[nv - 1];
+        Cm[nv - 2] = 0.0;
+        double cprev = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            vf[VF_A * nv + j] = 0.0; vf[VF_INV * nv + j] = 0.0; vf[VF_C * nv + j] = 0.0;
+        }
+        for (int j = 1; j <= nv - 2; ++j) {
+            const double den = Bm[j] - Am[j] * cprev;
+            cprev = Cm[j] / den;
+            vf[VF_A * nv + j] = Am[j];
+            vf[VF_INV * nv + j] = 1.0 / den;
+            vf[VF_C * nv + j] = cprev;
+        }
     }
     const Curve cv{m.f_level, m.f_slope, m.f_decay};
     const double T = p.expiry, TM = p.kind == HJM_BOND ? p.expiry : p.pay;
-    const double dt = T / n_steps;
     const double PT = cv.P(T), PM = cv.P(TM);
     for (int n = 0; n <= n_steps; ++n) {
         double* e = st + (size_t)kStepStride * n;
@@ -337,8 +482,10 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.rt = t;
     d.vt = t + (size_t)kRT * ax[0].n;
     d.yt = d.vt + (size_t)kVT * ax[1].n;
-    d.st = d.yt + (size_t)kYT * ax[2].n;
+    d.vf = d.yt + (size_t)kYT * ax[2].n;
+    d.st = d.vf + (size_t)kVF * ax[1].n + kVS;
     d.flag = flag;
+    d.r_mode = pl.r_spike ? R_SPIKE : R_CHAIN;
 }
 
 // 4-point Lagrange stencil in mesh coordinates (window centred on the
@@ -496,7 +643,7 @@ hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const h
     g->payoff = *payoff;
     g->n_steps = n_steps;
     std::memcpy(g->rows, g_rows, sizeof g->rows);
-    g->plan = make_plan(ax[0].n, ax[1].n, ax[2].n, g->rows);
+    g->plan = make_plan(ax[0].n, ax[1].n, ax[2].n, g->rows, r_spike_ok(ax, *model, *payoff, n_steps));
     g->stream = reinterpret_cast<hipStream_t>(hip_stream);
     g->base = reinterpret_cast<char*>(d_workspace);
     g->d_desc = reinterpret_cast<SolveDesc*>(g->base + gl.desc);
@@ -757,7 +904,7 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n_steps[a] > n_steps[c]; });
     for (int s = 0; s < n; ++s) {
         const hjm_axis* a = ax + 3 * s;
-        Plan pl = make_plan(a[0].n, a[1].n, a[2].n, b->rows);
+        Plan pl = make_plan(a[0].n, a[1].n, a[2].n, b->rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
         fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], pl, b->base, bl.s[s], b->d_flags + s);
         build_tables(a, model[s], payoff[s], n_steps[s], b->tables[s]);
         b->lds_r = std::max(b->lds_r, pl.r_lds);

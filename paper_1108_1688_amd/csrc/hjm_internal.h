@@ -10,16 +10,20 @@ namespace hjm {
 
 constexpr int kBlock = 256;        // threads per workgroup of every sweep kernel
 constexpr int kStepStride = 8;     // doubles per time level in the step table
+constexpr int kRed = 8;            // doubles per segment in the r-sweep reduced system
 
-// Per-solve descriptor, resident in device memory (read through the scalar
-// cache; never written by a kernel).
+// How the r lines are solved.
+enum { R_SPIKE = 0,   // segments eliminated in parallel, reduced system per line
+       R_CHAIN = 1 }; // Thomas in row order, segments chained through LDS
+
+// Per-solve descriptor, resident in device memory (read-only in kernels).
 struct SolveDesc {
     int32_t nr, nv, ny, n_steps;
     int32_t r_lo_dir, r_hi_dir, y_hi_dir, kind;
     // line-solve tiling: segments per line (S) and lines per workgroup (L)
     int32_t r_S, r_L, v_S, v_L;
     int32_t y_S, y_L, r_tiles, v_tiles;
-    int32_t y_tiles, r_pitch, pad0, pad1;
+    int32_t y_tiles, r_pitch, r_mode, pad0;
     double dt;          // time step
     double tdt;         // theta * dt, theta = 1/2
     double kappa;
@@ -33,17 +37,51 @@ struct SolveDesc {
     const double* rt;   // r-axis tables, kRT * nr
     const double* vt;   // v-axis tables, kVT * nv
     const double* yt;   // y-axis tables, kYT * ny
+    const double* vf;   // factors of the v-line matrix, kVF * nv + kVS
     const double* st;   // step table, kStepStride * (n_steps + 1)
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value
     int32_t* flag_pad;
 };
 
-// r-axis table rows (each nr long)
-enum { RT_R = 0, RT_A, RT_B1, RT_B2, RT_X, RT_Y, kRT };
-// v-axis table rows (each nv long)
-enum { VT_V = 0, VT_A, VT_B, VT_M, VT_X, kVT };
-// y-axis table rows (each ny long)
-enum { YT_Y = 0, YT_I, YT_K, kYT };
+// r-axis table rows (each nr long).  Row i of the r operator A1 (with the
+// reaction term) on a line with variance v and c = f_t + kappa f + y is
+//   e      = P c + Q                          (drift of r over J_r, / 2h)
+//   A1 row = (MLO e + ALO v,  MDI e + ADI v - RR,  MUP e + AUP v,  MEX e)
+// on offsets (-1, 0, +1, extra), where "extra" is +2 on the r_min face and
+// -2 on the r_max face.  Centred rows, one-sided outflow rows (section 7.3)
+// and Dirichlet rows (all zero) differ only in these entries.
+enum { RT_R = 0,   // r_i
+       RT_P,       // 1 / (2 h J_r)
+       RT_Q,       // -kappa r_i / (2 h J_r)
+       RT_MLO, RT_MDI, RT_MUP, RT_MEX,
+       RT_ALO, RT_ADI, RT_AUP,
+       RT_RR,      // r_i, 0 on a Dirichlet row
+       RT_X,       // lambda r^gamma / J_r, 0 on the r faces
+       RT_Y,       // lambda^2 r^{2 gamma}
+       kRT };
+// v-axis table rows (each nv long): the A2 row on offsets -2..+2 and the
+// v factor of the mixed term.
+enum { VT_V = 0,   // v_j
+       VT_O0, VT_O1, VT_O2, VT_O3, VT_O4,
+       VT_X,       // rho epsilon v / J_v / (4 h_r h_v), 0 on the v faces
+       kVT };
+// y-axis table rows (each ny long).  Explicit A3 at (i, j, k):
+//   (RT_Y[i] v_j YT_I[k] - YT_K[k]) * sum_w YT_W[w] U_{k+w}, w = -2..+2.
+// Implicit row of (I - theta dt A3) on line (i, j) with q = RT_Y[i] v_j:
+//   a = YT_T1 q + YT_T2,  row = (YT_MA a, 1 + YT_MB a, YT_MC a, YT_ME a).
+enum { YT_Y = 0,   // y_k
+       YT_I,       // 1 / J_y
+       YT_K,       // 2 kappa y / J_y
+       YT_W0, YT_W1, YT_W2, YT_W3, YT_W4,
+       YT_T1, YT_T2,
+       YT_MA, YT_MB, YT_MC, YT_ME,
+       kYT };
+// v-line factors: rows (each nv long) then scalars.  Forward sweep of row j:
+// d'_j = (d_j - VF_A[j] d'_{j-1}) * VF_INV[j]; back: x_j = d'_j - VF_C[j] x_{j+1}.
+enum { VF_A = 0, VF_INV, VF_C, kVF };
+// scalars after the rows: row 0 (b, c, e), factor eliminating x0 from row 1,
+// row n-1 (a, b, e), factor eliminating x_{n-1} from row n-2
+enum { VS_B0 = 0, VS_C0, VS_E0, VS_F1, VS_AL, VS_BL, VS_EL, VS_F2, kVS };
 // step table entries, per time level n (t_n = T - n dt)
 enum { ST_PHI = 0, ST_AT, ST_GT, ST_HT, ST_AM, ST_GM, ST_HM };
 

@@ -1,6 +1,7 @@
 // HIP kernels (gfx950) of the Douglas-ADI step for the single-factor HJM model
 // with stochastic volatility.  FP64 throughout; no MFMA (nothing here is a
-// dense contraction).
+// dense contraction: the step is a stencil plus tridiagonal recurrences and is
+// bound by memory traffic and latency).
 //
 // One Douglas step (section 5.1 of the paper, theta = 1/2, operators at
 // t_{n+1/2}) is three launches:
@@ -12,13 +13,35 @@
 //         U^{n+1} = U^n + D3.
 // Dirichlet nodes carry identity rows and D0 = g(t_{n+1}) - g(t_n).
 //
-// Line solves.  Each tridiagonal line of n rows is split into S segments of
-// at most ROWS rows held in the registers of S threads, and solved by the
-// Thomas algorithm in row order with the segments chained through LDS.
-// Outflow faces (section 7.3) add one entry beyond the tridiagonal band in
-// rows 0 and n-1; those unknowns are eliminated from rows 1 and n-2 first and
-// recovered last.  No pivoting: diagonals are >= 1 and the pivots are checked
-// (> 0) into the health flag.
+// Coefficients.  Every operator coefficient is affine in a couple of per-line
+// quantities (v_j and c = f_t + kappa f + y_k for r; q = lambda^2 r^{2 gamma}
+// v for y), so the host tabulates per node the few numbers that turn each one
+// into one or two FMAs (see the table layouts in hjm_internal.h).  Outflow
+// faces (one-sided rows of section 7.3) and Dirichlet rows are just other
+// table entries: the kernels have no face branches.
+//
+// Line solves.  The rows of a line are split into S segments of at most ROWS
+// rows held in the registers of S threads.  Outflow faces put one entry
+// beyond the band in rows 0 and n-1; those unknowns are eliminated from rows 1
+// and n-2 first and recovered last.  No pivoting: diagonals are >= 1 and the
+// pivots are checked (> 0) into the health flag.  Two ways of combining the
+// segments:
+//   chain  the Thomas recurrence in row order, segment s starting once segment
+//          s-1 has handed over (c', d') of its last row (LDS, one barrier per
+//          stage); the elimination order of a sequential solve, accurate for
+//          any of this problem's lines.  Used for y (advection only, Courant
+//          numbers up to ~1e4 in the far field) and v.
+//   spike  every segment eliminates at once, carrying the coupling to its
+//          neighbours as spikes; a per-line reduced system of the segments'
+//          end rows is then solved and each segment back-substitutes.  Fully
+//          parallel but only as accurate as the rows are diagonally dominant,
+//          so the host selects it for the r lines only when the cell Courant
+//          number theta dt |b| / (2 h) stays below 0.4 on every r row.
+// The v-line matrix depends on j alone, so its LU factors are built once per
+// solve on the host and every v line runs a division-free chained recurrence.
+// All per-row loops are fully unrolled and branch-free (rows outside a
+// segment's range are masked with selects), so table reads and loads are free
+// to be scheduled ahead of the serial recurrences.
 //
 // Work is described by (solve, tile) tasks so that one launch can cover many
 // independent solves of different shapes (batched mode); a null task list
@@ -29,7 +52,14 @@
 namespace hjm {
 namespace {
 
-__device__ __forceinline__ double dirichlet_value(const SolveDesc& s, const double* stn, double r, double y)
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(3))) double ldouble;
+
+__device__ __forceinline__ gdouble* gp(double* p) { return (gdouble*)p; }
+__device__ __forceinline__ gcdouble* gp(const double* p) { return (gcdouble*)p; }
+
+__device__ __forceinline__ double dirichlet_value(const SolveDesc& s, gcdouble* stn, double r, double y)
 {
     // p(t,T) = A exp(-G r - H y): bond reconstruction formula (section 3.1)
     // with the time-only factor A = P(0,T)/P(0,t) exp(G f(0,t)) and H = G^2/2
@@ -45,122 +75,24 @@ __device__ __forceinline__ double dirichlet_value(const SolveDesc& s, const doub
 
 __device__ __forceinline__ void raise_flag(const SolveDesc& s)
 {
-    // plain vector store of a constant; concurrent writers store the same value
-    *reinterpret_cast<volatile int32_t*>(s.flag) = 1;
+    // vector store of a constant; concurrent writers store the same value
+    *(__attribute__((address_space(1))) volatile int32_t*)s.flag = 1;
+}
+
+__device__ __forceinline__ int pow2_ceil(int n)
+{
+    int t = 1;
+    while (t < n) t <<= 1;
+    return t;
 }
 
 // ---------------------------------------------------------------------------
-// Implicit row functors: coefficients (A, B, C) of row m of (I - theta dt A_d)
-// and E, the entry beyond the band (column 2 in row 0, column n-3 in row n-1).
-// ---------------------------------------------------------------------------
-struct RowR {
-    const double* r;
-    const double* ra;
-    const double* rb1;
-    const double* rb2;
-    double v, drift0, kappa, tdt, ih2, i2h;
-    int nr;
-    int lo_dir, hi_dir;
-    __device__ __forceinline__ void operator()(int i, double& A, double& B, double& C, double& E) const
-    {
-        E = 0.0;
-        if ((i == 0 && lo_dir) || (i == nr - 1 && hi_dir)) { A = 0.0; B = 1.0; C = 0.0; return; }
-        const double ri = r[i];
-        const double mu = (drift0 - kappa * ri) * rb1[i];  // drift of r over J_r
-        if (i == 0) {
-            A = 0.0;
-            B = 1.0 - tdt * (-3.0 * mu * i2h - ri);
-            C = -tdt * (4.0 * mu * i2h);
-            E = -tdt * (-mu * i2h);
-        } else if (i == nr - 1) {
-            A = -tdt * (-4.0 * mu * i2h);
-            B = 1.0 - tdt * (3.0 * mu * i2h - ri);
-            C = 0.0;
-            E = -tdt * (mu * i2h);
-        } else {
-            const double a = ra[i] * v;
-            const double b = mu - v * rb2[i];
-            A = -tdt * (a * ih2 - b * i2h);
-            B = 1.0 - tdt * (-2.0 * a * ih2 - ri);
-            C = -tdt * (a * ih2 + b * i2h);
-        }
-    }
-};
-
-struct RowV {
-    const double* va;
-    const double* vb;
-    const double* vm;
-    double tdt, ih2, i2h;
-    int nv;
-    __device__ __forceinline__ void operator()(int j, double& A, double& B, double& C, double& E) const
-    {
-        E = 0.0;
-        if (j == 0) {
-            const double m = vm[0];
-            A = 0.0;
-            B = 1.0 - tdt * (-3.0 * m * i2h);
-            C = -tdt * (4.0 * m * i2h);
-            E = -tdt * (-m * i2h);
-        } else if (j == nv - 1) {
-            const double m = vm[j];
-            A = -tdt * (-4.0 * m * i2h);
-            B = 1.0 - tdt * (3.0 * m * i2h);
-            C = 0.0;
-            E = -tdt * (m * i2h);
-        } else {
-            const double a = va[j], b = vb[j];
-            A = -tdt * (a * ih2 - b * i2h);
-            B = 1.0 - tdt * (-2.0 * a * ih2);
-            C = -tdt * (a * ih2 + b * i2h);
-        }
-    }
-};
-
-struct RowY {
-    const double* yi;
-    const double* y2k;
-    double qv, tdt, i2h;
-    int ny;
-    int hi_dir;
-    __device__ __forceinline__ void operator()(int k, double& A, double& B, double& C, double& E) const
-    {
-        E = 0.0;
-        if (k == ny - 1 && hi_dir) { A = 0.0; B = 1.0; C = 0.0; return; }
-        const double b = (qv - y2k[k]) * yi[k];  // drift of y over J_y
-        if (k == 0) {
-            A = 0.0;
-            B = 1.0 - tdt * (-3.0 * b * i2h);
-            C = -tdt * (4.0 * b * i2h);
-            E = -tdt * (-b * i2h);
-        } else if (k == ny - 1) {
-            A = -tdt * (-4.0 * b * i2h);
-            B = 1.0 - tdt * (3.0 * b * i2h);
-            C = 0.0;
-            E = -tdt * (b * i2h);
-        } else {
-            A = -tdt * (-b * i2h);
-            B = 1.0;
-            C = -tdt * (b * i2h);
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
-// Chained line solver: the rows of one line are split into S segments of at
-// most ROWS consecutive rows, each held in the registers of one thread.  The
-// elimination itself is the plain Thomas algorithm in row order: segment s
-// runs its forward sweep once segment s-1 has handed over (c', d') of its last
-// row, and its back substitution once segment s+1 has handed back x of its
-// first row (hand-over through LDS, one workgroup barrier per stage).  Splitting
-// only distributes storage and memory traffic; the arithmetic is that of one
-// sequential Thomas solve, which stays accurate for the advection-dominated
-// lines of this problem (a spike / partition reduction does not).
+// Segments.
 // ---------------------------------------------------------------------------
 template <int ROWS>
 struct Seg {
     double d[ROWS];   // right-hand side -> d' -> solution
-    double cp[ROWS];  // modified super-diagonal c'
+    double cp[ROWS];  // super-diagonal, then modified super-diagonal c'
     int p, len, n, seg, S, lo, hi;
     double b0, c0, e0, d0;  // row 0 (first segment)
     double al, bl, el, dl;  // row n-1 (last segment)
@@ -174,22 +106,18 @@ __device__ __forceinline__ void seg_init(Seg<ROWS>& g, int n, int S, int seg)
     g.seg = seg;
     g.p = (seg * n) / S;
     g.len = ((seg + 1) * n) / S - g.p;
-}
-
-// Every thread of the workgroup calls this (barriers inside when S > 1).
-// `work` marks threads holding a segment of a line that needs solving; xch is
-// the line's two-double hand-over slot in LDS.
-template <int ROWS, class RowFn>
-__device__ __forceinline__ void line_solve(Seg<ROWS>& g, const RowFn& row, bool work, double* xch,
-                                           const SolveDesc& s)
-{
-    const bool first = g.seg == 0;
-    const bool last = g.seg == g.S - 1;
-    double b1m = 0.0, c1m = 0.0, a2m = 0.0, b2m = 0.0;
-    bool ok = true;
     g.lo = 0;
     g.hi = g.len - 1;
-    if (work && first) {
+}
+
+// Boundary-row eliminations of the first / last segment (row(m, A, B, C, E)
+// gives row m).  Returns the modified rows 1 and n-2 in (b1m, c1m), (a2m, b2m).
+template <int ROWS, class RowFn>
+__device__ __forceinline__ bool seg_ends(Seg<ROWS>& g, const RowFn& row, double& b1m, double& c1m, double& a2m,
+                                         double& b2m)
+{
+    bool ok = true;
+    if (g.seg == 0) {
         // eliminate x0 (row 0: b0 x0 + c0 x1 + e0 x2 = d0) from row 1
         double A, B, C, E;
         row(0, A, B, C, E);
@@ -203,15 +131,14 @@ __device__ __forceinline__ void line_solve(Seg<ROWS>& g, const RowFn& row, bool 
         g.lo = 1;
         ok = ok && (B > 0.0);
     }
-    if (work && last) {
+    if (g.seg == g.S - 1) {
         // eliminate x_{n-1} (row n-1: e x_{n-3} + a x_{n-2} + b x_{n-1}) from row n-2
         double A, B, C, E;
         row(g.n - 1, A, B, C, E);
         g.al = A; g.bl = B; g.el = E;
         double dl = 0.0;
 #pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm)
-            if (mm == g.len - 1) dl = g.d[mm];
+        for (int mm = 0; mm < ROWS; ++mm) dl = (mm == g.len - 1) ? g.d[mm] : dl;
         g.dl = dl;
         double A2, B2, C2, E2;
         row(g.n - 2, A2, B2, C2, E2);
@@ -219,135 +146,272 @@ __device__ __forceinline__ void line_solve(Seg<ROWS>& g, const RowFn& row, bool 
         a2m = A2 - f * E;
         b2m = B2 - f * A;
 #pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm)
-            if (mm == g.len - 2) g.d[mm] = g.d[mm] - f * dl;
+        for (int mm = 0; mm < ROWS; ++mm) g.d[mm] = (mm == g.len - 2) ? g.d[mm] - f * dl : g.d[mm];
         g.hi = g.len - 2;
         ok = ok && (B > 0.0);
     }
-    // forward sweep, segment after segment
+    return ok;
+}
+
+// Recover x0 and x_{n-1} from their own rows once the interior is solved.
+template <int ROWS>
+__device__ __forceinline__ void seg_finish(Seg<ROWS>& g)
+{
+    if (g.seg == 0) g.d[0] = (g.d0 - g.c0 * g.d[1] - g.e0 * g.d[2]) / g.b0;
+    if (g.seg == g.S - 1) {
+        double x3 = 0.0, x2 = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            x3 = (mm == g.len - 3) ? g.d[mm] : x3;
+            x2 = (mm == g.len - 2) ? g.d[mm] : x2;
+        }
+        const double xl = (g.dl - g.el * x3 - g.al * x2) / g.bl;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) g.d[mm] = (mm == g.len - 1) ? xl : g.d[mm];
+    }
+}
+
+// Chained Thomas on coefficients already in registers: ca (sub-diagonal), cb
+// (diagonal) and g.cp (super-diagonal) for rows lo..hi of the segment.  Every
+// thread of the workgroup calls it (barriers inside when S > 1); xch is the
+// line's two-double hand-over slot in LDS.
+template <int ROWS>
+__device__ __forceinline__ bool chain_core(Seg<ROWS>& g, const double (&ca)[ROWS], const double (&cb)[ROWS],
+                                           bool work, ldouble* xch)
+{
+    bool ok = true;
     for (int stage = 0; stage < g.S; ++stage) {
         if (work && g.seg == stage) {
             double cprev = 0.0, dprev = 0.0;
             if (stage > 0) { cprev = xch[0]; dprev = xch[1]; }
 #pragma unroll
             for (int mm = 0; mm < ROWS; ++mm) {
-                if (mm >= g.lo && mm <= g.hi) {
-                    double A, B, C, E;
-                    if (first && mm == 1) { A = 0.0; B = b1m; C = c1m; }
-                    else if (last && mm == g.len - 2) { A = a2m; B = b2m; C = 0.0; }
-                    else row(g.p + mm, A, B, C, E);
-                    const double den = B - A * cprev;
-                    ok = ok && (den > 0.0);
-                    cprev = C / den;
-                    dprev = (g.d[mm] - A * dprev) / den;
-                    g.cp[mm] = cprev;
-                    g.d[mm] = dprev;
-                }
+                const bool act = mm >= g.lo && mm <= g.hi;
+                const double den = cb[mm] - ca[mm] * cprev;
+                const double inv = 1.0 / den;
+                const double cn = g.cp[mm] * inv;
+                const double dn = (g.d[mm] - ca[mm] * dprev) * inv;
+                ok = ok && (!act || den > 0.0);
+                cprev = act ? cn : cprev;
+                dprev = act ? dn : dprev;
+                g.cp[mm] = act ? cn : 0.0;
+                g.d[mm] = act ? dn : g.d[mm];
             }
             xch[0] = cprev;
             xch[1] = dprev;
         }
         if (g.S > 1) __syncthreads();
     }
-    // back substitution, segment after segment
     for (int stage = g.S - 1; stage >= 0; --stage) {
         if (work && g.seg == stage) {
             double x = (stage < g.S - 1) ? xch[0] : 0.0;
 #pragma unroll
             for (int mm = ROWS - 1; mm >= 0; --mm) {
-                if (mm >= g.lo && mm <= g.hi) {
-                    x = g.d[mm] - g.cp[mm] * x;
-                    g.d[mm] = x;
-                }
+                const bool act = mm >= g.lo && mm <= g.hi;
+                const double xn = g.d[mm] - g.cp[mm] * x;
+                x = act ? xn : x;
+                g.d[mm] = act ? xn : g.d[mm];
             }
             xch[0] = x;
-            if (first) g.d[0] = (g.d0 - g.c0 * g.d[1] - g.e0 * g.d[2]) / g.b0;
-            if (last) {
-                double x3 = 0.0, x2 = 0.0;
-#pragma unroll
-                for (int mm = 0; mm < ROWS; ++mm) {
-                    if (mm == g.len - 3) x3 = g.d[mm];
-                    if (mm == g.len - 2) x2 = g.d[mm];
-                }
-                const double xl = (g.dl - g.el * x3 - g.al * x2) / g.bl;
-#pragma unroll
-                for (int mm = 0; mm < ROWS; ++mm)
-                    if (mm == g.len - 1) g.d[mm] = xl;
-            }
+            seg_finish(g);
         }
         if (g.S > 1) __syncthreads();
     }
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// r rows.  LDS table rt6 holds P, Q, ALO, ADI, AUP, RR (each nr long) for the
+// interior rows of the solve; the face rows are read from the full table.
+// ---------------------------------------------------------------------------
+struct RowRFull {  // any row, from the global table (face rows only)
+    gcdouble* rt;
+    int nr;
+    double v, c, tdt;
+    __device__ __forceinline__ void operator()(int i, double& A, double& B, double& C, double& E) const
+    {
+        const double e = rt[RT_P * nr + i] * c + rt[RT_Q * nr + i];
+        const double olo = rt[RT_MLO * nr + i] * e + rt[RT_ALO * nr + i] * v;
+        const double odi = rt[RT_MDI * nr + i] * e + rt[RT_ADI * nr + i] * v - rt[RT_RR * nr + i];
+        const double oup = rt[RT_MUP * nr + i] * e + rt[RT_AUP * nr + i] * v;
+        const double oex = rt[RT_MEX * nr + i] * e;
+        A = -tdt * olo;
+        B = 1.0 - tdt * odi;
+        C = -tdt * oup;
+        E = -tdt * oex;
+    }
+};
+
+// interior r row i of (I - theta dt A1) from the LDS table
+__device__ __forceinline__ void row_r_interior(const ldouble* rt6, int nr, int i, double v, double c, double tdt,
+                                               double& A, double& B, double& C)
+{
+    const double e = rt6[i] * c + rt6[nr + i];
+    A = -tdt * (rt6[2 * nr + i] * v - e);
+    B = 1.0 - tdt * (rt6[3 * nr + i] * v - rt6[5 * nr + i]);
+    C = -tdt * (rt6[4 * nr + i] * v + e);
+}
+
+// Spike (partition) solve of r lines.  Every thread calls it; red is the
+// line's S * kRed scratch in LDS.  After the local elimination each segment
+// leaves in red[seg] the first/last effective rows of its three local
+// solutions y (right-hand side), v (unit coupling to the previous segment)
+// and w (to the next): x = y - X_L v - X_R w.  One thread per line solves
+// the reduced system of the segments' end unknowns; every segment then
+// back-substitutes.
+template <int ROWS>
+__device__ __forceinline__ void spike_solve_r(Seg<ROWS>& g, const RowRFull& full, const ldouble* rt6, bool work,
+                                              ldouble* red, const SolveDesc& s)
+{
+    double vp[ROWS];
+    double b1m = 1.0, c1m = 0.0, a2m = 0.0, b2m = 1.0;
+    bool ok = true;
+    const bool first = g.seg == 0;
+    const bool last = g.seg == g.S - 1;
+    const int nr = g.n;
+    ldouble* slot = red + g.seg * kRed;
+    if (work) {
+        ok = seg_ends(g, full, b1m, c1m, a2m, b2m);
+        double cprev = 0.0, yprev = 0.0, vprev = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            const int i = min(g.p + mm, nr - 2);
+            double A, B, C;
+            row_r_interior(rt6, nr, i, full.v, full.c, full.tdt, A, B, C);
+            if (first && mm == 1) { A = 0.0; B = b1m; C = c1m; }
+            if (last && mm == g.len - 2) { A = a2m; B = b2m; C = 0.0; }
+            const bool act = mm >= g.lo && mm <= g.hi;
+            const bool top = mm == g.lo;
+            const double den = top ? B : B - A * cprev;
+            const double inv = 1.0 / den;
+            const double yv = (top ? g.d[mm] : g.d[mm] - A * yprev) * inv;
+            const double vv = (top ? A : -A * vprev) * inv;
+            const double cn = C * inv;
+            ok = ok && (!act || den > 0.0);
+            cprev = act ? cn : cprev;
+            yprev = act ? yv : yprev;
+            vprev = act ? vv : vprev;
+            g.cp[mm] = act ? cn : 0.0;
+            g.d[mm] = act ? yv : g.d[mm];
+            vp[mm] = act ? vv : 0.0;
+        }
+        if (g.S > 1) {
+            double yL = 0.0, vL = 0.0, wL = 0.0;
+#pragma unroll
+            for (int mm = 0; mm < ROWS; ++mm) {
+                const bool h = mm == g.hi;
+                yL = h ? g.d[mm] : yL;
+                vL = h ? vp[mm] : vL;
+                wL = h ? g.cp[mm] : wL;
+            }
+            double y = yL, v = vL, w = wL;
+#pragma unroll
+            for (int mm = ROWS - 1; mm >= 0; --mm) {
+                const bool act = mm >= g.lo && mm < g.hi;
+                const double yn = g.d[mm] - g.cp[mm] * y;
+                const double vn = vp[mm] - g.cp[mm] * v;
+                const double wn = -g.cp[mm] * w;
+                y = act ? yn : y;
+                v = act ? vn : v;
+                w = act ? wn : w;
+            }
+            slot[0] = y; slot[1] = v; slot[2] = w;
+            slot[3] = yL; slot[4] = vL; slot[5] = wL;
+        }
+    }
+    double XL = 0.0, XR = 0.0;
+    if (g.S > 1) {
+        __syncthreads();
+        if (work && first) {
+            // F_s = yF - vF L_{s-1} - wF F_{s+1};  L_s = yL - vL L_{s-1} - wL F_{s+1}
+            // forward: L_s = alp + bet F_{s+1}, F_s = gam + del F_{s+1}
+            double alp = 0.0, bet = 0.0;
+            for (int q = 0; q < g.S; ++q) {
+                ldouble* r = red + q * kRed;
+                const double yF = r[0], vF = r[1], wF = r[2], yL = r[3], vL = r[4], wL = r[5];
+                double gam, del, a, b;
+                if (q == 0) {
+                    gam = yF; del = -wF; a = yL; b = -wL;
+                } else {
+                    const double den = 1.0 + vF * bet;
+                    ok = ok && (den > 0.0);
+                    const double inv = 1.0 / den;
+                    gam = (yF - vF * alp) * inv;
+                    del = -wF * inv;
+                    a = yL - vL * alp - vL * bet * gam;
+                    b = -vL * bet * del - wL;
+                }
+                r[0] = gam; r[1] = del; r[2] = a; r[3] = b;
+                alp = a;
+                bet = b;
+            }
+            double Fnext = 0.0;
+            for (int q = g.S - 1; q >= 0; --q) {
+                ldouble* r = red + q * kRed;
+                const double F = r[0] + r[1] * Fnext;
+                const double Lq = r[2] + r[3] * Fnext;
+                r[6] = Fnext;  // X_R of segment q
+                r[5] = Lq;
+                Fnext = F;
+            }
+            for (int q = g.S - 1; q >= 1; --q) red[q * kRed + 7] = red[(q - 1) * kRed + 5];
+            red[7] = 0.0;
+        }
+        __syncthreads();
+        if (work) { XL = slot[7]; XR = slot[6]; }
+    }
+    if (work) {
+        double x = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            const double xn = g.d[mm] - XL * vp[mm] - XR * g.cp[mm];
+            x = (mm == g.hi) ? xn : x;
+        }
+#pragma unroll
+        for (int mm = ROWS - 1; mm >= 0; --mm) {
+            const bool h = mm == g.hi;
+            const bool act = mm >= g.lo && mm < g.hi;
+            const double xn = g.d[mm] - XL * vp[mm] - g.cp[mm] * x;
+            x = act ? xn : x;
+            g.d[mm] = (act || h) ? x : g.d[mm];
+        }
+        seg_finish(g);
+        if (!ok) raise_flag(s);
+    }
+}
+
+// Chained solve of r lines (fallback when the rows are not diagonally dominant).
+template <int ROWS>
+__device__ __forceinline__ void chain_solve_r(Seg<ROWS>& g, const RowRFull& full, const ldouble* rt6, bool work,
+                                              ldouble* xch, const SolveDesc& s)
+{
+    double ca[ROWS], cb[ROWS];
+    double b1m = 1.0, c1m = 0.0, a2m = 0.0, b2m = 1.0;
+    bool ok = true;
+    if (work) {
+        ok = seg_ends(g, full, b1m, c1m, a2m, b2m);
+        const bool first = g.seg == 0;
+        const bool last = g.seg == g.S - 1;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            const int i = min(g.p + mm, g.n - 2);
+            double A, B, C;
+            row_r_interior(rt6, g.n, i, full.v, full.c, full.tdt, A, B, C);
+            if (first && mm == 1) { A = 0.0; B = b1m; C = c1m; }
+            if (last && mm == g.len - 2) { A = a2m; B = b2m; C = 0.0; }
+            const bool act = mm >= g.lo && mm <= g.hi;
+            ca[mm] = act ? A : 0.0;
+            cb[mm] = act ? B : 1.0;
+            g.cp[mm] = act ? C : 0.0;
+        }
+    }
+    ok = chain_core(g, ca, cb, work, xch) && ok;
     if (work && !ok) raise_flag(s);
 }
 
-// ---------------------------------------------------------------------------
-// Explicit Douglas predictor at one node.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double explicit_point(const SolveDesc& s, int i, int j, int k, size_t q, double phi,
-                                                 const double* stn, const double* stn1)
-{
-    const int nr = s.nr, nv = s.nv, ny = s.ny;
-    const double* rt = s.rt;
-    const double* vt = s.vt;
-    const double* yt = s.yt;
-    const double ri = rt[RT_R * nr + i];
-    const double yk = yt[YT_Y * ny + k];
-    if ((i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir) || (k == ny - 1 && s.y_hi_dir))
-        return dirichlet_value(s, stn1, ri, yk) - dirichlet_value(s, stn, ri, yk);
-    const double* U = s.U;
-    const size_t sv = (size_t)nr;
-    const size_t sy = (size_t)nr * (size_t)nv;
-    const double u = U[q];
-    const double vj = vt[VT_V * nv + j];
-    // A1: r direction with the reaction term
-    const double mu = (phi + yk - s.kappa * ri) * rt[RT_B1 * nr + i];
-    double a1;
-    if (i == 0) {
-        a1 = mu * s.i2hr * (-3.0 * u + 4.0 * U[q + 1] - U[q + 2]) - ri * u;
-    } else if (i == nr - 1) {
-        a1 = mu * s.i2hr * (3.0 * u - 4.0 * U[q - 1] + U[q - 2]) - ri * u;
-    } else {
-        const double um = U[q - 1], up = U[q + 1];
-        const double a = rt[RT_A * nr + i] * vj;
-        const double b = mu - vj * rt[RT_B2 * nr + i];
-        a1 = a * s.ih2r * (up - 2.0 * u + um) + b * s.i2hr * (up - um) - ri * u;
-    }
-    // A2: v direction
-    double a2;
-    if (j == 0) {
-        a2 = vt[VT_M * nv] * s.i2hv * (-3.0 * u + 4.0 * U[q + sv] - U[q + 2 * sv]);
-    } else if (j == nv - 1) {
-        a2 = vt[VT_M * nv + j] * s.i2hv * (3.0 * u - 4.0 * U[q - sv] + U[q - 2 * sv]);
-    } else {
-        const double um = U[q - sv], up = U[q + sv];
-        a2 = vt[VT_A * nv + j] * s.ih2v * (up - 2.0 * u + um) + vt[VT_B * nv + j] * s.i2hv * (up - um);
-    }
-    // A3: y direction (advection only)
-    const double qy = rt[RT_Y * nr + i] * vj;
-    const double by = (qy - yt[YT_K * ny + k]) * yt[YT_I * ny + k];
-    double a3;
-    if (k == 0) {
-        a3 = by * s.i2hy * (-3.0 * u + 4.0 * U[q + sy] - U[q + 2 * sy]);
-    } else if (k == ny - 1) {
-        a3 = by * s.i2hy * (3.0 * u - 4.0 * U[q - sy] + U[q - 2 * sy]);
-    } else {
-        a3 = by * s.i2hy * (U[q + sy] - U[q - sy]);
-    }
-    // A0: mixed r-v derivative, interior of the (r, v) faces only
-    double a0 = 0.0;
-    if (i > 0 && i < nr - 1 && j > 0 && j < nv - 1) {
-        const double arv = rt[RT_X * nr + i] * vt[VT_X * nv + j];
-        a0 = arv * s.i4hrhv * ((U[q + 1 + sv] - U[q + 1 - sv]) - (U[q - 1 + sv] - U[q - 1 - sv]));
-    }
-    return s.dt * (((a1 + a2) + a3) + a0);
-}
-
-__device__ __forceinline__ int pow2_ceil(int n)
-{
-    int t = 1;
-    while (t < n) t <<= 1;
-    return t;
-}
+// per-line constants of the explicit phase, kLC doubles per line in LDS
+enum { LC_V = 0, LC_C, LC_O0, LC_O1, LC_O2, LC_O3, LC_O4, LC_VX, LC_PV, LC_K, LC_W0, LC_W1, LC_W2, LC_W3, LC_W4,
+       LC_Y, kLC };
 
 // ---------------------------------------------------------------------------
 // Kernels.
@@ -355,103 +419,242 @@ __device__ __forceinline__ int pow2_ceil(int n)
 __global__ __launch_bounds__(kBlock) void k_terminal(const SolveDesc* __restrict__ descs)
 {
     const SolveDesc& s = descs[blockIdx.y];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<volatile int32_t*>(s.flag) = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *(__attribute__((address_space(1))) volatile int32_t*)s.flag = 0;
     const int nr = s.nr, nv = s.nv;
     const int64_t npts = (int64_t)nr * nv * s.ny;
-    const double* r = s.rt + RT_R * nr;
-    const double* y = s.yt + YT_Y * s.ny;
+    gcdouble* r = gp(s.rt) + RT_R * nr;
+    gcdouble* y = gp(s.yt) + YT_Y * s.ny;
+    gdouble* U = gp(s.U);
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < npts; p += (int64_t)gridDim.x * kBlock) {
         const int i = (int)(p % nr);
         const int k = (int)(p / ((int64_t)nr * nv));
-        s.U[p] = dirichlet_value(s, s.st, r[i], y[k]);
+        U[p] = dirichlet_value(s, gp(s.st), r[i], y[k]);
     }
 }
 
+// Explicit predictor + r sweep.  Tile = L consecutive r lines (q = k nv + j)
+// with two halo lines on each side, each row stored as [0 0 u_0 .. u_{nr-1} 0 0]
+// (pitch >= nr + 4).  LDS: U tile (L+4) x pitch, r solve table 6 x nr,
+// per-line constants L x kLC, line-solve scratch.  In the explicit phase
+// thread t owns columns t % tpl (+ tpl c) of lines t / tpl + lpp m.
 template <int ROWS>
 __global__ __launch_bounds__(kBlock) void k_xr(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
                                                int step)
 {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
     const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const SolveDesc& s = descs[tk.x];
     if (step >= s.n_steps) return;  // whole workgroup: uniform
     const int nr = s.nr, nv = s.nv, ny = s.ny;
     const int L = s.r_L, S = s.r_S, pitch = s.r_pitch;
+    const int nlines = nv * ny;
     const int q0 = tk.y * L;
-    const int nl = min(L, nv * ny - q0);
-    double* tile = lds;
-    double* red = lds + (size_t)L * pitch;
-    const double* stn = s.st + kStepStride * step;
-    const double* stn1 = stn + kStepStride;
+    const int nl = min(L, nlines - q0);
+    const int t = threadIdx.x;
+    ldouble* ut = lds;
+    ldouble* rt6 = ut + (size_t)(L + 4) * pitch;
+    ldouble* lcon = rt6 + 6 * nr;
+    ldouble* red = lcon + (size_t)L * kLC;
+    gcdouble* U = gp(s.U);
+    gdouble* D = gp(s.D);
+    gcdouble* rt = gp(s.rt);
+    gcdouble* stn = gp(s.st) + kStepStride * step;
+    gcdouble* stn1 = stn + kStepStride;
     const double phi = stn[ST_PHI];
-
-    // Phase A: explicit predictor of the tile's lines into LDS (coalesced along r)
     const int tpl = min(kBlock, pow2_ceil(nr));
     const int lpp = kBlock / tpl;
-    for (int l = threadIdx.x / tpl; l < nl; l += lpp) {
+    const int ci = t % tpl;
+    const int lr = t / tpl;
+    const int creps = (nr + tpl - 1) / tpl;
+    const size_t sy = (size_t)nr * nv;
+
+    // Phase A: r solve table, per-line constants and the U tile into LDS
+    for (int i = t; i < nr; i += kBlock) {
+        rt6[i] = rt[RT_P * nr + i];
+        rt6[nr + i] = rt[RT_Q * nr + i];
+        rt6[2 * nr + i] = rt[RT_ALO * nr + i];
+        rt6[3 * nr + i] = rt[RT_ADI * nr + i];
+        rt6[4 * nr + i] = rt[RT_AUP * nr + i];
+        rt6[5 * nr + i] = rt[RT_RR * nr + i];
+    }
+    for (int l = t; l < nl; l += kBlock) {
         const int q = q0 + l;
         const int k = q / nv;
         const int j = q - k * nv;
-        const size_t base = (size_t)q * nr;
-        for (int i = threadIdx.x % tpl; i < nr; i += tpl)
-            tile[l * pitch + i] = explicit_point(s, i, j, k, base + i, phi, stn, stn1);
+        gcdouble* vt = gp(s.vt);
+        gcdouble* yt = gp(s.yt);
+        ldouble* c = lcon + l * kLC;
+        const double v = vt[VT_V * nv + j];
+        c[LC_V] = v;
+        c[LC_C] = phi + yt[YT_Y * ny + k];
+        for (int w = 0; w < 5; ++w) c[LC_O0 + w] = vt[(VT_O0 + w) * nv + j];
+        c[LC_VX] = vt[VT_X * nv + j];
+        c[LC_PV] = v * yt[YT_I * ny + k];
+        c[LC_K] = yt[YT_K * ny + k];
+        for (int w = 0; w < 5; ++w) c[LC_W0 + w] = yt[(YT_W0 + w) * ny + k];
+        c[LC_Y] = yt[YT_Y * ny + k];
+    }
+    {
+        // each thread loads its share of the tile into registers first, so
+        // that all of its loads are in flight together
+        const int nrows = nl + 4;
+        double buf[ROWS + 8];
+        int c = 0, lm = 0;
+#pragma unroll
+        for (int m = 0; m < ROWS + 8; ++m) {
+            const int lt = lr + lpp * lm;
+            const int i = ci + tpl * c;
+            const int q = q0 - 2 + lt;
+            buf[m] = (lt < nrows && i < nr && q >= 0 && q < nlines) ? U[(size_t)q * nr + i] : 0.0;
+            if (++c == creps) { c = 0; ++lm; }
+        }
+        c = 0;
+        lm = 0;
+#pragma unroll
+        for (int m = 0; m < ROWS + 8; ++m) {
+            const int lt = lr + lpp * lm;
+            const int i = ci + tpl * c;
+            if (lt < nrows && i < nr) ut[lt * pitch + 2 + i] = buf[m];
+            if (++c == creps) { c = 0; ++lm; }
+        }
+        for (int lt = lr; lt < nrows; lt += lpp)
+            if (ci < 2) {
+                ut[lt * pitch + ci] = 0.0;
+                ut[lt * pitch + nr + 2 + ci] = 0.0;
+            }
     }
     __syncthreads();
 
-    // Phase B: segmented solve of each r line in registers
-    const int l = threadIdx.x % L;
-    const int seg = threadIdx.x / L;
-    const int q = q0 + l;
+    // Phase B: explicit predictor, D0 kept in registers until the tile is free.
+    // Thread t handles columns ci + tpl c (c < creps) of lines lr + lpp m.
+    double dv[ROWS + 1];
+    {
+        double um[ROWS + 1], upv[ROWS + 1];
+        // y neighbours first, all loads in flight together; on a y face the
+        // missing neighbour is replaced by the node itself (weight zero)
+        {
+            int c = 0, lm = 0;
+#pragma unroll
+            for (int m = 0; m < ROWS + 1; ++m) {
+                const int l = lr + lpp * lm;
+                const int i = ci + tpl * c;
+                um[m] = 0.0;
+                upv[m] = 0.0;
+                if (l < nl && i < nr) {
+                    const int q = q0 + l;
+                    const int k = q / nv;
+                    const size_t gq = (size_t)q * nr + i;
+                    um[m] = U[k > 0 ? gq - sy : gq];
+                    upv[m] = U[k < ny - 1 ? gq + sy : gq];
+                }
+                if (++c == creps) { c = 0; ++lm; }
+            }
+        }
+        int c = 0, lm = 0;
+#pragma unroll
+        for (int m = 0; m < ROWS + 1; ++m) {
+            const int l = lr + lpp * lm;
+            const int i = ci + tpl * c;
+            dv[m] = 0.0;
+            if (l < nl && i < nr) {
+                const int q = q0 + l;
+                const int k = q / nv;
+                const ldouble* lc = lcon + l * kLC;
+                const ldouble* u0 = ut + (l + 2) * pitch + 2 + i;
+                const double u = u0[0];
+                const double v = lc[LC_V];
+                // A1 (r, with the reaction term): tabulated row, see hjm_internal.h
+                const double e = rt[RT_P * nr + i] * lc[LC_C] + rt[RT_Q * nr + i];
+                const double olo = rt[RT_MLO * nr + i] * e + rt[RT_ALO * nr + i] * v;
+                const double odi = rt[RT_MDI * nr + i] * e + rt[RT_ADI * nr + i] * v - rt[RT_RR * nr + i];
+                const double oup = rt[RT_MUP * nr + i] * e + rt[RT_AUP * nr + i] * v;
+                const double oex = rt[RT_MEX * nr + i] * e;
+                const double uex = i == 0 ? u0[2] : u0[-2];
+                const double a1 = olo * u0[-1] + odi * u + oup * u0[1] + oex * uex;
+                // A2 (v): offsets -2..+2 (the tile always holds them)
+                const double a2 = lc[LC_O0] * u0[-2 * pitch] + lc[LC_O1] * u0[-pitch] + lc[LC_O2] * u +
+                                  lc[LC_O3] * u0[pitch] + lc[LC_O4] * u0[2 * pitch];
+                // A3 (y, advection): the k -+ 2 neighbours only on outflow y faces
+                double ey = 0.0;
+                if (k == 0) ey = lc[LC_W4] * U[(size_t)q * nr + i + 2 * sy];
+                if (k == ny - 1 && !s.y_hi_dir) ey = lc[LC_W0] * U[(size_t)q * nr + i - 2 * sy];
+                const double by = rt[RT_Y * nr + i] * lc[LC_PV] - lc[LC_K];
+                const double a3 = by * (lc[LC_W1] * um[m] + lc[LC_W2] * u + lc[LC_W3] * upv[m] + ey);
+                // A0 (mixed r-v), zero on the (r, v) faces through the tables
+                const double cross = (u0[1 + pitch] - u0[1 - pitch]) - (u0[-1 + pitch] - u0[-1 - pitch]);
+                const double a0 = rt[RT_X * nr + i] * lc[LC_VX] * cross;
+                double val = s.dt * (((a1 + a2) + a3) + a0);
+                if ((i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir) || (k == ny - 1 && s.y_hi_dir)) {
+                    const double ri = rt[RT_R * nr + i], yk = lc[LC_Y];
+                    val = dirichlet_value(s, stn1, ri, yk) - dirichlet_value(s, stn, ri, yk);
+                }
+                dv[m] = val;
+            }
+            if (++c == creps) { c = 0; ++lm; }
+        }
+    }
+    __syncthreads();
+    {
+        int c = 0, lm = 0;
+#pragma unroll
+        for (int m = 0; m < ROWS + 1; ++m) {
+            const int l = lr + lpp * lm;
+            const int i = ci + tpl * c;
+            if (l < nl && i < nr) ut[(l + 2) * pitch + 2 + i] = dv[m];
+            if (++c == creps) { c = 0; ++lm; }
+        }
+    }
+    __syncthreads();
+
+    // Phase C: line solves (rows in registers)
+    const int l = t % L;
+    const int seg = t / L;
     const bool active = seg < S && l < nl;
+    const int q = q0 + l;
     const int k = q / nv;
-    const int j = q - k * nv;
     const bool line_dir = (k == ny - 1) && s.y_hi_dir;
     const bool work = active && !line_dir;
     Seg<ROWS> g;
     seg_init(g, nr, S, seg < S ? seg : 0);
+    ldouble* row_lds = ut + (l + 2) * pitch + 2 + g.p;
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) g.d[mm] = (work && mm < g.len) ? row_lds[mm] : 0.0;
+    RowRFull full;
+    full.rt = rt;
+    full.nr = nr;
+    full.v = active ? lcon[l * kLC + LC_V] : 0.0;
+    full.c = active ? lcon[l * kLC + LC_C] : 0.0;
+    full.tdt = s.tdt;
+    if (s.r_mode == R_SPIKE) spike_solve_r(g, full, rt6, work, red + (size_t)l * S * kRed, s);
+    else chain_solve_r(g, full, rt6, work, red + 2 * l, s);
     if (work) {
 #pragma unroll
         for (int mm = 0; mm < ROWS; ++mm)
-            if (mm < g.len) g.d[mm] = tile[l * pitch + g.p + mm];
-    }
-    RowR row;
-    row.r = s.rt + RT_R * nr;
-    row.ra = s.rt + RT_A * nr;
-    row.rb1 = s.rt + RT_B1 * nr;
-    row.rb2 = s.rt + RT_B2 * nr;
-    row.v = active ? s.vt[VT_V * nv + j] : 0.0;
-    row.drift0 = phi + (active ? s.yt[YT_Y * ny + k] : 0.0);
-    row.kappa = s.kappa;
-    row.tdt = s.tdt;
-    row.ih2 = s.ih2r;
-    row.i2h = s.i2hr;
-    row.nr = nr;
-    row.lo_dir = s.r_lo_dir;
-    row.hi_dir = s.r_hi_dir;
-    line_solve(g, row, work, red + 2 * l, s);
-    if (work) {
-#pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm)
-            if (mm < g.len) tile[l * pitch + g.p + mm] = g.d[mm];
+            if (mm < g.len) row_lds[mm] = g.d[mm];
     }
     __syncthreads();
 
-    // Phase C: D1 back to global memory (the tile's lines are contiguous)
-    double* D = s.D + (size_t)q0 * nr;
-    for (int ll = threadIdx.x / tpl; ll < nl; ll += lpp)
-        for (int i = threadIdx.x % tpl; i < nr; i += tpl) D[(size_t)ll * nr + i] = tile[ll * pitch + i];
+    // Phase D: D1 back to global memory (the tile's lines are contiguous)
+    gdouble* Dt = D + (size_t)q0 * nr;
+    for (int ll = lr; ll < nl; ll += lpp)
+        for (int i = ci; i < nr; i += tpl) Dt[(size_t)ll * nr + i] = ut[(ll + 2) * pitch + 2 + i];
 }
 
+// v sweep: shared factors of the v-line matrix, chained recurrence.
 template <int ROWS>
 __global__ __launch_bounds__(kBlock) void k_v(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
     const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const SolveDesc& s = descs[tk.x];
     const int nr = s.nr, nv = s.nv, ny = s.ny;
     const int L = s.v_L, S = s.v_S;
-    const int l = threadIdx.x % L;
-    const int seg = threadIdx.x / L;
+    const int t = threadIdx.x;
+    ldouble* xch = lds;
+    const int l = t % L;
+    const int seg = t / L;
     const int q = tk.y * L + l;  // line (i, k), q = k*nr + i
     const bool active = seg < S && q < nr * ny;
     const int k = q / nr;
@@ -460,21 +663,77 @@ __global__ __launch_bounds__(kBlock) void k_v(const SolveDesc* __restrict__ desc
     const bool work = active && !line_dir;  // identity lines keep D
     Seg<ROWS> g;
     seg_init(g, nv, S, seg < S ? seg : 0);
-    double* base = s.D + (size_t)k * nv * nr + i + (size_t)g.p * nr;
-    if (work) {
+    gdouble* base = gp(s.D) + (size_t)k * nv * nr + i + (size_t)g.p * nr;
+    // the segment's factors (same for every line) and its rows
+    gcdouble* vf = gp(s.vf);
+    double fa[ROWS], fi[ROWS];
 #pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm)
-            if (mm < g.len) g.d[mm] = base[(size_t)mm * nr];
+    for (int mm = 0; mm < ROWS; ++mm) {
+        const int jj = min(g.p + mm, nv - 1);
+        fa[mm] = vf[VF_A * nv + jj];
+        fi[mm] = vf[VF_INV * nv + jj];
+        g.cp[mm] = vf[VF_C * nv + jj];
+        g.d[mm] = (work && mm < g.len) ? base[(size_t)mm * nr] : 0.0;
     }
-    RowV row;
-    row.va = s.vt + VT_A * nv;
-    row.vb = s.vt + VT_B * nv;
-    row.vm = s.vt + VT_M * nv;
-    row.tdt = s.tdt;
-    row.ih2 = s.ih2v;
-    row.i2h = s.i2hv;
-    row.nv = nv;
-    line_solve(g, row, work, lds + 2 * l, s);
+    const bool first = g.seg == 0;
+    const bool last = g.seg == S - 1;
+    gcdouble* fs = vf + kVF * nv;
+    if (work && first) {
+        g.d0 = g.d[0];
+        g.d[1] = g.d[1] - fs[VS_F1] * g.d[0];
+        g.lo = 1;
+    }
+    if (work && last) {
+        double dl = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) dl = (mm == g.len - 1) ? g.d[mm] : dl;
+        g.dl = dl;
+        const double f2 = fs[VS_F2];
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) g.d[mm] = (mm == g.len - 2) ? g.d[mm] - f2 * dl : g.d[mm];
+        g.hi = g.len - 2;
+    }
+    ldouble* x2 = xch + 2 * l;
+    for (int stage = 0; stage < S; ++stage) {
+        if (work && seg == stage) {
+            double dprev = stage > 0 ? x2[1] : 0.0;
+#pragma unroll
+            for (int mm = 0; mm < ROWS; ++mm) {
+                const bool act = mm >= g.lo && mm <= g.hi;
+                const double dn = (g.d[mm] - fa[mm] * dprev) * fi[mm];
+                dprev = act ? dn : dprev;
+                g.d[mm] = act ? dn : g.d[mm];
+            }
+            x2[1] = dprev;
+        }
+        if (S > 1) __syncthreads();
+    }
+    for (int stage = S - 1; stage >= 0; --stage) {
+        if (work && seg == stage) {
+            double x = stage < S - 1 ? x2[0] : 0.0;
+#pragma unroll
+            for (int mm = ROWS - 1; mm >= 0; --mm) {
+                const bool act = mm >= g.lo && mm <= g.hi;
+                const double xn = g.d[mm] - g.cp[mm] * x;
+                x = act ? xn : x;
+                g.d[mm] = act ? xn : g.d[mm];
+            }
+            x2[0] = x;
+            if (first) g.d[0] = (g.d0 - fs[VS_C0] * g.d[1] - fs[VS_E0] * g.d[2]) / fs[VS_B0];
+            if (last) {
+                double x3 = 0.0, xn2 = 0.0;
+#pragma unroll
+                for (int mm = 0; mm < ROWS; ++mm) {
+                    x3 = (mm == g.len - 3) ? g.d[mm] : x3;
+                    xn2 = (mm == g.len - 2) ? g.d[mm] : xn2;
+                }
+                const double xl = (g.dl - fs[VS_EL] * x3 - fs[VS_AL] * xn2) / fs[VS_BL];
+#pragma unroll
+                for (int mm = 0; mm < ROWS; ++mm) g.d[mm] = (mm == g.len - 1) ? xl : g.d[mm];
+            }
+        }
+        if (S > 1) __syncthreads();
+    }
     if (work) {
 #pragma unroll
         for (int mm = 0; mm < ROWS; ++mm)
@@ -482,43 +741,85 @@ __global__ __launch_bounds__(kBlock) void k_v(const SolveDesc* __restrict__ desc
     }
 }
 
+// y row k of (I - theta dt A3) on a line with q = lambda^2 r^{2 gamma} v
+struct RowY {
+    gcdouble* yt;
+    int ny;
+    double qv;
+    __device__ __forceinline__ void operator()(int k, double& A, double& B, double& C, double& E) const
+    {
+        const double a = yt[YT_T1 * ny + k] * qv + yt[YT_T2 * ny + k];
+        A = yt[YT_MA * ny + k] * a;
+        B = 1.0 + yt[YT_MB * ny + k] * a;
+        C = yt[YT_MC * ny + k] * a;
+        E = yt[YT_ME * ny + k] * a;
+    }
+};
+
+// y sweep + update: chained Thomas per line (i, j), then U += D3.
 template <int ROWS>
 __global__ __launch_bounds__(kBlock) void k_yu(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
     const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const SolveDesc& s = descs[tk.x];
     const int nr = s.nr, nv = s.nv, ny = s.ny;
     const int L = s.y_L, S = s.y_S;
-    const int l = threadIdx.x % L;
-    const int seg = threadIdx.x / L;
+    const int t = threadIdx.x;
+    ldouble* xch = lds;
+    const int l = t % L;
+    const int seg = t / L;
     const int q = tk.y * L + l;  // line (i, j), q = j*nr + i
     const bool active = seg < S && q < nr * nv;
     const int j = q / nr;
     const int i = q - j * nr;
     const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir);
+    const bool work = active && !line_dir;
     Seg<ROWS> g;
     seg_init(g, ny, S, seg < S ? seg : 0);
     const size_t sy = (size_t)nr * nv;
     const size_t off = (size_t)q + (size_t)g.p * sy;
-    if (active) {
+    gcdouble* D = gp(s.D);
+    gdouble* U = gp(s.U);
+    gcdouble* yt = gp(s.yt);
+    double u[ROWS];
 #pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm)
-            if (mm < g.len) g.d[mm] = s.D[off + (size_t)mm * sy];
+    for (int mm = 0; mm < ROWS; ++mm) {
+        const bool in = active && mm < g.len;
+        g.d[mm] = in ? D[off + (size_t)mm * sy] : 0.0;
+        u[mm] = in ? U[off + (size_t)mm * sy] : 0.0;
     }
     RowY row;
-    row.yi = s.yt + YT_I * ny;
-    row.y2k = s.yt + YT_K * ny;
-    row.qv = active ? s.rt[RT_Y * nr + i] * s.vt[VT_V * nv + j] : 0.0;
-    row.tdt = s.tdt;
-    row.i2h = s.i2hy;
+    row.yt = yt;
     row.ny = ny;
-    row.hi_dir = s.y_hi_dir;
-    line_solve(g, row, active && !line_dir, lds + 2 * l, s);
+    row.qv = active ? gp(s.rt)[RT_Y * nr + i] * gp(s.vt)[VT_V * nv + j] : 0.0;
+    double ca[ROWS], cb[ROWS];
+    double b1m = 1.0, c1m = 0.0, a2m = 0.0, b2m = 1.0;
+    bool ok = true;
+    if (work) {
+        ok = seg_ends(g, row, b1m, c1m, a2m, b2m);
+        const bool first = g.seg == 0;
+        const bool last = g.seg == S - 1;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            const int kk = min(g.p + mm, ny - 1);
+            double A, B, C, E;
+            row(kk, A, B, C, E);
+            if (first && mm == 1) { A = 0.0; B = b1m; C = c1m; }
+            if (last && mm == g.len - 2) { A = a2m; B = b2m; C = 0.0; }
+            const bool act = mm >= g.lo && mm <= g.hi;
+            ca[mm] = act ? A : 0.0;
+            cb[mm] = act ? B : 1.0;
+            g.cp[mm] = act ? C : 0.0;
+        }
+    }
+    ok = chain_core(g, ca, cb, work, xch + 2 * l) && ok;
+    if (work && !ok) raise_flag(s);
     if (active) {
 #pragma unroll
         for (int mm = 0; mm < ROWS; ++mm)
-            if (mm < g.len) s.U[off + (size_t)mm * sy] += g.d[mm];
+            if (mm < g.len) U[off + (size_t)mm * sy] = u[mm] + g.d[mm];
     }
 }
 
@@ -529,10 +830,11 @@ __global__ void k_readout(const SolveDesc* __restrict__ descs, const Readout* __
     if (t >= n) return;
     const Readout R = rq[t];
     const SolveDesc& s = descs[R.solve];
+    gcdouble* U = gp(s.U);
     double acc = 0.0;
     for (int b = 0; b < 4; ++b)
         for (int a = 0; a < 4; ++a)
-            acc += R.wv[b] * R.wr[a] * s.U[(size_t)(R.j0 + b) * s.nr + (R.i0 + a)];
+            acc += R.wv[b] * R.wr[a] * U[(size_t)(R.j0 + b) * s.nr + (R.i0 + a)];
     out[t] = acc;
 }
 
@@ -540,9 +842,10 @@ __global__ __launch_bounds__(kBlock) void k_health(const SolveDesc* __restrict__
 {
     const SolveDesc& s = descs[blockIdx.y];
     const int64_t npts = (int64_t)s.nr * s.nv * s.ny;
+    gcdouble* U = gp(s.U);
     bool bad = false;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < npts; p += (int64_t)gridDim.x * kBlock)
-        bad = bad || !isfinite(s.U[p]);
+        bad = bad || !isfinite(U[p]);
     if (bad) raise_flag(s);
 }
 
@@ -605,27 +908,21 @@ hipError_t launch_xr(int rows, const SolveDesc* d_desc, const int2* tasks, int n
                      hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    HJM_DISPATCH_ROWS(rows, {
-        hipLaunchKernelGGL(k_xr<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step);
-    })
+    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_xr<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step))
     return hipGetLastError();
 }
 
 hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, size_t lds, hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    HJM_DISPATCH_ROWS(rows, {
-        hipLaunchKernelGGL(k_v<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks);
-    })
+    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_v<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 
 hipError_t launch_yu(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, size_t lds, hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    HJM_DISPATCH_ROWS(rows, {
-        hipLaunchKernelGGL(k_yu<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks);
-    })
+    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_yu<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 
