@@ -26,10 +26,27 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per grid point per launch of each pass
 PASS_BYTES = {"explicit+r": 16.0, "v": 16.0, "y+update": 24.0}
 PASS_NAMES = ["explicit+r", "v", "y+update"]
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (FETCH_SIZE
+# scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain copy kernel of
+# known size reads), valid only for the kernel sources and line tiles they were
+# taken on: reported as null otherwise.
+MEASURED_TRAFFIC = {
+    "sources_sha256": "a643ff4bd9ab94849ee4ac99cdef74d9f2c487f3b4bc5421bcb99f156ef59fd0"
+                      ":cf0c5da7fc1a4aae00b39733e57a17ac1bdcaf6cfd453d104ba2ba4c2e4b5c9e",
+    "line_tile": (8, 16, 16),
+    "bytes": {"explicit+r": 84864000, "v": 66792448, "y+update": 100994253},
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1108_1688_amd", "csrc")
+    return ":".join(hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()
+                    for f in ("hjm_kernels.hip", "hjm_internal.h"))
 
 
 def cpu_baseline(seconds: float):
@@ -126,12 +143,17 @@ def main():
         gbs = PASS_BYTES[name] * points / (avg_ms * 1e-3) / 1e9
         passes[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": pass_n[q], "GB/s": round(gbs, 1),
                         "share": round(pass_ms[q] / max(sum(pass_ms), 1e-12), 3)}
+    traffic_ok = (kernel_sources_sha256() == MEASURED_TRAFFIC["sources_sha256"]
+                  and tuple(hjm.get_line_tile()) == MEASURED_TRAFFIC["line_tile"])
+    for name in PASS_NAMES:
+        passes[name]["traffic_bytes"] = MEASURED_TRAFFIC["bytes"][name] if traffic_ok else None
     dom = max(range(3), key=lambda q: pass_ms[q])
     dname = PASS_NAMES[dom]
     achieved = passes[dname]["GB/s"]
     step_gbs = sum(PASS_BYTES.values()) * points / (sum(pass_ms) / max(pass_n[0], 1) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": passes[dname]["traffic_bytes"],
+                "traffic_unit": "bytes/launch",
                 "bytes_per_point": PASS_BYTES[dname], "points_per_launch": points,
                 "douglas_step_GBs": round(step_gbs, 1), "passes": passes}
     log(f"prices (1..10y): {[round(p, 8) for p in prices]}")

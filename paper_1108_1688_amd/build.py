@@ -1,4 +1,5 @@
-"""Builds libhjm.so (HIP kernels + host layer, gfx950) in the package directory.
+"""Builds libhjm.so (HIP kernels + host layer, gfx950) and the hjm_run
+command-line runner (host code over the C ABI) in the package directory.
 
     python -m paper_1108_1688_amd.build
 """
@@ -13,6 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhjm.so")
 SOURCES = ["hjm_kernels.hip", "hjm_host.hip"]
+RUNNER = os.path.join(HERE, "hjm_run")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -38,7 +40,27 @@ def build(verbose: bool = False) -> str:
     if verbose and err.strip():
         print(err, file=sys.stderr)
     os.replace(tmp, LIB)
+    build_runner(verbose)
     return LIB
+
+
+def build_runner(verbose: bool = False) -> str:
+    """hjm_run (host code over the C ABI plus one reference copy kernel) links
+    libhjm.so from its own directory."""
+    tmp = RUNNER + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-Wall",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"),
+           "-o", tmp, os.path.join(CSRC, "hjm_run.hip"), "-L", HERE, "-lhjm", "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
+    if verbose and err.strip():
+        print(err, file=sys.stderr)
+    os.replace(tmp, RUNNER)
+    return RUNNER
 
 
 if __name__ == "__main__":

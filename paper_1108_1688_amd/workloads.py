@@ -215,3 +215,30 @@ def with_shape(s: SolveSpec, nr: int, nv: int, ny: int, n_steps: int | None = No
     """Same problem on another mesh (and optionally another step count)."""
     ax = tuple(replace(a, n=n) for a, n in zip(s.axes, (nr, nv, ny)))
     return replace(s, axes=ax, n_steps=s.n_steps if n_steps is None else n_steps)
+
+
+def spec_line(s: SolveSpec) -> str:
+    """One solve as the 37 numbers the hjm_run command-line runner reads:
+    3 x (n z_min z_max center alpha lo_face hi_face), the model, the payoff,
+    then n_steps r0 v0."""
+    f = []
+    for a in s.axes:
+        f += [a.n, a.z_min, a.z_max, a.center, a.alpha, a.lo_face, a.hi_face]
+    m = s.model
+    f += [m.kappa, m.theta_v, m.lam, m.gamma, m.epsilon, m.rho, m.f_level, m.f_slope, m.f_decay]
+    f += [s.payoff.kind, s.payoff.expiry, s.payoff.pay, s.payoff.strike, s.n_steps, s.r0, s.v0]
+    return " ".join(repr(float(x)) if isinstance(x, float) else str(int(x)) for x in f)
+
+
+WORKLOADS = {"config1": config1, "config2": config2, "config3": config3, "config4": config4}
+
+
+if __name__ == "__main__":
+    import sys
+    names = sys.argv[1:] or ["config3"]
+    for name in names:
+        if name not in WORKLOADS:
+            sys.exit(f"unknown workload {name!r}; one of {sorted(WORKLOADS)}")
+        print(f"# {name}: {WORKLOADS[name].__doc__.splitlines()[0]}")
+        for s in WORKLOADS[name]():
+            print(spec_line(s))
