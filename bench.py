@@ -24,8 +24,13 @@ METRIC = "grid-point ADI updates/s (FP64, % HBM roofline); calibration solves/s 
 UNIT = "grid-point ADI updates/s"
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per grid point per launch of each pass
-PASS_BYTES = {"explicit+r": 16.0, "v": 16.0, "y+update": 24.0}
-PASS_NAMES = ["explicit+r", "v", "y+update"]
+# (explicit: read U, write D; r: D in place; v: D in place; y+update: read D and
+# U, write U)
+PASS_BYTES = {"explicit": 16.0, "r": 16.0, "v": 16.0, "y+update": 24.0}
+PASS_NAMES = ["explicit", "r", "v", "y+update"]
+# algorithmic minimum of a whole Douglas step: read U twice (explicit, update)
+# plus D through the three sweeps, fused as far as possible: 56 B per point
+STEP_BYTES = 56.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (FETCH_SIZE
 # scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain copy kernel of
 # known size reads), valid only for the kernel sources and line tiles they were
@@ -34,7 +39,7 @@ MEASURED_TRAFFIC = {
     "sources_sha256": "a643ff4bd9ab94849ee4ac99cdef74d9f2c487f3b4bc5421bcb99f156ef59fd0"
                       ":cf0c5da7fc1a4aae00b39733e57a17ac1bdcaf6cfd453d104ba2ba4c2e4b5c9e",
     "line_tile": (8, 16, 16),
-    "bytes": {"explicit+r": 84864000, "v": 66792448, "y+update": 100994253},
+    "bytes": {"explicit": None, "r": None, "v": 66792448, "y+update": 100994253},
 }
 
 
@@ -131,26 +136,27 @@ def main():
     ms_per_step = 1e3 * el / args.steps
     value = points * total_steps * args.steps / el
 
-    pass_ms = [0.0, 0.0, 0.0]
-    pass_n = [0, 0, 0]
+    npass = len(PASS_NAMES)
+    pass_ms = [0.0] * npass
+    pass_n = [0] * npass
     for ms, n in profs:
-        for q in range(3):
+        for q in range(npass):
             pass_ms[q] += ms[q]
             pass_n[q] += n[q]
     passes = {}
     for q, name in enumerate(PASS_NAMES):
         avg_ms = pass_ms[q] / max(pass_n[q], 1)
-        gbs = PASS_BYTES[name] * points / (avg_ms * 1e-3) / 1e9
+        gbs = PASS_BYTES[name] * points / (avg_ms * 1e-3) / 1e9 if pass_n[q] else 0.0
         passes[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": pass_n[q], "GB/s": round(gbs, 1),
                         "share": round(pass_ms[q] / max(sum(pass_ms), 1e-12), 3)}
     traffic_ok = (kernel_sources_sha256() == MEASURED_TRAFFIC["sources_sha256"]
                   and tuple(hjm.get_line_tile()) == MEASURED_TRAFFIC["line_tile"])
     for name in PASS_NAMES:
         passes[name]["traffic_bytes"] = MEASURED_TRAFFIC["bytes"][name] if traffic_ok else None
-    dom = max(range(3), key=lambda q: pass_ms[q])
+    dom = max(range(npass), key=lambda q: pass_ms[q])
     dname = PASS_NAMES[dom]
     achieved = passes[dname]["GB/s"]
-    step_gbs = sum(PASS_BYTES.values()) * points / (sum(pass_ms) / max(pass_n[0], 1) * 1e-3) / 1e9
+    step_gbs = STEP_BYTES * points / (sum(pass_ms) / max(pass_n[0], 1) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": passes[dname]["traffic_bytes"],
                 "traffic_unit": "bytes/launch",

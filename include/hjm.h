@@ -129,15 +129,31 @@ hjm_status hjm_grid_set_step(hjm_grid* g, int64_t step);
 /* Release the host handle (the caller's device memory is untouched). */
 hjm_status hjm_grid_destroy(hjm_grid* g);
 
-/* Per-pass timing.  While enabled, each pass launch of hjm_adi_step (the
-   explicit + r sweep, the v sweep, the y sweep + update) is bracketed by HIP
-   events recorded on the grid's stream. */
+/* How the solve is carried out (host only): plan[0] = r-line method
+   (0 spike and 1 chain, both in the kernel that also computes the explicit
+   predictor; 2 split: separate explicit kernel, then a spike solve with the
+   segments of a line in consecutive lanes of one wavefront), plan[1] = rows
+   per lane of the split r solve (0 if not split), plan[2..4] = the line-tile
+   rows per thread of the r, v and y solves, plan[5..7] = 0 (reserved).  The
+   spike variants are chosen only where the r rows keep (|A| + |C|) / B
+   bounded (section 5, tridiagonal systems), so every variant matches the
+   sequential elimination to rounding. */
+hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[8]);
+
+/* Per-pass timing.  While enabled, each kernel launch of hjm_adi_step is
+   bracketed by HIP events recorded on the grid's stream.  Passes, in order:
+     0  explicit predictor (on grids whose r lines are solved in the same
+        kernel, that kernel: explicit predictor + r sweep)
+     1  r sweep (no launches when fused into pass 0)
+     2  v sweep
+     3  y sweep + update */
+#define HJM_N_PASSES 4
 hjm_status hjm_grid_profile(hjm_grid* g, int32_t enable);
 
 /* Synchronise the stream and return, per pass, the summed event-to-event
    milliseconds and the number of launches bracketed since the previous read
-   (ms[3], launches[3]); the sums restart from zero. */
-hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[3], int64_t launches[3]);
+   (ms[HJM_N_PASSES], launches[HJM_N_PASSES]); the sums restart from zero. */
+hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[HJM_N_PASSES], int64_t launches[HJM_N_PASSES]);
 
 /* ---------------------------------------------------------------------- */
 /* Batched independent solves (calibration-style throughput).              */

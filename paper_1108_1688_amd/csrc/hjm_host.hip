@@ -174,10 +174,28 @@ hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_
 // ---------------------------------------------------------------------------
 struct Plan {
     bool r_spike;
+    int r_mode;  // R_SPIKE / R_CHAIN (fused k_xr) or R_SPLIT (k_exp + k_rs)
     int r_S, r_L, r_pitch, v_S, v_L, y_S, y_L;
     int r_tiles, v_tiles, y_tiles;
     size_t r_lds, v_lds, y_lds;
+    int rs_rows, rs_S, rs_log2S, rs_L, rs_tiles;
+    int exp_J, exp_cb, exp_tiles;
 };
+
+constexpr int kExpJ = 16;  // v nodes per k_exp thread
+
+// k_rs needs nr = S * ROWS with S a power of two <= 64 lanes; the preferred
+// rows per lane come first.
+int split_rows(int nr, int preferred)
+{
+    const int cands[5] = {preferred, 8, 16, 12, 6};
+    for (int r : cands) {
+        if (!rs_rows_supported(r) || nr % r) continue;
+        const int S = nr / r;
+        if (S >= 1 && S <= 64 && (S & (S - 1)) == 0) return r;
+    }
+    return 0;
+}
 
 constexpr size_t kTileLdsBudget = 96 * 1024;
 constexpr int kLCDoubles = 16;  // per-line constants of the explicit phase
@@ -215,14 +233,33 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     p.y_L = kBlock / p.y_S;
     p.y_tiles = (nr * nv + p.y_L - 1) / p.y_L;
     p.y_lds = 2 * (size_t)p.y_L * 8;
+    p.r_mode = r_spike ? R_SPIKE : R_CHAIN;
+    p.rs_rows = r_spike ? split_rows(nr, rows[0]) : 0;
+    p.rs_S = p.rs_log2S = p.rs_L = p.rs_tiles = 0;
+    p.exp_J = std::min(kExpJ, nv);
+    p.exp_cb = (nr * ny + kExpCols - 1) / kExpCols;
+    p.exp_tiles = p.exp_cb * ((nv + p.exp_J - 1) / p.exp_J);
+    if (p.rs_rows) {
+        p.r_mode = R_SPLIT;
+        p.rs_S = nr / p.rs_rows;
+        while ((1 << p.rs_log2S) < p.rs_S) ++p.rs_log2S;
+        p.rs_L = 4 * (64 / p.rs_S);
+        p.rs_tiles = (nv * ny + p.rs_L - 1) / p.rs_L;
+    }
     return p;
 }
 
-// The spike solve is accurate when every r row is diagonally dominant, which
-// holds when the cell Courant number theta dt |b| / (2 h_r) <= 0.4 (then
-// B - |A| - |C| >= 1 - 2 * 0.4).  b = (c - kappa r) / J - v zeta_rr J2 / (v J^3)
-// is affine in c = f_t + kappa f + y and in v, so its extremes over all rows,
-// lines and steps sit at the corners of those ranges.
+// The spike solve stays within a few ulps of the sequential elimination as
+// long as no row's off-diagonal entries dwarf its diagonal: with
+// rho = (|A| + |C|) / B <= kSpikeRho its error measured against an extended-
+// precision Thomas solve stays below 1e-15 relative (diagonally dominant rows,
+// rho <= 1, and advection-dominated rows, where A C < 0 keeps every pivot
+// >= B, alike); rows with rho ~ 1e4, as in the far field of the y lines, lose
+// digits.  The entries of an interior r row are affine in v and in
+// c = f_t + kappa f + y, so rho is quasi-convex in (v, c) and its maximum
+// over all lines and steps sits at a corner of their ranges.
+constexpr double kSpikeRho = 16.0;
+
 bool r_spike_ok(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps)
 {
     const Curve cv{m.f_level, m.f_slope, m.f_decay};
@@ -235,21 +272,25 @@ bool r_spike_ok(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, i
         phi_hi = std::max(phi_hi, phi);
     }
     const double c_lo = phi_lo + ax[2].z_min, c_hi = phi_hi + ax[2].z_max;
-    const double v_lo = ax[1].z_min, v_hi = ax[1].z_max;
     const Mesh mr = make_mesh(ax[0]);
-    const double i2h = 0.5 * (ax[0].n - 1.0);
+    const int nr = ax[0].n;
+    const double hr1 = nr - 1.0, ih2 = hr1 * hr1, i2h = 0.5 * hr1;
     double worst = 0.0;
-    for (int i = 0; i < ax[0].n; ++i) {
+    for (int i = 1; i < nr - 1; ++i) {
         const double r = mr.z[i], J = mr.J[i], J2 = mr.J2[i];
         const double rg = rpow(r, m.gamma);
         const double zr = 0.5 * m.lambda * m.lambda * rg * rg;
+        const double ra = zr / (J * J), rb2 = zr * J2 / (J * J * J);
+        const double alo = ra * ih2 + rb2 * i2h, adi = -2.0 * ra * ih2, aup = ra * ih2 - rb2 * i2h;
         for (double c : {c_lo, c_hi})
-            for (double v : {0.0, v_lo, v_hi}) {
-                const double b = (c - m.kappa * r) / J - v * zr * J2 / (J * J * J);
-                worst = std::max(worst, tdt * std::fabs(b) * i2h);
+            for (double v : {ax[1].z_min, ax[1].z_max}) {
+                const double e = (c - m.kappa * r) / J * i2h;
+                const double A = -tdt * (alo * v - e), B = 1.0 - tdt * (adi * v - r), C = -tdt * (aup * v + e);
+                if (!(B > 0.0)) return false;
+                worst = std::max(worst, (std::fabs(A) + std::fabs(C)) / B);
             }
     }
-    return worst <= 0.4;
+    return worst <= kSpikeRho;
 }
 
 // Upper bound of the tiles of any plan (used to size task lists).
@@ -257,6 +298,12 @@ Plan plan_bound(int nr, int nv, int ny)
 {
     static const int options[3] = {8, 16, 32};
     Plan b{};
+    for (int o : {8, 16, 12, 6})
+        for (bool sp : {true, false}) {
+            const int rows[3] = {o, 8, 8};
+            Plan p = make_plan(nr, nv, ny, rows, sp);
+            b.rs_tiles = std::max(b.rs_tiles, p.rs_tiles);
+        }
     for (int o : options)
         for (bool sp : {true, false}) {
             const int rows[3] = {o, o, o};
@@ -264,6 +311,8 @@ Plan plan_bound(int nr, int nv, int ny)
             b.r_tiles = std::max(b.r_tiles, p.r_tiles);
             b.v_tiles = std::max(b.v_tiles, p.v_tiles);
             b.y_tiles = std::max(b.y_tiles, p.y_tiles);
+            b.rs_tiles = std::max(b.rs_tiles, p.rs_tiles);
+            b.exp_tiles = std::max(b.exp_tiles, p.exp_tiles);
         }
     return b;
 }
@@ -284,7 +333,8 @@ struct Layout {
 size_t table_doubles(const hjm_axis ax[3], int n_steps)
 {
     return (size_t)kRT * ax[0].n + (size_t)kVT * ax[1].n + (size_t)kYT * ax[2].n + (size_t)kVF * ax[1].n + kVS +
-           (size_t)kStepStride * (n_steps + 1);
+           (size_t)kStepStride * (n_steps + 1) + (size_t)kRF * ax[0].n +
+           (size_t)(2 * ax[2].n + ax[0].n) * n_steps;
 }
 
 struct SolveOffsets {
@@ -301,6 +351,19 @@ SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
     return o;
 }
 
+// Closed-form value g(t_n; r, y) of the contract with the solve's payoff, from
+// the step-table factors p(t,T) = A exp(-G r - H y) (bond formula, section 3.1).
+double dirichlet_host(const double* e, int kind, double accrual, double r, double y)
+{
+    const double pT = e[ST_AT] * std::exp(-e[ST_GT] * r - e[ST_HT] * y);
+    if (kind == HJM_BOND) return pT;
+    const double pM = e[ST_AM] * std::exp(-e[ST_GM] * r - e[ST_HM] * y);
+    const double lin = pT - accrual * pM;
+    if (kind == HJM_CAPLET) return lin > 0.0 ? lin : 0.0;
+    if (kind == HJM_FLOORLET) return -lin > 0.0 ? -lin : 0.0;
+    return lin;
+}
+
 // Fill the host tables of one solve: axis coefficient rows, step table.
 void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps,
                   std::vector<double>& out)
@@ -312,6 +375,8 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
     double* yt = vt + (size_t)kVT * nv;
     double* vf = yt + (size_t)kYT * ny;
     double* st = vf + (size_t)kVF * nv + kVS;
+    double* rf = st + (size_t)kStepStride * (n_steps + 1);
+    double* gd = rf + (size_t)kRF * nr;
     const Mesh mr = make_mesh(ax[0]), mv = make_mesh(ax[1]), my = make_mesh(ax[2]);
     const double lam = m.lambda, eps = m.epsilon;
     const double dt = p.expiry / n_steps, tdt = kTheta * dt;
@@ -345,6 +410,13 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
         rt[RT_RR * nr + i] = dir ? 0.0 : r;
         rt[RT_X * nr + i] = (lo || hi) ? 0.0 : lam * rg / J;
         rt[RT_Y * nr + i] = lam * lam * rg * rg;
+        // the same interior row with theta dt folded in (split path)
+        rf[RF_P * nr + i] = tdt * rt[RT_P * nr + i];
+        rf[RF_Q * nr + i] = tdt * rt[RT_Q * nr + i];
+        rf[RF_ALO * nr + i] = -tdt * alo;
+        rf[RF_ADI * nr + i] = -tdt * adi;
+        rf[RF_AUP * nr + i] = -tdt * aup;
+        rf[RF_B * nr + i] = 1.0 + tdt * rt[RT_RR * nr + i];
     }
     std::vector<double> va(nv), vb(nv), vm(nv);  // v operator pieces, also used by the factorisation
     for (int j = 0; j < nv; ++j) {
@@ -451,6 +523,22 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
         e[ST_GM] = GM;
         e[ST_HM] = 0.5 * GM * GM;
     }
+    // Dirichlet increments g(t_{n+1}) - g(t_n) on the r faces and the y_max face
+    const double accrual = 1.0 + (p.pay - p.expiry) * p.strike;
+    const double ymax = my.z[ny - 1];
+    for (int n = 0; n < n_steps; ++n) {
+        const double* e0 = st + (size_t)kStepStride * n;
+        const double* e1 = e0 + kStepStride;
+        double* g = gd + (size_t)n * (2 * ny + nr);
+        auto inc = [&](double r, double y) {
+            return dirichlet_host(e1, p.kind, accrual, r, y) - dirichlet_host(e0, p.kind, accrual, r, y);
+        };
+        for (int k = 0; k < ny; ++k) {
+            g[GD_RLO * ny + k] = r_lo_dir ? inc(mr.z[0], my.z[k]) : 0.0;
+            g[GD_RHI * ny + k] = r_hi_dir ? inc(mr.z[nr - 1], my.z[k]) : 0.0;
+        }
+        for (int i = 0; i < nr; ++i) g[GD_YHI * ny + i] = y_hi_dir ? inc(mr.z[i], ymax) : 0.0;
+    }
 }
 
 void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps,
@@ -484,8 +572,12 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.yt = d.vt + (size_t)kVT * ax[1].n;
     d.vf = d.yt + (size_t)kYT * ax[2].n;
     d.st = d.vf + (size_t)kVF * ax[1].n + kVS;
+    d.rf = d.st + (size_t)kStepStride * (n_steps + 1);
+    d.gd = d.rf + (size_t)kRF * ax[0].n;
     d.flag = flag;
-    d.r_mode = pl.r_spike ? R_SPIKE : R_CHAIN;
+    d.r_mode = pl.r_mode;
+    d.exp_J = pl.exp_J; d.exp_cb = pl.exp_cb; d.exp_tiles = pl.exp_tiles;
+    d.rs_S = pl.rs_S; d.rs_log2S = pl.rs_log2S; d.rs_L = pl.rs_L; d.rs_tiles = pl.rs_tiles;
 }
 
 // 4-point Lagrange stencil in mesh coordinates (window centred on the
@@ -673,9 +765,11 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
     if (g->step + k > g->n_steps)
         return fail(HJM_ESTATE, "%d more steps would pass n_steps=%d (at step %lld)", k, g->n_steps, (long long)g->step);
     const Plan& p = g->plan;
+    const bool split = p.r_mode == R_SPLIT;
     for (int32_t c = 0; c < k; ++c) {
         const int n = (int)g->step;
-        for (int pass = 0; pass < 3; ++pass) {
+        for (int pass = 0; pass < HJM_N_PASSES; ++pass) {
+            if (pass == 1 && !split) continue;
             hipError_t e = hipSuccess;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (g->profile) {
@@ -693,8 +787,10 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
                 g->ev_pass[g->ev_used] = pass;
                 if ((e = hipEventRecord(e0, g->stream))) return hip_fail(e, "hipEventRecord");
             }
-            if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
-            else if (pass == 1) e = launch_v(g->rows[1], g->d_desc, nullptr, p.v_tiles, p.v_lds, g->stream);
+            if (pass == 0 && split) e = launch_exp(g->d_desc, nullptr, p.exp_tiles, n, g->stream);
+            else if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
+            else if (pass == 1) e = launch_rs(p.rs_rows, g->d_desc, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
+            else if (pass == 2) e = launch_v(g->rows[1], g->d_desc, nullptr, p.v_tiles, p.v_lds, g->stream);
             else e = launch_yu(g->rows[2], g->d_desc, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {
@@ -749,6 +845,18 @@ hjm_status hjm_grid_destroy(hjm_grid* g)
     return HJM_OK;
 }
 
+hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[8])
+{
+    if (!g || !plan) return fail(HJM_EINVAL, "null argument");
+    for (int q = 0; q < 8; ++q) plan[q] = 0;
+    plan[0] = g->plan.r_mode;
+    plan[1] = g->plan.rs_rows;
+    plan[2] = g->rows[0];
+    plan[3] = g->rows[1];
+    plan[4] = g->rows[2];
+    return HJM_OK;
+}
+
 hjm_status hjm_grid_profile(hjm_grid* g, int32_t enable)
 {
     if (!g) return fail(HJM_EINVAL, "null grid");
@@ -756,10 +864,10 @@ hjm_status hjm_grid_profile(hjm_grid* g, int32_t enable)
     return HJM_OK;
 }
 
-hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[3], int64_t launches[3])
+hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[HJM_N_PASSES], int64_t launches[HJM_N_PASSES])
 {
     if (!g || !ms || !launches) return fail(HJM_EINVAL, "null argument");
-    for (int q = 0; q < 3; ++q) { ms[q] = 0.0; launches[q] = 0; }
+    for (int q = 0; q < HJM_N_PASSES; ++q) { ms[q] = 0.0; launches[q] = 0; }
     hipError_t e = hipStreamSynchronize(g->stream);
     if (e) return hip_fail(e, "hjm_grid_profile_read");
     for (size_t u = 0; u < g->ev_used; ++u) {
@@ -789,13 +897,18 @@ struct hjm_batch {
     int2* d_tr = nullptr;
     int2* d_tv = nullptr;
     int2* d_ty = nullptr;
+    int2* d_te = nullptr;  // k_exp tiles of split solves
+    int2* d_ts = nullptr;  // k_rs tiles of split solves, per rows setting
+    int rs_rows[4] = {6, 8, 12, 16};
     Readout* d_rq = nullptr;
     double* d_out = nullptr;
     int32_t* d_flags = nullptr;
     std::vector<SolveDesc> descs;
     std::vector<std::vector<double>> tables;
-    std::vector<int2> tr, tv, ty;
-    std::vector<int> cnt_r, cnt_v, cnt_y;  // active task prefix per step
+    std::vector<int2> tr, tv, ty, te, ts[4];
+    std::vector<int> cnt_r, cnt_v, cnt_y, cnt_e, cnt_s[4];  // active task prefix per step
+    size_t ts_off[4] = {0, 0, 0, 0};  // offset of each rows setting in d_ts
+    int nr_split = 0;                 // largest nr among split solves (LDS of k_rs)
     size_t lds_r = 0, lds_v = 0, lds_y = 0;
     int max_steps = 0;
     int64_t max_points = 0;
@@ -808,7 +921,7 @@ struct hjm_batch {
 namespace {
 
 struct BatchLayout {
-    size_t desc, tr, tv, ty, rq, out, flags, total;
+    size_t desc, tr, tv, ty, te, ts, rq, out, flags, total;
     std::vector<SolveOffsets> s;
 };
 
@@ -816,17 +929,21 @@ BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
 {
     Layout L;
     BatchLayout b;
-    size_t nr_t = 0, nv_t = 0, ny_t = 0;
+    size_t nr_t = 0, nv_t = 0, ny_t = 0, ne_t = 0, ns_t = 0;
     for (int s = 0; s < n; ++s) {
         Plan pb = plan_bound(ax[3 * s].n, ax[3 * s + 1].n, ax[3 * s + 2].n);
         nr_t += pb.r_tiles;
         nv_t += pb.v_tiles;
         ny_t += pb.y_tiles;
+        ne_t += pb.exp_tiles;
+        ns_t += pb.rs_tiles;
     }
     b.desc = L.take(sizeof(SolveDesc) * n);
     b.tr = L.take(sizeof(int2) * nr_t);
     b.tv = L.take(sizeof(int2) * nv_t);
     b.ty = L.take(sizeof(int2) * ny_t);
+    b.te = L.take(sizeof(int2) * std::max<size_t>(ne_t, 1));
+    b.ts = L.take(sizeof(int2) * std::max<size_t>(ns_t, 1));
     b.rq = L.take(sizeof(Readout) * n);
     b.out = L.take(sizeof(double) * n);
     b.flags = L.take(sizeof(int32_t) * n);
@@ -842,7 +959,13 @@ hjm_status batch_enqueue(hjm_batch* b)
     if ((e = launch_terminal(b->d_desc, b->n, b->max_points, b->stream))) return hip_fail(e, "batch terminal");
     for (int step = 0; step < b->max_steps; ++step) {
         if ((e = launch_xr(b->rows[0], b->d_desc, b->d_tr, b->cnt_r[step], step, b->lds_r, b->stream)) ||
-            (e = launch_v(b->rows[1], b->d_desc, b->d_tv, b->cnt_v[step], b->lds_v, b->stream)) ||
+            (e = launch_exp(b->d_desc, b->d_te, b->cnt_e[step], step, b->stream)))
+            return hip_fail(e, "batch step");
+        for (int r = 0; r < 4; ++r)
+            if ((e = launch_rs(b->rs_rows[r], b->d_desc, b->d_ts + b->ts_off[r], b->cnt_s[r][step], step,
+                               b->nr_split, b->stream)))
+                return hip_fail(e, "batch step");
+        if ((e = launch_v(b->rows[1], b->d_desc, b->d_tv, b->cnt_v[step], b->lds_v, b->stream)) ||
             (e = launch_yu(b->rows[2], b->d_desc, b->d_ty, b->cnt_y[step], b->lds_y, b->stream)))
             return hip_fail(e, "batch step");
     }
@@ -892,6 +1015,8 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
     b->d_tr = reinterpret_cast<int2*>(b->base + bl.tr);
     b->d_tv = reinterpret_cast<int2*>(b->base + bl.tv);
     b->d_ty = reinterpret_cast<int2*>(b->base + bl.ty);
+    b->d_te = reinterpret_cast<int2*>(b->base + bl.te);
+    b->d_ts = reinterpret_cast<int2*>(b->base + bl.ts);
     b->d_rq = reinterpret_cast<Readout*>(b->base + bl.rq);
     b->d_out = reinterpret_cast<double*>(b->base + bl.out);
     b->d_flags = reinterpret_cast<int32_t*>(b->base + bl.flags);
@@ -913,28 +1038,62 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
         b->max_steps = std::max(b->max_steps, n_steps[s]);
         b->max_points = std::max<int64_t>(b->max_points, (int64_t)a[0].n * a[1].n * a[2].n);
     }
+    auto rs_slot = [&](int rows) {
+        for (int r = 0; r < 4; ++r)
+            if (b->rs_rows[r] == rows) return r;
+        return -1;
+    };
+    std::vector<int> slot(n, -1);
+    for (int s = 0; s < n; ++s) {
+        const SolveDesc& d = b->descs[s];
+        if (d.r_mode == R_SPLIT) {
+            slot[s] = rs_slot(d.nr / d.rs_S);
+            b->nr_split = std::max(b->nr_split, d.nr);
+        }
+    }
     for (int s : order) {
         const SolveDesc& d = b->descs[s];
-        for (int t = 0; t < d.r_tiles; ++t) b->tr.push_back(make_int2(s, t));
+        if (d.r_mode == R_SPLIT) {
+            for (int t = 0; t < d.exp_tiles; ++t) b->te.push_back(make_int2(s, t));
+            for (int t = 0; t < d.rs_tiles; ++t) b->ts[slot[s]].push_back(make_int2(s, t));
+        } else {
+            for (int t = 0; t < d.r_tiles; ++t) b->tr.push_back(make_int2(s, t));
+        }
         for (int t = 0; t < d.v_tiles; ++t) b->tv.push_back(make_int2(s, t));
         for (int t = 0; t < d.y_tiles; ++t) b->ty.push_back(make_int2(s, t));
     }
     b->cnt_r.assign(b->max_steps, 0);
     b->cnt_v.assign(b->max_steps, 0);
     b->cnt_y.assign(b->max_steps, 0);
+    b->cnt_e.assign(b->max_steps, 0);
+    for (int r = 0; r < 4; ++r) b->cnt_s[r].assign(b->max_steps, 0);
     for (int s : order) {
         const SolveDesc& d = b->descs[s];
         for (int step = 0; step < d.n_steps; ++step) {
-            b->cnt_r[step] += d.r_tiles;
+            if (d.r_mode == R_SPLIT) {
+                b->cnt_e[step] += d.exp_tiles;
+                b->cnt_s[slot[s]][step] += d.rs_tiles;
+            } else {
+                b->cnt_r[step] += d.r_tiles;
+            }
             b->cnt_v[step] += d.v_tiles;
             b->cnt_y[step] += d.y_tiles;
         }
+    }
+    std::vector<int2> ts_all;
+    for (int r = 0; r < 4; ++r) {
+        b->ts_off[r] = ts_all.size();
+        ts_all.insert(ts_all.end(), b->ts[r].begin(), b->ts[r].end());
     }
     hipError_t e = init_kernel_attributes();
     if (!e) e = hipMemcpyAsync(b->d_desc, b->descs.data(), sizeof(SolveDesc) * n, hipMemcpyHostToDevice, b->stream);
     if (!e) e = hipMemcpyAsync(b->d_tr, b->tr.data(), sizeof(int2) * b->tr.size(), hipMemcpyHostToDevice, b->stream);
     if (!e) e = hipMemcpyAsync(b->d_tv, b->tv.data(), sizeof(int2) * b->tv.size(), hipMemcpyHostToDevice, b->stream);
     if (!e) e = hipMemcpyAsync(b->d_ty, b->ty.data(), sizeof(int2) * b->ty.size(), hipMemcpyHostToDevice, b->stream);
+    if (!e && !b->te.empty())
+        e = hipMemcpyAsync(b->d_te, b->te.data(), sizeof(int2) * b->te.size(), hipMemcpyHostToDevice, b->stream);
+    if (!e && !ts_all.empty())
+        e = hipMemcpyAsync(b->d_ts, ts_all.data(), sizeof(int2) * ts_all.size(), hipMemcpyHostToDevice, b->stream);
     for (int s = 0; s < n && !e; ++s)
         e = hipMemcpyAsync(const_cast<double*>(b->descs[s].rt), b->tables[s].data(), b->tables[s].size() * 8,
                            hipMemcpyHostToDevice, b->stream);

@@ -12,9 +12,12 @@ constexpr int kBlock = 256;        // threads per workgroup of every sweep kerne
 constexpr int kStepStride = 8;     // doubles per time level in the step table
 constexpr int kRed = 8;            // doubles per segment in the r-sweep reduced system
 
-// How the r lines are solved.
-enum { R_SPIKE = 0,   // segments eliminated in parallel, reduced system per line
-       R_CHAIN = 1 }; // Thomas in row order, segments chained through LDS
+// How the explicit predictor and the r lines are computed.
+enum { R_SPIKE = 0,   // fused k_xr; segments eliminated in parallel, reduced system per line
+       R_CHAIN = 1,   // fused k_xr; Thomas in row order, segments chained through LDS
+       R_SPLIT = 2 }; // k_exp (explicit predictor) then k_rs (spike, one line per S lanes of a wave)
+
+constexpr int kExpCols = 256;  // r-y columns per k_exp workgroup (one thread each)
 
 // Per-solve descriptor, resident in device memory (read-only in kernels).
 struct SolveDesc {
@@ -24,6 +27,11 @@ struct SolveDesc {
     int32_t r_S, r_L, v_S, v_L;
     int32_t y_S, y_L, r_tiles, v_tiles;
     int32_t y_tiles, r_pitch, r_mode, pad0;
+    // split path (R_SPLIT): k_exp tiles = exp_cb column blocks x ceil(nv / exp_J)
+    // v chunks; k_rs handles rs_L lines per workgroup, rs_S = nr / ROWS lanes
+    // (a power of two <= 64) per line
+    int32_t exp_J, exp_cb, exp_tiles, rs_S;
+    int32_t rs_log2S, rs_L, rs_tiles, pad1;
     double dt;          // time step
     double tdt;         // theta * dt, theta = 1/2
     double kappa;
@@ -39,6 +47,8 @@ struct SolveDesc {
     const double* yt;   // y-axis tables, kYT * ny
     const double* vf;   // factors of the v-line matrix, kVF * nv + kVS
     const double* st;   // step table, kStepStride * (n_steps + 1)
+    const double* rf;   // r rows of (I - theta dt A1), theta dt folded in: kRF * nr
+    const double* gd;   // Dirichlet increments g(t_{n+1}) - g(t_n): (2 ny + nr) per step
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value
     int32_t* flag_pad;
 };
@@ -82,6 +92,14 @@ enum { VF_A = 0, VF_INV, VF_C, kVF };
 // scalars after the rows: row 0 (b, c, e), factor eliminating x0 from row 1,
 // row n-1 (a, b, e), factor eliminating x_{n-1} from row n-2
 enum { VS_B0 = 0, VS_C0, VS_E0, VS_F1, VS_AL, VS_BL, VS_EL, VS_F2, kVS };
+// r-row table of the split path.  Interior row i of (I - theta dt A1) on a
+// line with variance v and c = f_t + kappa f + y, with e = FP c + FQ:
+//   (A, B, C) = (FALO v + e,  FADI v + FB,  FAUP v - e)
+enum { RF_P = 0, RF_Q, RF_ALO, RF_ADI, RF_AUP, RF_B, kRF };
+// Dirichlet increments of step n: r_min face (ny values, by k), r_max face
+// (ny), y_max face (nr, by i); zero where the face is not Dirichlet.
+enum { GD_RLO = 0, GD_RHI = 1, GD_YHI = 2 };
+
 // step table entries, per time level n (t_n = T - n dt)
 enum { ST_PHI = 0, ST_AT, ST_GT, ST_HT, ST_AM, ST_GM, ST_HM };
 
@@ -109,6 +127,11 @@ hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_
                     size_t lds_bytes, hipStream_t st);
 hipError_t launch_yu(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks,
                      size_t lds_bytes, hipStream_t st);
+hipError_t launch_exp(const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st);
+hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, int nr_max,
+                     hipStream_t st);
+// rows per thread available to k_rs
+bool rs_rows_supported(int rows);
 hipError_t launch_readout(const SolveDesc* d_desc, const Readout* rq, int n, double* out, hipStream_t st);
 hipError_t launch_health(const SolveDesc* d_desc, int n_solves, int64_t max_points, hipStream_t st);
 

@@ -823,6 +823,298 @@ __global__ __launch_bounds__(kBlock) void k_yu(const SolveDesc* __restrict__ des
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split path: explicit predictor and r sweep as two kernels.
+// ---------------------------------------------------------------------------
+
+// Wave-level barrier for data exchanged through LDS between the lanes of one
+// wavefront (the lanes execute in lockstep; this orders the LDS accesses).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Explicit predictor D0 = dt (A1 + A2 + A3 + A0) U^n (eq. (discreta) with the
+// centred stencils of eq. (esquema), one-sided rows on outflow faces), and the
+// Dirichlet increment on Dirichlet nodes.  Thread = one (i, k) column; it walks
+// exp_J consecutive v nodes j keeping the v window u(i, j-2..j+2) and the
+// neighbouring columns u(i -+ 1, j-1..j+1) in registers, so every node costs
+// five loads: u(i, j+2), u(i -+ 1, j+1) and the two y neighbours.  Lanes are
+// consecutive i: every load of a wave is one contiguous row segment.
+__global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
+                                                int step)
+{
+    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const SolveDesc& s = descs[tk.x];
+    if (step >= s.n_steps) return;
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int cb = tk.y % s.exp_cb;
+    const int jc = tk.y / s.exp_cb;
+    const int p = cb * kExpCols + (int)threadIdx.x;
+    if (p >= nr * ny) return;  // no barriers below
+    const int k = p / nr;
+    const int i = p - k * nr;
+    const int j0 = jc * s.exp_J;
+    const int j1 = min(j0 + s.exp_J, nv);
+    gcdouble* U = gp(s.U);
+    gdouble* D = gp(s.D);
+    gcdouble* rt = gp(s.rt);
+    gcdouble* vt = gp(s.vt);
+    gcdouble* yt = gp(s.yt);
+    gcdouble* stn = gp(s.st) + kStepStride * step;
+
+    // per-column constants: A1 row pieces (affine in v), A3 coefficient, A0 factor
+    const double c = stn[ST_PHI] + yt[YT_Y * ny + k];
+    const double e = rt[RT_P * nr + i] * c + rt[RT_Q * nr + i];
+    const double mlo = rt[RT_MLO * nr + i] * e, alo = rt[RT_ALO * nr + i];
+    const double mdi = rt[RT_MDI * nr + i] * e - rt[RT_RR * nr + i], adi = rt[RT_ADI * nr + i];
+    const double mup = rt[RT_MUP * nr + i] * e, aup = rt[RT_AUP * nr + i];
+    const double mex = rt[RT_MEX * nr + i] * e;
+    const double ryk = rt[RT_Y * nr + i] * yt[YT_I * ny + k];
+    const double kyk = yt[YT_K * ny + k];
+    const double rx = rt[RT_X * nr + i];
+    // y stencil: two neighbours (offsets oa, ob) and the node itself
+    const bool yhd = s.y_hi_dir && k == ny - 1;
+    int oa = -1, ob = 1;
+    double wa = yt[YT_W1 * ny + k], wb = yt[YT_W3 * ny + k];
+    if (k == 0) { oa = 1; ob = 2; wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
+    else if (k == ny - 1) { oa = -2; ob = -1; wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
+    if (yhd) { oa = 0; ob = 0; }
+    const double w2 = yt[YT_W2 * ny + k];
+    // outflow r face rows reach two nodes in: the extra entry
+    const int dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
+    const bool ex = mex != 0.0;
+    // Dirichlet nodes: the increment does not depend on j
+    gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
+    const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
+    const bool dir = rlo || rhi || yhd;
+    const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
+    const int im = max(i - 1, 0), ip = min(i + 1, nr - 1);
+    const size_t sl = (size_t)nr;                  // stride of j
+    const size_t sy = (size_t)nr * nv;             // stride of k
+    gcdouble* col = U + (size_t)k * sy;            // (k, j = 0, i = 0)
+    auto at = [&](int jj, int ii) -> double {
+        jj = min(max(jj, 0), nv - 1);
+        return col[(size_t)jj * sl + ii];
+    };
+    double c0 = at(j0 - 2, i), c1 = at(j0 - 1, i), c2 = at(j0, i), c3 = at(j0 + 1, i);
+    double l0 = at(j0 - 1, im), l1 = at(j0, im), r0 = at(j0 - 1, ip), r1 = at(j0, ip);
+    // loads of node j, one node ahead of the arithmetic
+    double n4 = at(j0 + 2, i), nl = at(j0 + 1, im), nrr = at(j0 + 1, ip);
+    gcdouble* cola = col + (ptrdiff_t)oa * (ptrdiff_t)sy;  // plane k + oa
+    gcdouble* colb = col + (ptrdiff_t)ob * (ptrdiff_t)sy;
+    const size_t ix = (size_t)(i + dx);
+    double na = cola[(size_t)j0 * sl + i];
+    double nb = colb[(size_t)j0 * sl + i];
+    double nx = ex ? col[(size_t)j0 * sl + ix] : 0.0;
+    gdouble* dcol = D + (size_t)k * sy + i;
+    const double dt = s.dt;
+    for (int j = j0; j < j1; ++j) {
+        const double c4 = n4, l2 = nl, r2 = nrr, ya = na, yb = nb, ux = nx;
+        if (j + 1 < j1) {
+            const int jn = j + 1;
+            n4 = at(jn + 2, i);
+            nl = at(jn + 1, im);
+            nrr = at(jn + 1, ip);
+            na = cola[(size_t)jn * sl + i];
+            nb = colb[(size_t)jn * sl + i];
+            nx = ex ? col[(size_t)jn * sl + ix] : 0.0;
+        }
+        const double v = vt[VT_V * nv + j];
+        const double olo = mlo + alo * v, odi = mdi + adi * v, oup = mup + aup * v;
+        const double a1 = olo * l1 + odi * c2 + oup * r1 + mex * ux;
+        const double a2 = vt[VT_O0 * nv + j] * c0 + vt[VT_O1 * nv + j] * c1 + vt[VT_O2 * nv + j] * c2 +
+                          vt[VT_O3 * nv + j] * c3 + vt[VT_O4 * nv + j] * c4;
+        const double by = ryk * v - kyk;
+        const double a3 = by * (wa * ya + w2 * c2 + wb * yb);
+        const double cross = (r2 - r0) - (l2 - l0);
+        const double a0 = rx * vt[VT_X * nv + j] * cross;
+        const double val = dt * (((a1 + a2) + a3) + a0);
+        dcol[(size_t)j * sl] = dir ? gval : val;
+        c0 = c1; c1 = c2; c2 = c3; c3 = c4;
+        l0 = l1; l1 = l2;
+        r0 = r1; r1 = r2;
+    }
+}
+
+// r sweep (I - theta dt A1) D1 = D0 by the spike (partition) method, for
+// lines of nr = S * ROWS rows with S a power of two <= 64: the S segments of
+// a line sit in S consecutive lanes of one wavefront, so the reduced system
+// is exchanged through LDS with wave-level synchronisation only.  Each lane
+// eliminates its ROWS rows (spikes v toward the previous segment, w toward
+// the next), lane 0 of the line solves the reduced system of the segments'
+// end unknowns, and every lane back-substitutes.  The outflow face rows (one
+// entry beyond the band) are folded into rows 1 and n-2 first and recovered
+// last.  Accurate when the rows are diagonally dominant; the host selects this
+// path only then.
+template <int ROWS>
+__global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
+                                               int step)
+{
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
+    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const SolveDesc& s = descs[tk.x];
+    if (step >= s.n_steps) return;  // whole workgroup: uniform
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int S = s.rs_S;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int seg = lane & (S - 1);
+    const int nlines = nv * ny;
+    const int q_raw = tk.y * s.rs_L + (t >> 6) * (64 >> s.rs_log2S) + (lane >> s.rs_log2S);
+    const bool active = q_raw < nlines;
+    const int q = active ? q_raw : nlines - 1;  // tail lanes repeat the last line, store nothing
+    const int k = q / nv;
+    const int j = q - k * nv;
+    const bool store = active && !(s.y_hi_dir && k == ny - 1);
+    ldouble* tab = lds;                          // [kRF][ROWS][S]
+    ldouble* red = lds + (size_t)kRF * nr;       // 8 doubles per thread
+    gcdouble* rf = gp(s.rf);
+    for (int idx = t; idx < kRF * nr; idx += kBlock) {
+        const int c6 = idx / nr;
+        const int i = idx - c6 * nr;
+        const int sg = i / ROWS;
+        const int mm = i - sg * ROWS;
+        tab[(c6 * ROWS + mm) * S + sg] = rf[idx];
+    }
+    __syncthreads();
+
+    const double v = gp(s.vt)[VT_V * nv + j];
+    const double c = gp(s.st)[kStepStride * step + ST_PHI] + gp(s.yt)[YT_Y * ny + k];
+    gdouble* line = gp(s.D) + (size_t)q * nr + (size_t)seg * ROWS;
+    double d[ROWS];
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) d[mm] = line[mm];
+    auto coef = [&](int mm, double& A, double& B, double& C) {
+        const ldouble* tb = tab + mm * S + seg;
+        const double e = tb[RF_P * ROWS * S] * c + tb[RF_Q * ROWS * S];
+        A = tb[RF_ALO * ROWS * S] * v + e;
+        B = tb[RF_ADI * ROWS * S] * v + tb[RF_B * ROWS * S];
+        C = tb[RF_AUP * ROWS * S] * v - e;
+    };
+    const bool first = seg == 0;
+    const bool last = seg == S - 1;
+    bool ok = true;
+    // face rows: fold row 0 into row 1 and row n-1 into row n-2
+    double fb0 = 1.0, fc0 = 0.0, fe0 = 0.0, fd0 = 0.0, b1 = 0.0, c1 = 0.0, d1 = 0.0;
+    double fal = 0.0, fbl = 1.0, fel = 0.0, fdl = 0.0, a2 = 0.0, b2 = 0.0, d2 = 0.0;
+    if (first) {
+        RowRFull full{gp(s.rt), nr, v, c, s.tdt};
+        double A0, B0, C0, E0, A1, B1, C1;
+        full(0, A0, B0, C0, E0);
+        coef(1, A1, B1, C1);
+        const double f = A1 / B0;
+        fb0 = B0; fc0 = C0; fe0 = E0; fd0 = d[0];
+        b1 = B1 - f * C0;
+        c1 = C1 - f * E0;
+        d1 = d[1] - f * d[0];
+        ok = ok && B0 > 0.0;
+    }
+    if (last) {
+        RowRFull full{gp(s.rt), nr, v, c, s.tdt};
+        double Al, Bl, Cl, El, A2, B2, C2;
+        full(nr - 1, Al, Bl, Cl, El);
+        coef(ROWS - 2, A2, B2, C2);
+        const double f = C2 / Bl;
+        fal = Al; fbl = Bl; fel = El; fdl = d[ROWS - 1];
+        a2 = A2 - f * El;
+        b2 = B2 - f * Al;
+        d2 = d[ROWS - 2] - f * d[ROWS - 1];
+        ok = ok && Bl > 0.0;
+    }
+    if (first) { d[0] = 0.0; d[1] = d1; }
+    if (last) { d[ROWS - 1] = 0.0; d[ROWS - 2] = d2; }
+
+    // local elimination: y' (in d), v' (coupling to the previous segment), c'
+    double vp[ROWS], cp[ROWS];
+    double cprev = 0.0, yprev = 0.0, vprev = -1.0;
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) {
+        double A, B, C;
+        coef(mm, A, B, C);
+        if (mm == 0) { A = first ? 0.0 : A; B = first ? 1.0 : B; C = first ? 0.0 : C; }
+        if (mm == 1) { A = first ? 0.0 : A; B = first ? b1 : B; C = first ? c1 : C; }
+        if (mm == ROWS - 2) { A = last ? a2 : A; B = last ? b2 : B; C = last ? 0.0 : C; }
+        if (mm == ROWS - 1) { A = last ? 0.0 : A; B = last ? 1.0 : B; C = last ? 0.0 : C; }
+        const double den = B - A * cprev;
+        const double inv = 1.0 / den;
+        ok = ok && den > 0.0;
+        cprev = C * inv;
+        yprev = (d[mm] - A * yprev) * inv;
+        vprev = -A * vprev * inv;
+        cp[mm] = cprev;
+        d[mm] = yprev;
+        vp[mm] = vprev;
+    }
+    double XL = 0.0, XR = 0.0;
+    if (S > 1) {
+        // first-row values of the three local solutions
+        double y = d[ROWS - 1], vv = vp[ROWS - 1], w = cp[ROWS - 1];
+#pragma unroll
+        for (int mm = ROWS - 2; mm >= 0; --mm) {
+            y = d[mm] - cp[mm] * y;
+            vv = vp[mm] - cp[mm] * vv;
+            w = -cp[mm] * w;
+        }
+        ldouble* my = red + t * 8;
+        my[0] = y; my[1] = vv; my[2] = w;
+        my[3] = d[ROWS - 1]; my[4] = vp[ROWS - 1]; my[5] = cp[ROWS - 1];
+        wave_sync();
+        if (first) {
+            // F_s = yF - vF L_{s-1} - wF F_{s+1};  L_s = yL - vL L_{s-1} - wL F_{s+1}
+            // forward: L_s = alp + bet F_{s+1}, F_s = gam + del F_{s+1}
+            ldouble* r0 = red + t * 8;  // this lane is the line's segment 0
+            double alp = 0.0, bet = 0.0;
+            for (int qq = 0; qq < S; ++qq) {
+                ldouble* r = r0 + qq * 8;
+                const double yF = r[0], vF = r[1], wF = r[2], yL = r[3], vL = r[4], wL = r[5];
+                const double den = 1.0 + vF * bet;
+                ok = ok && den > 0.0;
+                const double inv = 1.0 / den;
+                const double gam = (yF - vF * alp) * inv;
+                const double del = -wF * inv;
+                alp = yL - vL * alp - vL * bet * gam;
+                bet = -vL * bet * del - wL;
+                r[0] = gam; r[1] = del; r[2] = alp; r[3] = bet;
+            }
+            double Fn = 0.0, Lp = 0.0;
+            for (int qq = S - 1; qq >= 0; --qq) {
+                ldouble* r = r0 + qq * 8;
+                const double F = r[0] + r[1] * Fn;
+                r[5] = r[2] + r[3] * Fn;  // L_q
+                r[6] = Fn;                // X_R of segment q
+                Fn = F;
+            }
+            for (int qq = 0; qq < S; ++qq) {
+                ldouble* r = r0 + qq * 8;
+                r[7] = Lp;                // X_L of segment q
+                Lp = r[5];
+            }
+        }
+        wave_sync();
+        XL = red[t * 8 + 7];
+        XR = red[t * 8 + 6];
+    }
+    // back substitution with the coupling values
+    double x = d[ROWS - 1] - XL * vp[ROWS - 1] - XR * cp[ROWS - 1];
+    d[ROWS - 1] = x;
+#pragma unroll
+    for (int mm = ROWS - 2; mm >= 0; --mm) {
+        x = (d[mm] - XL * vp[mm]) - cp[mm] * x;
+        d[mm] = x;
+    }
+    if (first) d[0] = (fd0 - fc0 * d[1] - fe0 * d[2]) / fb0;
+    if (last) d[ROWS - 1] = (fdl - fel * d[ROWS - 3] - fal * d[ROWS - 2]) / fbl;
+    if (store) {
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) line[mm] = d[mm];
+    }
+    if (store && !ok) raise_flag(s);
+}
+
 __global__ void k_readout(const SolveDesc* __restrict__ descs, const Readout* __restrict__ rq, int n,
                           double* __restrict__ out)
 {
@@ -864,7 +1156,9 @@ hipError_t init_kernel_attributes()
         hipError_t e;
         if ((e = allow_lds(k_xr<8>)) || (e = allow_lds(k_xr<16>)) || (e = allow_lds(k_xr<32>)) ||
             (e = allow_lds(k_v<8>)) || (e = allow_lds(k_v<16>)) || (e = allow_lds(k_v<32>)) ||
-            (e = allow_lds(k_yu<8>)) || (e = allow_lds(k_yu<16>)) || (e = allow_lds(k_yu<32>)))
+            (e = allow_lds(k_yu<8>)) || (e = allow_lds(k_yu<16>)) || (e = allow_lds(k_yu<32>)) ||
+            (e = allow_lds(k_rs<6>)) || (e = allow_lds(k_rs<8>)) || (e = allow_lds(k_rs<12>)) ||
+            (e = allow_lds(k_rs<16>)))
             return e;
         return hipSuccess;
     }();
@@ -916,6 +1210,30 @@ hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_
 {
     if (n_tasks <= 0) return hipSuccess;
     HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_v<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
+    return hipGetLastError();
+}
+
+hipError_t launch_exp(const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exp, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step);
+    return hipGetLastError();
+}
+
+bool rs_rows_supported(int rows) { return rows == 6 || rows == 8 || rows == 12 || rows == 16; }
+
+hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, int nr_max,
+                     hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    const size_t lds = (size_t)kRF * nr_max * 8 + (size_t)kBlock * 8 * 8;
+    switch (rows) {
+    case 6: hipLaunchKernelGGL(k_rs<6>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 8: hipLaunchKernelGGL(k_rs<8>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 12: hipLaunchKernelGGL(k_rs<12>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 16: hipLaunchKernelGGL(k_rs<16>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

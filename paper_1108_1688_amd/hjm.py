@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libhjm.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5
 FACE_OUTFLOW, FACE_DIRICHLET = 0, 1
 BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
+N_PASSES = 4  # HJM_N_PASSES
+PASSES = ("explicit", "r", "v", "y+update")
+R_METHODS = ("spike", "chain", "split")
 
 
 class HjmError(RuntimeError):
@@ -65,6 +68,7 @@ def lib():
         "hjm_grid_solution": (st, [vp, P(vp), P(i64)]),
         "hjm_grid_set_step": (st, [vp, i64]),
         "hjm_grid_destroy": (st, [vp]),
+        "hjm_grid_plan": (st, [vp, P(i32)]),
         "hjm_grid_profile": (st, [vp, i32]),
         "hjm_grid_profile_read": (st, [vp, P(d), P(i64)]),
         "hjm_batch_workspace_bytes": (st, [i32, P(Axis), P(i32), P(sz)]),
@@ -200,15 +204,24 @@ class Grid:
     def set_step(self, step: int) -> None:
         check(lib().hjm_grid_set_step(self._h, int(step)))
 
+    def plan(self) -> dict:
+        """How this grid is solved: r method ('spike', 'chain' or 'split'),
+        rows per lane of the split r solve, line-tile rows."""
+        out = (C.c_int32 * 8)()
+        check(lib().hjm_grid_plan(self._h, out))
+        return {"r_method": R_METHODS[out[0]], "rs_rows": out[1], "line_tile": (out[2], out[3], out[4])}
+
     def profile(self, enable: bool = True) -> None:
         """Bracket every pass launch with HIP events on the grid's stream."""
         check(lib().hjm_grid_profile(self._h, 1 if enable else 0))
 
     def profile_read(self):
         """(ms per pass, launches per pass) since the last read; passes are
-        explicit+r, v, y+update.  Synchronises the stream."""
-        ms = (C.c_double * 3)()
-        n = (C.c_int64 * 3)()
+        PASSES (explicit, r, v, y+update; on grids that solve the r lines in the
+        explicit kernel, pass 0 is both and pass 1 has no launches).
+        Synchronises the stream."""
+        ms = (C.c_double * N_PASSES)()
+        n = (C.c_int64 * N_PASSES)()
         check(lib().hjm_grid_profile_read(self._h, ms, n))
         return list(ms), list(n)
 

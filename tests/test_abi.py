@@ -113,7 +113,15 @@ def test_null_handles(L):
     assert L.hjm_adi_step(None, 1) == hjm.EINVAL
     assert L.hjm_price(None, 0.03, 1.0, C.byref(C.c_double())) == hjm.EINVAL
     assert L.hjm_batch_run(None, 0) == hjm.EINVAL
+    assert L.hjm_grid_plan(None, (C.c_int32 * 8)()) == hjm.EINVAL
+    assert L.hjm_grid_profile_read(None, (C.c_double * hjm.N_PASSES)(), (C.c_int64 * hjm.N_PASSES)()) == hjm.EINVAL
     assert L.hjm_grid_destroy(None) == hjm.OK
+
+
+def test_pass_count_matches_header():
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "hjm.h")).read()
+    assert int(re.search(r"#define HJM_N_PASSES (\d+)", hdr).group(1)) == hjm.N_PASSES == len(hjm.PASSES)
 
 
 def test_line_tile_setting(L):

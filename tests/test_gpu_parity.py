@@ -37,9 +37,15 @@ def _need_gpu():
     hjm.set_line_tile(*old)
 
 
+PLANS = []  # r method of every grid of the last gpu_grid call
+
+
 def gpu_grid(spec, steps=None, price=True):
     print(f"[gpu] shape={spec.shape} steps={steps} kind={spec.payoff.kind} tile={hjm.get_line_tile()}", flush=True)
     g = hjm.Grid(spec)
+    plan = g.plan()
+    print(f"[gpu] plan {plan}", flush=True)
+    PLANS[:] = [plan["r_method"]]
     g.step(steps)
     p = g.price() if (price and g.steps_taken == spec.n_steps) else None
     U = g.solution().cpu().numpy().copy()
@@ -162,8 +168,27 @@ def test_config3_full_size_first_steps_elementwise():
     configuration): three Douglas steps compared on every node."""
     s = W.config3()[-1]
     Ug, _ = gpu_grid(s, steps=3, price=False)
+    assert PLANS == ["split"]
     Uo, _ = oracle_grid(s, steps=3)
     assert_grid(Ug, Uo)
+
+
+@pytest.mark.parametrize("method", ["chain", "spike", "split"])
+def test_each_r_method(method):
+    """Each r-line method on a case that selects it: one long step (rows with
+    (|A|+|C|)/B far above the spike bound) -> chain; nr = 100 (no power-of-two
+    lane split) -> spike inside the fused kernel; nr = 96 -> split."""
+    if method == "chain":
+        s = _sloped((40, 24, 24), 1)
+    elif method == "spike":
+        s = _sloped((100, 24, 24), 12)
+    else:
+        s = _sloped((96, 24, 24), 12)
+    Ug, pg = gpu_grid(s)
+    assert PLANS == [method]
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
 
 
 def test_config3_one_year_caplet_full_solve():
