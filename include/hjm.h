@@ -92,9 +92,11 @@ typedef struct hjm_grid hjm_grid;
 typedef struct hjm_batch hjm_batch;
 
 /* Bytes of device workspace hjm_grid_create needs for these axes and step
-   count: the grid U and the Douglas increment D (nr*nv*ny doubles each) plus
-   1D tables (axis coefficients, per-step curve and bond-factor scalars,
-   readout weights and a health flag).  Host only. */
+   count: the grid U, the Douglas increment D and the pivots of the y-line
+   matrices (which do not change from step to step), nr*nv*ny doubles each,
+   plus 1D tables (axis coefficients, per-step curve and bond-factor scalars,
+   per-step Dirichlet increments on the r and y_max faces, (2 ny + nr) doubles
+   per step, readout weights and a health flag).  Host only. */
 hjm_status hjm_workspace_bytes(const hjm_axis ax[3], int32_t n_steps, size_t* bytes);
 
 /* Validate the problem, lay out the caller's workspace (d_workspace, at least
@@ -134,7 +136,9 @@ hjm_status hjm_grid_destroy(hjm_grid* g);
    predictor; 2 split: separate explicit kernel, then a spike solve with the
    segments of a line in consecutive lanes of one wavefront), plan[1] = rows
    per lane of the split r solve (0 if not split), plan[2..4] = the line-tile
-   rows per thread of the r, v and y solves, plan[5..7] = 0 (reserved).  The
+   rows per thread of the r, v and y solves, plan[5] = rows per segment of the
+   segmented v solve (0: the chained v solve), plan[6] = rows per segment of
+   the y solve on stored pivots (0: the per-step elimination), plan[7] = 0.  The
    spike variants are chosen only where the r rows keep (|A| + |C|) / B
    bounded (section 5, tridiagonal systems), so every variant matches the
    sequential elimination to rounding. */

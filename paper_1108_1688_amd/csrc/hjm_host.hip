@@ -17,7 +17,7 @@ using namespace hjm;
 namespace {
 
 thread_local std::string g_last_error;
-int g_rows[3] = {8, 16, 16};  // rows per thread of the r, v, y line solves
+int g_rows[3] = {16, 16, 8};  // rows per thread of the r, v, y line solves
 
 hjm_status fail(hjm_status code, const char* fmt, ...)
 {
@@ -180,7 +180,29 @@ struct Plan {
     size_t r_lds, v_lds, y_lds;
     int rs_rows, rs_S, rs_log2S, rs_L, rs_tiles;
     int exp_J, exp_cb, exp_tiles;
+    int vs_rows, vs_S, vs_tiles;        // segmented v solve (0: chained k_v)
+    int yc_rows, yc_S, yc_L, yc_tiles;  // y solve on stored pivots (0: k_yu)
 };
+
+// Segmented v solve: nv = S * ROWS with S <= 4 waves; preferred rows first.
+// The host also requires the segment products to stay <= 1 in magnitude
+// (decided in build_tables, where the factors are known).
+int vs_rows_for(int nv, int preferred)
+{
+    const int cands[4] = {preferred, 32, 16, 8};
+    for (int r : cands)
+        if (vs_rows_supported(r) && nv % r == 0 && nv / r >= 1 && nv / r <= 4) return r;
+    return 0;
+}
+
+// y solve on stored pivots: ny = S * ROWS with at least 8 lines per workgroup.
+int yc_rows_for(int ny, int preferred)
+{
+    const int cands[4] = {preferred, 16, 32, 8};
+    for (int r : cands)
+        if (yc_rows_supported(r) && ny % r == 0 && ny / r <= kBlock / 8) return r;
+    return 0;
+}
 
 constexpr int kExpJ = 16;  // v nodes per k_exp thread
 
@@ -239,6 +261,13 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     p.exp_J = std::min(kExpJ, nv);
     p.exp_cb = (nr * ny + kExpCols - 1) / kExpCols;
     p.exp_tiles = p.exp_cb * ((nv + p.exp_J - 1) / p.exp_J);
+    p.vs_rows = vs_rows_for(nv, rows[1]);
+    p.vs_S = p.vs_rows ? nv / p.vs_rows : 0;
+    p.vs_tiles = p.vs_rows ? (nr * ny + 63) / 64 : 0;
+    p.yc_rows = yc_rows_for(ny, rows[2]);
+    p.yc_S = p.yc_rows ? ny / p.yc_rows : 0;
+    p.yc_L = p.yc_rows ? kBlock / p.yc_S : 0;
+    p.yc_tiles = p.yc_rows ? (nr * nv + p.yc_L - 1) / p.yc_L : 0;
     if (p.rs_rows) {
         p.r_mode = R_SPLIT;
         p.rs_S = nr / p.rs_rows;
@@ -313,6 +342,8 @@ Plan plan_bound(int nr, int nv, int ny)
             b.y_tiles = std::max(b.y_tiles, p.y_tiles);
             b.rs_tiles = std::max(b.rs_tiles, p.rs_tiles);
             b.exp_tiles = std::max(b.exp_tiles, p.exp_tiles);
+            b.vs_tiles = std::max(b.vs_tiles, p.vs_tiles);
+            b.yc_tiles = std::max(b.yc_tiles, p.yc_tiles);
         }
     return b;
 }
@@ -334,11 +365,11 @@ size_t table_doubles(const hjm_axis ax[3], int n_steps)
 {
     return (size_t)kRT * ax[0].n + (size_t)kVT * ax[1].n + (size_t)kYT * ax[2].n + (size_t)kVF * ax[1].n + kVS +
            (size_t)kStepStride * (n_steps + 1) + (size_t)kRF * ax[0].n +
-           (size_t)(2 * ax[2].n + ax[0].n) * n_steps;
+           (size_t)(2 * ax[2].n + ax[0].n) * n_steps + (size_t)kVG * ax[1].n;
 }
 
 struct SolveOffsets {
-    size_t U, D, tables;
+    size_t U, D, CP, tables;
 };
 
 SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
@@ -347,6 +378,7 @@ SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
     SolveOffsets o;
     o.U = L.take(pts * 8);
     o.D = L.take(pts * 8);
+    o.CP = L.take(pts * 8);
     o.tables = L.take(table_doubles(ax, n_steps) * 8);
     return o;
 }
@@ -365,7 +397,7 @@ double dirichlet_host(const double* e, int kind, double accrual, double r, doubl
 }
 
 // Fill the host tables of one solve: axis coefficient rows, step table.
-void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps,
+void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps, Plan& plan,
                   std::vector<double>& out)
 {
     const int nr = ax[0].n, nv = ax[1].n, ny = ax[2].n;
@@ -377,6 +409,7 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
     double* st = vf + (size_t)kVF * nv + kVS;
     double* rf = st + (size_t)kStepStride * (n_steps + 1);
     double* gd = rf + (size_t)kRF * nr;
+    double* vg = gd + (size_t)(2 * ny + nr) * n_steps;
     const Mesh mr = make_mesh(ax[0]), mv = make_mesh(ax[1]), my = make_mesh(ax[2]);
     const double lam = m.lambda, eps = m.epsilon;
     const double dt = p.expiry / n_steps, tdt = kTheta * dt;
@@ -505,6 +538,34 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
             vf[VF_INV * nv + j] = 1.0 / den;
             vf[VF_C * nv + j] = cprev;
         }
+        // segmented form: rows 0 and n-1 pass through (recovered from their
+        // own rows); per segment the products G (forward) and H (backward)
+        for (int j = 0; j < nv; ++j) {
+            const bool mid = j >= 1 && j <= nv - 2;
+            vg[VG_INV * nv + j] = mid ? vf[VF_INV * nv + j] : 1.0;
+            vg[VG_AL * nv + j] = mid ? -vf[VF_A * nv + j] * vf[VF_INV * nv + j] : 0.0;
+            vg[VG_CP * nv + j] = mid ? vf[VF_C * nv + j] : 0.0;
+        }
+        const int R = plan.vs_rows;
+        double worst = 0.0;
+        for (int s0 = 0; R > 0 && s0 < nv; s0 += R) {
+            double g = 1.0, h = 1.0;
+            for (int j = s0; j < s0 + R; ++j) {
+                g *= vg[VG_AL * nv + j];
+                vg[VG_G * nv + j] = g;
+                worst = std::max(worst, std::fabs(g));
+            }
+            for (int j = s0 + R - 1; j >= s0; --j) {
+                h *= -vg[VG_CP * nv + j];
+                vg[VG_H * nv + j] = h;
+                worst = std::max(worst, std::fabs(h));
+            }
+        }
+        // the segment corrections add G d'_in and H x_in: keep them from
+        // amplifying (they are products of |AL|, |CP| < 1 on dominant rows)
+        if (R > 0 && !(worst <= 1.0)) {
+            plan.vs_rows = plan.vs_S = plan.vs_tiles = 0;
+        }
     }
     const Curve cv{m.f_level, m.f_slope, m.f_decay};
     const double T = p.expiry, TM = p.kind == HJM_BOND ? p.expiry : p.pay;
@@ -578,6 +639,10 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.r_mode = pl.r_mode;
     d.exp_J = pl.exp_J; d.exp_cb = pl.exp_cb; d.exp_tiles = pl.exp_tiles;
     d.rs_S = pl.rs_S; d.rs_log2S = pl.rs_log2S; d.rs_L = pl.rs_L; d.rs_tiles = pl.rs_tiles;
+    d.vg = d.gd + (size_t)(2 * ax[2].n + ax[0].n) * n_steps;
+    d.cp = reinterpret_cast<double*>(base + o.CP);
+    d.vs_S = pl.vs_S; d.vs_tiles = pl.vs_tiles;
+    d.yc_S = pl.yc_S; d.yc_L = pl.yc_L; d.yc_tiles = pl.yc_tiles;
 }
 
 // 4-point Lagrange stencil in mesh coordinates (window centred on the
@@ -742,14 +807,15 @@ hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const h
     g->d_rq = reinterpret_cast<Readout*>(g->base + gl.rq);
     g->d_out = reinterpret_cast<double*>(g->base + gl.out);
     g->d_flag = reinterpret_cast<int32_t*>(g->base + gl.flag);
+    build_tables(ax, *model, *payoff, n_steps, g->plan, g->tables);
     fill_desc(g->desc, ax, *model, *payoff, n_steps, g->plan, g->base, gl.s, g->d_flag);
-    build_tables(ax, *model, *payoff, n_steps, g->tables);
     hipError_t e;
     if ((e = init_kernel_attributes()) ||
         (e = hipMemcpyAsync(g->d_desc, &g->desc, sizeof(SolveDesc), hipMemcpyHostToDevice, g->stream)) ||
         (e = hipMemcpyAsync(const_cast<double*>(g->desc.rt), g->tables.data(), g->tables.size() * 8,
                             hipMemcpyHostToDevice, g->stream)) ||
         (e = launch_terminal(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n * ax[2].n, g->stream)) ||
+        (e = launch_ypiv(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n, g->stream)) ||
         (e = hipStreamSynchronize(g->stream))) {
         delete g;
         return hip_fail(e, "hjm_grid_create");
@@ -790,7 +856,9 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
             if (pass == 0 && split) e = launch_exp(g->d_desc, nullptr, p.exp_tiles, n, g->stream);
             else if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
             else if (pass == 1) e = launch_rs(p.rs_rows, g->d_desc, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
+            else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, g->d_desc, nullptr, p.vs_tiles, p.vs_S, g->stream);
             else if (pass == 2) e = launch_v(g->rows[1], g->d_desc, nullptr, p.v_tiles, p.v_lds, g->stream);
+            else if (p.yc_rows) e = launch_yc(p.yc_rows, g->d_desc, nullptr, p.yc_tiles, g->stream);
             else e = launch_yu(g->rows[2], g->d_desc, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {
@@ -854,6 +922,8 @@ hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[8])
     plan[2] = g->rows[0];
     plan[3] = g->rows[1];
     plan[4] = g->rows[2];
+    plan[5] = g->plan.vs_rows;
+    plan[6] = g->plan.yc_rows;
     return HJM_OK;
 }
 
@@ -886,6 +956,21 @@ hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[HJM_N_PASSES], int64_t l
 // ---------------------------------------------------------------------------
 // Batched solves.
 // ---------------------------------------------------------------------------
+// A batch launches each kernel of a Douglas step once for all the solves
+// that use it.  Launch groups: one per (kernel, rows per thread); a group
+// holds the (solve, tile) tasks of its solves, ordered by step count (longest
+// first) so that the solves still running at step n are a prefix.
+enum { G_XR = 0, G_EXP, G_RS, G_V, G_VS, G_YU, G_YC, kGroupKinds };
+
+struct LaunchGroup {
+    int kind = 0, rows = 0;
+    size_t off = 0;           // first task in the batch's task array
+    std::vector<int2> tasks;
+    std::vector<int> cnt;     // active task prefix per step
+    size_t lds = 0;           // dynamic LDS (k_xr, k_v, k_yu)
+    int aux = 0;              // k_rs: largest nr; k_vs: most segments
+};
+
 struct hjm_batch {
     int n = 0;
     std::vector<hjm_axis> ax;  // 3 per solve
@@ -894,24 +979,15 @@ struct hjm_batch {
     hipStream_t stream = nullptr;
     char* base = nullptr;
     SolveDesc* d_desc = nullptr;
-    int2* d_tr = nullptr;
-    int2* d_tv = nullptr;
-    int2* d_ty = nullptr;
-    int2* d_te = nullptr;  // k_exp tiles of split solves
-    int2* d_ts = nullptr;  // k_rs tiles of split solves, per rows setting
-    int rs_rows[4] = {6, 8, 12, 16};
+    int2* d_tasks = nullptr;
     Readout* d_rq = nullptr;
     double* d_out = nullptr;
     int32_t* d_flags = nullptr;
     std::vector<SolveDesc> descs;
     std::vector<std::vector<double>> tables;
-    std::vector<int2> tr, tv, ty, te, ts[4];
-    std::vector<int> cnt_r, cnt_v, cnt_y, cnt_e, cnt_s[4];  // active task prefix per step
-    size_t ts_off[4] = {0, 0, 0, 0};  // offset of each rows setting in d_ts
-    int nr_split = 0;                 // largest nr among split solves (LDS of k_rs)
-    size_t lds_r = 0, lds_v = 0, lds_y = 0;
+    std::vector<LaunchGroup> groups;
     int max_steps = 0;
-    int64_t max_points = 0;
+    int64_t max_points = 0, max_ylines = 0;
     hipGraphExec_t graph = nullptr;
     bool ran = false;
     std::vector<Readout> rq;
@@ -921,29 +997,26 @@ struct hjm_batch {
 namespace {
 
 struct BatchLayout {
-    size_t desc, tr, tv, ty, te, ts, rq, out, flags, total;
+    size_t desc, tasks, rq, out, flags, total;
     std::vector<SolveOffsets> s;
 };
+
+// Upper bound of the tasks of one solve over every plan it could get.
+size_t task_bound(const hjm_axis* a)
+{
+    const Plan pb = plan_bound(a[0].n, a[1].n, a[2].n);
+    return (size_t)std::max(pb.r_tiles, pb.exp_tiles) + pb.rs_tiles + std::max(pb.v_tiles, pb.vs_tiles) +
+           std::max(pb.y_tiles, pb.yc_tiles) + (size_t)pb.exp_tiles;
+}
 
 BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
 {
     Layout L;
     BatchLayout b;
-    size_t nr_t = 0, nv_t = 0, ny_t = 0, ne_t = 0, ns_t = 0;
-    for (int s = 0; s < n; ++s) {
-        Plan pb = plan_bound(ax[3 * s].n, ax[3 * s + 1].n, ax[3 * s + 2].n);
-        nr_t += pb.r_tiles;
-        nv_t += pb.v_tiles;
-        ny_t += pb.y_tiles;
-        ne_t += pb.exp_tiles;
-        ns_t += pb.rs_tiles;
-    }
+    size_t nt = 0;
+    for (int s = 0; s < n; ++s) nt += task_bound(ax + 3 * s);
     b.desc = L.take(sizeof(SolveDesc) * n);
-    b.tr = L.take(sizeof(int2) * nr_t);
-    b.tv = L.take(sizeof(int2) * nv_t);
-    b.ty = L.take(sizeof(int2) * ny_t);
-    b.te = L.take(sizeof(int2) * std::max<size_t>(ne_t, 1));
-    b.ts = L.take(sizeof(int2) * std::max<size_t>(ns_t, 1));
+    b.tasks = L.take(sizeof(int2) * std::max<size_t>(nt, 1));
     b.rq = L.take(sizeof(Readout) * n);
     b.out = L.take(sizeof(double) * n);
     b.flags = L.take(sizeof(int32_t) * n);
@@ -953,22 +1026,28 @@ BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
     return b;
 }
 
+hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step)
+{
+    const int nt = g.cnt[step];
+    const int2* t = b->d_tasks + g.off;
+    switch (g.kind) {
+    case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, b->stream);
+    case G_EXP: return launch_exp(b->d_desc, t, nt, step, b->stream);
+    case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, b->stream);
+    case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, b->stream);
+    case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, b->stream);
+    case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, b->stream);
+    default: return launch_yc(g.rows, b->d_desc, t, nt, b->stream);
+    }
+}
+
 hjm_status batch_enqueue(hjm_batch* b)
 {
     hipError_t e;
     if ((e = launch_terminal(b->d_desc, b->n, b->max_points, b->stream))) return hip_fail(e, "batch terminal");
-    for (int step = 0; step < b->max_steps; ++step) {
-        if ((e = launch_xr(b->rows[0], b->d_desc, b->d_tr, b->cnt_r[step], step, b->lds_r, b->stream)) ||
-            (e = launch_exp(b->d_desc, b->d_te, b->cnt_e[step], step, b->stream)))
-            return hip_fail(e, "batch step");
-        for (int r = 0; r < 4; ++r)
-            if ((e = launch_rs(b->rs_rows[r], b->d_desc, b->d_ts + b->ts_off[r], b->cnt_s[r][step], step,
-                               b->nr_split, b->stream)))
-                return hip_fail(e, "batch step");
-        if ((e = launch_v(b->rows[1], b->d_desc, b->d_tv, b->cnt_v[step], b->lds_v, b->stream)) ||
-            (e = launch_yu(b->rows[2], b->d_desc, b->d_ty, b->cnt_y[step], b->lds_y, b->stream)))
-            return hip_fail(e, "batch step");
-    }
+    for (int step = 0; step < b->max_steps; ++step)
+        for (const LaunchGroup& g : b->groups)  // groups are in step-pass order
+            if ((e = launch_group(b, g, step))) return hip_fail(e, "batch step");
     return HJM_OK;
 }
 
@@ -1012,91 +1091,71 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);
     b->base = reinterpret_cast<char*>(d_workspace);
     b->d_desc = reinterpret_cast<SolveDesc*>(b->base + bl.desc);
-    b->d_tr = reinterpret_cast<int2*>(b->base + bl.tr);
-    b->d_tv = reinterpret_cast<int2*>(b->base + bl.tv);
-    b->d_ty = reinterpret_cast<int2*>(b->base + bl.ty);
-    b->d_te = reinterpret_cast<int2*>(b->base + bl.te);
-    b->d_ts = reinterpret_cast<int2*>(b->base + bl.ts);
+    b->d_tasks = reinterpret_cast<int2*>(b->base + bl.tasks);
     b->d_rq = reinterpret_cast<Readout*>(b->base + bl.rq);
     b->d_out = reinterpret_cast<double*>(b->base + bl.out);
     b->d_flags = reinterpret_cast<int32_t*>(b->base + bl.flags);
     b->descs.resize(n);
     b->tables.resize(n);
-    // Solves ordered by step count, longest first: the solves still running
-    // at step n are a prefix, so each launch covers a prefix of the task list.
+    std::vector<Plan> plans(n);
+    for (int s = 0; s < n; ++s) {
+        const hjm_axis* a = ax + 3 * s;
+        plans[s] = make_plan(a[0].n, a[1].n, a[2].n, b->rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
+        build_tables(a, model[s], payoff[s], n_steps[s], plans[s], b->tables[s]);
+        fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], plans[s], b->base, bl.s[s], b->d_flags + s);
+        b->max_steps = std::max(b->max_steps, n_steps[s]);
+        b->max_points = std::max<int64_t>(b->max_points, (int64_t)a[0].n * a[1].n * a[2].n);
+        b->max_ylines = std::max<int64_t>(b->max_ylines, (int64_t)a[0].n * a[1].n);
+    }
     std::vector<int> order(n);
     for (int s = 0; s < n; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n_steps[a] > n_steps[c]; });
-    for (int s = 0; s < n; ++s) {
-        const hjm_axis* a = ax + 3 * s;
-        Plan pl = make_plan(a[0].n, a[1].n, a[2].n, b->rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
-        fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], pl, b->base, bl.s[s], b->d_flags + s);
-        build_tables(a, model[s], payoff[s], n_steps[s], b->tables[s]);
-        b->lds_r = std::max(b->lds_r, pl.r_lds);
-        b->lds_v = std::max(b->lds_v, pl.v_lds);
-        b->lds_y = std::max(b->lds_y, pl.y_lds);
-        b->max_steps = std::max(b->max_steps, n_steps[s]);
-        b->max_points = std::max<int64_t>(b->max_points, (int64_t)a[0].n * a[1].n * a[2].n);
-    }
-    auto rs_slot = [&](int rows) {
-        for (int r = 0; r < 4; ++r)
-            if (b->rs_rows[r] == rows) return r;
-        return -1;
+    // (kind, rows) -> group, created in pass order
+    auto group = [&](int kind, int rows) -> LaunchGroup& {
+        for (LaunchGroup& g : b->groups)
+            if (g.kind == kind && g.rows == rows) return g;
+        b->groups.emplace_back();
+        b->groups.back().kind = kind;
+        b->groups.back().rows = rows;
+        b->groups.back().cnt.assign(b->max_steps, 0);
+        return b->groups.back();
     };
-    std::vector<int> slot(n, -1);
-    for (int s = 0; s < n; ++s) {
-        const SolveDesc& d = b->descs[s];
-        if (d.r_mode == R_SPLIT) {
-            slot[s] = rs_slot(d.nr / d.rs_S);
-            b->nr_split = std::max(b->nr_split, d.nr);
-        }
-    }
-    for (int s : order) {
-        const SolveDesc& d = b->descs[s];
-        if (d.r_mode == R_SPLIT) {
-            for (int t = 0; t < d.exp_tiles; ++t) b->te.push_back(make_int2(s, t));
-            for (int t = 0; t < d.rs_tiles; ++t) b->ts[slot[s]].push_back(make_int2(s, t));
-        } else {
-            for (int t = 0; t < d.r_tiles; ++t) b->tr.push_back(make_int2(s, t));
-        }
-        for (int t = 0; t < d.v_tiles; ++t) b->tv.push_back(make_int2(s, t));
-        for (int t = 0; t < d.y_tiles; ++t) b->ty.push_back(make_int2(s, t));
-    }
-    b->cnt_r.assign(b->max_steps, 0);
-    b->cnt_v.assign(b->max_steps, 0);
-    b->cnt_y.assign(b->max_steps, 0);
-    b->cnt_e.assign(b->max_steps, 0);
-    for (int r = 0; r < 4; ++r) b->cnt_s[r].assign(b->max_steps, 0);
-    for (int s : order) {
-        const SolveDesc& d = b->descs[s];
-        for (int step = 0; step < d.n_steps; ++step) {
-            if (d.r_mode == R_SPLIT) {
-                b->cnt_e[step] += d.exp_tiles;
-                b->cnt_s[slot[s]][step] += d.rs_tiles;
-            } else {
-                b->cnt_r[step] += d.r_tiles;
+    for (int kind = 0; kind < kGroupKinds; ++kind)
+        for (int s : order) {
+            const Plan& pl = plans[s];
+            const int ns = n_steps[s];
+            int rows = 0, tiles = 0;
+            size_t lds = 0;
+            int aux = 0;
+            switch (kind) {
+            case G_XR: if (pl.r_mode != R_SPLIT) { rows = b->rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; } break;
+            case G_EXP: if (pl.r_mode == R_SPLIT) { rows = 1; tiles = pl.exp_tiles; } break;
+            case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
+            case G_V: if (!pl.vs_rows) { rows = b->rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
+            case G_VS: if (pl.vs_rows) { rows = pl.vs_rows; tiles = pl.vs_tiles; aux = pl.vs_S; } break;
+            case G_YU: if (!pl.yc_rows) { rows = b->rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
+            default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; } break;
             }
-            b->cnt_v[step] += d.v_tiles;
-            b->cnt_y[step] += d.y_tiles;
+            if (!tiles) continue;
+            LaunchGroup& g = group(kind, rows);
+            for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(s, t));
+            for (int step = 0; step < ns; ++step) g.cnt[step] += tiles;
+            g.lds = std::max(g.lds, lds);
+            g.aux = std::max(g.aux, aux);
         }
-    }
-    std::vector<int2> ts_all;
-    for (int r = 0; r < 4; ++r) {
-        b->ts_off[r] = ts_all.size();
-        ts_all.insert(ts_all.end(), b->ts[r].begin(), b->ts[r].end());
+    std::vector<int2> all;
+    for (LaunchGroup& g : b->groups) {
+        g.off = all.size();
+        all.insert(all.end(), g.tasks.begin(), g.tasks.end());
     }
     hipError_t e = init_kernel_attributes();
     if (!e) e = hipMemcpyAsync(b->d_desc, b->descs.data(), sizeof(SolveDesc) * n, hipMemcpyHostToDevice, b->stream);
-    if (!e) e = hipMemcpyAsync(b->d_tr, b->tr.data(), sizeof(int2) * b->tr.size(), hipMemcpyHostToDevice, b->stream);
-    if (!e) e = hipMemcpyAsync(b->d_tv, b->tv.data(), sizeof(int2) * b->tv.size(), hipMemcpyHostToDevice, b->stream);
-    if (!e) e = hipMemcpyAsync(b->d_ty, b->ty.data(), sizeof(int2) * b->ty.size(), hipMemcpyHostToDevice, b->stream);
-    if (!e && !b->te.empty())
-        e = hipMemcpyAsync(b->d_te, b->te.data(), sizeof(int2) * b->te.size(), hipMemcpyHostToDevice, b->stream);
-    if (!e && !ts_all.empty())
-        e = hipMemcpyAsync(b->d_ts, ts_all.data(), sizeof(int2) * ts_all.size(), hipMemcpyHostToDevice, b->stream);
+    if (!e && !all.empty())
+        e = hipMemcpyAsync(b->d_tasks, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, b->stream);
     for (int s = 0; s < n && !e; ++s)
         e = hipMemcpyAsync(const_cast<double*>(b->descs[s].rt), b->tables[s].data(), b->tables[s].size() * 8,
                            hipMemcpyHostToDevice, b->stream);
+    if (!e) e = launch_ypiv(b->d_desc, n, b->max_ylines, b->stream);
     if (!e) e = hipStreamSynchronize(b->stream);
     if (e) {
         delete b;

@@ -32,6 +32,11 @@ struct SolveDesc {
     // (a power of two <= 64) per line
     int32_t exp_J, exp_cb, exp_tiles, rs_S;
     int32_t rs_log2S, rs_L, rs_tiles, pad1;
+    // segmented v solve (k_vs, vs_S > 0): vs_S segments of nv / vs_S rows, one
+    // wave of 64 consecutive i per segment; chained y solve on stored pivots
+    // (k_yc, yc_S > 0): yc_S segments of ny / yc_S rows, yc_L lines per workgroup
+    int32_t vs_S, vs_tiles, yc_S, yc_L;
+    int32_t yc_tiles, pad2, pad3, pad4;
     double dt;          // time step
     double tdt;         // theta * dt, theta = 1/2
     double kappa;
@@ -49,6 +54,8 @@ struct SolveDesc {
     const double* st;   // step table, kStepStride * (n_steps + 1)
     const double* rf;   // r rows of (I - theta dt A1), theta dt folded in: kRF * nr
     const double* gd;   // Dirichlet increments g(t_{n+1}) - g(t_n): (2 ny + nr) per step
+    const double* vg;   // segmented v-solve constants, kVG * nv
+    double* cp;         // y-line pivots c'_k of (I - theta dt A3), nr*nv*ny (written once per solve)
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value
     int32_t* flag_pad;
 };
@@ -96,6 +103,14 @@ enum { VS_B0 = 0, VS_C0, VS_E0, VS_F1, VS_AL, VS_BL, VS_EL, VS_F2, kVS };
 // line with variance v and c = f_t + kappa f + y, with e = FP c + FQ:
 //   (A, B, C) = (FALO v + e,  FADI v + FB,  FAUP v - e)
 enum { RF_P = 0, RF_Q, RF_ALO, RF_ADI, RF_AUP, RF_B, kRF };
+// Segmented v solve (the v-line matrix depends on j alone).  With the faces
+// folded into rows 1 and n-2 (rows 0 and n-1 pass through as identity and are
+// recovered last), the forward sweep is d'_j = INV_j d_j + AL_j d'_{j-1} and
+// the backward x_j = d'_j - CP_j x_{j+1}.  Each segment runs both from zero
+// and adds G_j d'_in (G_j: product of AL from the segment start to j) and
+// H_j x_in (H_j: product of -CP from j to the segment end).
+enum { VG_INV = 0, VG_AL, VG_CP, VG_G, VG_H, kVG };
+
 // Dirichlet increments of step n: r_min face (ny values, by k), r_max face
 // (ny), y_max face (nr, by i); zero where the face is not Dirichlet.
 enum { GD_RLO = 0, GD_RHI = 1, GD_YHI = 2 };
@@ -132,6 +147,12 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
                      hipStream_t st);
 // rows per thread available to k_rs
 bool rs_rows_supported(int rows);
+hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);
+hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines, hipStream_t st);
+hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st);
+// rows per thread available to k_vs and k_yc
+bool vs_rows_supported(int rows);
+bool yc_rows_supported(int rows);
 hipError_t launch_readout(const SolveDesc* d_desc, const Readout* rq, int n, double* out, hipStream_t st);
 hipError_t launch_health(const SolveDesc* d_desc, int n_solves, int64_t max_points, hipStream_t st);
 

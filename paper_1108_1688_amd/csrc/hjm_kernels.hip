@@ -1115,6 +1115,242 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     if (store && !ok) raise_flag(s);
 }
 
+// v sweep, segmented: the v-line matrix is the same on every line, so its
+// factors and the segment products G, H are host constants (see VG_* in
+// hjm_internal.h).  Workgroup = vs_S waves; wave w holds rows
+// [w ROWS, (w+1) ROWS) of 64 consecutive lines (i, k) (lanes = consecutive i:
+// every load and store is one contiguous row segment).  Each segment sweeps
+// forward and backward from zero; the segment-end values cross the workgroup
+// through LDS once per direction.
+template <int ROWS>
+__global__ __launch_bounds__(kBlock) void k_vs(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
+{
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
+    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const SolveDesc& s = descs[tk.x];
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int S = s.vs_S;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int seg = __builtin_amdgcn_readfirstlane(t >> 6);
+    const bool in_seg = seg < S;
+    const int nlines = nr * ny;
+    const int q_raw = tk.y * 64 + lane;
+    const bool active = q_raw < nlines;
+    const int q = active ? q_raw : nlines - 1;
+    const int k = q / nr;
+    const int i = q - k * nr;
+    const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir) || (k == ny - 1 && s.y_hi_dir);
+    const int sg = in_seg ? seg : 0;
+    gdouble* base = gp(s.D) + ((size_t)k * nv + (size_t)sg * ROWS) * nr + i;
+    gcdouble* vg = gp(s.vg) + sg * ROWS;
+    gcdouble* fs = gp(s.vf) + kVF * nv;
+    const bool first = sg == 0;
+    const bool last = sg == S - 1;
+    double d[ROWS];
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) d[mm] = base[(size_t)mm * nr];
+    const double d0 = d[0], dl = d[ROWS - 1];
+    if (first) d[1] = d[1] - fs[VS_F1] * d0;
+    if (last) d[ROWS - 2] = d[ROWS - 2] - fs[VS_F2] * dl;
+    double l = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) {
+        l = vg[VG_INV * nv + mm] * d[mm] + vg[VG_AL * nv + mm] * l;
+        d[mm] = l;
+    }
+    ldouble* lend = lds;
+    ldouble* bfirst = lds + (size_t)4 * 64;
+    if (in_seg) lend[seg * 64 + lane] = d[ROWS - 1];
+    __syncthreads();
+    double din = 0.0;
+    for (int qq = 0; qq < sg; ++qq) din = lend[qq * 64 + lane] + gp(s.vg)[VG_G * nv + qq * ROWS + ROWS - 1] * din;
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) d[mm] = d[mm] + vg[VG_G * nv + mm] * din;
+    double x = 0.0;
+#pragma unroll
+    for (int mm = ROWS - 1; mm >= 0; --mm) {
+        x = d[mm] - vg[VG_CP * nv + mm] * x;
+        d[mm] = x;
+    }
+    if (in_seg) bfirst[seg * 64 + lane] = d[0];
+    __syncthreads();
+    double xin = 0.0;
+    for (int qq = S - 1; qq > sg; --qq) xin = bfirst[qq * 64 + lane] + gp(s.vg)[VG_H * nv + qq * ROWS] * xin;
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) d[mm] = d[mm] + vg[VG_H * nv + mm] * xin;
+    if (first) d[0] = (d0 - fs[VS_C0] * d[1] - fs[VS_E0] * d[2]) / fs[VS_B0];
+    if (last) d[ROWS - 1] = (dl - fs[VS_EL] * d[ROWS - 3] - fs[VS_AL] * d[ROWS - 2]) / fs[VS_BL];
+    if (in_seg && active && !line_dir) {
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) base[(size_t)mm * nr] = d[mm];
+    }
+}
+
+// Pivots c'_k of every y line (i, j) of (I - theta dt A3), which does not
+// change from step to step: the Thomas forward recurrence in row order, with
+// the outflow row 0 folded into row 1 and the last row into row n-2 exactly
+// as in the per-step solve.  One thread per line, written once per solve.
+__global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ descs)
+{
+    const SolveDesc& s = descs[blockIdx.y];
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    if (s.yc_S == 0) return;
+    const int q = blockIdx.x * kBlock + threadIdx.x;  // q = j nr + i
+    if (q >= nr * nv) return;
+    const int j = q / nr;
+    const int i = q - j * nr;
+    const size_t sy = (size_t)nr * nv;
+    gdouble* cp = gp(s.cp) + q;
+    RowY row;
+    row.yt = gp(s.yt);
+    row.ny = ny;
+    row.qv = gp(s.rt)[RT_Y * nr + i] * gp(s.vt)[VT_V * nv + j];
+    double A0, B0, C0, E0, A1, B1, C1, E1, Al, Bl, Cl, El, A2, B2, C2, E2;
+    row(0, A0, B0, C0, E0);
+    row(1, A1, B1, C1, E1);
+    row(ny - 1, Al, Bl, Cl, El);
+    row(ny - 2, A2, B2, C2, E2);
+    const double f1 = A1 / B0, f2 = C2 / Bl;
+    bool ok = B0 > 0.0 && Bl > 0.0;
+    double cprev = 0.0;
+    cp[0] = 0.0;
+    for (int kk = 1; kk < ny - 1; ++kk) {
+        double A, B, C, E;
+        row(kk, A, B, C, E);
+        if (kk == 1) { A = 0.0; B = B1 - f1 * C0; C = C1 - f1 * E0; }
+        if (kk == ny - 2) { A = A2 - f2 * El; B = B2 - f2 * Al; C = 0.0; }
+        const double den = B - A * cprev;
+        ok = ok && den > 0.0;
+        cprev = C / den;
+        cp[(size_t)kk * sy] = cprev;
+    }
+    cp[(size_t)(ny - 1) * sy] = 0.0;
+    const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir);
+    if (!ok && !line_dir) raise_flag(s);
+}
+
+// y sweep + update on the stored pivots: Thomas in row order, segments of
+// ROWS rows chained through LDS (segment s runs once segment s-1 has handed
+// over d' of its last row); the only serial work per row is one FMA forward
+// and one backward.  Then U^{n+1} = U^n + D3.
+template <int ROWS>
+__global__ __launch_bounds__(kBlock) void k_yc(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
+{
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
+    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const SolveDesc& s = descs[tk.x];
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int S = s.yc_S, L = s.yc_L;
+    const int t = threadIdx.x;
+    const int l = t % L;
+    const int seg = t / L;
+    const int q = tk.y * L + l;  // line (i, j), q = j nr + i
+    const bool active = seg < S && q < nr * nv;
+    const int qc = active ? q : 0;
+    const int j = qc / nr;
+    const int i = qc - j * nr;
+    const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir);
+    const bool work = active && !line_dir;
+    const int sg = seg < S ? seg : 0;
+    const size_t sy = (size_t)nr * nv;
+    const size_t off = (size_t)qc + (size_t)sg * ROWS * sy;
+    gdouble* D = gp(s.D);
+    gdouble* U = gp(s.U);
+    gcdouble* CPg = gp(s.cp);
+    gcdouble* yt = gp(s.yt);
+    const bool first = sg == 0;
+    const bool last = sg == S - 1;
+    double d[ROWS], al[ROWS], cp[ROWS];
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) {
+        d[mm] = active ? D[off + (size_t)mm * sy] : 0.0;
+        cp[mm] = active ? CPg[off + (size_t)mm * sy] : 0.0;
+    }
+    double cpm = (active && !first) ? CPg[off - sy] : 0.0;
+    RowY row;
+    row.yt = yt;
+    row.ny = ny;
+    row.qv = gp(s.rt)[RT_Y * nr + i] * gp(s.vt)[VT_V * nv + j];
+    double d0 = 0.0, B0 = 1.0, C0 = 0.0, E0 = 0.0, dl = 0.0, Al = 0.0, Bl = 1.0, El = 0.0;
+    double b1m = 1.0, a2m = 0.0, b2m = 1.0;
+    if (work && first) {
+        double A0, A1, B1, C1, E1;
+        row(0, A0, B0, C0, E0);
+        row(1, A1, B1, C1, E1);
+        const double f = A1 / B0;
+        b1m = B1 - f * C0;
+        d0 = d[0];
+        d[1] = d[1] - f * d0;
+    }
+    if (work && last) {
+        double Cl, A2, B2, C2, E2;
+        row(ny - 1, Al, Bl, Cl, El);
+        row(ny - 2, A2, B2, C2, E2);
+        const double f = C2 / Bl;
+        a2m = A2 - f * El;
+        b2m = B2 - f * Al;
+        dl = d[ROWS - 1];
+        d[ROWS - 2] = d[ROWS - 2] - f * dl;
+    }
+    bool ok = true;
+    // pivots from the stored c'_{k-1}: den_k = B_k - A_k c'_{k-1}; the
+    // recurrence becomes d'_k = d_k / den_k + (-A_k / den_k) d'_{k-1}
+    // (lines on a Dirichlet r face keep D: identity rows)
+    if (work) {
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) {
+        const int kk = sg * ROWS + mm;
+        double A, B, C, E;
+        row(kk, A, B, C, E);
+        if (mm == 0) { A = first ? 0.0 : A; B = first ? 1.0 : B; }
+        if (mm == 1) { B = first ? b1m : B; A = first ? 0.0 : A; }
+        if (mm == ROWS - 2) { A = last ? a2m : A; B = last ? b2m : B; }
+        if (mm == ROWS - 1) { A = last ? 0.0 : A; B = last ? 1.0 : B; }
+        const double cprev = mm == 0 ? cpm : cp[mm - 1];
+        const double den = B - A * cprev;
+        const double inv = 1.0 / den;
+        ok = ok && den > 0.0;
+        al[mm] = -A * inv;
+        d[mm] = d[mm] * inv;
+    }
+    }
+    ldouble* xch = lds + 2 * l;
+    for (int stage = 0; stage < S; ++stage) {
+        if (work && seg == stage) {
+            double dp = stage > 0 ? xch[0] : 0.0;
+#pragma unroll
+            for (int mm = 0; mm < ROWS; ++mm) {
+                dp = d[mm] + al[mm] * dp;
+                d[mm] = dp;
+            }
+            xch[0] = dp;
+        }
+        if (S > 1) __syncthreads();
+    }
+    for (int stage = S - 1; stage >= 0; --stage) {
+        if (work && seg == stage) {
+            double x = stage < S - 1 ? xch[1] : 0.0;
+#pragma unroll
+            for (int mm = ROWS - 1; mm >= 0; --mm) {
+                x = d[mm] - cp[mm] * x;
+                d[mm] = x;
+            }
+            xch[1] = x;
+            if (first) d[0] = (d0 - C0 * d[1] - E0 * d[2]) / B0;
+            if (last) d[ROWS - 1] = (dl - El * d[ROWS - 3] - Al * d[ROWS - 2]) / Bl;
+        }
+        if (S > 1) __syncthreads();
+    }
+    if (active) {
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) U[off + (size_t)mm * sy] = U[off + (size_t)mm * sy] + d[mm];
+    }
+    if (work && !ok) raise_flag(s);
+}
+
 __global__ void k_readout(const SolveDesc* __restrict__ descs, const Readout* __restrict__ rq, int n,
                           double* __restrict__ out)
 {
@@ -1158,7 +1394,9 @@ hipError_t init_kernel_attributes()
             (e = allow_lds(k_v<8>)) || (e = allow_lds(k_v<16>)) || (e = allow_lds(k_v<32>)) ||
             (e = allow_lds(k_yu<8>)) || (e = allow_lds(k_yu<16>)) || (e = allow_lds(k_yu<32>)) ||
             (e = allow_lds(k_rs<6>)) || (e = allow_lds(k_rs<8>)) || (e = allow_lds(k_rs<12>)) ||
-            (e = allow_lds(k_rs<16>)))
+            (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
+            (e = allow_lds(k_vs<32>)) || (e = allow_lds(k_yc<8>)) || (e = allow_lds(k_yc<16>)) ||
+            (e = allow_lds(k_yc<32>)))
             return e;
         return hipSuccess;
     }();
@@ -1234,6 +1472,34 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     case 16: hipLaunchKernelGGL(k_rs<16>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+bool vs_rows_supported(int rows) { return rows == 8 || rows == 16 || rows == 32; }
+bool yc_rows_supported(int rows) { return rows == 8 || rows == 16 || rows == 32; }
+
+hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    if (S_max < 1 || S_max > 4) return hipErrorInvalidValue;
+    const size_t lds = (size_t)2 * 4 * 64 * 8;
+    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_vs<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
+    return hipGetLastError();
+}
+
+hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines, hipStream_t st)
+{
+    const int64_t blocks = (max_lines + kBlock - 1) / kBlock;
+    if (blocks < 1 || n_solves < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_ypiv, dim3((unsigned)blocks, (unsigned)n_solves), dim3(kBlock), 0, st, d_desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    const size_t lds = (size_t)2 * kBlock * 8;
+    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_yc<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 

@@ -206,10 +206,13 @@ class Grid:
 
     def plan(self) -> dict:
         """How this grid is solved: r method ('spike', 'chain' or 'split'),
-        rows per lane of the split r solve, line-tile rows."""
+        rows per lane of the split r solve, line-tile rows, rows per segment
+        of the segmented v solve and of the stored-pivot y solve (0 where the
+        chained per-line solves are used instead)."""
         out = (C.c_int32 * 8)()
         check(lib().hjm_grid_plan(self._h, out))
-        return {"r_method": R_METHODS[out[0]], "rs_rows": out[1], "line_tile": (out[2], out[3], out[4])}
+        return {"r_method": R_METHODS[out[0]], "rs_rows": out[1], "line_tile": (out[2], out[3], out[4]),
+                "vs_rows": out[5], "yc_rows": out[6]}
 
     def profile(self, enable: bool = True) -> None:
         """Bracket every pass launch with HIP events on the grid's stream."""

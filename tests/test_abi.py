@@ -58,10 +58,11 @@ def test_workspace_bytes(L):
     nb = C.c_size_t()
     assert L.hjm_workspace_bytes(hjm.make_axes(s.axes), s.n_steps, C.byref(nb)) == 0
     pts = 32 ** 3
-    assert 2 * pts * 8 <= nb.value <= 2 * pts * 8 + 64 * 1024
+    per_step = (2 * 32 + 32) * 8 * s.n_steps  # Dirichlet increments
+    assert 3 * pts * 8 <= nb.value <= 3 * pts * 8 + per_step + 64 * 1024
     s3 = W.config3()[-1]
     assert L.hjm_workspace_bytes(hjm.make_axes(s3.axes), s3.n_steps, C.byref(nb)) == 0
-    assert nb.value >= 2 * 256 * 128 * 128 * 8
+    assert nb.value >= 3 * 256 * 128 * 128 * 8
     assert L.hjm_workspace_bytes(hjm.make_axes(s.axes), 0, C.byref(nb)) == hjm.EINVAL
 
 

@@ -45,7 +45,7 @@ def gpu_grid(spec, steps=None, price=True):
     g = hjm.Grid(spec)
     plan = g.plan()
     print(f"[gpu] plan {plan}", flush=True)
-    PLANS[:] = [plan["r_method"]]
+    PLANS[:] = [plan["r_method"], plan["vs_rows"] > 0, plan["yc_rows"] > 0]
     g.step(steps)
     p = g.price() if (price and g.steps_taken == spec.n_steps) else None
     U = g.solution().cpu().numpy().copy()
@@ -168,7 +168,7 @@ def test_config3_full_size_first_steps_elementwise():
     configuration): three Douglas steps compared on every node."""
     s = W.config3()[-1]
     Ug, _ = gpu_grid(s, steps=3, price=False)
-    assert PLANS == ["split"]
+    assert PLANS == ["split", True, True]
     Uo, _ = oracle_grid(s, steps=3)
     assert_grid(Ug, Uo)
 
@@ -185,7 +185,22 @@ def test_each_r_method(method):
     else:
         s = _sloped((96, 24, 24), 12)
     Ug, pg = gpu_grid(s)
-    assert PLANS == [method]
+    assert PLANS[0] == method
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+@pytest.mark.parametrize("shape,vs,yc", [((48, 40, 41), False, False), ((48, 48, 40), True, True),
+                                         ((64, 24, 17), True, False), ((64, 29, 32), False, True)],
+                         ids=["v-chain,y-chain", "v-seg,y-piv", "v-seg,y-chain", "v-chain,y-piv"])
+def test_v_and_y_methods(shape, vs, yc):
+    """Segmented v solve where nv = S * ROWS (S <= 4) and its segment products
+    stay <= 1, the chained one elsewhere; y on stored pivots where ny = S * ROWS,
+    the per-step elimination elsewhere."""
+    s = _sloped(shape, 15)
+    Ug, pg = gpu_grid(s)
+    assert PLANS[1:] == [vs, yc]
     Uo, po = oracle_grid(s)
     assert_grid(Ug, Uo)
     assert_price(pg, po)
