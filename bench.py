@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
+    ap.add_argument("--exp-chunk", type=int, default=None, help="v nodes per explicit-kernel thread (4, 8, 16)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -102,6 +103,8 @@ def main():
 
     if args.tile:
         hjm.set_line_tile(*[int(x) for x in args.tile.split(",")])
+    if args.exp_chunk:
+        hjm.set_explicit_chunk(args.exp_chunk)
     torch.cuda.set_device(0)
     specs = W.config3()
     points = specs[0].points
@@ -171,6 +174,7 @@ def main():
            "config": {"workload": "256x128x128 grid (r x v x y), 10 ATM caplets expiring 1..10y paid +1y, "
                                   "dt=0.025 (2200 Douglas steps per bench step), seeded parameters (seed 2)",
                       "grid": [256, 128, 128], "douglas_steps": total_steps, "line_tile": list(hjm.get_line_tile()),
+                      "explicit_chunk": hjm.get_explicit_chunk(),
                       "parallelism": "single GPU"},
            "roofline": roofline}
     if not args.no_cpu_baseline:

@@ -198,6 +198,12 @@ hjm_status hjm_batch_destroy(hjm_batch* b);
 hjm_status hjm_set_line_tile(int32_t r_rows, int32_t v_rows, int32_t y_rows);
 hjm_status hjm_get_line_tile(int32_t* r_rows, int32_t* v_rows, int32_t* y_rows);
 
+/* Nodes along v that one thread of the explicit-predictor kernel computes
+   (4, 8 or 16; HJM_EINVAL otherwise).  Process-wide, read when a grid or
+   batch is created, like the line tile. */
+hjm_status hjm_set_explicit_chunk(int32_t J);
+hjm_status hjm_get_explicit_chunk(int32_t* J);
+
 const char* hjm_status_str(hjm_status s);
 const char* hjm_last_error(void);
 

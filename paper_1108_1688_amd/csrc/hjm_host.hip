@@ -17,7 +17,7 @@ using namespace hjm;
 namespace {
 
 thread_local std::string g_last_error;
-int g_rows[3] = {16, 16, 8};  // rows per thread of the r, v, y line solves
+int g_rows[3] = {16, 16, 16};  // rows per thread of the r, v, y line solves
 
 hjm_status fail(hjm_status code, const char* fmt, ...)
 {
@@ -195,16 +195,16 @@ int vs_rows_for(int nv, int preferred)
     return 0;
 }
 
-// y solve on stored pivots: ny = S * ROWS with at least 8 lines per workgroup.
+// y solve on stored pivots: ny = S * ROWS with S <= 128 / ROWS waves per workgroup.
 int yc_rows_for(int ny, int preferred)
 {
     const int cands[4] = {preferred, 16, 32, 8};
     for (int r : cands)
-        if (yc_rows_supported(r) && ny % r == 0 && ny / r <= kBlock / 8) return r;
+        if (yc_rows_supported(r) && ny % r == 0 && ny / r <= yc_max_segments(r)) return r;
     return 0;
 }
 
-constexpr int kExpJ = 16;  // v nodes per k_exp thread
+int g_exp_J = 8;  // v nodes per k_exp thread (4, 8 or 16)
 
 // k_rs needs nr = S * ROWS with S a power of two <= 64 lanes; the preferred
 // rows per lane come first.
@@ -258,7 +258,7 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     p.r_mode = r_spike ? R_SPIKE : R_CHAIN;
     p.rs_rows = r_spike ? split_rows(nr, rows[0]) : 0;
     p.rs_S = p.rs_log2S = p.rs_L = p.rs_tiles = 0;
-    p.exp_J = std::min(kExpJ, nv);
+    p.exp_J = g_exp_J;
     p.exp_cb = (nr * ny + kExpCols - 1) / kExpCols;
     p.exp_tiles = p.exp_cb * ((nv + p.exp_J - 1) / p.exp_J);
     p.vs_rows = vs_rows_for(nv, rows[1]);
@@ -266,7 +266,7 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     p.vs_tiles = p.vs_rows ? (nr * ny + 63) / 64 : 0;
     p.yc_rows = yc_rows_for(ny, rows[2]);
     p.yc_S = p.yc_rows ? ny / p.yc_rows : 0;
-    p.yc_L = p.yc_rows ? kBlock / p.yc_S : 0;
+    p.yc_L = p.yc_rows ? 64 : 0;
     p.yc_tiles = p.yc_rows ? (nr * nv + p.yc_L - 1) / p.yc_L : 0;
     if (p.rs_rows) {
         p.r_mode = R_SPLIT;
@@ -327,6 +327,14 @@ Plan plan_bound(int nr, int nv, int ny)
 {
     static const int options[3] = {8, 16, 32};
     Plan b{};
+    {
+        // the most k_exp tiles: the smallest v chunk
+        const int save = g_exp_J;
+        g_exp_J = 4;
+        const int rows[3] = {8, 8, 8};
+        b.exp_tiles = make_plan(nr, nv, ny, rows, true).exp_tiles;
+        g_exp_J = save;
+    }
     for (int o : {8, 16, 12, 6})
         for (bool sp : {true, false}) {
             const int rows[3] = {o, 8, 8};
@@ -763,6 +771,20 @@ hjm_status hjm_set_line_tile(int32_t r_rows, int32_t v_rows, int32_t y_rows)
     return HJM_OK;
 }
 
+hjm_status hjm_set_explicit_chunk(int32_t J)
+{
+    if (J != 4 && J != 8 && J != 16) return fail(HJM_EINVAL, "explicit chunk must be 4, 8 or 16 (got %d)", J);
+    g_exp_J = J;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_explicit_chunk(int32_t* J)
+{
+    if (!J) return fail(HJM_EINVAL, "null argument");
+    *J = g_exp_J;
+    return HJM_OK;
+}
+
 hjm_status hjm_get_line_tile(int32_t* r_rows, int32_t* v_rows, int32_t* y_rows)
 {
     if (!r_rows || !v_rows || !y_rows) return fail(HJM_EINVAL, "null argument");
@@ -853,12 +875,12 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
                 g->ev_pass[g->ev_used] = pass;
                 if ((e = hipEventRecord(e0, g->stream))) return hip_fail(e, "hipEventRecord");
             }
-            if (pass == 0 && split) e = launch_exp(g->d_desc, nullptr, p.exp_tiles, n, g->stream);
+            if (pass == 0 && split) e = launch_exp(p.exp_J, g->d_desc, nullptr, p.exp_tiles, n, g->stream);
             else if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
             else if (pass == 1) e = launch_rs(p.rs_rows, g->d_desc, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
             else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, g->d_desc, nullptr, p.vs_tiles, p.vs_S, g->stream);
             else if (pass == 2) e = launch_v(g->rows[1], g->d_desc, nullptr, p.v_tiles, p.v_lds, g->stream);
-            else if (p.yc_rows) e = launch_yc(p.yc_rows, g->d_desc, nullptr, p.yc_tiles, g->stream);
+            else if (p.yc_rows) e = launch_yc(p.yc_rows, g->d_desc, nullptr, p.yc_tiles, p.yc_S, g->stream);
             else e = launch_yu(g->rows[2], g->d_desc, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {
@@ -1032,12 +1054,12 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step)
     const int2* t = b->d_tasks + g.off;
     switch (g.kind) {
     case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, b->stream);
-    case G_EXP: return launch_exp(b->d_desc, t, nt, step, b->stream);
+    case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, b->stream);
     case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, b->stream);
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, b->stream);
     case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, b->stream);
     case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, b->stream);
-    default: return launch_yc(g.rows, b->d_desc, t, nt, b->stream);
+    default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, b->stream);
     }
 }
 
@@ -1129,12 +1151,12 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
             int aux = 0;
             switch (kind) {
             case G_XR: if (pl.r_mode != R_SPLIT) { rows = b->rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; } break;
-            case G_EXP: if (pl.r_mode == R_SPLIT) { rows = 1; tiles = pl.exp_tiles; } break;
+            case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
             case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
             case G_V: if (!pl.vs_rows) { rows = b->rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
             case G_VS: if (pl.vs_rows) { rows = pl.vs_rows; tiles = pl.vs_tiles; aux = pl.vs_S; } break;
             case G_YU: if (!pl.yc_rows) { rows = b->rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
-            default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; } break;
+            default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; aux = pl.yc_S; } break;
             }
             if (!tiles) continue;
             LaunchGroup& g = group(kind, rows);

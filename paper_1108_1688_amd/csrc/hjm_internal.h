@@ -34,7 +34,8 @@ struct SolveDesc {
     int32_t rs_log2S, rs_L, rs_tiles, pad1;
     // segmented v solve (k_vs, vs_S > 0): vs_S segments of nv / vs_S rows, one
     // wave of 64 consecutive i per segment; chained y solve on stored pivots
-    // (k_yc, yc_S > 0): yc_S segments of ny / yc_S rows, yc_L lines per workgroup
+    // (k_yc, yc_S > 0): yc_S segments of ny / yc_S rows (one wave each), 64
+    // lines per workgroup (yc_L)
     int32_t vs_S, vs_tiles, yc_S, yc_L;
     int32_t yc_tiles, pad2, pad3, pad4;
     double dt;          // time step
@@ -142,14 +143,18 @@ hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_
                     size_t lds_bytes, hipStream_t st);
 hipError_t launch_yu(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks,
                      size_t lds_bytes, hipStream_t st);
-hipError_t launch_exp(const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st);
+// J: v nodes per k_exp thread (4, 8 or 16)
+hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st);
 hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, int nr_max,
                      hipStream_t st);
 // rows per thread available to k_rs
 bool rs_rows_supported(int rows);
 hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);
 hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines, hipStream_t st);
-hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st);
+hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);
+// k_yc holds 4 ROWS-long arrays per thread: workgroups of at most 128 / ROWS
+// waves keep them in registers
+constexpr int yc_max_segments(int rows) { return 128 / rows; }
 // rows per thread available to k_vs and k_yc
 bool vs_rows_supported(int rows);
 bool yc_rows_supported(int rows);

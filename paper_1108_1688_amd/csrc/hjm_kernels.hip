@@ -59,6 +59,13 @@ typedef __attribute__((address_space(3))) double ldouble;
 __device__ __forceinline__ gdouble* gp(double* p) { return (gdouble*)p; }
 __device__ __forceinline__ gcdouble* gp(const double* p) { return (gcdouble*)p; }
 
+// The coefficient tables are written by the host before a solve starts and
+// only read by kernels: reading them through the constant address space lets
+// wave-uniform reads go through scalar loads (which the kernels' own stores
+// to the grid arrays cannot alias).
+typedef __attribute__((address_space(4))) const double kcdouble;
+__device__ __forceinline__ kcdouble* kp(const double* p) { return (kcdouble*)(uintptr_t)p; }
+
 __device__ __forceinline__ double dirichlet_value(const SolveDesc& s, gcdouble* stn, double r, double y)
 {
     // p(t,T) = A exp(-G r - H y): bond reconstruction formula (section 3.1)
@@ -77,6 +84,17 @@ __device__ __forceinline__ void raise_flag(const SolveDesc& s)
 {
     // vector store of a constant; concurrent writers store the same value
     *(__attribute__((address_space(1))) volatile int32_t*)s.flag = 1;
+}
+
+// Workgroups are dealt to the 8 XCDs (each with its own L2) in turn, by
+// workgroup index mod 8.  Give each XCD a contiguous range of tiles instead,
+// so that tiles that read each other's halo lines run on the same L2 (a
+// bijection on [0, n): the tail beyond a multiple of 8 keeps its index).
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int per = n >> 3;
+    if (b >= per * 8) return b;
+    return (b & 7) * per + (b >> 3);
 }
 
 __device__ __forceinline__ int pow2_ceil(int n)
@@ -838,15 +856,17 @@ __device__ __forceinline__ void wave_sync()
 
 // Explicit predictor D0 = dt (A1 + A2 + A3 + A0) U^n (eq. (discreta) with the
 // centred stencils of eq. (esquema), one-sided rows on outflow faces), and the
-// Dirichlet increment on Dirichlet nodes.  Thread = one (i, k) column; it walks
-// exp_J consecutive v nodes j keeping the v window u(i, j-2..j+2) and the
-// neighbouring columns u(i -+ 1, j-1..j+1) in registers, so every node costs
-// five loads: u(i, j+2), u(i -+ 1, j+1) and the two y neighbours.  Lanes are
-// consecutive i: every load of a wave is one contiguous row segment.
+// Dirichlet increment on Dirichlet nodes.  Thread = one (i, k) column and J
+// consecutive v nodes j: it loads the v window u(i, j0-2 .. j0+J+1), the
+// neighbouring columns u(i -+ 1, j0-1 .. j0+J), the two y neighbours and the
+// outflow extra entry of each node, all up front, then computes the J nodes.
+// Lanes are consecutive i: every load of a wave is one contiguous row segment.
+template <int J>
 __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
                                                 int step)
 {
-    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const int bi = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int2 tk = tasks ? tasks[bi] : make_int2(0, bi);
     const SolveDesc& s = descs[tk.x];
     if (step >= s.n_steps) return;
     const int nr = s.nr, nv = s.nv, ny = s.ny;
@@ -856,14 +876,46 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     if (p >= nr * ny) return;  // no barriers below
     const int k = p / nr;
     const int i = p - k * nr;
-    const int j0 = jc * s.exp_J;
-    const int j1 = min(j0 + s.exp_J, nv);
+    // j is the same on every lane: keep it (and the v-table reads) scalar
+    const int j0 = __builtin_amdgcn_readfirstlane(jc * J);
     gcdouble* U = gp(s.U);
     gdouble* D = gp(s.D);
     gcdouble* rt = gp(s.rt);
-    gcdouble* vt = gp(s.vt);
+    kcdouble* vt = kp(s.vt);
     gcdouble* yt = gp(s.yt);
     gcdouble* stn = gp(s.st) + kStepStride * step;
+
+    const size_t sl = (size_t)nr;       // stride of j
+    const size_t sy = (size_t)nr * nv;  // stride of k
+    gcdouble* col = U + (size_t)k * sy; // (k, j = 0, i = 0)
+    const int im = max(i - 1, 0), ip = min(i + 1, nr - 1);
+    // y stencil: two neighbours (offsets oa, ob) and the node itself
+    const bool yhd = s.y_hi_dir && k == ny - 1;
+    int oa = -1, ob = 1;
+    if (k == 0) { oa = 1; ob = 2; }
+    else if (k == ny - 1) { oa = -2; ob = -1; }
+    if (yhd) { oa = 0; ob = 0; }
+    gcdouble* cola = col + (ptrdiff_t)oa * (ptrdiff_t)sy;  // plane k + oa
+    gcdouble* colb = col + (ptrdiff_t)ob * (ptrdiff_t)sy;
+    // outflow r face rows reach two nodes in: the extra entry (interior
+    // columns read their own node, with weight zero)
+    const int dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
+    const size_t ix = (size_t)(i + dx);
+    auto jcl = [&](int jj) { return (size_t)min(max(jj, 0), nv - 1) * sl; };
+    double cw[J + 4], lw[J + 2], rw[J + 2], ya[J], yb[J], ux[J];
+#pragma unroll
+    for (int m = 0; m < J + 4; ++m) cw[m] = col[jcl(j0 - 2 + m) + i];
+#pragma unroll
+    for (int m = 0; m < J + 2; ++m) {
+        lw[m] = col[jcl(j0 - 1 + m) + im];
+        rw[m] = col[jcl(j0 - 1 + m) + ip];
+    }
+#pragma unroll
+    for (int m = 0; m < J; ++m) {
+        ya[m] = cola[jcl(j0 + m) + i];
+        yb[m] = colb[jcl(j0 + m) + i];
+        ux[m] = col[jcl(j0 + m) + ix];
+    }
 
     // per-column constants: A1 row pieces (affine in v), A3 coefficient, A0 factor
     const double c = stn[ST_PHI] + yt[YT_Y * ny + k];
@@ -875,67 +927,33 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     const double ryk = rt[RT_Y * nr + i] * yt[YT_I * ny + k];
     const double kyk = yt[YT_K * ny + k];
     const double rx = rt[RT_X * nr + i];
-    // y stencil: two neighbours (offsets oa, ob) and the node itself
-    const bool yhd = s.y_hi_dir && k == ny - 1;
-    int oa = -1, ob = 1;
     double wa = yt[YT_W1 * ny + k], wb = yt[YT_W3 * ny + k];
-    if (k == 0) { oa = 1; ob = 2; wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
-    else if (k == ny - 1) { oa = -2; ob = -1; wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
-    if (yhd) { oa = 0; ob = 0; }
+    if (k == 0) { wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
+    else if (k == ny - 1) { wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
     const double w2 = yt[YT_W2 * ny + k];
-    // outflow r face rows reach two nodes in: the extra entry
-    const int dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
-    const bool ex = mex != 0.0;
     // Dirichlet nodes: the increment does not depend on j
     gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
     const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
     const bool dir = rlo || rhi || yhd;
     const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
-    const int im = max(i - 1, 0), ip = min(i + 1, nr - 1);
-    const size_t sl = (size_t)nr;                  // stride of j
-    const size_t sy = (size_t)nr * nv;             // stride of k
-    gcdouble* col = U + (size_t)k * sy;            // (k, j = 0, i = 0)
-    auto at = [&](int jj, int ii) -> double {
-        jj = min(max(jj, 0), nv - 1);
-        return col[(size_t)jj * sl + ii];
-    };
-    double c0 = at(j0 - 2, i), c1 = at(j0 - 1, i), c2 = at(j0, i), c3 = at(j0 + 1, i);
-    double l0 = at(j0 - 1, im), l1 = at(j0, im), r0 = at(j0 - 1, ip), r1 = at(j0, ip);
-    // loads of node j, one node ahead of the arithmetic
-    double n4 = at(j0 + 2, i), nl = at(j0 + 1, im), nrr = at(j0 + 1, ip);
-    gcdouble* cola = col + (ptrdiff_t)oa * (ptrdiff_t)sy;  // plane k + oa
-    gcdouble* colb = col + (ptrdiff_t)ob * (ptrdiff_t)sy;
-    const size_t ix = (size_t)(i + dx);
-    double na = cola[(size_t)j0 * sl + i];
-    double nb = colb[(size_t)j0 * sl + i];
-    double nx = ex ? col[(size_t)j0 * sl + ix] : 0.0;
     gdouble* dcol = D + (size_t)k * sy + i;
     const double dt = s.dt;
-    for (int j = j0; j < j1; ++j) {
-        const double c4 = n4, l2 = nl, r2 = nrr, ya = na, yb = nb, ux = nx;
-        if (j + 1 < j1) {
-            const int jn = j + 1;
-            n4 = at(jn + 2, i);
-            nl = at(jn + 1, im);
-            nrr = at(jn + 1, ip);
-            na = cola[(size_t)jn * sl + i];
-            nb = colb[(size_t)jn * sl + i];
-            nx = ex ? col[(size_t)jn * sl + ix] : 0.0;
-        }
+#pragma unroll
+    for (int m = 0; m < J; ++m) {
+        const int j = j0 + m;
+        if (j >= nv) break;  // wave-uniform
         const double v = vt[VT_V * nv + j];
         const double olo = mlo + alo * v, odi = mdi + adi * v, oup = mup + aup * v;
-        const double a1 = olo * l1 + odi * c2 + oup * r1 + mex * ux;
-        const double a2 = vt[VT_O0 * nv + j] * c0 + vt[VT_O1 * nv + j] * c1 + vt[VT_O2 * nv + j] * c2 +
-                          vt[VT_O3 * nv + j] * c3 + vt[VT_O4 * nv + j] * c4;
+        const double a1 = olo * lw[m + 1] + odi * cw[m + 2] + oup * rw[m + 1] + mex * ux[m];
+        const double a2 = vt[VT_O0 * nv + j] * cw[m] + vt[VT_O1 * nv + j] * cw[m + 1] +
+                          vt[VT_O2 * nv + j] * cw[m + 2] + vt[VT_O3 * nv + j] * cw[m + 3] +
+                          vt[VT_O4 * nv + j] * cw[m + 4];
         const double by = ryk * v - kyk;
-        const double a3 = by * (wa * ya + w2 * c2 + wb * yb);
-        const double cross = (r2 - r0) - (l2 - l0);
+        const double a3 = by * (wa * ya[m] + w2 * cw[m + 2] + wb * yb[m]);
+        const double cross = (rw[m + 2] - rw[m]) - (lw[m + 2] - lw[m]);
         const double a0 = rx * vt[VT_X * nv + j] * cross;
         const double val = dt * (((a1 + a2) + a3) + a0);
         dcol[(size_t)j * sl] = dir ? gval : val;
-        c0 = c1; c1 = c2; c2 = c3; c3 = c4;
-        l0 = l1; l1 = l2;
-        r0 = r1; r1 = r2;
     }
 }
 
@@ -1234,20 +1252,22 @@ __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ d
 // y sweep + update on the stored pivots: Thomas in row order, segments of
 // ROWS rows chained through LDS (segment s runs once segment s-1 has handed
 // over d' of its last row); the only serial work per row is one FMA forward
-// and one backward.  Then U^{n+1} = U^n + D3.
+// and one backward.  Then U^{n+1} = U^n + D3.  Workgroup = yc_S waves; wave w
+// holds rows [w ROWS, (w+1) ROWS) of 64 consecutive lines (i, j), so row
+// reads are contiguous and the y-table reads are wave-uniform.
 template <int ROWS>
-__global__ __launch_bounds__(kBlock) void k_yc(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
+__global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
     extern __shared__ double lds_raw[];
     ldouble* lds = (ldouble*)lds_raw;
     const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const SolveDesc& s = descs[tk.x];
     const int nr = s.nr, nv = s.nv, ny = s.ny;
-    const int S = s.yc_S, L = s.yc_L;
+    const int S = s.yc_S;
     const int t = threadIdx.x;
-    const int l = t % L;
-    const int seg = t / L;
-    const int q = tk.y * L + l;  // line (i, j), q = j nr + i
+    const int l = t & 63;
+    const int seg = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int q = tk.y * 64 + l;  // line (i, j), q = j nr + i
     const bool active = seg < S && q < nr * nv;
     const int qc = active ? q : 0;
     const int j = qc / nr;
@@ -1260,32 +1280,37 @@ __global__ __launch_bounds__(kBlock) void k_yc(const SolveDesc* __restrict__ des
     gdouble* D = gp(s.D);
     gdouble* U = gp(s.U);
     gcdouble* CPg = gp(s.cp);
-    gcdouble* yt = gp(s.yt);
+    kcdouble* yt = kp(s.yt);
     const bool first = sg == 0;
     const bool last = sg == S - 1;
-    double d[ROWS], al[ROWS], cp[ROWS];
+    double d[ROWS], al[ROWS], cp[ROWS], u[ROWS];
 #pragma unroll
     for (int mm = 0; mm < ROWS; ++mm) {
         d[mm] = active ? D[off + (size_t)mm * sy] : 0.0;
         cp[mm] = active ? CPg[off + (size_t)mm * sy] : 0.0;
+        u[mm] = active ? U[off + (size_t)mm * sy] : 0.0;
     }
-    double cpm = (active && !first) ? CPg[off - sy] : 0.0;
-    RowY row;
-    row.yt = yt;
-    row.ny = ny;
-    row.qv = gp(s.rt)[RT_Y * nr + i] * gp(s.vt)[VT_V * nv + j];
+    const double cpm = (active && !first) ? CPg[off - sy] : 0.0;
+    const double qv = gp(s.rt)[RT_Y * nr + i] * gp(s.vt)[VT_V * nv + j];
+    auto row = [&](int kk, double& A, double& B, double& C, double& E) {
+        const double a = yt[YT_T1 * ny + kk] * qv + yt[YT_T2 * ny + kk];
+        A = yt[YT_MA * ny + kk] * a;
+        B = 1.0 + yt[YT_MB * ny + kk] * a;
+        C = yt[YT_MC * ny + kk] * a;
+        E = yt[YT_ME * ny + kk] * a;
+    };
     double d0 = 0.0, B0 = 1.0, C0 = 0.0, E0 = 0.0, dl = 0.0, Al = 0.0, Bl = 1.0, El = 0.0;
     double b1m = 1.0, a2m = 0.0, b2m = 1.0;
-    if (work && first) {
+    if (first) {
         double A0, A1, B1, C1, E1;
         row(0, A0, B0, C0, E0);
         row(1, A1, B1, C1, E1);
         const double f = A1 / B0;
         b1m = B1 - f * C0;
         d0 = d[0];
-        d[1] = d[1] - f * d0;
+        if (work) d[1] = d[1] - f * d0;
     }
-    if (work && last) {
+    if (last) {
         double Cl, A2, B2, C2, E2;
         row(ny - 1, Al, Bl, Cl, El);
         row(ny - 2, A2, B2, C2, E2);
@@ -1293,13 +1318,12 @@ __global__ __launch_bounds__(kBlock) void k_yc(const SolveDesc* __restrict__ des
         a2m = A2 - f * El;
         b2m = B2 - f * Al;
         dl = d[ROWS - 1];
-        d[ROWS - 2] = d[ROWS - 2] - f * dl;
+        if (work) d[ROWS - 2] = d[ROWS - 2] - f * dl;
     }
     bool ok = true;
     // pivots from the stored c'_{k-1}: den_k = B_k - A_k c'_{k-1}; the
     // recurrence becomes d'_k = d_k / den_k + (-A_k / den_k) d'_{k-1}
     // (lines on a Dirichlet r face keep D: identity rows)
-    if (work) {
 #pragma unroll
     for (int mm = 0; mm < ROWS; ++mm) {
         const int kk = sg * ROWS + mm;
@@ -1312,10 +1336,9 @@ __global__ __launch_bounds__(kBlock) void k_yc(const SolveDesc* __restrict__ des
         const double cprev = mm == 0 ? cpm : cp[mm - 1];
         const double den = B - A * cprev;
         const double inv = 1.0 / den;
-        ok = ok && den > 0.0;
-        al[mm] = -A * inv;
-        d[mm] = d[mm] * inv;
-    }
+        ok = ok && (!work || den > 0.0);
+        al[mm] = work ? -A * inv : 0.0;
+        d[mm] = work ? d[mm] * inv : d[mm];
     }
     ldouble* xch = lds + 2 * l;
     for (int stage = 0; stage < S; ++stage) {
@@ -1346,7 +1369,7 @@ __global__ __launch_bounds__(kBlock) void k_yc(const SolveDesc* __restrict__ des
     }
     if (active) {
 #pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm) U[off + (size_t)mm * sy] = U[off + (size_t)mm * sy] + d[mm];
+        for (int mm = 0; mm < ROWS; ++mm) U[off + (size_t)mm * sy] = u[mm] + d[mm];
     }
     if (work && !ok) raise_flag(s);
 }
@@ -1451,10 +1474,15 @@ hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_
     return hipGetLastError();
 }
 
-hipError_t launch_exp(const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st)
+hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_exp, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step);
+    switch (J) {
+    case 4: hipLaunchKernelGGL(k_exp<4>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 8: hipLaunchKernelGGL(k_exp<8>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 16: hipLaunchKernelGGL(k_exp<16>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1495,11 +1523,12 @@ hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines,
     return hipGetLastError();
 }
 
-hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st)
+hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    const size_t lds = (size_t)2 * kBlock * 8;
-    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_yc<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
+    if (S_max < 1 || S_max > yc_max_segments(rows)) return hipErrorInvalidValue;
+    const size_t lds = (size_t)2 * 64 * 8;
+    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_yc<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 

@@ -78,6 +78,8 @@ def lib():
         "hjm_batch_destroy": (st, [vp]),
         "hjm_set_line_tile": (st, [i32, i32, i32]),
         "hjm_get_line_tile": (st, [P(i32), P(i32), P(i32)]),
+        "hjm_set_explicit_chunk": (st, [i32]),
+        "hjm_get_explicit_chunk": (st, [P(i32)]),
         "hjm_status_str": (C.c_char_p, [st]),
         "hjm_last_error": (C.c_char_p, []),
     }
@@ -120,6 +122,17 @@ def get_line_tile():
     r, v, y = C.c_int32(), C.c_int32(), C.c_int32()
     check(lib().hjm_get_line_tile(C.byref(r), C.byref(v), C.byref(y)))
     return r.value, v.value, y.value
+
+
+def set_explicit_chunk(J: int) -> None:
+    """v nodes per thread of the explicit-predictor kernel (4, 8 or 16) for handles created afterwards."""
+    check(lib().hjm_set_explicit_chunk(J))
+
+
+def get_explicit_chunk() -> int:
+    J = C.c_int32()
+    check(lib().hjm_get_explicit_chunk(C.byref(J)))
+    return J.value
 
 
 def _torch():
