@@ -16,6 +16,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -81,6 +83,60 @@ def cpu_baseline(seconds: float):
             "sample": f"{done} Douglas steps of the 256x128x128 10-year caplet grid ({el:.1f} s)"}
 
 
+def calibration(hjm, W, torch, stream, n_solves: int, tune: bool):
+    """Calibration-style throughput: n_solves independent caplet solves with
+    uneven grids ({32,48,64,96} per axis, 50..200 steps, seeded parameters),
+    priced one by one (plain single-solve ADI) and as one batch replayed from
+    a HIP graph (line tiles chosen by the autotuner on the batch's shapes)."""
+    from paper_1108_1688_amd import autotune
+    specs = W.config4(n_solves)
+    old = hjm.get_line_tile(), hjm.get_explicit_chunk()
+    out = {"workload": f"{n_solves} caplet solves, grids from {{32,48,64,96}}^3, 50-200 steps (seed 3)",
+           "point_steps": int(sum(s.points * s.n_steps for s in specs))}
+    try:
+        if tune:
+            t = autotune.tune(specs, steps=4)
+            out["tuned_setting"] = list(t.setting)
+        # plain: one grid at a time, reusing one workspace
+        nbytes = max(hjm.workspace_bytes(s) for s in specs)
+        ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+        plain = []
+        for s in specs[:4]:  # warm-up
+            g = hjm.Grid(s, stream=stream, workspace=ws)
+            g.step()
+            g.price()
+            g.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in specs:
+            g = hjm.Grid(s, stream=stream, workspace=ws)
+            g.step()
+            plain.append(g.price())
+            g.close()
+        torch.cuda.synchronize()
+        el_plain = time.perf_counter() - t0
+        del ws
+        # batched, replayed from a HIP graph (captured on a stream of its own)
+        gstream = torch.cuda.Stream()
+        b = hjm.Batch(specs, stream=gstream)
+        b.run(graph=True)
+        b.prices()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(graph=True)
+        batched = b.prices()
+        el_batch = time.perf_counter() - t0
+        b.close()
+        plain = np.array(plain)
+        out.update({"plain_solves_per_s": n_solves / el_plain, "batched_graph_solves_per_s": n_solves / el_batch,
+                    "batched_speedup": el_plain / el_batch,
+                    "max_rel_diff_batched_vs_plain": float(np.max(np.abs(batched - plain) / np.abs(plain)))})
+    finally:
+        hjm.set_line_tile(*old[0])
+        hjm.set_explicit_chunk(old[1])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +144,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-calibration", action="store_true", help="skip the batched calibration throughput")
+    ap.add_argument("--calib-solves", type=int, default=512)
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
     ap.add_argument("--exp-chunk", type=int, default=None, help="v nodes per explicit-kernel thread (4, 8, 16)")
     args = ap.parse_args()
@@ -177,6 +235,9 @@ def main():
                       "explicit_chunk": hjm.get_explicit_chunk(),
                       "parallelism": "single GPU"},
            "roofline": roofline}
+    if not args.no_calibration:
+        out["calibration"] = calibration(hjm, W, torch, stream, args.calib_solves, tune=True)
+        log(f"calibration: {out['calibration']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

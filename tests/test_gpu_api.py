@@ -88,9 +88,11 @@ def test_stream_argument_is_used():
 
 def _batch_specs():
     specs = W.config4(n=12, seed=7)
-    # shrink the step counts so the test stays short; shapes stay uneven
+    # shrink most step counts so the test stays short (long steps put the r
+    # lines on the chained solve); two keep theirs (split r solve); shapes stay
+    # uneven, so the batch mixes every kernel variant
     from dataclasses import replace
-    return [replace(sp, n_steps=max(3, sp.n_steps // 10)) for sp in specs]
+    return [replace(sp, n_steps=max(3, sp.n_steps // 10)) for sp in specs[:10]] + specs[10:]
 
 
 def test_batch_equals_single_solves_bitwise():
