@@ -198,6 +198,60 @@ hjm_status hjm_batch_destroy(hjm_batch* b);
 hjm_status hjm_set_line_tile(int32_t r_rows, int32_t v_rows, int32_t y_rows);
 hjm_status hjm_get_line_tile(int32_t* r_rows, int32_t* v_rows, int32_t* y_rows);
 
+/* ---------------------------------------------------------------------- */
+/* Learned surrogate (caplet prices inside a box of model inputs).          */
+/* ---------------------------------------------------------------------- */
+/* An MLP 8 -> 256 -> 256 -> 256 -> 256 -> 1 with GELU activations, trained on
+   the solver's own prices.  Inputs (float32, 8 per row, physical units):
+   kappa, epsilon, rho, v0, curve level, curve slope, strike offset from the
+   at-the-money strike, expiry.  Each is mapped to [-1, 1] over the training
+   box; matrix products take BF16 operands and accumulate in FP32 on the matrix
+   cores; master weights, biases, gradients and Adam state are FP32.  The
+   network output y is reported as y * out_scale + out_shift.  Parameters are
+   one float32 vector of HJM_MLP_PARAMS: W1 (256 x 8), b1, W2 (256 x 256), b2,
+   W3, b3, W4, b4, w5 (256), b5, weights row-major (output x input).  All device
+   memory (parameters, optimiser state, activations for up to max_batch rows)
+   lives in the caller's workspace. */
+typedef struct hjm_mlp hjm_mlp;
+#define HJM_MLP_PARAMS 199937
+
+/* Workspace bytes for batches of up to max_batch rows (1 <= max_batch <= 2^26). */
+hjm_status hjm_mlp_workspace_bytes(int64_t max_batch, size_t* bytes);
+
+/* Create with the training box (lo < hi per input) and the output map; the
+   parameters start at zero (set them with hjm_mlp_set_params).  Synchronises. */
+hjm_status hjm_mlp_create(const float box_lo[8], const float box_hi[8], float out_scale, float out_shift,
+                          int64_t max_batch, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                          hjm_mlp** out);
+
+/* Copy HJM_MLP_PARAMS host floats in (resets the Adam state) or out. */
+hjm_status hjm_mlp_set_params(hjm_mlp* m, const float* params, int64_t n);
+hjm_status hjm_mlp_get_params(hjm_mlp* m, float* params, int64_t n);
+
+/* Loss and gradients of the mean squared error over n <= max_batch rows:
+   d_x (n x 8 float32, device), d_t (n targets in network units, device).
+   The gradient stays in the workspace (read it with hjm_mlp_get_grads);
+   *sse (may be null) receives the summed squared error, synchronising. */
+hjm_status hjm_mlp_gradients(hjm_mlp* m, const float* d_x, const float* d_t, int64_t n, double* sse);
+hjm_status hjm_mlp_get_grads(hjm_mlp* m, float* grads, int64_t n);
+
+/* One Adam step (Kingma and Ba) with the current gradient. */
+hjm_status hjm_mlp_adam(hjm_mlp* m, float lr, float beta1, float beta2, float eps);
+
+/* One pass over n rows in minibatches of `batch` rows, in order (shuffle the
+   rows beforehand): gradients then Adam (beta 0.9, 0.999, eps 1e-8) per
+   minibatch.  *mean_loss (may be null) receives the mean squared error seen. */
+hjm_status hjm_mlp_train_epoch(hjm_mlp* m, const float* d_x, const float* d_t, int64_t n, int64_t batch,
+                               float lr, double* mean_loss);
+
+/* Prices of n rows (any n; processed max_batch rows at a time): d_y[r] =
+   network(d_x[r]) * out_scale + out_shift, and d_in_box[r] = 1 where every
+   input lies inside the training box, else 0 (there the caller falls back to
+   the solver; d_in_box may be null).  Asynchronous. */
+hjm_status hjm_mlp_infer(hjm_mlp* m, const float* d_x, int64_t n, float* d_y, uint8_t* d_in_box);
+
+hjm_status hjm_mlp_destroy(hjm_mlp* m);
+
 /* Nodes along v that one thread of the explicit-predictor kernel computes
    (4, 8 or 16; HJM_EINVAL otherwise).  Process-wide, read when a grid or
    batch is created, like the line tile. */

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhjm.so")
-SOURCES = ["hjm_kernels.hip", "hjm_host.hip"]
+SOURCES = ["hjm_kernels.hip", "hjm_host.hip", "hjm_mlp.hip"]
 RUNNER = os.path.join(HERE, "hjm_run")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

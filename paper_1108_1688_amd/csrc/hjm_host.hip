@@ -2,6 +2,7 @@
 // line-solve tiling, workspace layout and the C ABI of include/hjm.h.
 #include "hjm.h"
 #include "hjm_internal.h"
+#include "hjm_mlp.h"
 
 #include <algorithm>
 #include <cmath>
@@ -743,6 +744,12 @@ GridLayout grid_layout(const hjm_axis ax[3], int n_steps)
 }
 
 }  // namespace
+
+int32_t hjm::report_error(int32_t code, const char* msg)
+{
+    g_last_error = msg;
+    return code;
+}
 
 extern "C" {
 

@@ -22,6 +22,7 @@ BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
 N_PASSES = 4  # HJM_N_PASSES
 PASSES = ("explicit", "r", "v", "y+update")
 R_METHODS = ("spike", "chain", "split")
+MLP_PARAMS = 199937  # HJM_MLP_PARAMS
 
 
 class HjmError(RuntimeError):
@@ -80,6 +81,16 @@ def lib():
         "hjm_get_line_tile": (st, [P(i32), P(i32), P(i32)]),
         "hjm_set_explicit_chunk": (st, [i32]),
         "hjm_get_explicit_chunk": (st, [P(i32)]),
+        "hjm_mlp_workspace_bytes": (st, [i64, P(sz)]),
+        "hjm_mlp_create": (st, [P(C.c_float), P(C.c_float), C.c_float, C.c_float, i64, vp, sz, vp, P(vp)]),
+        "hjm_mlp_set_params": (st, [vp, P(C.c_float), i64]),
+        "hjm_mlp_get_params": (st, [vp, P(C.c_float), i64]),
+        "hjm_mlp_gradients": (st, [vp, vp, vp, i64, P(d)]),
+        "hjm_mlp_get_grads": (st, [vp, P(C.c_float), i64]),
+        "hjm_mlp_adam": (st, [vp, C.c_float, C.c_float, C.c_float, C.c_float]),
+        "hjm_mlp_train_epoch": (st, [vp, vp, vp, i64, i64, C.c_float, P(d)]),
+        "hjm_mlp_infer": (st, [vp, vp, i64, vp, vp]),
+        "hjm_mlp_destroy": (st, [vp]),
         "hjm_status_str": (C.c_char_p, [st]),
         "hjm_last_error": (C.c_char_p, []),
     }
@@ -297,6 +308,94 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib().hjm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The surrogate network: parameters, optimiser state and activations in a
+    workspace tensor, work on a torch stream.  Inputs are float32 (n, 8)
+    device tensors in physical units; targets are in network units."""
+
+    def __init__(self, box_lo, box_hi, out_scale: float, out_shift: float = 0.0, max_batch: int = 65536,
+                 stream=None, device: Optional[str] = None):
+        torch = _torch()
+        L = lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.box_lo = np.asarray(box_lo, dtype=np.float32)
+        self.box_hi = np.asarray(box_hi, dtype=np.float32)
+        self.out_scale, self.out_shift, self.max_batch = float(out_scale), float(out_shift), int(max_batch)
+        nbytes = C.c_size_t()
+        check(L.hjm_mlp_workspace_bytes(self.max_batch, C.byref(nbytes)))
+        self.ws = _workspace(nbytes.value, self.device)
+        fp = C.POINTER(C.c_float)
+        h = C.c_void_p()
+        check(L.hjm_mlp_create(self.box_lo.ctypes.data_as(fp), self.box_hi.ctypes.data_as(fp), self.out_scale,
+                               self.out_shift, self.max_batch, C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                               _stream_handle(self.stream), C.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def _f32(a: np.ndarray):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+    def set_params(self, params: np.ndarray) -> None:
+        a, ptr = self._f32(params)
+        check(lib().hjm_mlp_set_params(self._h, ptr, a.size))
+
+    def params(self) -> np.ndarray:
+        a = np.empty(MLP_PARAMS, dtype=np.float32)
+        check(lib().hjm_mlp_get_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    @staticmethod
+    def _dev(t, cols=None):
+        torch = _torch()
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("expected a contiguous float32 CUDA tensor")
+        if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+            raise ValueError(f"expected shape (n, {cols})")
+        return C.c_void_p(t.data_ptr())
+
+    def gradients(self, x, t) -> float:
+        """Summed squared error; the gradient stays on the device (grads())."""
+        sse = C.c_double()
+        check(lib().hjm_mlp_gradients(self._h, self._dev(x, 8), self._dev(t), x.shape[0], C.byref(sse)))
+        return sse.value
+
+    def grads(self) -> np.ndarray:
+        a = np.empty(MLP_PARAMS, dtype=np.float32)
+        check(lib().hjm_mlp_get_grads(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size))
+        return a
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+        check(lib().hjm_mlp_adam(self._h, lr, beta1, beta2, eps))
+
+    def train_epoch(self, x, t, batch: int, lr: float) -> float:
+        loss = C.c_double()
+        check(lib().hjm_mlp_train_epoch(self._h, self._dev(x, 8), self._dev(t), x.shape[0], batch, lr,
+                                        C.byref(loss)))
+        return loss.value
+
+    def infer(self, x):
+        """(prices, in_box) device tensors for the rows of x."""
+        torch = _torch()
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        inb = torch.empty(n, dtype=torch.uint8, device=x.device)
+        check(lib().hjm_mlp_infer(self._h, self._dev(x, 8), n, C.c_void_p(y.data_ptr()), C.c_void_p(inb.data_ptr())))
+        return y, inb
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().hjm_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

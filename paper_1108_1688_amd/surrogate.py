@@ -1,0 +1,129 @@
+"""Learned surrogate of the caplet price, trained on the Douglas-ADI solver.
+
+Workflow (each step runs in the library's kernels; this module only moves
+arguments):
+  training_set   ADI solves at 64^3 (batched), 16 readouts v0 per solve;
+  init_params    seeded initial weights (an input of the training, so that a
+                 reference computation can start from the same point);
+  fit            epochs of shuffled minibatches (GPU forward, backward, Adam);
+  price          surrogate inside the training box, ADI outside it.
+
+Inputs per row: kappa, epsilon, rho, v0, curve level, curve slope, strike
+offset from the at-the-money strike, expiry (the caplet pays one year after
+expiry); the network predicts price / OUT_SCALE.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import hjm
+from . import workloads as W
+
+OUT_SCALE = 1e-3  # network units: prices in units of 1e-3
+
+
+def init_params(seed: int) -> np.ndarray:
+    """Seeded initial parameters: weights N(0, 2 / fan_in), biases zero
+    (fan-in scaling for GELU layers); the output layer N(0, 1 / 256)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((256, 8), (256, 256), (256, 256), (256, 256)):
+        parts.append(rng.standard_normal((fan_out, fan_in)).ravel() * math.sqrt(2.0 / fan_in))
+        parts.append(np.zeros(fan_out))
+    parts.append(rng.standard_normal(256) / 16.0)
+    parts.append(np.zeros(1))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == hjm.MLP_PARAMS
+    return p
+
+
+def training_set(n_solves: int, seed: int, n: int = W.SURROGATE_N, chunk: int = 256, stream=None):
+    """Inputs (n_solves * 16, 8) float32 and ADI prices (float64): every solve
+    is read out at the 16 values of W.SURROGATE_V0."""
+    params = W.surrogate_params(n_solves, seed)
+    xs, ps = [], []
+    v0s = np.array(W.SURROGATE_V0)
+    for c0 in range(0, n_solves, chunk):
+        rows = params[c0:c0 + chunk]
+        specs = [W.surrogate_solve(x, n) for x in rows]
+        b = hjm.Batch(specs, stream=stream)
+        b.run()
+        r0 = np.array([s.r0 for s in specs])
+        for v0 in v0s:
+            prices = b.prices(r0, np.full(len(specs), v0))
+            x = rows.copy()
+            x[:, 3] = v0
+            xs.append(x)
+            ps.append(prices)
+        b.close()
+    return np.concatenate(xs).astype(np.float32), np.concatenate(ps)
+
+
+def adi_prices(x: np.ndarray, n: int = W.SURROGATE_N, chunk: int = 256, stream=None) -> np.ndarray:
+    """Reference prices of arbitrary rows by the ADI solver (one solve per row)."""
+    out = np.empty(len(x))
+    for c0 in range(0, len(x), chunk):
+        rows = x[c0:c0 + chunk]
+        specs = [W.surrogate_solve(r, n) for r in rows]
+        b = hjm.Batch(specs, stream=stream)
+        b.run()
+        out[c0:c0 + chunk] = b.prices()
+        b.close()
+    return out
+
+
+def make_mlp(max_batch: int = 65536, stream=None) -> hjm.Mlp:
+    return hjm.Mlp(W.SURROGATE_BOX_LO, W.SURROGATE_BOX_HI, OUT_SCALE, 0.0, max_batch=max_batch, stream=stream)
+
+
+@dataclass
+class FitResult:
+    losses: list
+    seconds: float
+
+
+def fit(mlp: hjm.Mlp, x: np.ndarray, prices: np.ndarray, epochs: int, batch: int = 1024, lr: float = 1e-3,
+        lr_final: Optional[float] = None, seed: int = 0) -> FitResult:
+    """Train on (x, prices): per epoch the rows are shuffled (seeded) on the
+    host and one GPU pass over minibatches runs; the learning rate decays
+    geometrically from lr to lr_final."""
+    import torch
+    dev = mlp.device
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    td = torch.from_numpy((prices / OUT_SCALE).astype(np.float32)).to(dev)
+    rng = np.random.default_rng(seed)
+    losses = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        rate = lr if lr_final is None or epochs == 1 else lr * (lr_final / lr) ** (ep / (epochs - 1))
+        perm = torch.from_numpy(rng.permutation(len(x))).to(dev)
+        xe = xd.index_select(0, perm).contiguous()
+        te = td.index_select(0, perm).contiguous()
+        losses.append(mlp.train_epoch(xe, te, batch, rate))
+    torch.cuda.synchronize(dev)
+    return FitResult(losses, time.perf_counter() - t0)
+
+
+@dataclass
+class Priced:
+    prices: np.ndarray     # float64
+    in_box: np.ndarray     # bool
+    n_fallback: int
+
+
+def price(mlp: hjm.Mlp, x: np.ndarray, n: int = W.SURROGATE_N, stream=None) -> Priced:
+    """Surrogate prices inside the training box, ADI prices outside it."""
+    import torch
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(mlp.device)
+    y, inb = mlp.infer(xd)
+    out = y.double().cpu().numpy()
+    inside = inb.cpu().numpy().astype(bool)
+    outside = np.nonzero(~inside)[0]
+    if len(outside):
+        out[outside] = adi_prices(x[outside].astype(np.float64), n=n, stream=stream)
+    return Priced(out, inside, len(outside))

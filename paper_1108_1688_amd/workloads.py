@@ -188,17 +188,23 @@ def surrogate_params(n_solves: int, seed: int) -> np.ndarray:
     return SURROGATE_BOX_LO + (SURROGATE_BOX_HI - SURROGATE_BOX_LO) * rng.random((n_solves, 8))
 
 
+# Coordinates that can leave the box while the problem stays valid for the
+# solver (|rho| <= 1, epsilon >= 0, a forward curve that keeps the r = 0 face
+# outflowing, a positive strike): (column, side) with side -1 below the box,
+# +1 above.
+_OUTSIDE_MOVES = ((0, +1), (3, -1), (3, +1), (4, +1), (6, +1), (7, +1))
+
+
 def surrogate_outside(n: int, seed: int) -> np.ndarray:
-    """Rows with one coordinate pushed outside the box (fallback routing test)."""
+    """Rows with one coordinate pushed 5-30 % of its span outside the box
+    (fallback routing test); only moves that keep the problem valid."""
     rng = np.random.default_rng(seed)
     x = surrogate_params(n, seed + 1000)
     span = SURROGATE_BOX_HI - SURROGATE_BOX_LO
     for r in range(n):
-        c = int(rng.integers(0, 8))
-        if rng.random() < 0.5:
-            x[r, c] = SURROGATE_BOX_LO[c] - span[c] * float(rng.uniform(0.05, 0.3))
-        else:
-            x[r, c] = SURROGATE_BOX_HI[c] + span[c] * float(rng.uniform(0.05, 0.3))
+        c, side = _OUTSIDE_MOVES[int(rng.integers(0, len(_OUTSIDE_MOVES)))]
+        d = span[c] * float(rng.uniform(0.05, 0.3))
+        x[r, c] = SURROGATE_BOX_LO[c] - d if side < 0 else SURROGATE_BOX_HI[c] + d
     return x
 
 
