@@ -137,6 +137,48 @@ def calibration(hjm, W, torch, stream, n_solves: int, tune: bool):
     return out
 
 
+def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int, outside_frac: float):
+    """Surrogate pricing: train on ADI prices (n_train_solves solves at 64^3,
+    16 readouts each), then price n_query rows, a fraction outside the box
+    (priced by ADI), and state the surrogate's error against ADI on rows in
+    the box."""
+    from paper_1108_1688_amd import surrogate as S
+    t0 = time.perf_counter()
+    x, prices = S.training_set(n_train_solves, seed=21)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    m = S.make_mlp(max_batch=65536)
+    m.set_params(S.init_params(22))
+    fitres = S.fit(m, x, prices, epochs=epochs, batch=1024, lr=2e-3, lr_final=1e-4, seed=23)
+    # queries: fresh rows in the box plus a fraction pushed outside it
+    n_out = int(round(outside_frac * n_query))
+    xq = W.surrogate_params(n_query, seed=24)
+    if n_out:
+        xq[:n_out] = W.surrogate_outside(n_out, seed=25)
+    xq = xq.astype(np.float32)
+    S.price(m, xq[:1024])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pr = S.price(m, xq)
+    el = time.perf_counter() - t0
+    # error against ADI on in-box rows (validation solves read out at v0)
+    nv = 256
+    xv = xq[n_out:n_out + nv].astype(np.float64)
+    ref = S.adi_prices(xv)
+    err = np.abs(pr.prices[n_out:n_out + nv] - ref)
+    big = ref > 1e-4
+    m.close()
+    return {"train_rows": int(len(x)), "train_solves": n_train_solves, "epochs": epochs,
+            "train_data_s": round(t_data, 2), "train_s": round(fitres.seconds, 2),
+            "final_train_mse_net_units": fitres.losses[-1],
+            "query_rows": n_query, "fallback_rows": pr.n_fallback,
+            "solves_per_s": n_query / el,
+            "error_vs_adi": {"rows": nv, "rms_abs": float(np.sqrt(np.mean(err ** 2))),
+                             "median_rel": float(np.median(err[big] / ref[big])),
+                             "p95_rel": float(np.percentile(err[big] / ref[big], 95)),
+                             "rel_rows": "prices above 1e-4"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +188,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-calibration", action="store_true", help="skip the batched calibration throughput")
     ap.add_argument("--calib-solves", type=int, default=512)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg of the calibration")
+    ap.add_argument("--sur-solves", type=int, default=4096, help="ADI solves for the surrogate's training set")
+    ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
     ap.add_argument("--exp-chunk", type=int, default=None, help="v nodes per explicit-kernel thread (4, 8, 16)")
     args = ap.parse_args()
@@ -237,6 +282,11 @@ def main():
            "roofline": roofline}
     if not args.no_calibration:
         out["calibration"] = calibration(hjm, W, torch, stream, args.calib_solves, tune=True)
+        if not args.no_surrogate:
+            out["calibration"]["surrogate"] = surrogate_leg(hjm, W, torch, args.sur_solves, args.sur_epochs,
+                                                            65536, 0.01)
+            plain = out["calibration"]["plain_solves_per_s"]
+            out["calibration"]["surrogate_speedup_vs_plain"] = out["calibration"]["surrogate"]["solves_per_s"] / plain
         log(f"calibration: {out['calibration']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
