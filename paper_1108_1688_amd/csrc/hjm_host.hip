@@ -880,7 +880,7 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
                 e0 = g->events[2 * g->ev_used];
                 e1 = g->events[2 * g->ev_used + 1];
                 g->ev_pass[g->ev_used] = pass;
-                if ((e = hipEventRecord(e0, g->stream))) return hip_fail(e, "hipEventRecord");
+                set_launch_events(e0, e1);
             }
             if (pass == 0 && split) e = launch_exp(p.exp_J, g->d_desc, nullptr, p.exp_tiles, n, g->stream);
             else if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
@@ -891,7 +891,7 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
             else e = launch_yu(g->rows[2], g->d_desc, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {
-                if ((e = hipEventRecord(e1, g->stream))) return hip_fail(e, "hipEventRecord");
+                set_launch_events(nullptr, nullptr);  // a launch with no tiles records nothing
                 g->ev_used += 1;
             }
         }

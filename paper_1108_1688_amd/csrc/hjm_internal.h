@@ -130,6 +130,10 @@ struct Readout {
     double wv[4];
 };
 
+// Record the next sweep launch of the calling thread between these two
+// events (written by the dispatch itself; used for per-kernel timing).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 // Raise the dynamic-LDS limit of every sweep kernel (once per process).
 hipError_t init_kernel_attributes();
 

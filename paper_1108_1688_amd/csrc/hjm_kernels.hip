@@ -47,6 +47,8 @@
 // independent solves of different shapes (batched mode); a null task list
 // means one solve whose tile index is the workgroup index.
 
+#include <hip/hip_ext.h>
+
 #include "hjm_internal.h"
 
 namespace hjm {
@@ -1409,6 +1411,26 @@ hipError_t allow_lds(K kernel)
 
 }  // namespace
 
+// Timing events for the next sweep launch of this thread (profiling): the
+// dispatch itself records them, so they bracket exactly the kernel.
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop)
+{
+    g_ev_start = start;
+    g_ev_stop = stop;
+}
+
+#define HJM_LAUNCH(K, GRID, BLOCK, LDS, ST, ...)                                                     \
+    do {                                                                                             \
+        if (g_ev_start) {                                                                            \
+            hipExtLaunchKernelGGL(K, GRID, BLOCK, LDS, ST, g_ev_start, g_ev_stop, 0, __VA_ARGS__);   \
+            g_ev_start = g_ev_stop = nullptr;                                                        \
+        } else {                                                                                     \
+            hipLaunchKernelGGL(K, GRID, BLOCK, LDS, ST, __VA_ARGS__);                                \
+        }                                                                                            \
+    } while (0)
+
 hipError_t init_kernel_attributes()
 {
     static hipError_t status = [] {
@@ -1463,14 +1485,14 @@ hipError_t launch_xr(int rows, const SolveDesc* d_desc, const int2* tasks, int n
                      hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_xr<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step))
+    HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_xr<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step))
     return hipGetLastError();
 }
 
 hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, size_t lds, hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_v<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
+    HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_v<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 
@@ -1478,9 +1500,9 @@ hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_t
 {
     if (n_tasks <= 0) return hipSuccess;
     switch (J) {
-    case 4: hipLaunchKernelGGL(k_exp<4>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
-    case 8: hipLaunchKernelGGL(k_exp<8>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
-    case 16: hipLaunchKernelGGL(k_exp<16>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 4: HJM_LAUNCH(k_exp<4>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 8: HJM_LAUNCH(k_exp<8>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 16: HJM_LAUNCH(k_exp<16>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1494,10 +1516,10 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     if (n_tasks <= 0) return hipSuccess;
     const size_t lds = (size_t)kRF * nr_max * 8 + (size_t)kBlock * 8 * 8;
     switch (rows) {
-    case 6: hipLaunchKernelGGL(k_rs<6>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
-    case 8: hipLaunchKernelGGL(k_rs<8>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
-    case 12: hipLaunchKernelGGL(k_rs<12>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
-    case 16: hipLaunchKernelGGL(k_rs<16>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 6: HJM_LAUNCH(k_rs<6>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 8: HJM_LAUNCH(k_rs<8>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 12: HJM_LAUNCH(k_rs<12>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 16: HJM_LAUNCH(k_rs<16>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1511,7 +1533,7 @@ hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     if (n_tasks <= 0) return hipSuccess;
     if (S_max < 1 || S_max > 4) return hipErrorInvalidValue;
     const size_t lds = (size_t)2 * 4 * 64 * 8;
-    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_vs<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
+    HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_vs<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 
@@ -1528,14 +1550,14 @@ hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     if (n_tasks <= 0) return hipSuccess;
     if (S_max < 1 || S_max > yc_max_segments(rows)) return hipErrorInvalidValue;
     const size_t lds = (size_t)2 * 64 * 8;
-    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_yc<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
+    HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_yc<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 
 hipError_t launch_yu(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, size_t lds, hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    HJM_DISPATCH_ROWS(rows, hipLaunchKernelGGL(k_yu<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
+    HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_yu<R>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks))
     return hipGetLastError();
 }
 
