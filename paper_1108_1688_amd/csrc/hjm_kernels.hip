@@ -82,6 +82,19 @@ __device__ __forceinline__ double dirichlet_value(const SolveDesc& s, gcdouble* 
     return lin;
 }
 
+// 1/x for the positive pivots of the line solves: the hardware estimate
+// refined by two Newton-Raphson steps r <- r + r (1 - x r) (each doubles the
+// number of correct bits), a few ulps from the correctly rounded quotient at
+// half the instructions of the IEEE division sequence.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ void raise_flag(const SolveDesc& s)
 {
     // vector store of a constant; concurrent writers store the same value
@@ -990,15 +1003,18 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     const int k = q / nv;
     const int j = q - k * nv;
     const bool store = active && !(s.y_hi_dir && k == ny - 1);
-    ldouble* tab = lds;                          // [kRF][ROWS][S]
-    ldouble* red = lds + (size_t)kRF * nr;       // 8 doubles per thread
+    // row table, one block per segment: [seg][kRF * ROWS + 1] (the odd pitch
+    // spreads the segments of a wave over the LDS banks)
+    constexpr int TP = kRF * ROWS + 1;
+    ldouble* tab = lds;
+    ldouble* red = lds + (size_t)TP * S;  // 8 doubles per thread
     gcdouble* rf = gp(s.rf);
     for (int idx = t; idx < kRF * nr; idx += kBlock) {
         const int c6 = idx / nr;
         const int i = idx - c6 * nr;
         const int sg = i / ROWS;
         const int mm = i - sg * ROWS;
-        tab[(c6 * ROWS + mm) * S + sg] = rf[idx];
+        tab[sg * TP + c6 * ROWS + mm] = rf[idx];
     }
     __syncthreads();
 
@@ -1008,12 +1024,13 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     double d[ROWS];
 #pragma unroll
     for (int mm = 0; mm < ROWS; ++mm) d[mm] = line[mm];
+    const ldouble* tseg = tab + seg * TP;
     auto coef = [&](int mm, double& A, double& B, double& C) {
-        const ldouble* tb = tab + mm * S + seg;
-        const double e = tb[RF_P * ROWS * S] * c + tb[RF_Q * ROWS * S];
-        A = tb[RF_ALO * ROWS * S] * v + e;
-        B = tb[RF_ADI * ROWS * S] * v + tb[RF_B * ROWS * S];
-        C = tb[RF_AUP * ROWS * S] * v - e;
+        const ldouble* tb = tseg + mm;
+        const double e = tb[RF_P * ROWS] * c + tb[RF_Q * ROWS];
+        A = tb[RF_ALO * ROWS] * v + e;
+        B = tb[RF_ADI * ROWS] * v + tb[RF_B * ROWS];
+        C = tb[RF_AUP * ROWS] * v - e;
     };
     const bool first = seg == 0;
     const bool last = seg == S - 1;
@@ -1060,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
         if (mm == ROWS - 2) { A = last ? a2 : A; B = last ? b2 : B; C = last ? 0.0 : C; }
         if (mm == ROWS - 1) { A = last ? 0.0 : A; B = last ? 1.0 : B; C = last ? 0.0 : C; }
         const double den = B - A * cprev;
-        const double inv = 1.0 / den;
+        const double inv = rcp_nr(den);
         ok = ok && den > 0.0;
         cprev = C * inv;
         yprev = (d[mm] - A * yprev) * inv;
@@ -1088,12 +1105,13 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
             // forward: L_s = alp + bet F_{s+1}, F_s = gam + del F_{s+1}
             ldouble* r0 = red + t * 8;  // this lane is the line's segment 0
             double alp = 0.0, bet = 0.0;
+#pragma unroll 4
             for (int qq = 0; qq < S; ++qq) {
                 ldouble* r = r0 + qq * 8;
                 const double yF = r[0], vF = r[1], wF = r[2], yL = r[3], vL = r[4], wL = r[5];
                 const double den = 1.0 + vF * bet;
                 ok = ok && den > 0.0;
-                const double inv = 1.0 / den;
+                const double inv = rcp_nr(den);
                 const double gam = (yF - vF * alp) * inv;
                 const double del = -wF * inv;
                 alp = yL - vL * alp - vL * bet * gam;
@@ -1101,6 +1119,7 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
                 r[0] = gam; r[1] = del; r[2] = alp; r[3] = bet;
             }
             double Fn = 0.0, Lp = 0.0;
+#pragma unroll 4
             for (int qq = S - 1; qq >= 0; --qq) {
                 ldouble* r = r0 + qq * 8;
                 const double F = r[0] + r[1] * Fn;
@@ -1337,7 +1356,7 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
         if (mm == ROWS - 1) { A = last ? 0.0 : A; B = last ? 1.0 : B; }
         const double cprev = mm == 0 ? cpm : cp[mm - 1];
         const double den = B - A * cprev;
-        const double inv = 1.0 / den;
+        const double inv = rcp_nr(den);
         ok = ok && (!work || den > 0.0);
         al[mm] = work ? -A * inv : 0.0;
         d[mm] = work ? d[mm] * inv : d[mm];
@@ -1514,7 +1533,9 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
                      hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    const size_t lds = (size_t)kRF * nr_max * 8 + (size_t)kBlock * 8 * 8;
+    // row table (kRF * ROWS + 1 per segment, at most nr_max / ROWS + 1
+    // segments) and 8 doubles per thread for the reduced systems
+    const size_t lds = ((size_t)kRF * nr_max + (size_t)(nr_max / rows + 1) * (kRF + 1)) * 8 + (size_t)kBlock * 8 * 8;
     switch (rows) {
     case 6: HJM_LAUNCH(k_rs<6>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
     case 8: HJM_LAUNCH(k_rs<8>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
