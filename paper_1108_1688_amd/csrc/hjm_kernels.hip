@@ -1003,6 +1003,14 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     const int k = q / nv;
     const int j = q - k * nv;
     const bool store = active && !(s.y_hi_dir && k == ny - 1);
+    // the line's rows first, so that their loads are in flight while the row
+    // table is staged
+    const double v = gp(s.vt)[VT_V * nv + j];
+    const double c = gp(s.st)[kStepStride * step + ST_PHI] + gp(s.yt)[YT_Y * ny + k];
+    gdouble* line = gp(s.D) + (size_t)q * nr + (size_t)seg * ROWS;
+    double d[ROWS];
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) d[mm] = line[mm];
     // row table, one block per segment: [seg][kRF * ROWS + 1] (the odd pitch
     // spreads the segments of a wave over the LDS banks)
     constexpr int TP = kRF * ROWS + 1;
@@ -1017,13 +1025,6 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
         tab[sg * TP + c6 * ROWS + mm] = rf[idx];
     }
     __syncthreads();
-
-    const double v = gp(s.vt)[VT_V * nv + j];
-    const double c = gp(s.st)[kStepStride * step + ST_PHI] + gp(s.yt)[YT_Y * ny + k];
-    gdouble* line = gp(s.D) + (size_t)q * nr + (size_t)seg * ROWS;
-    double d[ROWS];
-#pragma unroll
-    for (int mm = 0; mm < ROWS; ++mm) d[mm] = line[mm];
     const ldouble* tseg = tab + seg * TP;
     auto coef = [&](int mm, double& A, double& B, double& C) {
         const ldouble* tb = tseg + mm;
