@@ -186,6 +186,16 @@ hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph);
    at (r0[s], v0[s]) as hjm_price does. */
 hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, double* out);
 
+/* Per-kernel timing of eager runs (hjm_batch_run with use_graph = 0): every
+   launch of the first `steps` Douglas steps is bracketed by HIP events the
+   dispatch records (0 turns it off; graph runs are never timed).  The read
+   synchronises and returns, per pass (as for grids), the summed milliseconds,
+   the launches and the grid points those launches advanced by one step; the
+   sums restart from zero. */
+hjm_status hjm_batch_profile(hjm_batch* b, int32_t steps);
+hjm_status hjm_batch_profile_read(hjm_batch* b, double ms[HJM_N_PASSES], int64_t launches[HJM_N_PASSES],
+                                  int64_t points[HJM_N_PASSES]);
+
 hjm_status hjm_batch_destroy(hjm_batch* b);
 
 /* ---------------------------------------------------------------------- */

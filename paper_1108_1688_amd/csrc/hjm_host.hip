@@ -996,6 +996,7 @@ struct LaunchGroup {
     size_t off = 0;           // first task in the batch's task array
     std::vector<int2> tasks;
     std::vector<int> cnt;     // active task prefix per step
+    std::vector<int64_t> pts; // grid points of the solves active per step
     size_t lds = 0;           // dynamic LDS (k_xr, k_v, k_yu)
     int aux = 0;              // k_rs: largest nr; k_vs: most segments
 };
@@ -1021,6 +1022,16 @@ struct hjm_batch {
     bool ran = false;
     std::vector<Readout> rq;
     std::vector<int32_t> flags_host;
+    // per-kernel timing of the first profile_steps steps of eager runs
+    int profile_steps = 0;
+    std::vector<hipEvent_t> events;  // pool, 2 per timed launch
+    std::vector<int> ev_pass;
+    std::vector<int64_t> ev_pts;
+    size_t ev_used = 0;
+    ~hjm_batch()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -1070,13 +1081,44 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step)
     }
 }
 
-hjm_status batch_enqueue(hjm_batch* b)
+int group_pass(int kind)
+{
+    switch (kind) {
+    case G_XR: case G_EXP: return 0;
+    case G_RS: return 1;
+    case G_V: case G_VS: return 2;
+    default: return 3;
+    }
+}
+
+hjm_status batch_enqueue(hjm_batch* b, bool timed)
 {
     hipError_t e;
     if ((e = launch_terminal(b->d_desc, b->n, b->max_points, b->stream))) return hip_fail(e, "batch terminal");
     for (int step = 0; step < b->max_steps; ++step)
-        for (const LaunchGroup& g : b->groups)  // groups are in step-pass order
-            if ((e = launch_group(b, g, step))) return hip_fail(e, "batch step");
+        for (const LaunchGroup& g : b->groups) {  // groups are in step-pass order
+            const bool time_it = timed && step < b->profile_steps && g.cnt[step] > 0;
+            if (time_it) {
+                if (b->events.size() < 2 * (b->ev_used + 1)) {
+                    for (int q = 0; q < 2; ++q) {
+                        hipEvent_t ev;
+                        if ((e = hipEventCreate(&ev))) return hip_fail(e, "batch profile events");
+                        b->events.push_back(ev);
+                    }
+                    b->ev_pass.resize(b->events.size() / 2);
+                    b->ev_pts.resize(b->events.size() / 2);
+                }
+                b->ev_pass[b->ev_used] = group_pass(g.kind);
+                b->ev_pts[b->ev_used] = g.pts[step];
+                set_launch_events(b->events[2 * b->ev_used], b->events[2 * b->ev_used + 1]);
+            }
+            e = launch_group(b, g, step);
+            if (time_it) {
+                set_launch_events(nullptr, nullptr);
+                b->ev_used += 1;
+            }
+            if (e) return hip_fail(e, "batch step");
+        }
     return HJM_OK;
 }
 
@@ -1147,6 +1189,7 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
         b->groups.back().kind = kind;
         b->groups.back().rows = rows;
         b->groups.back().cnt.assign(b->max_steps, 0);
+        b->groups.back().pts.assign(b->max_steps, 0);
         return b->groups.back();
     };
     for (int kind = 0; kind < kGroupKinds; ++kind)
@@ -1168,7 +1211,11 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
             if (!tiles) continue;
             LaunchGroup& g = group(kind, rows);
             for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(s, t));
-            for (int step = 0; step < ns; ++step) g.cnt[step] += tiles;
+            const int64_t pts = (int64_t)ax[3 * s].n * ax[3 * s + 1].n * ax[3 * s + 2].n;
+            for (int step = 0; step < ns; ++step) {
+                g.cnt[step] += tiles;
+                g.pts[step] += pts;
+            }
             g.lds = std::max(g.lds, lds);
             g.aux = std::max(g.aux, aux);
         }
@@ -1198,7 +1245,7 @@ hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph)
 {
     if (!b) return fail(HJM_EINVAL, "null batch");
     if (!use_graph) {
-        hjm_status st = batch_enqueue(b);
+        hjm_status st = batch_enqueue(b, true);
         if (st) return st;
         b->ran = true;
         return HJM_OK;
@@ -1209,7 +1256,7 @@ hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph)
         hipGraph_t graph = nullptr;
         if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)))
             return hip_fail(e, "hipStreamBeginCapture");
-        hjm_status st = batch_enqueue(b);
+        hjm_status st = batch_enqueue(b, false);
         e = hipStreamEndCapture(b->stream, &graph);
         if (st) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -1249,6 +1296,33 @@ hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, do
         return hip_fail(e, "hjm_batch_prices");
     for (int s = 0; s < b->n; ++s)
         if (b->flags_host[s]) return fail(HJM_ENUMERIC, "solve %d: non-finite value or non-positive pivot", s);
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_profile(hjm_batch* b, int32_t steps)
+{
+    if (!b) return fail(HJM_EINVAL, "null batch");
+    if (steps < 0) return fail(HJM_EINVAL, "negative step count");
+    b->profile_steps = steps;
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_profile_read(hjm_batch* b, double ms[HJM_N_PASSES], int64_t launches[HJM_N_PASSES],
+                                  int64_t points[HJM_N_PASSES])
+{
+    if (!b || !ms || !launches || !points) return fail(HJM_EINVAL, "null argument");
+    for (int q = 0; q < HJM_N_PASSES; ++q) { ms[q] = 0.0; launches[q] = 0; points[q] = 0; }
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e) return hip_fail(e, "hjm_batch_profile_read");
+    for (size_t u = 0; u < b->ev_used; ++u) {
+        float t = 0.0f;
+        if ((e = hipEventElapsedTime(&t, b->events[2 * u], b->events[2 * u + 1])))
+            return hip_fail(e, "hipEventElapsedTime");
+        ms[b->ev_pass[u]] += t;
+        launches[b->ev_pass[u]] += 1;
+        points[b->ev_pass[u]] += b->ev_pts[u];
+    }
+    b->ev_used = 0;
     return HJM_OK;
 }
 

@@ -1,7 +1,7 @@
 // hjm_run: price a list of solves through the C ABI from a plain-text spec,
 // without Python (for profilers and for callers that embed the library).
 //
-//   hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y]
+//   hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y] [--batch]
 //   hjm_run --copy MIB
 //
 // SPEC holds one solve per line ('#' starts a comment), 37 numbers:
@@ -12,6 +12,9 @@
 // Each repeat creates every grid (workspaces are allocated once), runs every
 // Douglas step and reads the price out, as one pass over the list.  With
 // --steps K only the first K steps of each solve run and no price is read.
+// With --batch the list is priced as one batch (hjm_batch_*: at every Douglas
+// step one launch per kernel covers all solves still running); --steps does
+// not apply there.
 // Prints the prices of the last repeat and the throughput in grid-point
 // Douglas steps per second.  Exit status 0 on success, 1 on a bad spec or
 // argument, 2 on a library or HIP error.
@@ -79,7 +82,7 @@ int lib_fail(const char* what, hjm_status st) {
 }
 
 int usage() {
-    std::fprintf(stderr, "usage: hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y]\n"
+    std::fprintf(stderr, "usage: hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y] [--batch]\n"
                          "       hjm_run --copy MIB\n");
     return 1;
 }
@@ -118,13 +121,73 @@ int run_copy(int mib) {
     return 0;
 }
 
+int run_batch(const std::vector<Solve>& solves, hipStream_t stream, int repeat, int warmup) {
+    const int32_t n = int32_t(solves.size());
+    std::vector<hjm_axis> ax(3 * solves.size());
+    std::vector<hjm_model> model(solves.size());
+    std::vector<hjm_payoff> payoff(solves.size());
+    std::vector<int32_t> steps(solves.size());
+    std::vector<double> r0(solves.size()), v0(solves.size()), prices(solves.size(), 0.0);
+    int64_t per_pass = 0;
+    for (size_t q = 0; q < solves.size(); ++q) {
+        for (int a = 0; a < 3; ++a) ax[3 * q + a] = solves[q].ax[a];
+        model[q] = solves[q].model;
+        payoff[q] = solves[q].payoff;
+        steps[q] = solves[q].n_steps;
+        r0[q] = solves[q].r0;
+        v0[q] = solves[q].v0;
+        per_pass += solves[q].points() * solves[q].n_steps;
+    }
+    size_t bytes = 0;
+    hjm_status st = hjm_batch_workspace_bytes(n, ax.data(), steps.data(), &bytes);
+    if (st != HJM_OK) return lib_fail("batch workspace size", st);
+    void* ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) {
+        std::fprintf(stderr, "hjm_run: hipMalloc of %zu bytes failed\n", bytes);
+        return 2;
+    }
+    int64_t point_steps = 0;
+    double seconds = 0.0;
+    for (int it = 0; it < warmup + repeat; ++it) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return lib_fail("sync", HJM_EDEVICE);
+        auto t0 = std::chrono::steady_clock::now();
+        hjm_batch* b = nullptr;
+        st = hjm_batch_create(n, ax.data(), model.data(), payoff.data(), steps.data(), ws, bytes, stream, &b);
+        if (st != HJM_OK) return lib_fail("batch create", st);
+        st = hjm_batch_run(b, 0);
+        if (st == HJM_OK) st = hjm_batch_prices(b, r0.data(), v0.data(), prices.data());
+        hjm_batch_destroy(b);
+        if (st != HJM_OK) return lib_fail("batch run", st);
+        double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        std::printf("hjm_run: batch pass %d of %d%s: %.3f ms\n", it + 1, warmup + repeat,
+                    it < warmup ? " (warmup)" : "", 1e3 * el);
+        std::fflush(stdout);
+        if (it >= warmup) {
+            point_steps += per_pass;
+            seconds += el;
+        }
+    }
+    for (size_t q = 0; q < solves.size(); ++q)
+        std::printf("solve %zu: %dx%dx%d, %d steps, price %.17g\n", q, solves[q].ax[0].n, solves[q].ax[1].n,
+                    solves[q].ax[2].n, solves[q].n_steps, prices[q]);
+    std::printf("hjm_run: %lld grid-point Douglas steps in %.6f s: %.4g per second\n", (long long)point_steps,
+                seconds, point_steps / seconds);
+    (void)hipFree(ws);
+    return 0;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
     if (argc < 2) return usage();
     if (!std::strcmp(argv[1], "--copy")) return argc == 3 ? run_copy(std::atoi(argv[2])) : usage();
     int repeat = 1, warmup = 0, steps_cap = 0;
+    bool batch = false;
     for (int a = 2; a < argc; ++a) {
+        if (!std::strcmp(argv[a], "--batch")) {
+            batch = true;
+            continue;
+        }
         if (a + 1 >= argc) return usage();
         if (!std::strcmp(argv[a], "--repeat")) {
             repeat = std::atoi(argv[++a]);
@@ -141,7 +204,7 @@ int main(int argc, char** argv) {
             return usage();
         }
     }
-    if (repeat < 1 || warmup < 0 || steps_cap < 0) return usage();
+    if (repeat < 1 || warmup < 0 || steps_cap < 0 || (batch && steps_cap > 0)) return usage();
 
     std::ifstream file(argv[1]);
     if (!file) {
@@ -170,6 +233,11 @@ int main(int argc, char** argv) {
     if (hipStreamCreate(&stream) != hipSuccess) {
         std::fprintf(stderr, "hjm_run: hipStreamCreate failed\n");
         return 2;
+    }
+    if (batch) {
+        int rc = run_batch(solves, stream, repeat, warmup);
+        (void)hipStreamDestroy(stream);
+        return rc;
     }
     std::vector<void*> ws(solves.size(), nullptr);
     std::vector<size_t> ws_bytes(solves.size(), 0);

@@ -77,6 +77,8 @@ def lib():
         "hjm_batch_run": (st, [vp, i32]),
         "hjm_batch_prices": (st, [vp, P(d), P(d), P(d)]),
         "hjm_batch_destroy": (st, [vp]),
+        "hjm_batch_profile": (st, [vp, i32]),
+        "hjm_batch_profile_read": (st, [vp, P(d), P(i64), P(i64)]),
         "hjm_set_line_tile": (st, [i32, i32, i32]),
         "hjm_get_line_tile": (st, [P(i32), P(i32), P(i32)]),
         "hjm_set_explicit_chunk": (st, [i32]),
@@ -295,6 +297,18 @@ class Batch:
     def run(self, graph: bool = False) -> "Batch":
         check(lib().hjm_batch_run(self._h, 1 if graph else 0))
         return self
+
+    def profile(self, steps: int) -> None:
+        """Time every launch of the first `steps` Douglas steps of eager runs."""
+        check(lib().hjm_batch_profile(self._h, int(steps)))
+
+    def profile_read(self):
+        """(ms, launches, grid points) per pass since the last read."""
+        ms = (C.c_double * N_PASSES)()
+        n = (C.c_int64 * N_PASSES)()
+        pts = (C.c_int64 * N_PASSES)()
+        check(lib().hjm_batch_profile_read(self._h, ms, n, pts))
+        return list(ms), list(n), list(pts)
 
     def prices(self, r0=None, v0=None) -> np.ndarray:
         n = len(self.specs)

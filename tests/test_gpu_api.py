@@ -125,3 +125,33 @@ def test_batch_subset_against_oracle():
         p = to_oracle(sp)
         po, _ = O.price(p, sp.r0, sp.v0)
         assert abs(pg - po) <= 1e-12 * abs(po), (pg, po)
+
+
+def test_batch_profile_counts_and_prices():
+    """Timing a batch's first steps changes no price; the points each pass
+    reports are the grid points of the solves still running at those steps
+    (the r pass only counts solves whose r lines have a kernel of their own)."""
+    specs = _batch_specs()
+    st = torch.cuda.Stream()
+    plain = hjm.Batch(specs, stream=st).run().prices()
+    k = 5
+    b = hjm.Batch(specs, stream=st)
+    b.profile(k)
+    b.run()
+    assert np.array_equal(b.prices(), plain)
+    ms, n, pts = b.profile_read()
+    split = [hjm.Grid(sp).plan()["r_method"] == "split" for sp in specs]
+    total = sum(sp.points * min(k, sp.n_steps) for sp in specs)
+    total_split = sum(sp.points * min(k, sp.n_steps) for sp, s in zip(specs, split) if s)
+    assert pts[0] == pts[2] == pts[3] == total
+    assert pts[1] == total_split
+    for q in range(hjm.N_PASSES):
+        assert (n[q] > 0) == (pts[q] > 0)
+        assert n[q] <= k * len(specs)
+        if n[q]:
+            assert ms[q] > 0.0
+    # the sums restart after a read; graph runs are never timed
+    assert b.profile_read()[1] == [0] * hjm.N_PASSES
+    b.run(graph=True)
+    assert np.array_equal(b.prices(), plain)
+    assert b.profile_read()[1] == [0] * hjm.N_PASSES
