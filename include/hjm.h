@@ -92,7 +92,7 @@ typedef struct hjm_grid hjm_grid;
 typedef struct hjm_batch hjm_batch;
 
 /* Bytes of device workspace hjm_grid_create needs for these axes and step
-   count: the grid U, the Douglas increment D and the pivots of the y-line
+   count: the grid U, the Douglas increment D and the reciprocal pivots of the y-line
    matrices (which do not change from step to step), nr*nv*ny doubles each,
    plus 1D tables (axis coefficients, per-step curve and bond-factor scalars,
    per-step Dirichlet increments on the r and y_max faces, (2 ny + nr) doubles
@@ -134,8 +134,10 @@ hjm_status hjm_grid_destroy(hjm_grid* g);
 /* How the solve is carried out (host only): plan[0] = r-line method
    (0 spike and 1 chain, both in the kernel that also computes the explicit
    predictor; 2 split: separate explicit kernel, then a spike solve with the
-   segments of a line in consecutive lanes of one wavefront), plan[1] = rows
-   per lane of the split r solve (0 if not split), plan[2..4] = the line-tile
+   segments of a line in consecutive lanes of one wavefront; 3 fused: the
+   explicit predictor of a tile into LDS and that spike solve in one kernel,
+   for nr <= 256 with at least 8 rows per lane), plan[1] = rows per lane of
+   the split or fused r solve (0 otherwise), plan[2..4] = the line-tile
    rows per thread of the r, v and y solves, plan[5] = rows per segment of the
    segmented v solve (0: the chained v solve), plan[6] = rows per segment of
    the y solve on stored pivots (0: the per-step elimination), plan[7] = 0.  The
@@ -267,6 +269,13 @@ hjm_status hjm_mlp_destroy(hjm_mlp* m);
    batch is created, like the line tile. */
 hjm_status hjm_set_explicit_chunk(int32_t J);
 hjm_status hjm_get_explicit_chunk(int32_t* J);
+
+/* Whether grids and batches created afterwards fuse the explicit predictor
+   with the spike r solve where they can (plan method 3; on by default).  Off,
+   those solves take the split pair of kernels instead: the same arithmetic,
+   16 more bytes of memory traffic per grid point and step.  Process-wide. */
+hjm_status hjm_set_r_fusion(int32_t on);
+hjm_status hjm_get_r_fusion(int32_t* on);
 
 const char* hjm_status_str(hjm_status s);
 const char* hjm_last_error(void);

@@ -175,12 +175,14 @@ hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_
 // ---------------------------------------------------------------------------
 struct Plan {
     bool r_spike;
-    int r_mode;  // R_SPIKE / R_CHAIN (fused k_xr) or R_SPLIT (k_exp + k_rs)
+    int r_mode;  // R_SPIKE / R_CHAIN (k_xr), R_SPLIT (k_exp + k_rs) or R_FUSED (k_exr)
     int r_S, r_L, r_pitch, v_S, v_L, y_S, y_L;
     int r_tiles, v_tiles, y_tiles;
     size_t r_lds, v_lds, y_lds;
     int rs_rows, rs_S, rs_log2S, rs_L, rs_tiles;
     int exp_J, exp_cb, exp_tiles;
+    int exr_P, exr_tiles, exr_tab;      // fused explicit + r solve
+    size_t exr_lds;
     int vs_rows, vs_S, vs_tiles;        // segmented v solve (0: chained k_v)
     int yc_rows, yc_S, yc_L, yc_tiles;  // y solve on stored pivots (0: k_yu)
 };
@@ -205,7 +207,8 @@ int yc_rows_for(int ny, int preferred)
     return 0;
 }
 
-int g_exp_J = 8;  // v nodes per k_exp thread (4, 8 or 16)
+int g_exp_J = 8;      // v nodes per k_exp thread (4, 8 or 16)
+bool g_fuse_r = true;  // fuse the explicit predictor with the spike r solve where k_exr applies
 
 // k_rs needs nr = S * ROWS with S a power of two <= 64 lanes; the preferred
 // rows per lane come first.
@@ -276,6 +279,14 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
         p.rs_L = 4 * (64 / p.rs_S);
         p.rs_tiles = (nv * ny + p.rs_L - 1) / p.rs_L;
     }
+    p.exr_P = p.exr_tiles = p.exr_tab = 0;
+    p.exr_lds = 0;
+    if (p.rs_rows >= 8 && nr <= kExrMaxNr) {
+        p.exr_P = kBlock / nr;
+        p.exr_tiles = ((ny + p.exr_P - 1) / p.exr_P) * ((nv + kExrJ - 1) / kExrJ);
+        exr_lds(nr, p.rs_rows, &p.exr_lds, &p.exr_tab);
+        if (g_fuse_r) p.r_mode = R_FUSED;
+    }
     return p;
 }
 
@@ -341,6 +352,7 @@ Plan plan_bound(int nr, int nv, int ny)
             const int rows[3] = {o, 8, 8};
             Plan p = make_plan(nr, nv, ny, rows, sp);
             b.rs_tiles = std::max(b.rs_tiles, p.rs_tiles);
+            b.exr_tiles = std::max(b.exr_tiles, p.exr_tiles);
         }
     for (int o : options)
         for (bool sp : {true, false}) {
@@ -351,6 +363,7 @@ Plan plan_bound(int nr, int nv, int ny)
             b.y_tiles = std::max(b.y_tiles, p.y_tiles);
             b.rs_tiles = std::max(b.rs_tiles, p.rs_tiles);
             b.exp_tiles = std::max(b.exp_tiles, p.exp_tiles);
+            b.exr_tiles = std::max(b.exr_tiles, p.exr_tiles);
             b.vs_tiles = std::max(b.vs_tiles, p.vs_tiles);
             b.yc_tiles = std::max(b.yc_tiles, p.yc_tiles);
         }
@@ -378,7 +391,7 @@ size_t table_doubles(const hjm_axis ax[3], int n_steps)
 }
 
 struct SolveOffsets {
-    size_t U, D, CP, tables;
+    size_t U, D, YI, tables;
 };
 
 SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
@@ -387,7 +400,7 @@ SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
     SolveOffsets o;
     o.U = L.take(pts * 8);
     o.D = L.take(pts * 8);
-    o.CP = L.take(pts * 8);
+    o.YI = L.take(pts * 8);
     o.tables = L.take(table_doubles(ax, n_steps) * 8);
     return o;
 }
@@ -648,8 +661,9 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.r_mode = pl.r_mode;
     d.exp_J = pl.exp_J; d.exp_cb = pl.exp_cb; d.exp_tiles = pl.exp_tiles;
     d.rs_S = pl.rs_S; d.rs_log2S = pl.rs_log2S; d.rs_L = pl.rs_L; d.rs_tiles = pl.rs_tiles;
+    d.exr_P = pl.exr_P; d.exr_tiles = pl.exr_tiles; d.exr_tab = pl.exr_tab;
     d.vg = d.gd + (size_t)(2 * ax[2].n + ax[0].n) * n_steps;
-    d.cp = reinterpret_cast<double*>(base + o.CP);
+    d.yinv = reinterpret_cast<double*>(base + o.YI);
     d.vs_S = pl.vs_S; d.vs_tiles = pl.vs_tiles;
     d.yc_S = pl.yc_S; d.yc_L = pl.yc_L; d.yc_tiles = pl.yc_tiles;
 }
@@ -785,6 +799,19 @@ hjm_status hjm_set_explicit_chunk(int32_t J)
     return HJM_OK;
 }
 
+hjm_status hjm_set_r_fusion(int32_t on)
+{
+    g_fuse_r = on != 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_r_fusion(int32_t* on)
+{
+    if (!on) return fail(HJM_EINVAL, "null argument");
+    *on = g_fuse_r ? 1 : 0;
+    return HJM_OK;
+}
+
 hjm_status hjm_get_explicit_chunk(int32_t* J)
 {
     if (!J) return fail(HJM_EINVAL, "null argument");
@@ -883,6 +910,8 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
                 set_launch_events(e0, e1);
             }
             if (pass == 0 && split) e = launch_exp(p.exp_J, g->d_desc, nullptr, p.exp_tiles, n, g->stream);
+            else if (pass == 0 && p.r_mode == R_FUSED)
+                e = launch_exr(p.rs_rows, g->d_desc, nullptr, p.exr_tiles, n, p.exr_lds, g->stream);
             else if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
             else if (pass == 1) e = launch_rs(p.rs_rows, g->d_desc, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
             else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, g->d_desc, nullptr, p.vs_tiles, p.vs_S, g->stream);
@@ -989,7 +1018,7 @@ hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[HJM_N_PASSES], int64_t l
 // that use it.  Launch groups: one per (kernel, rows per thread); a group
 // holds the (solve, tile) tasks of its solves, ordered by step count (longest
 // first) so that the solves still running at step n are a prefix.
-enum { G_XR = 0, G_EXP, G_RS, G_V, G_VS, G_YU, G_YC, kGroupKinds };
+enum { G_XR = 0, G_EXR, G_EXP, G_RS, G_V, G_VS, G_YU, G_YC, kGroupKinds };
 
 struct LaunchGroup {
     int kind = 0, rows = 0;
@@ -1045,7 +1074,8 @@ struct BatchLayout {
 size_t task_bound(const hjm_axis* a)
 {
     const Plan pb = plan_bound(a[0].n, a[1].n, a[2].n);
-    return (size_t)std::max(pb.r_tiles, pb.exp_tiles) + pb.rs_tiles + std::max(pb.v_tiles, pb.vs_tiles) +
+    return (size_t)std::max(std::max(pb.r_tiles, pb.exp_tiles), pb.exr_tiles) + pb.rs_tiles +
+           std::max(pb.v_tiles, pb.vs_tiles) +
            std::max(pb.y_tiles, pb.yc_tiles) + (size_t)pb.exp_tiles;
 }
 
@@ -1072,6 +1102,7 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step)
     const int2* t = b->d_tasks + g.off;
     switch (g.kind) {
     case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, b->stream);
+    case G_EXR: return launch_exr(g.rows, b->d_desc, t, nt, step, g.lds, b->stream);
     case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, b->stream);
     case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, b->stream);
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, b->stream);
@@ -1084,7 +1115,7 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step)
 int group_pass(int kind)
 {
     switch (kind) {
-    case G_XR: case G_EXP: return 0;
+    case G_XR: case G_EXR: case G_EXP: return 0;
     case G_RS: return 1;
     case G_V: case G_VS: return 2;
     default: return 3;
@@ -1200,7 +1231,10 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
             size_t lds = 0;
             int aux = 0;
             switch (kind) {
-            case G_XR: if (pl.r_mode != R_SPLIT) { rows = b->rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; } break;
+            case G_XR:
+                if (pl.r_mode == R_SPIKE || pl.r_mode == R_CHAIN) { rows = b->rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; }
+                break;
+            case G_EXR: if (pl.r_mode == R_FUSED) { rows = pl.rs_rows; tiles = pl.exr_tiles; lds = pl.exr_lds; } break;
             case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
             case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
             case G_V: if (!pl.vs_rows) { rows = b->rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;

@@ -15,9 +15,12 @@ constexpr int kRed = 8;            // doubles per segment in the r-sweep reduced
 // How the explicit predictor and the r lines are computed.
 enum { R_SPIKE = 0,   // fused k_xr; segments eliminated in parallel, reduced system per line
        R_CHAIN = 1,   // fused k_xr; Thomas in row order, segments chained through LDS
-       R_SPLIT = 2 }; // k_exp (explicit predictor) then k_rs (spike, one line per S lanes of a wave)
+       R_SPLIT = 2,   // k_exp (explicit predictor) then k_rs (spike, one line per S lanes of a wave)
+       R_FUSED = 3 }; // k_exr: explicit predictor into LDS, then the k_rs spike solve, one kernel
 
 constexpr int kExpCols = 256;  // r-y columns per k_exp workgroup (one thread each)
+constexpr int kExrJ = 16;      // v nodes per k_exr tile (computed 8 at a time)
+constexpr int kExrMaxNr = kBlock;  // k_exr: one thread per r node of a plane
 
 // Per-solve descriptor, resident in device memory (read-only in kernels).
 struct SolveDesc {
@@ -31,13 +34,16 @@ struct SolveDesc {
     // v chunks; k_rs handles rs_L lines per workgroup, rs_S = nr / ROWS lanes
     // (a power of two <= 64) per line
     int32_t exp_J, exp_cb, exp_tiles, rs_S;
-    int32_t rs_log2S, rs_L, rs_tiles, pad1;
+    int32_t rs_log2S, rs_L, rs_tiles, exr_P;
+    // fused path (R_FUSED): k_exr tiles = ceil(ny / exr_P) plane blocks x
+    // ceil(nv / kExrJ) v blocks, exr_P = kBlock / nr planes per tile; the
+    // row table sits exr_tab doubles into the dynamic LDS, after the tile
     // segmented v solve (k_vs, vs_S > 0): vs_S segments of nv / vs_S rows, one
     // wave of 64 consecutive i per segment; chained y solve on stored pivots
     // (k_yc, yc_S > 0): yc_S segments of ny / yc_S rows (one wave each), 64
     // lines per workgroup (yc_L)
     int32_t vs_S, vs_tiles, yc_S, yc_L;
-    int32_t yc_tiles, pad2, pad3, pad4;
+    int32_t yc_tiles, exr_tiles, exr_tab, pad4;
     double dt;          // time step
     double tdt;         // theta * dt, theta = 1/2
     double kappa;
@@ -56,7 +62,7 @@ struct SolveDesc {
     const double* rf;   // r rows of (I - theta dt A1), theta dt folded in: kRF * nr
     const double* gd;   // Dirichlet increments g(t_{n+1}) - g(t_n): (2 ny + nr) per step
     const double* vg;   // segmented v-solve constants, kVG * nv
-    double* cp;         // y-line pivots c'_k of (I - theta dt A3), nr*nv*ny (written once per solve)
+    double* yinv;       // y-line reciprocal pivots 1 / den_k of (I - theta dt A3), nr*nv*ny (once per solve)
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value
     int32_t* flag_pad;
 };
@@ -151,6 +157,11 @@ hipError_t launch_yu(int rows, const SolveDesc* d_desc, const int2* tasks, int n
 hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st);
 hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, int nr_max,
                      hipStream_t st);
+// k_exr dynamic LDS (bytes) and table offset (doubles) for nr = S * rows
+// (rows >= 8: a pass's scratch, 8 doubles per lane, fits in its rows)
+void exr_lds(int nr, int rows, size_t* bytes, int* tab);
+hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
+                      hipStream_t st);
 // rows per thread available to k_rs
 bool rs_rows_supported(int rows);
 hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);

@@ -871,30 +871,18 @@ __device__ __forceinline__ void wave_sync()
 
 // Explicit predictor D0 = dt (A1 + A2 + A3 + A0) U^n (eq. (discreta) with the
 // centred stencils of eq. (esquema), one-sided rows on outflow faces), and the
-// Dirichlet increment on Dirichlet nodes.  Thread = one (i, k) column and J
-// consecutive v nodes j: it loads the v window u(i, j0-2 .. j0+J+1), the
-// neighbouring columns u(i -+ 1, j0-1 .. j0+J), the two y neighbours and the
-// outflow extra entry of each node, all up front, then computes the J nodes.
-// Lanes are consecutive i: every load of a wave is one contiguous row segment.
-template <int J>
-__global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
-                                                int step)
+// Dirichlet increment on Dirichlet nodes, at the J nodes (i, j0 + m, k),
+// m < J, j0 + m < nv; put(m, value) receives each.  The caller's lanes are
+// consecutive i, so every load of a wave is one contiguous row segment.  All
+// loads are issued up front: the v window u(i, j0-2 .. j0+J+1), the
+// neighbouring columns u(i -+ 1, j0-1 .. j0+J) and the two y neighbours; the
+// outflow extra entry (two nodes in) only on the r faces, where its weight is
+// not zero.  j0 must be wave-uniform (the v-table reads are scalar).
+template <int J, class Put>
+__device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k, int j0, int step, const Put& put)
 {
-    const int bi = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int2 tk = tasks ? tasks[bi] : make_int2(0, bi);
-    const SolveDesc& s = descs[tk.x];
-    if (step >= s.n_steps) return;
     const int nr = s.nr, nv = s.nv, ny = s.ny;
-    const int cb = tk.y % s.exp_cb;
-    const int jc = tk.y / s.exp_cb;
-    const int p = cb * kExpCols + (int)threadIdx.x;
-    if (p >= nr * ny) return;  // no barriers below
-    const int k = p / nr;
-    const int i = p - k * nr;
-    // j is the same on every lane: keep it (and the v-table reads) scalar
-    const int j0 = __builtin_amdgcn_readfirstlane(jc * J);
     gcdouble* U = gp(s.U);
-    gdouble* D = gp(s.D);
     gcdouble* rt = gp(s.rt);
     kcdouble* vt = kp(s.vt);
     gcdouble* yt = gp(s.yt);
@@ -912,10 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     if (yhd) { oa = 0; ob = 0; }
     gcdouble* cola = col + (ptrdiff_t)oa * (ptrdiff_t)sy;  // plane k + oa
     gcdouble* colb = col + (ptrdiff_t)ob * (ptrdiff_t)sy;
-    // outflow r face rows reach two nodes in: the extra entry (interior
-    // columns read their own node, with weight zero)
     const int dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
-    const size_t ix = (size_t)(i + dx);
     auto jcl = [&](int jj) { return (size_t)min(max(jj, 0), nv - 1) * sl; };
     double cw[J + 4], lw[J + 2], rw[J + 2], ya[J], yb[J], ux[J];
 #pragma unroll
@@ -929,7 +914,15 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     for (int m = 0; m < J; ++m) {
         ya[m] = cola[jcl(j0 + m) + i];
         yb[m] = colb[jcl(j0 + m) + i];
-        ux[m] = col[jcl(j0 + m) + ix];
+    }
+    if (dx != 0) {
+        // outflow r face rows reach two nodes in
+#pragma unroll
+        for (int m = 0; m < J; ++m) ux[m] = col[jcl(j0 + m) + (size_t)(i + dx)];
+    } else {
+        // interior rows: the extra entry has weight zero
+#pragma unroll
+        for (int m = 0; m < J; ++m) ux[m] = cw[m + 2];
     }
 
     // per-column constants: A1 row pieces (affine in v), A3 coefficient, A0 factor
@@ -951,7 +944,6 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
     const bool dir = rlo || rhi || yhd;
     const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
-    gdouble* dcol = D + (size_t)k * sy + i;
     const double dt = s.dt;
 #pragma unroll
     for (int m = 0; m < J; ++m) {
@@ -968,64 +960,49 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
         const double cross = (rw[m + 2] - rw[m]) - (lw[m + 2] - lw[m]);
         const double a0 = rx * vt[VT_X * nv + j] * cross;
         const double val = dt * (((a1 + a2) + a3) + a0);
-        dcol[(size_t)j * sl] = dir ? gval : val;
+        put(m, dir ? gval : val);
     }
 }
 
-// r sweep (I - theta dt A1) D1 = D0 by the spike (partition) method, for
-// lines of nr = S * ROWS rows with S a power of two <= 64: the S segments of
-// a line sit in S consecutive lanes of one wavefront, so the reduced system
-// is exchanged through LDS with wave-level synchronisation only.  Each lane
-// eliminates its ROWS rows (spikes v toward the previous segment, w toward
-// the next), lane 0 of the line solves the reduced system of the segments'
-// end unknowns, and every lane back-substitutes.  The outflow face rows (one
-// entry beyond the band) are folded into rows 1 and n-2 first and recovered
-// last.  Accurate when the rows are diagonally dominant; the host selects this
-// path only then.
-template <int ROWS>
-__global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
-                                               int step)
+// Explicit predictor alone (split path).  Thread = one (i, k) column and J
+// consecutive v nodes.
+template <int J>
+__global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
+                                                int step)
 {
-    extern __shared__ double lds_raw[];
-    ldouble* lds = (ldouble*)lds_raw;
-    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const int bi = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int2 tk = tasks ? tasks[bi] : make_int2(0, bi);
     const SolveDesc& s = descs[tk.x];
-    if (step >= s.n_steps) return;  // whole workgroup: uniform
-    const int nr = s.nr, nv = s.nv, ny = s.ny;
-    const int S = s.rs_S;
-    const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int seg = lane & (S - 1);
-    const int nlines = nv * ny;
-    const int q_raw = tk.y * s.rs_L + (t >> 6) * (64 >> s.rs_log2S) + (lane >> s.rs_log2S);
-    const bool active = q_raw < nlines;
-    const int q = active ? q_raw : nlines - 1;  // tail lanes repeat the last line, store nothing
-    const int k = q / nv;
-    const int j = q - k * nv;
-    const bool store = active && !(s.y_hi_dir && k == ny - 1);
-    // the line's rows first, so that their loads are in flight while the row
-    // table is staged
-    const double v = gp(s.vt)[VT_V * nv + j];
-    const double c = gp(s.st)[kStepStride * step + ST_PHI] + gp(s.yt)[YT_Y * ny + k];
-    gdouble* line = gp(s.D) + (size_t)q * nr + (size_t)seg * ROWS;
-    double d[ROWS];
-#pragma unroll
-    for (int mm = 0; mm < ROWS; ++mm) d[mm] = line[mm];
-    // row table, one block per segment: [seg][kRF * ROWS + 1] (the odd pitch
-    // spreads the segments of a wave over the LDS banks)
-    constexpr int TP = kRF * ROWS + 1;
-    ldouble* tab = lds;
-    ldouble* red = lds + (size_t)TP * S;  // 8 doubles per thread
-    gcdouble* rf = gp(s.rf);
-    for (int idx = t; idx < kRF * nr; idx += kBlock) {
-        const int c6 = idx / nr;
-        const int i = idx - c6 * nr;
-        const int sg = i / ROWS;
-        const int mm = i - sg * ROWS;
-        tab[sg * TP + c6 * ROWS + mm] = rf[idx];
-    }
-    __syncthreads();
-    const ldouble* tseg = tab + seg * TP;
+    if (step >= s.n_steps) return;
+    const int nr = s.nr;
+    const int cb = tk.y % s.exp_cb;
+    const int jc = tk.y / s.exp_cb;
+    const int p = cb * kExpCols + (int)threadIdx.x;
+    if (p >= nr * s.ny) return;  // no barriers below
+    const int k = p / nr;
+    const int i = p - k * nr;
+    // j is the same on every lane: keep it (and the v-table reads) scalar
+    const int j0 = __builtin_amdgcn_readfirstlane(jc * J);
+    gdouble* dcol = gp(s.D) + (size_t)k * nr * s.nv + (size_t)j0 * nr + i;
+    explicit_nodes<J>(s, i, k, j0, step, [&](int m, double x) { dcol[(size_t)m * nr] = x; });
+}
+
+// The spike solve of one r line of nr = S * ROWS rows (S a power of two <=
+// 64) by S consecutive lanes of a wavefront: this lane holds rows
+// [seg ROWS, (seg + 1) ROWS) in d (right-hand side in, solution out).  tseg
+// is the segment's block of the staged row table, my the lane's 8-double
+// slot of LDS scratch (the line's lanes' slots are consecutive).  Each lane
+// eliminates its rows (spikes v toward the previous segment, w toward the
+// next), lane 0 of the line solves the reduced system of the segments' end
+// unknowns, and every lane back-substitutes.  The outflow face rows (one
+// entry beyond the band) are folded into rows 1 and n-2 first and recovered
+// last.  Accurate when the rows are diagonally dominant (the host selects
+// this path only then).  Returns false after a non-positive pivot.
+template <int ROWS>
+__device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* tseg, ldouble* my, int seg, int S,
+                                             double v, double c, double (&d)[ROWS])
+{
+    const int nr = s.nr;
     auto coef = [&](int mm, double& A, double& B, double& C) {
         const ldouble* tb = tseg + mm;
         const double e = tb[RF_P * ROWS] * c + tb[RF_Q * ROWS];
@@ -1097,18 +1074,16 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
             vv = vp[mm] - cp[mm] * vv;
             w = -cp[mm] * w;
         }
-        ldouble* my = red + t * 8;
         my[0] = y; my[1] = vv; my[2] = w;
         my[3] = d[ROWS - 1]; my[4] = vp[ROWS - 1]; my[5] = cp[ROWS - 1];
         wave_sync();
         if (first) {
             // F_s = yF - vF L_{s-1} - wF F_{s+1};  L_s = yL - vL L_{s-1} - wL F_{s+1}
             // forward: L_s = alp + bet F_{s+1}, F_s = gam + del F_{s+1}
-            ldouble* r0 = red + t * 8;  // this lane is the line's segment 0
             double alp = 0.0, bet = 0.0;
 #pragma unroll 4
             for (int qq = 0; qq < S; ++qq) {
-                ldouble* r = r0 + qq * 8;
+                ldouble* r = my + qq * 8;
                 const double yF = r[0], vF = r[1], wF = r[2], yL = r[3], vL = r[4], wL = r[5];
                 const double den = 1.0 + vF * bet;
                 ok = ok && den > 0.0;
@@ -1122,21 +1097,21 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
             double Fn = 0.0, Lp = 0.0;
 #pragma unroll 4
             for (int qq = S - 1; qq >= 0; --qq) {
-                ldouble* r = r0 + qq * 8;
+                ldouble* r = my + qq * 8;
                 const double F = r[0] + r[1] * Fn;
                 r[5] = r[2] + r[3] * Fn;  // L_q
                 r[6] = Fn;                // X_R of segment q
                 Fn = F;
             }
             for (int qq = 0; qq < S; ++qq) {
-                ldouble* r = r0 + qq * 8;
+                ldouble* r = my + qq * 8;
                 r[7] = Lp;                // X_L of segment q
                 Lp = r[5];
             }
         }
         wave_sync();
-        XL = red[t * 8 + 7];
-        XR = red[t * 8 + 6];
+        XL = my[7];
+        XR = my[6];
     }
     // back substitution with the coupling values
     double x = d[ROWS - 1] - XL * vp[ROWS - 1] - XR * cp[ROWS - 1];
@@ -1148,11 +1123,158 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     }
     if (first) d[0] = (fd0 - fc0 * d[1] - fe0 * d[2]) / fb0;
     if (last) d[ROWS - 1] = (fdl - fel * d[ROWS - 3] - fal * d[ROWS - 2]) / fbl;
+    return ok;
+}
+
+// Stage the split-path r row table into LDS, one block per segment:
+// [seg][kRF * ROWS + 1] (the odd pitch spreads the segments of a wave over
+// the LDS banks).  The caller synchronises the workgroup before reading it.
+template <int ROWS>
+__device__ __forceinline__ void stage_rf(const SolveDesc& s, ldouble* tab)
+{
+    constexpr int TP = kRF * ROWS + 1;
+    const int nr = s.nr;
+    gcdouble* rf = gp(s.rf);
+    for (int idx = (int)threadIdx.x; idx < kRF * nr; idx += kBlock) {
+        const int c6 = idx / nr;
+        const int i = idx - c6 * nr;
+        const int sg = i / ROWS;
+        const int mm = i - sg * ROWS;
+        tab[sg * TP + c6 * ROWS + mm] = rf[idx];
+    }
+}
+
+// r sweep (I - theta dt A1) D1 = D0 by the spike method (split path): lines
+// of nr = S * ROWS rows, S a power of two <= 64, each solved by S consecutive
+// lanes of a wavefront.
+template <int ROWS>
+__global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
+                                               int step)
+{
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
+    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const SolveDesc& s = descs[tk.x];
+    if (step >= s.n_steps) return;  // whole workgroup: uniform
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int S = s.rs_S;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int seg = lane & (S - 1);
+    const int nlines = nv * ny;
+    const int q_raw = tk.y * s.rs_L + (t >> 6) * (64 >> s.rs_log2S) + (lane >> s.rs_log2S);
+    const bool active = q_raw < nlines;
+    const int q = active ? q_raw : nlines - 1;  // tail lanes repeat the last line, store nothing
+    const int k = q / nv;
+    const int j = q - k * nv;
+    const bool store = active && !(s.y_hi_dir && k == ny - 1);
+    // the line's rows first, so that their loads are in flight while the row
+    // table is staged
+    const double v = gp(s.vt)[VT_V * nv + j];
+    const double c = gp(s.st)[kStepStride * step + ST_PHI] + gp(s.yt)[YT_Y * ny + k];
+    gdouble* line = gp(s.D) + (size_t)q * nr + (size_t)seg * ROWS;
+    double d[ROWS];
+#pragma unroll
+    for (int mm = 0; mm < ROWS; ++mm) d[mm] = line[mm];
+    constexpr int TP = kRF * ROWS + 1;
+    ldouble* tab = lds;
+    ldouble* red = lds + (size_t)TP * S;  // 8 doubles per thread
+    stage_rf<ROWS>(s, tab);
+    __syncthreads();
+    const bool ok = spike_r_lane<ROWS>(s, tab + seg * TP, red + t * 8, seg, S, v, c, d);
     if (store) {
 #pragma unroll
         for (int mm = 0; mm < ROWS; ++mm) line[mm] = d[mm];
     }
     if (store && !ok) raise_flag(s);
+}
+
+// Explicit predictor and r sweep in one kernel (nr <= 256, nr = S * ROWS as
+// for k_rs, ROWS >= 8): the workgroup computes D0 on kExrJ consecutive v nodes of
+// exr_P = 256 / nr whole y planes (thread = (i, plane)) into an LDS tile,
+// then solves the tile's exr_P * kExrJ r lines with the spike method, S lanes
+// per line, and writes D1.  D0 never goes to memory: 16 bytes per point less
+// than the split pair.  Tile layout: line (plane kk, node jj) at
+// (kk kExrJ + jj) S (ROWS + 1), its segment g at g (ROWS + 1) (the pad spreads
+// a wave's segments over the banks).  The lanes of pass p reuse their own
+// lines' part of the tile as the reduced-system scratch once every lane has
+// read its rows (pass p's scratch is its first 8 kBlock doubles, inside its
+// kBlock / S lines; the tile is sized to whole passes).  Three waves per SIMD
+// (at most 168 VGPRs; a few spill) measured faster than two without spills.
+template <int ROWS>
+__global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
+                                                int step)
+{
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
+    const int bi = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int2 tk = tasks ? tasks[bi] : make_int2(0, bi);
+    const SolveDesc& s = descs[tk.x];
+    if (step >= s.n_steps) return;  // whole workgroup: uniform
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int P = s.exr_P;
+    const int S = s.rs_S;
+    const int log2S = s.rs_log2S;
+    constexpr int SP = ROWS + 1;
+    const int LP = S * SP;
+    const int nvb = (nv + kExrJ - 1) / kExrJ;
+    const int kb = tk.y / nvb;
+    const int jb = tk.y - kb * nvb;
+    const int k0 = kb * P;
+    const int j0 = __builtin_amdgcn_readfirstlane(jb * kExrJ);
+    const int t = threadIdx.x;
+    ldouble* tile = lds;
+    constexpr int TP = kRF * ROWS + 1;
+    ldouble* tab = lds + s.exr_tab;  // after the tile, rounded up to whole passes
+    stage_rf<ROWS>(s, tab);
+    {
+        // explicit phase: thread (i, plane kk); planes past ny do nothing
+        const int kk = t / nr;
+        const int i = t - kk * nr;
+        const int k = k0 + kk;
+        if (kk < P && k < ny) {
+            const int g = i / ROWS;
+            ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
+#pragma unroll 1
+            for (int jc = 0; jc < kExrJ; jc += 8)
+                explicit_nodes<8>(s, i, k, j0 + jc, step,
+                                  [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; });
+        }
+    }
+    __syncthreads();
+    const double phi = gp(s.st)[kStepStride * step + ST_PHI];
+    const int L = P * kExrJ;
+    for (int base = 0; base < L * S; base += kBlock) {  // uniform trip count
+        const int u = base + t;
+        const int ln = u >> log2S;
+        const int seg = u & (S - 1);
+        const int kk = ln / kExrJ;
+        const int jj = ln - kk * kExrJ;
+        const int k = min(k0 + kk, ny - 1);
+        const int j = min(j0 + jj, nv - 1);
+        const bool active = ln < L && k0 + kk < ny && j0 + jj < nv;
+        double d[ROWS];
+        const ldouble* src = tile + (size_t)min(ln, L - 1) * LP + seg * SP;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) d[mm] = src[mm];
+        __syncthreads();  // every lane of the pass has read its rows: the scratch may overwrite them
+        // Dirichlet y_max lines keep D0 (wave-uniform: a wave's lines share the plane)
+        const bool ydir = s.y_hi_dir && k == ny - 1;
+        bool ok = true;
+        if (!ydir) {
+            const double v = gp(s.vt)[VT_V * nv + j];
+            const double c = phi + gp(s.yt)[YT_Y * ny + k];
+            ok = spike_r_lane<ROWS>(s, tab + seg * TP, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
+        }
+        if (active) {
+            gdouble* line = gp(s.D) + ((size_t)k * nv + j) * nr + (size_t)seg * ROWS;
+#pragma unroll
+            for (int mm = 0; mm < ROWS; ++mm) line[mm] = d[mm];
+            if (!ok) raise_flag(s);
+        }
+        // the next pass reads only its own lines' rows, which this pass's
+        // scratch does not reach: no barrier needed here
+    }
 }
 
 // v sweep, segmented: the v-line matrix is the same on every line, so its
@@ -1228,10 +1350,13 @@ __global__ __launch_bounds__(kBlock) void k_vs(const SolveDesc* __restrict__ des
     }
 }
 
-// Pivots c'_k of every y line (i, j) of (I - theta dt A3), which does not
-// change from step to step: the Thomas forward recurrence in row order, with
-// the outflow row 0 folded into row 1 and the last row into row n-2 exactly
-// as in the per-step solve.  One thread per line, written once per solve.
+// Reciprocal pivots 1 / den_k of every y line (i, j) of (I - theta dt A3),
+// which do not change from step to step: the Thomas forward recurrence
+// den_k = B_k - A_k c'_{k-1}, c'_k = C_k / den_k in row order (the quotient
+// taken as C_k times the reciprocal, as the sweep does), with the outflow row
+// 0 folded into row 1 and the last row into row n-2 exactly as in the
+// per-step solve; rows 0 and n-1 are identity rows (1).  One thread per line,
+// written once per solve; a non-positive pivot raises the health flag.
 __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ descs)
 {
     const SolveDesc& s = descs[blockIdx.y];
@@ -1242,7 +1367,7 @@ __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ d
     const int j = q / nr;
     const int i = q - j * nr;
     const size_t sy = (size_t)nr * nv;
-    gdouble* cp = gp(s.cp) + q;
+    gdouble* yinv = gp(s.yinv) + q;
     RowY row;
     row.yt = gp(s.yt);
     row.ny = ny;
@@ -1255,7 +1380,7 @@ __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ d
     const double f1 = A1 / B0, f2 = C2 / Bl;
     bool ok = B0 > 0.0 && Bl > 0.0;
     double cprev = 0.0;
-    cp[0] = 0.0;
+    yinv[0] = 1.0;
     for (int kk = 1; kk < ny - 1; ++kk) {
         double A, B, C, E;
         row(kk, A, B, C, E);
@@ -1263,20 +1388,21 @@ __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ d
         if (kk == ny - 2) { A = A2 - f2 * El; B = B2 - f2 * Al; C = 0.0; }
         const double den = B - A * cprev;
         ok = ok && den > 0.0;
-        cprev = C / den;
-        cp[(size_t)kk * sy] = cprev;
+        const double inv = rcp_nr(den);
+        cprev = C * inv;
+        yinv[(size_t)kk * sy] = inv;
     }
-    cp[(size_t)(ny - 1) * sy] = 0.0;
+    yinv[(size_t)(ny - 1) * sy] = 1.0;
     const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir);
     if (!ok && !line_dir) raise_flag(s);
 }
 
-// y sweep + update on the stored pivots: Thomas in row order, segments of
-// ROWS rows chained through LDS (segment s runs once segment s-1 has handed
-// over d' of its last row); the only serial work per row is one FMA forward
-// and one backward.  Then U^{n+1} = U^n + D3.  Workgroup = yc_S waves; wave w
-// holds rows [w ROWS, (w+1) ROWS) of 64 consecutive lines (i, j), so row
-// reads are contiguous and the y-table reads are wave-uniform.
+// y sweep + update on the stored reciprocal pivots: Thomas in row order,
+// segments of ROWS rows chained through LDS (segment s runs once segment s-1
+// has handed over d' of its last row); the only serial work per row is one
+// FMA forward and one backward.  Then U^{n+1} = U^n + D3.  Workgroup = yc_S
+// waves; wave w holds rows [w ROWS, (w+1) ROWS) of 64 consecutive lines
+// (i, j), so row reads are contiguous and the y-table reads are wave-uniform.
 template <int ROWS>
 __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
@@ -1301,18 +1427,22 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
     const size_t off = (size_t)qc + (size_t)sg * ROWS * sy;
     gdouble* D = gp(s.D);
     gdouble* U = gp(s.U);
-    gcdouble* CPg = gp(s.cp);
+    gcdouble* YI = gp(s.yinv);
     kcdouble* yt = kp(s.yt);
     const bool first = sg == 0;
     const bool last = sg == S - 1;
-    double d[ROWS], al[ROWS], cp[ROWS], u[ROWS];
+    // inactive lanes read line 0 of segment 0 (in bounds; never stored), so
+    // the loads need no branches.  C inv waits in LDS and U^n is read only at
+    // the end, so that the chains hold just d and -A inv in registers and two
+    // workgroups fit on a compute unit.
+    double d[ROWS], al[ROWS], iv[ROWS];
 #pragma unroll
     for (int mm = 0; mm < ROWS; ++mm) {
-        d[mm] = active ? D[off + (size_t)mm * sy] : 0.0;
-        cp[mm] = active ? CPg[off + (size_t)mm * sy] : 0.0;
-        u[mm] = active ? U[off + (size_t)mm * sy] : 0.0;
+        d[mm] = D[off + (size_t)mm * sy];
+        iv[mm] = YI[off + (size_t)mm * sy];
     }
-    const double cpm = (active && !first) ? CPg[off - sy] : 0.0;
+    // C inv goes to LDS (it is needed only by the backward chain), [row][lane]
+    ldouble* cpl = lds + 128 + (size_t)sg * ROWS * 64 + l;
     const double qv = gp(s.rt)[RT_Y * nr + i] * gp(s.vt)[VT_V * nv + j];
     auto row = [&](int kk, double& A, double& B, double& C, double& E) {
         const double a = yt[YT_T1 * ny + kk] * qv + yt[YT_T2 * ny + kk];
@@ -1322,13 +1452,13 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
         E = yt[YT_ME * ny + kk] * a;
     };
     double d0 = 0.0, B0 = 1.0, C0 = 0.0, E0 = 0.0, dl = 0.0, Al = 0.0, Bl = 1.0, El = 0.0;
-    double b1m = 1.0, a2m = 0.0, b2m = 1.0;
+    double c1m = 0.0, a2m = 0.0;
     if (first) {
         double A0, A1, B1, C1, E1;
         row(0, A0, B0, C0, E0);
         row(1, A1, B1, C1, E1);
         const double f = A1 / B0;
-        b1m = B1 - f * C0;
+        c1m = C1 - f * E0;
         d0 = d[0];
         if (work) d[1] = d[1] - f * d0;
     }
@@ -1338,27 +1468,23 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
         row(ny - 2, A2, B2, C2, E2);
         const double f = C2 / Bl;
         a2m = A2 - f * El;
-        b2m = B2 - f * Al;
         dl = d[ROWS - 1];
         if (work) d[ROWS - 2] = d[ROWS - 2] - f * dl;
     }
-    bool ok = true;
-    // pivots from the stored c'_{k-1}: den_k = B_k - A_k c'_{k-1}; the
-    // recurrence becomes d'_k = d_k / den_k + (-A_k / den_k) d'_{k-1}
-    // (lines on a Dirichlet r face keep D: identity rows)
+    // with inv_k = 1 / den_k the recurrences are d'_k = inv_k d_k +
+    // (-A_k inv_k) d'_{k-1} and x_k = d'_k - (C_k inv_k) x_{k+1}; rows 0 and
+    // n-1 are identity rows (lines on a Dirichlet r face keep D)
 #pragma unroll
     for (int mm = 0; mm < ROWS; ++mm) {
         const int kk = sg * ROWS + mm;
         double A, B, C, E;
         row(kk, A, B, C, E);
-        if (mm == 0) { A = first ? 0.0 : A; B = first ? 1.0 : B; }
-        if (mm == 1) { B = first ? b1m : B; A = first ? 0.0 : A; }
-        if (mm == ROWS - 2) { A = last ? a2m : A; B = last ? b2m : B; }
-        if (mm == ROWS - 1) { A = last ? 0.0 : A; B = last ? 1.0 : B; }
-        const double cprev = mm == 0 ? cpm : cp[mm - 1];
-        const double den = B - A * cprev;
-        const double inv = rcp_nr(den);
-        ok = ok && (!work || den > 0.0);
+        if (mm == 0) { A = first ? 0.0 : A; C = first ? 0.0 : C; }
+        if (mm == 1) { A = first ? 0.0 : A; C = first ? c1m : C; }
+        if (mm == ROWS - 2) { A = last ? a2m : A; C = last ? 0.0 : C; }
+        if (mm == ROWS - 1) { A = last ? 0.0 : A; C = last ? 0.0 : C; }
+        const double inv = iv[mm];
+        if (seg < S) cpl[mm * 64] = C * inv;  // waves past S (batches) share segment 0's rows: no write
         al[mm] = work ? -A * inv : 0.0;
         d[mm] = work ? d[mm] * inv : d[mm];
     }
@@ -1380,7 +1506,7 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
             double x = stage < S - 1 ? xch[1] : 0.0;
 #pragma unroll
             for (int mm = ROWS - 1; mm >= 0; --mm) {
-                x = d[mm] - cp[mm] * x;
+                x = d[mm] - cpl[mm * 64] * x;
                 d[mm] = x;
             }
             xch[1] = x;
@@ -1390,10 +1516,12 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
         if (S > 1) __syncthreads();
     }
     if (active) {
+        double u[ROWS];
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) u[mm] = U[off + (size_t)mm * sy];
 #pragma unroll
         for (int mm = 0; mm < ROWS; ++mm) U[off + (size_t)mm * sy] = u[mm] + d[mm];
     }
-    if (work && !ok) raise_flag(s);
 }
 
 __global__ void k_readout(const SolveDesc* __restrict__ descs, const Readout* __restrict__ rq, int n,
@@ -1459,7 +1587,8 @@ hipError_t init_kernel_attributes()
             (e = allow_lds(k_v<8>)) || (e = allow_lds(k_v<16>)) || (e = allow_lds(k_v<32>)) ||
             (e = allow_lds(k_yu<8>)) || (e = allow_lds(k_yu<16>)) || (e = allow_lds(k_yu<32>)) ||
             (e = allow_lds(k_rs<6>)) || (e = allow_lds(k_rs<8>)) || (e = allow_lds(k_rs<12>)) ||
-            (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
+            (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_exr<8>)) || (e = allow_lds(k_exr<12>)) ||
+            (e = allow_lds(k_exr<16>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
             (e = allow_lds(k_vs<32>)) || (e = allow_lds(k_yc<8>)) || (e = allow_lds(k_yc<16>)) ||
             (e = allow_lds(k_yc<32>)))
             return e;
@@ -1547,6 +1676,30 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     return hipGetLastError();
 }
 
+void exr_lds(int nr, int rows, size_t* bytes, int* tab)
+{
+    const int S = nr / rows;
+    const int P = kBlock / nr;
+    const int lanes = P * kExrJ * S;
+    const int passes = (lanes + kBlock - 1) / kBlock;
+    const int tile = passes * kBlock * (rows + 1);  // whole passes: the last pass's scratch stays inside
+    *tab = tile;
+    *bytes = ((size_t)tile + (size_t)S * (kRF * rows + 1)) * 8;
+}
+
+hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
+                      hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    switch (rows) {
+    case 8: HJM_LAUNCH(k_exr<8>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 12: HJM_LAUNCH(k_exr<12>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 16: HJM_LAUNCH(k_exr<16>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 bool vs_rows_supported(int rows) { return rows == 8 || rows == 16 || rows == 32; }
 bool yc_rows_supported(int rows) { return rows == 8 || rows == 16 || rows == 32; }
 
@@ -1571,7 +1724,8 @@ hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n
 {
     if (n_tasks <= 0) return hipSuccess;
     if (S_max < 1 || S_max > yc_max_segments(rows)) return hipErrorInvalidValue;
-    const size_t lds = (size_t)2 * 64 * 8;
+    // the exchange slots (2 per lane) and C inv of every row of the lines
+    const size_t lds = (size_t)(2 + (size_t)S_max * rows) * 64 * 8;
     HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_yc<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
     return hipGetLastError();
 }

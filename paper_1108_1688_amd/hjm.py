@@ -21,7 +21,7 @@ FACE_OUTFLOW, FACE_DIRICHLET = 0, 1
 BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
 N_PASSES = 4  # HJM_N_PASSES
 PASSES = ("explicit", "r", "v", "y+update")
-R_METHODS = ("spike", "chain", "split")
+R_METHODS = ("spike", "chain", "split", "fused")
 MLP_PARAMS = 199937  # HJM_MLP_PARAMS
 
 
@@ -83,6 +83,8 @@ def lib():
         "hjm_get_line_tile": (st, [P(i32), P(i32), P(i32)]),
         "hjm_set_explicit_chunk": (st, [i32]),
         "hjm_get_explicit_chunk": (st, [P(i32)]),
+        "hjm_set_r_fusion": (st, [i32]),
+        "hjm_get_r_fusion": (st, [P(i32)]),
         "hjm_mlp_workspace_bytes": (st, [i64, P(sz)]),
         "hjm_mlp_create": (st, [P(C.c_float), P(C.c_float), C.c_float, C.c_float, i64, vp, sz, vp, P(vp)]),
         "hjm_mlp_set_params": (st, [vp, P(C.c_float), i64]),
@@ -146,6 +148,18 @@ def get_explicit_chunk() -> int:
     J = C.c_int32()
     check(lib().hjm_get_explicit_chunk(C.byref(J)))
     return J.value
+
+
+def set_r_fusion(on: bool) -> None:
+    """Fuse the explicit predictor with the spike r solve where possible
+    (default) or keep them as two kernels, for handles created afterwards."""
+    check(lib().hjm_set_r_fusion(1 if on else 0))
+
+
+def get_r_fusion() -> bool:
+    on = C.c_int32()
+    check(lib().hjm_get_r_fusion(C.byref(on)))
+    return bool(on.value)
 
 
 def _torch():
@@ -231,8 +245,8 @@ class Grid:
         check(lib().hjm_grid_set_step(self._h, int(step)))
 
     def plan(self) -> dict:
-        """How this grid is solved: r method ('spike', 'chain' or 'split'),
-        rows per lane of the split r solve, line-tile rows, rows per segment
+        """How this grid is solved: r method ('spike', 'chain', 'split' or
+        'fused'), rows per lane of the split or fused r solve, line-tile rows, rows per segment
         of the segmented v solve and of the stored-pivot y solve (0 where the
         chained per-line solves are used instead)."""
         out = (C.c_int32 * 8)()

@@ -33,8 +33,10 @@ def _need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     old = hjm.get_line_tile()
+    fused = hjm.get_r_fusion()
     yield
     hjm.set_line_tile(*old)
+    hjm.set_r_fusion(fused)
 
 
 PLANS = []  # r method of every grid of the last gpu_grid call
@@ -168,24 +170,48 @@ def test_config3_full_size_first_steps_elementwise():
     configuration): three Douglas steps compared on every node."""
     s = W.config3()[-1]
     Ug, _ = gpu_grid(s, steps=3, price=False)
-    assert PLANS == ["split", True, True]
+    assert PLANS == ["fused", True, True]
     Uo, _ = oracle_grid(s, steps=3)
     assert_grid(Ug, Uo)
 
 
-@pytest.mark.parametrize("method", ["chain", "spike", "split"])
+@pytest.mark.parametrize("method", ["chain", "spike", "split", "fused"])
 def test_each_r_method(method):
     """Each r-line method on a case that selects it: one long step (rows with
     (|A|+|C|)/B far above the spike bound) -> chain; nr = 100 (no power-of-two
-    lane split) -> spike inside the fused kernel; nr = 96 -> split."""
+    lane split) -> spike inside the per-line kernel; nr = 96 (8 lanes of 12
+    rows) -> the explicit kernel and the lane-split spike solve fused into one,
+    or as two kernels with the fusion switched off."""
     if method == "chain":
         s = _sloped((40, 24, 24), 1)
     elif method == "spike":
         s = _sloped((100, 24, 24), 12)
     else:
         s = _sloped((96, 24, 24), 12)
+        hjm.set_r_fusion(method == "fused")
     Ug, pg = gpu_grid(s)
     assert PLANS[0] == method
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+@pytest.mark.parametrize("shape,tile", [((64, 24, 17), 16), ((64, 24, 17), 8), ((32, 20, 13), 16),
+                                        ((32, 20, 13), 8), ((256, 24, 9), 16), ((256, 19, 9), 8),
+                                        ((192, 20, 10), 16), ((16, 33, 7), 16)],
+                         ids=lambda x: "x".join(map(str, x)) if isinstance(x, tuple) else f"rows{x}")
+def test_fused_explicit_r_tiles(shape, tile):
+    """The fused explicit + r kernel over its tilings: 256 / nr whole y planes
+    per workgroup (1 to 16), one or two passes of spike lanes (16 v nodes x
+    planes x nr / rows lanes), several planes per wavefront (nr = 16, 32),
+    ragged plane and v blocks (ny, nv not multiples of the tile), and nr = 192
+    (12 rows per lane, a quarter of the threads idle in the explicit phase).
+    Fine r meshes take 80 steps: with 9 the rows exceed the spike bound and
+    the r lines go to the chained solve."""
+    hjm.set_line_tile(tile, 16, 16)
+    s = _sloped(shape, 9 if shape[0] <= 64 else 80)
+    Ug, pg = gpu_grid(s)
+    assert PLANS[0] == "fused"
     Uo, po = oracle_grid(s)
     assert_grid(Ug, Uo)
     assert_price(pg, po)
