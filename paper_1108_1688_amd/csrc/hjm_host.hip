@@ -405,19 +405,6 @@ SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
     return o;
 }
 
-// Closed-form value g(t_n; r, y) of the contract with the solve's payoff, from
-// the step-table factors p(t,T) = A exp(-G r - H y) (bond formula, section 3.1).
-double dirichlet_host(const double* e, int kind, double accrual, double r, double y)
-{
-    const double pT = e[ST_AT] * std::exp(-e[ST_GT] * r - e[ST_HT] * y);
-    if (kind == HJM_BOND) return pT;
-    const double pM = e[ST_AM] * std::exp(-e[ST_GM] * r - e[ST_HM] * y);
-    const double lin = pT - accrual * pM;
-    if (kind == HJM_CAPLET) return lin > 0.0 ? lin : 0.0;
-    if (kind == HJM_FLOORLET) return -lin > 0.0 ? -lin : 0.0;
-    return lin;
-}
-
 // Fill the host tables of one solve: axis coefficient rows, step table.
 void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps, Plan& plan,
                   std::vector<double>& out)
@@ -606,22 +593,7 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
         e[ST_GM] = GM;
         e[ST_HM] = 0.5 * GM * GM;
     }
-    // Dirichlet increments g(t_{n+1}) - g(t_n) on the r faces and the y_max face
-    const double accrual = 1.0 + (p.pay - p.expiry) * p.strike;
-    const double ymax = my.z[ny - 1];
-    for (int n = 0; n < n_steps; ++n) {
-        const double* e0 = st + (size_t)kStepStride * n;
-        const double* e1 = e0 + kStepStride;
-        double* g = gd + (size_t)n * (2 * ny + nr);
-        auto inc = [&](double r, double y) {
-            return dirichlet_host(e1, p.kind, accrual, r, y) - dirichlet_host(e0, p.kind, accrual, r, y);
-        };
-        for (int k = 0; k < ny; ++k) {
-            g[GD_RLO * ny + k] = r_lo_dir ? inc(mr.z[0], my.z[k]) : 0.0;
-            g[GD_RHI * ny + k] = r_hi_dir ? inc(mr.z[nr - 1], my.z[k]) : 0.0;
-        }
-        for (int i = 0; i < nr; ++i) g[GD_YHI * ny + i] = y_hi_dir ? inc(mr.z[i], ymax) : 0.0;
-    }
+    // the Dirichlet increments (gd) are computed on the device (k_gd)
 }
 
 void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps,
@@ -666,6 +638,17 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.yinv = reinterpret_cast<double*>(base + o.YI);
     d.vs_S = pl.vs_S; d.vs_tiles = pl.vs_tiles;
     d.yc_S = pl.yc_S; d.yc_L = pl.yc_L; d.yc_tiles = pl.yc_tiles;
+}
+
+// Upload a solve's host tables, all but the Dirichlet increments (gd), which
+// k_gd computes on the device.
+hipError_t upload_tables(const SolveDesc& d, const std::vector<double>& t, hipStream_t st)
+{
+    const size_t gd_off = (size_t)(d.gd - d.rt), vg_off = (size_t)(d.vg - d.rt);
+    hipError_t e = hipMemcpyAsync(const_cast<double*>(d.rt), t.data(), gd_off * 8, hipMemcpyHostToDevice, st);
+    if (!e) e = hipMemcpyAsync(const_cast<double*>(d.vg), t.data() + vg_off, (t.size() - vg_off) * 8,
+                               hipMemcpyHostToDevice, st);
+    return e;
 }
 
 // 4-point Lagrange stencil in mesh coordinates (window centred on the
@@ -868,8 +851,8 @@ hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const h
     hipError_t e;
     if ((e = init_kernel_attributes()) ||
         (e = hipMemcpyAsync(g->d_desc, &g->desc, sizeof(SolveDesc), hipMemcpyHostToDevice, g->stream)) ||
-        (e = hipMemcpyAsync(const_cast<double*>(g->desc.rt), g->tables.data(), g->tables.size() * 8,
-                            hipMemcpyHostToDevice, g->stream)) ||
+        (e = upload_tables(g->desc, g->tables, g->stream)) ||
+        (e = launch_gd(g->d_desc, 1, (int64_t)(2 * ax[2].n + ax[0].n) * n_steps, g->stream)) ||
         (e = launch_terminal(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n * ax[2].n, g->stream)) ||
         (e = launch_ypiv(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n, g->stream)) ||
         (e = hipStreamSynchronize(g->stream))) {
@@ -1262,9 +1245,12 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
     if (!e) e = hipMemcpyAsync(b->d_desc, b->descs.data(), sizeof(SolveDesc) * n, hipMemcpyHostToDevice, b->stream);
     if (!e && !all.empty())
         e = hipMemcpyAsync(b->d_tasks, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, b->stream);
-    for (int s = 0; s < n && !e; ++s)
-        e = hipMemcpyAsync(const_cast<double*>(b->descs[s].rt), b->tables[s].data(), b->tables[s].size() * 8,
-                           hipMemcpyHostToDevice, b->stream);
+    int64_t max_gd = 0;
+    for (int s = 0; s < n && !e; ++s) {
+        e = upload_tables(b->descs[s], b->tables[s], b->stream);
+        max_gd = std::max<int64_t>(max_gd, (int64_t)(2 * ax[3 * s + 2].n + ax[3 * s].n) * n_steps[s]);
+    }
+    if (!e) e = launch_gd(b->d_desc, n, max_gd, b->stream);
     if (!e) e = launch_ypiv(b->d_desc, n, b->max_ylines, b->stream);
     if (!e) e = hipStreamSynchronize(b->stream);
     if (e) {

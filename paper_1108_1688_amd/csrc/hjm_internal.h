@@ -165,6 +165,9 @@ hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int 
 // rows per thread available to k_rs
 bool rs_rows_supported(int rows);
 hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);
+// Dirichlet increments of every step into each solve's gd table; max_entries
+// = the largest (2 ny + nr) n_steps of the solves
+hipError_t launch_gd(const SolveDesc* d_desc, int n_solves, int64_t max_entries, hipStream_t st);
 hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines, hipStream_t st);
 hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);
 // k_yc holds 4 ROWS-long arrays per thread: workgroups of at most 128 / ROWS

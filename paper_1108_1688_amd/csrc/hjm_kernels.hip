@@ -1524,6 +1524,37 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
     }
 }
 
+// Dirichlet increments g(t_{n+1}) - g(t_n) of every step (the Douglas D0 on
+// Dirichlet nodes): r_min face by k, r_max face by k, y_max face by i; zero
+// where the face is not Dirichlet.  Once per solve; thread = (step, entry).
+__global__ __launch_bounds__(kBlock) void k_gd(const SolveDesc* __restrict__ descs)
+{
+    const SolveDesc& s = descs[blockIdx.y];
+    const int nr = s.nr, ny = s.ny;
+    const int W = 2 * ny + nr;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (int64_t)W * s.n_steps) return;
+    const int n = (int)(idx / W);
+    const int e = (int)(idx - (int64_t)n * W);
+    gcdouble* rt = gp(s.rt);
+    gcdouble* yt = gp(s.yt);
+    gcdouble* stn = gp(s.st) + (size_t)kStepStride * n;
+    bool dir;
+    double r, y;
+    if (e < 2 * ny) {
+        const bool hi = e >= ny;
+        dir = hi ? s.r_hi_dir : s.r_lo_dir;
+        r = rt[RT_R * nr + (hi ? nr - 1 : 0)];
+        y = yt[YT_Y * ny + (hi ? e - ny : e)];
+    } else {
+        dir = s.y_hi_dir;
+        r = rt[RT_R * nr + (e - 2 * ny)];
+        y = yt[YT_Y * ny + ny - 1];
+    }
+    const double inc = dir ? dirichlet_value(s, stn + kStepStride, r, y) - dirichlet_value(s, stn, r, y) : 0.0;
+    gp(const_cast<double*>(s.gd))[idx] = inc;
+}
+
 __global__ void k_readout(const SolveDesc* __restrict__ descs, const Readout* __restrict__ rq, int n,
                           double* __restrict__ out)
 {
@@ -1709,6 +1740,14 @@ hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     if (S_max < 1 || S_max > 4) return hipErrorInvalidValue;
     const size_t lds = (size_t)2 * 4 * 64 * 8;
     HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_vs<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
+    return hipGetLastError();
+}
+
+hipError_t launch_gd(const SolveDesc* d_desc, int n_solves, int64_t max_entries, hipStream_t st)
+{
+    const int64_t blocks = (max_entries + kBlock - 1) / kBlock;
+    if (blocks < 1 || n_solves < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_gd, dim3((unsigned)blocks, (unsigned)n_solves), dim3(kBlock), 0, st, d_desc);
     return hipGetLastError();
 }
 
