@@ -35,17 +35,23 @@ PASS_NAMES = ["explicit", "r", "v", "y+update"]
 # algorithmic minimum of a whole Douglas step: read U twice (explicit, update)
 # plus D through the v and y sweeps, D0 never leaving the chip: 56 B per point
 STEP_BYTES = 56.0
-PROFILED_STEPS = 20  # per solve and bench step (host-side event handling slows the enqueue)
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (FETCH_SIZE
-# scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain copy kernel of
-# known size reads), valid only for the kernel sources and line tiles they were
-# taken on: reported as null otherwise.
+# Douglas steps whose kernel launches are timed: the first 20 of the batch (or of
+# each grid in --mode grids).  Every step of a solve does the same work; events
+# on every launch of the batch measured 3.5 % slower end to end (the dispatch
+# records the timestamps), and in --mode grids they make the host the
+# bottleneck.
+PROFILED_STEPS = 20
+# HBM bytes per grid point of each pass's kernel from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes over one-grid launches (FETCH_SIZE scaled by 2.000 and
+# WRITE_SIZE by 1.000, the factors a plain copy kernel of known size reads),
+# valid only for the kernel sources and settings they were taken on: reported
+# as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "a6fb5a21a4fefa8f48dda49e2fcb78c83567ae74aa550a2fd3778d9b62374a22"
-                      ":e5e3a2bc939b3b6e15cc32fcb1b62bf9f8a90bf09cf0b4aa77d7cab970e20db5",
+    "sources_sha256": "",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
-    "bytes": {'explicit': 80077619, 'r': 67135488, 'v': 67004416, 'y+update': 134466765},
+    "r_fusion": True,
+    "bytes_per_point": {},
 }
 
 
@@ -197,6 +203,10 @@ def main():
     ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
     ap.add_argument("--exp-chunk", type=int, default=None, help="v nodes per explicit-kernel thread (4, 8, 16)")
+    ap.add_argument("--profile-steps", type=int, default=PROFILED_STEPS,
+                    help="batch mode: time the launches of the first N Douglas steps (0: all)")
+    ap.add_argument("--no-fusion", action="store_true",
+                    help="keep the explicit predictor and the r sweep as two kernels")
     ap.add_argument("--mode", choices=("batch", "grids"), default="batch",
                     help="price the ten caplets as one batch (default) or one grid after the other")
     args = ap.parse_args()
@@ -214,6 +224,8 @@ def main():
         hjm.set_line_tile(*[int(x) for x in args.tile.split(",")])
     if args.exp_chunk:
         hjm.set_explicit_chunk(args.exp_chunk)
+    if args.no_fusion:
+        hjm.set_r_fusion(False)
     torch.cuda.set_device(0)
     specs = W.config3()
     points = specs[0].points
@@ -226,7 +238,7 @@ def main():
             # kernel covering every caplet still running
             b = hjm.Batch(specs, stream=stream)
             if profile:
-                b.profile(PROFILED_STEPS)
+                b.profile(args.profile_steps or max(s.n_steps for s in specs))
             b.run()
             prices = list(b.prices())
             prof = [b.profile_read()] if profile else None
@@ -270,10 +282,9 @@ def main():
     ms_per_step = 1e3 * el / args.steps
     value = points * total_steps * args.steps / el
 
-    # every launch of the first PROFILED_STEPS Douglas steps of every caplet is
-    # timed by HIP events its dispatch records (each step does the same work);
-    # achieved GB/s = algorithmic bytes of the grid points those launches
-    # advanced / their summed duration
+    # the launches of the first profiled steps carry HIP events their dispatch
+    # records; achieved GB/s = algorithmic bytes of the grid points those
+    # launches advanced / their summed duration
     npass = len(PASS_NAMES)
     pass_ms = [0.0] * npass
     pass_n = [0] * npass
@@ -298,17 +309,20 @@ def main():
                         "share": round(pass_ms[q] / max(sum(pass_ms), 1e-12), 3)}
     traffic_ok = (kernel_sources_sha256() == MEASURED_TRAFFIC["sources_sha256"]
                   and tuple(hjm.get_line_tile()) == MEASURED_TRAFFIC["line_tile"]
-                  and hjm.get_explicit_chunk() == MEASURED_TRAFFIC["explicit_chunk"])
+                  and hjm.get_explicit_chunk() == MEASURED_TRAFFIC["explicit_chunk"]
+                  and hjm.get_r_fusion() == MEASURED_TRAFFIC["r_fusion"])
     for name in passes:
-        b = MEASURED_TRAFFIC["bytes"].get(name)
-        passes[name]["traffic_bytes"] = b if (traffic_ok and b is not None) else None
+        b = MEASURED_TRAFFIC["bytes_per_point"].get(name)
+        ok = traffic_ok and b is not None
+        passes[name]["traffic_bytes_per_point"] = b if ok else None
+        passes[name]["traffic_bytes"] = round(b * passes[name]["points_per_launch"]) if ok else None
     dom = max(range(npass), key=lambda q: pass_ms[q])
     dname = names[dom]
     achieved = passes[dname]["GB/s"]
     step_gbs = STEP_BYTES * pass_pts[0] / (sum(pass_ms) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": passes[dname]["traffic_bytes"],
-                "traffic_unit": "bytes per 4,194,304-point grid and launch",
+                "traffic_unit": "HBM bytes per launch (measured bytes per point x points per launch)",
                 "bytes_per_point": PASS_BYTES[dname], "points_per_launch": passes[dname]["points_per_launch"],
                 "douglas_step_GBs": round(step_gbs, 1), "passes": passes}
     log(f"prices (1..10y): {[round(p, 8) for p in prices]}")
@@ -324,7 +338,7 @@ def main():
                                      "priced one grid after the other"),
                       "mode": args.mode,
                       "grid": [256, 128, 128], "douglas_steps": total_steps, "line_tile": list(hjm.get_line_tile()),
-                      "explicit_chunk": hjm.get_explicit_chunk(),
+                      "explicit_chunk": hjm.get_explicit_chunk(), "r_fusion": hjm.get_r_fusion(),
                       "parallelism": "single GPU"},
            "roofline": roofline}
     if not args.no_calibration:

@@ -1094,20 +1094,19 @@ __device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* 
                 bet = -vL * bet * del - wL;
                 r[0] = gam; r[1] = del; r[2] = alp; r[3] = bet;
             }
-            double Fn = 0.0, Lp = 0.0;
+            // backward: F_q and L_q from F_{q+1}; segment q+1 couples to L_q
+            // on its left and segment q to F_{q+1} on its right
+            double Fn = 0.0;
 #pragma unroll 4
             for (int qq = S - 1; qq >= 0; --qq) {
                 ldouble* r = my + qq * 8;
                 const double F = r[0] + r[1] * Fn;
-                r[5] = r[2] + r[3] * Fn;  // L_q
-                r[6] = Fn;                // X_R of segment q
+                const double L = r[2] + r[3] * Fn;
+                r[6] = Fn;                        // X_R of segment q
+                if (qq + 1 < S) r[8 + 7] = L;     // X_L of segment q+1
                 Fn = F;
             }
-            for (int qq = 0; qq < S; ++qq) {
-                ldouble* r = my + qq * 8;
-                r[7] = Lp;                // X_L of segment q
-                Lp = r[5];
-            }
+            my[7] = 0.0;                          // X_L of segment 0
         }
         wave_sync();
         XL = my[7];
