@@ -136,6 +136,24 @@ def test_line_tile_setting(L):
         hjm.set_line_tile(*old)
 
 
+def test_tuning_knobs(L):
+    """Explicit chunk and r fusion: process-wide host settings, read back as
+    set; invalid chunks rejected."""
+    old_J, old_f = hjm.get_explicit_chunk(), hjm.get_r_fusion()
+    try:
+        for J in (4, 8, 16):
+            hjm.set_explicit_chunk(J)
+            assert hjm.get_explicit_chunk() == J
+        with pytest.raises(hjm.HjmError):
+            hjm.set_explicit_chunk(6)
+        for on in (False, True):
+            hjm.set_r_fusion(on)
+            assert hjm.get_r_fusion() is on
+    finally:
+        hjm.set_explicit_chunk(old_J)
+        hjm.set_r_fusion(old_f)
+
+
 def test_batch_validation(L):
     specs = W.config4(n=4)
     n = len(specs)
