@@ -873,12 +873,17 @@ __device__ __forceinline__ void wave_sync()
 // centred stencils of eq. (esquema), one-sided rows on outflow faces), and the
 // Dirichlet increment on Dirichlet nodes, at the J nodes (i, j0 + m, k),
 // m < J, j0 + m < nv; put(m, value) receives each.  The caller's lanes are
-// consecutive i, so every load of a wave is one contiguous row segment.  All
-// loads are issued up front: the v window u(i, j0-2 .. j0+J+1), the
-// neighbouring columns u(i -+ 1, j0-1 .. j0+J) and the two y neighbours; the
-// outflow extra entry (two nodes in) only on the r faces, where its weight is
-// not zero.  j0 must be wave-uniform (the v-table reads are scalar).
-template <int J, class Put>
+// consecutive i (lane = threadIdx.x mod 64, whole waves), so every load of a
+// wave is one contiguous row segment.  The loads are issued up front: the v
+// window u(i, j0-2 .. j0+J+1) and the two y neighbours; the outflow extra
+// entry (two nodes in) only on the r faces, where its weight is not zero.
+// The neighbouring columns u(i -+ 1, j0-1 .. j0+J) are loaded too (SHFL
+// false) or taken from the neighbouring lanes' v windows by cross-lane
+// permutes, the wave's edge lanes loading theirs (SHFL true: fewer loads and
+// registers, one more LDS-pipe latency before the arithmetic; measured
+// faster inside the fused kernel, slower in the explicit kernel alone).  j0
+// must be wave-uniform (the v-table reads are scalar).
+template <int J, bool SHFL, class Put>
 __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k, int j0, int step, const Put& put)
 {
     const int nr = s.nr, nv = s.nv, ny = s.ny;
@@ -906,14 +911,34 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
 #pragma unroll
     for (int m = 0; m < J + 4; ++m) cw[m] = col[jcl(j0 - 2 + m) + i];
 #pragma unroll
-    for (int m = 0; m < J + 2; ++m) {
-        lw[m] = col[jcl(j0 - 1 + m) + im];
-        rw[m] = col[jcl(j0 - 1 + m) + ip];
-    }
-#pragma unroll
     for (int m = 0; m < J; ++m) {
         ya[m] = cola[jcl(j0 + m) + i];
         yb[m] = colb[jcl(j0 + m) + i];
+    }
+    if (SHFL) {
+        // the r faces clamp to the node itself
+        const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+        for (int m = 0; m < J + 2; ++m) {
+            const double lo = __shfl_up(cw[m + 1], 1);
+            const double hi = __shfl_down(cw[m + 1], 1);
+            lw[m] = i == 0 ? cw[m + 1] : lo;
+            rw[m] = i == nr - 1 ? cw[m + 1] : hi;
+        }
+        if (lane == 0 && i > 0) {
+#pragma unroll
+            for (int m = 0; m < J + 2; ++m) lw[m] = col[jcl(j0 - 1 + m) + im];
+        }
+        if (lane == 63 && i < nr - 1) {
+#pragma unroll
+            for (int m = 0; m < J + 2; ++m) rw[m] = col[jcl(j0 - 1 + m) + ip];
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < J + 2; ++m) {
+            lw[m] = col[jcl(j0 - 1 + m) + im];
+            rw[m] = col[jcl(j0 - 1 + m) + ip];
+        }
     }
     if (dx != 0) {
         // outflow r face rows reach two nodes in
@@ -984,7 +1009,7 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     // j is the same on every lane: keep it (and the v-table reads) scalar
     const int j0 = __builtin_amdgcn_readfirstlane(jc * J);
     gdouble* dcol = gp(s.D) + (size_t)k * nr * s.nv + (size_t)j0 * nr + i;
-    explicit_nodes<J>(s, i, k, j0, step, [&](int m, double x) { dcol[(size_t)m * nr] = x; });
+    explicit_nodes<J, false>(s, i, k, j0, step, [&](int m, double x) { dcol[(size_t)m * nr] = x; });
 }
 
 // The spike solve of one r line of nr = S * ROWS rows (S a power of two <=
@@ -1236,7 +1261,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
             ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
 #pragma unroll 1
             for (int jc = 0; jc < kExrJ; jc += 8)
-                explicit_nodes<8>(s, i, k, j0 + jc, step,
+                explicit_nodes<8, true>(s, i, k, j0 + jc, step,
                                   [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; });
         }
     }
