@@ -35,12 +35,13 @@ PASS_NAMES = ["explicit", "r", "v", "y+update"]
 # algorithmic minimum of a whole Douglas step: read U twice (explicit, update)
 # plus D through the v and y sweeps, D0 never leaving the chip: 56 B per point
 STEP_BYTES = 56.0
-# Douglas steps whose kernel launches are timed: the first 20 of the batch (or of
-# each grid in --mode grids).  Every step of a solve does the same work; events
-# on every launch of the batch measured 3.5 % slower end to end (the dispatch
-# records the timestamps), and in --mode grids they make the host the
-# bottleneck.
-PROFILED_STEPS = 20
+# Douglas steps whose kernel launches are timed: the first 10 of the batch (or of
+# each grid in --mode grids).  Every step of a solve does the same work.  The
+# timed steps run one launch at a time (no stream-lane overlap) and their
+# events cost a few us per launch (timing every launch of the batch measured
+# 3.5 % slower end to end; in --mode grids the host would become the
+# bottleneck), so only a sample is timed.
+PROFILED_STEPS = 10
 # HBM bytes per grid point of each pass's kernel from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE passes over one-grid launches (FETCH_SIZE scaled by 2.000 and
 # WRITE_SIZE by 1.000, the factors a plain copy kernel of known size reads),
@@ -206,6 +207,8 @@ def main():
     ap.add_argument("--exp-chunk", type=int, default=None, help="v nodes per explicit-kernel thread (4, 8, 16)")
     ap.add_argument("--profile-steps", type=int, default=PROFILED_STEPS,
                     help="batch mode: time the launches of the first N Douglas steps (0: all)")
+    ap.add_argument("--streams", type=int, default=None,
+                    help="stream lanes the batch spreads its solves over (library default 2)")
     ap.add_argument("--no-fusion", action="store_true",
                     help="keep the explicit predictor and the r sweep as two kernels")
     ap.add_argument("--mode", choices=("batch", "grids"), default="batch",
@@ -227,6 +230,8 @@ def main():
         hjm.set_explicit_chunk(args.exp_chunk)
     if args.no_fusion:
         hjm.set_r_fusion(False)
+    if args.streams:
+        hjm.set_batch_streams(args.streams)
     torch.cuda.set_device(0)
     specs = W.config3()
     points = specs[0].points
@@ -334,12 +339,13 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "256x128x128 grid (r x v x y), 10 ATM caplets expiring 1..10y paid +1y, "
                                   "dt=0.025 (2200 Douglas steps per bench step), seeded parameters (seed 2); "
-                                  + ("priced as one batch (one launch per kernel and Douglas step for all "
-                                     "caplets still running)" if args.mode == "batch" else
+                                  + ("priced as one batch (one launch per kernel, Douglas step and stream "
+                                     "lane for its caplets still running)" if args.mode == "batch" else
                                      "priced one grid after the other"),
                       "mode": args.mode,
                       "grid": [256, 128, 128], "douglas_steps": total_steps, "line_tile": list(hjm.get_line_tile()),
                       "explicit_chunk": hjm.get_explicit_chunk(), "r_fusion": hjm.get_r_fusion(),
+                      "stream_lanes": hjm.get_batch_streams() if args.mode == "batch" else 1,
                       "parallelism": "single GPU"},
            "roofline": roofline}
     if not args.no_calibration:

@@ -179,8 +179,12 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
 
 /* Enqueue a complete solve of every problem: terminal data at t = T, then
    every Douglas step, where at step n one launch per pass covers all solves
-   with more than n steps.  use_graph != 0 captures the launches into a HIP
-   graph on the first call (the stream must not be the null stream) and
+   with more than n steps.  The solves are dealt to hjm_get_batch_streams()
+   stream lanes (snake order by work), each launched on a stream the batch
+   owns, forked from and joined back to the batch's stream with events, so
+   that kernels of different lanes run concurrently; every result stays
+   bit-identical.  use_graph != 0 captures the launches (lanes included) into
+   a HIP graph on the first call (the stream must not be the null stream) and
    replays it afterwards. */
 hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph);
 
@@ -190,7 +194,9 @@ hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, do
 
 /* Per-kernel timing of eager runs (hjm_batch_run with use_graph = 0): every
    launch of the first `steps` Douglas steps is bracketed by HIP events the
-   dispatch records (0 turns it off; graph runs are never timed).  The read
+   dispatch records (0 turns it off; graph runs are never timed).  Those steps
+   run one launch at a time on the batch's stream (no lane overlap), so each
+   duration is the kernel's own.  The read
    synchronises and returns, per pass (as for grids), the summed milliseconds,
    the launches and the grid points those launches advanced by one step; the
    sums restart from zero. */
@@ -276,6 +282,12 @@ hjm_status hjm_get_explicit_chunk(int32_t* J);
    16 more bytes of memory traffic per grid point and step.  Process-wide. */
 hjm_status hjm_set_r_fusion(int32_t on);
 hjm_status hjm_get_r_fusion(int32_t* on);
+
+/* Stream lanes of batches created afterwards (1..8, default 2; HJM_EINVAL
+   otherwise).  More lanes overlap more kernels at fewer solves per launch.
+   Process-wide. */
+hjm_status hjm_set_batch_streams(int32_t n);
+hjm_status hjm_get_batch_streams(int32_t* n);
 
 const char* hjm_status_str(hjm_status s);
 const char* hjm_last_error(void);

@@ -209,6 +209,8 @@ int yc_rows_for(int ny, int preferred)
 
 int g_exp_J = 8;      // v nodes per k_exp thread (4, 8 or 16)
 bool g_fuse_r = true;  // fuse the explicit predictor with the spike r solve where k_exr applies
+constexpr int kMaxBatchLanes = 8;
+int g_batch_lanes = 2;  // streams a batch spreads its solves over
 
 // k_rs needs nr = S * ROWS with S a power of two <= 64 lanes; the preferred
 // rows per lane come first.
@@ -788,6 +790,20 @@ hjm_status hjm_set_r_fusion(int32_t on)
     return HJM_OK;
 }
 
+hjm_status hjm_set_batch_streams(int32_t n)
+{
+    if (n < 1 || n > kMaxBatchLanes) return fail(HJM_EINVAL, "batch streams must be 1..%d (got %d)", kMaxBatchLanes, n);
+    g_batch_lanes = n;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_batch_streams(int32_t* n)
+{
+    if (!n) return fail(HJM_EINVAL, "null argument");
+    *n = g_batch_lanes;
+    return HJM_OK;
+}
+
 hjm_status hjm_get_r_fusion(int32_t* on)
 {
     if (!on) return fail(HJM_EINVAL, "null argument");
@@ -1011,6 +1027,7 @@ struct LaunchGroup {
     std::vector<int64_t> pts; // grid points of the solves active per step
     size_t lds = 0;           // dynamic LDS (k_xr, k_v, k_yu)
     int aux = 0;              // k_rs: largest nr; k_vs: most segments
+    int lane = 0;             // the batch stream lane it is launched on
 };
 
 struct hjm_batch {
@@ -1040,9 +1057,18 @@ struct hjm_batch {
     std::vector<int> ev_pass;
     std::vector<int64_t> ev_pts;
     size_t ev_used = 0;
+    // stream lanes: the solves are split into n_lanes groups of similar work,
+    // each launched on a stream of its own, forked from and joined back to
+    // `stream` with events, so that kernels of different groups overlap
+    int n_lanes = 1;
+    std::vector<hipStream_t> lane_st;
+    std::vector<hipEvent_t> fork_ev, join_ev;
     ~hjm_batch()
     {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : fork_ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
+        for (hipStream_t st : lane_st) (void)hipStreamDestroy(st);
     }
 };
 
@@ -1079,19 +1105,19 @@ BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
     return b;
 }
 
-hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step)
+hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step, hipStream_t st)
 {
     const int nt = g.cnt[step];
     const int2* t = b->d_tasks + g.off;
     switch (g.kind) {
-    case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, b->stream);
-    case G_EXR: return launch_exr(g.rows, b->d_desc, t, nt, step, g.lds, b->stream);
-    case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, b->stream);
-    case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, b->stream);
-    case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, b->stream);
-    case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, b->stream);
-    case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, b->stream);
-    default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, b->stream);
+    case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, st);
+    case G_EXR: return launch_exr(g.rows, b->d_desc, t, nt, step, g.lds, st);
+    case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, st);
+    case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, st);
+    case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, st);
+    case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
+    case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, st);
+    default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, st);
     }
 }
 
@@ -1105,12 +1131,22 @@ int group_pass(int kind)
     }
 }
 
+// Enqueue a whole solve of the batch.  Steps before fork_at run on the
+// batch's stream one group after another (the timed steps: each launch alone
+// on the GPU); from fork_at on, each lane's launches go to its own stream.
 hjm_status batch_enqueue(hjm_batch* b, bool timed)
 {
     hipError_t e;
     if ((e = launch_terminal(b->d_desc, b->n, b->max_points, b->stream))) return hip_fail(e, "batch terminal");
-    for (int step = 0; step < b->max_steps; ++step)
-        for (const LaunchGroup& g : b->groups) {  // groups are in step-pass order
+    const int fork_at = b->n_lanes < 2 ? b->max_steps : (timed ? std::min(b->profile_steps, b->max_steps) : 0);
+    for (int step = 0; step < b->max_steps; ++step) {
+        if (step == fork_at) {
+            if ((e = hipEventRecord(b->fork_ev[0], b->stream))) return hip_fail(e, "batch fork");
+            for (hipStream_t st : b->lane_st)
+                if ((e = hipStreamWaitEvent(st, b->fork_ev[0], 0))) return hip_fail(e, "batch fork");
+        }
+        for (const LaunchGroup& g : b->groups) {  // lane by lane, each in step-pass order
+            const hipStream_t st = step < fork_at ? b->stream : b->lane_st[g.lane];
             const bool time_it = timed && step < b->profile_steps && g.cnt[step] > 0;
             if (time_it) {
                 if (b->events.size() < 2 * (b->ev_used + 1)) {
@@ -1126,13 +1162,19 @@ hjm_status batch_enqueue(hjm_batch* b, bool timed)
                 b->ev_pts[b->ev_used] = g.pts[step];
                 set_launch_events(b->events[2 * b->ev_used], b->events[2 * b->ev_used + 1]);
             }
-            e = launch_group(b, g, step);
+            e = launch_group(b, g, step, st);
             if (time_it) {
                 set_launch_events(nullptr, nullptr);
                 b->ev_used += 1;
             }
             if (e) return hip_fail(e, "batch step");
         }
+    }
+    if (fork_at < b->max_steps)
+        for (size_t l = 0; l < b->lane_st.size(); ++l)
+            if ((e = hipEventRecord(b->join_ev[l], b->lane_st[l])) ||
+                (e = hipStreamWaitEvent(b->stream, b->join_ev[l], 0)))
+                return hip_fail(e, "batch join");
     return HJM_OK;
 }
 
@@ -1195,19 +1237,35 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
     std::vector<int> order(n);
     for (int s = 0; s < n; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n_steps[a] > n_steps[c]; });
-    // (kind, rows) -> group, created in pass order
-    auto group = [&](int kind, int rows) -> LaunchGroup& {
+    // stream lanes: solves by decreasing work (points x steps) dealt to the
+    // lanes in snake order, which balances the lanes' work
+    b->n_lanes = std::max(1, std::min(g_batch_lanes, n));
+    std::vector<int> lane_of(n, 0);
+    {
+        std::vector<int> by_work(order);
+        auto work = [&](int q) { return (double)ax[3 * q].n * ax[3 * q + 1].n * ax[3 * q + 2].n * n_steps[q]; };
+        std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int c) { return work(a) > work(c); });
+        for (int r = 0; r < n; ++r) {
+            const int m = r % (2 * b->n_lanes);
+            lane_of[by_work[r]] = m < b->n_lanes ? m : 2 * b->n_lanes - 1 - m;
+        }
+    }
+    // (lane, kind, rows) -> group, created lane by lane in pass order
+    auto group = [&](int lane, int kind, int rows) -> LaunchGroup& {
         for (LaunchGroup& g : b->groups)
-            if (g.kind == kind && g.rows == rows) return g;
+            if (g.lane == lane && g.kind == kind && g.rows == rows) return g;
         b->groups.emplace_back();
+        b->groups.back().lane = lane;
         b->groups.back().kind = kind;
         b->groups.back().rows = rows;
         b->groups.back().cnt.assign(b->max_steps, 0);
         b->groups.back().pts.assign(b->max_steps, 0);
         return b->groups.back();
     };
+    for (int lane = 0; lane < b->n_lanes; ++lane)
     for (int kind = 0; kind < kGroupKinds; ++kind)
         for (int s : order) {
+            if (lane_of[s] != lane) continue;
             const Plan& pl = plans[s];
             const int ns = n_steps[s];
             int rows = 0, tiles = 0;
@@ -1226,7 +1284,7 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
             default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; aux = pl.yc_S; } break;
             }
             if (!tiles) continue;
-            LaunchGroup& g = group(kind, rows);
+            LaunchGroup& g = group(lane, kind, rows);
             for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(s, t));
             const int64_t pts = (int64_t)ax[3 * s].n * ax[3 * s + 1].n * ax[3 * s + 2].n;
             for (int step = 0; step < ns; ++step) {
@@ -1242,6 +1300,16 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
         all.insert(all.end(), g.tasks.begin(), g.tasks.end());
     }
     hipError_t e = init_kernel_attributes();
+    if (b->n_lanes > 1) {
+        // default priority streams; events without timing (fork and join only)
+        for (int l = 0; l < b->n_lanes && !e; ++l) {
+            hipStream_t st = nullptr;
+            hipEvent_t f = nullptr, j = nullptr;
+            if (!(e = hipStreamCreate(&st))) b->lane_st.push_back(st);
+            if (!e && !(e = hipEventCreateWithFlags(&f, hipEventDisableTiming))) b->fork_ev.push_back(f);
+            if (!e && !(e = hipEventCreateWithFlags(&j, hipEventDisableTiming))) b->join_ev.push_back(j);
+        }
+    }
     if (!e) e = hipMemcpyAsync(b->d_desc, b->descs.data(), sizeof(SolveDesc) * n, hipMemcpyHostToDevice, b->stream);
     if (!e && !all.empty())
         e = hipMemcpyAsync(b->d_tasks, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, b->stream);

@@ -85,6 +85,8 @@ def lib():
         "hjm_get_explicit_chunk": (st, [P(i32)]),
         "hjm_set_r_fusion": (st, [i32]),
         "hjm_get_r_fusion": (st, [P(i32)]),
+        "hjm_set_batch_streams": (st, [i32]),
+        "hjm_get_batch_streams": (st, [P(i32)]),
         "hjm_mlp_workspace_bytes": (st, [i64, P(sz)]),
         "hjm_mlp_create": (st, [P(C.c_float), P(C.c_float), C.c_float, C.c_float, i64, vp, sz, vp, P(vp)]),
         "hjm_mlp_set_params": (st, [vp, P(C.c_float), i64]),
@@ -160,6 +162,17 @@ def get_r_fusion() -> bool:
     on = C.c_int32()
     check(lib().hjm_get_r_fusion(C.byref(on)))
     return bool(on.value)
+
+
+def set_batch_streams(n: int) -> None:
+    """Stream lanes of batches created afterwards (1..8)."""
+    check(lib().hjm_set_batch_streams(int(n)))
+
+
+def get_batch_streams() -> int:
+    n = C.c_int32()
+    check(lib().hjm_get_batch_streams(C.byref(n)))
+    return n.value
 
 
 def _torch():

@@ -137,8 +137,8 @@ def test_line_tile_setting(L):
 
 
 def test_tuning_knobs(L):
-    """Explicit chunk and r fusion: process-wide host settings, read back as
-    set; invalid chunks rejected."""
+    """Explicit chunk, r fusion and batch stream lanes: process-wide host
+    settings, read back as set; invalid values rejected."""
     old_J, old_f = hjm.get_explicit_chunk(), hjm.get_r_fusion()
     try:
         for J in (4, 8, 16):
@@ -149,6 +149,16 @@ def test_tuning_knobs(L):
         for on in (False, True):
             hjm.set_r_fusion(on)
             assert hjm.get_r_fusion() is on
+        old_n = hjm.get_batch_streams()
+        try:
+            for n in (1, 3, 8):
+                hjm.set_batch_streams(n)
+                assert hjm.get_batch_streams() == n
+            for bad in (0, 9):
+                with pytest.raises(hjm.HjmError):
+                    hjm.set_batch_streams(bad)
+        finally:
+            hjm.set_batch_streams(old_n)
     finally:
         hjm.set_explicit_chunk(old_J)
         hjm.set_r_fusion(old_f)

@@ -155,3 +155,24 @@ def test_batch_profile_counts_and_prices():
     b.run(graph=True)
     assert np.array_equal(b.prices(), plain)
     assert b.profile_read()[1] == [0] * hjm.N_PASSES
+
+
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_batch_stream_lanes_bitwise(lanes):
+    """Spreading the solves over stream lanes changes no bit, eager or from a
+    graph, against the default (two lanes) and against single solves."""
+    specs = _batch_specs()
+    st = torch.cuda.Stream()
+    ref = hjm.Batch(specs, stream=st).run().prices()
+    old = hjm.get_batch_streams()
+    try:
+        hjm.set_batch_streams(lanes)
+        b = hjm.Batch(specs, stream=st)
+        assert np.array_equal(b.run().prices(), ref)
+        for _ in range(2):
+            b.run(graph=True)
+            assert np.array_equal(b.prices(), ref)
+    finally:
+        hjm.set_batch_streams(old)
+    for sp, p in list(zip(specs, ref))[::5]:
+        assert p == hjm.Grid(sp).step().price()
