@@ -29,6 +29,9 @@ _LIB = os.path.join(_HERE, "libhjm_oracle.so")
 OUTFLOW = 0
 DIRICHLET = 1
 BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
+# ADI schemes: the paper's Douglas, Craig-Sneyd, modified Craig-Sneyd,
+# Hundsdorfer-Verwer
+DOUGLAS, CS, MCS, HV = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -52,6 +55,7 @@ class _Problem(C.Structure):
         ("f_level", C.c_double), ("f_slope", C.c_double), ("f_decay", C.c_double),
         ("kind", C.c_int), ("expiry", C.c_double), ("pay", C.c_double),
         ("strike", C.c_double), ("n_steps", C.c_int),
+        ("scheme", C.c_int), ("theta", C.c_double),
     ]
 
 
@@ -130,6 +134,8 @@ class Problem:
     pay: float = 2.0
     strike: float = 0.03
     n_steps: int = 50
+    scheme: int = DOUGLAS
+    theta: float = 0.5
     _c: _Problem = field(default=None, repr=False, compare=False)
 
     @property
@@ -153,6 +159,7 @@ class Problem:
         p.f_level, p.f_slope, p.f_decay = self.f_level, self.f_slope, self.f_decay
         p.kind, p.expiry, p.pay, p.strike = self.kind, self.expiry, self.pay, self.strike
         p.n_steps = self.n_steps
+        p.scheme, p.theta = self.scheme, self.theta
         self._c = p
         return p
 

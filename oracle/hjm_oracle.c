@@ -22,7 +22,9 @@
  *   - one-sided second-order rows at outflow faces (section 7.3);
  *   - tridiagonal line solves by Gaussian elimination without pivoting
  *     (the Thomas algorithm, section 5);
- *   - the Douglas ADI step of section 5.1 with theta = 1/2;
+ *   - the Douglas ADI step of section 5.1 with theta = 1/2, and the three
+ *     correction schemes of the same family (Craig-Sneyd, which the paper
+ *     tried, modified Craig-Sneyd, Hundsdorfer-Verwer) with any theta;
  *   - the readout C(t=0; r0, v0, y=0) by 4-point Lagrange interpolation;
  *   - the Gaussian (gamma = 0, epsilon = 0) caplet closed form used as a pin.
  *
@@ -72,11 +74,22 @@ typedef struct {
     double pay;         /* T_M */
     double strike;      /* K */
     int n_steps;        /* N: dt = T / N */
+    int scheme;         /* ORC_DOUGLAS (the paper's), ORC_CS, ORC_MCS, ORC_HV */
+    double theta;       /* implicit weight of the line solves (the paper: 1/2) */
 } orc_problem;
 
 #define ORC_OUTFLOW 0
 #define ORC_DIRICHLET 1
-#define THETA_CN 0.5   /* Crank-Nicolson weight, section 5 */
+/* ADI schemes: the paper's Douglas scheme (section 5.1) and the three
+   schemes that add a correction stage for the mixed derivative: Craig and
+   Sneyd (the paper tried it, section 5.1, without giving its stages), and
+   the modified Craig-Sneyd and Hundsdorfer-Verwer schemes (in 't Hout and
+   Welfert, "Stability of ADI schemes applied to convection-diffusion
+   equations with mixed derivative terms", Appl. Numer. Math. 57 (2007)). */
+#define ORC_DOUGLAS 0
+#define ORC_CS 1
+#define ORC_MCS 2
+#define ORC_HV 3
 
 void orc_set_threads(int n)
 {
@@ -492,11 +505,11 @@ static int sweep(const orc_problem* p, const mesh* M, int d, double t, double dt
                     continue;
                 }
                 oprow o = op_row(p, M, d, i, j, k, f, ft);
-                a[m] = -THETA_CN * dt * o.lo;
-                b[m] = 1.0 - THETA_CN * dt * o.di;
-                c[m] = -THETA_CN * dt * o.up;
-                if (m == 0) e_lo = -THETA_CN * dt * o.ex;
-                if (m == n - 1) e_hi = -THETA_CN * dt * o.ex;
+                a[m] = -p->theta * dt * o.lo;
+                b[m] = 1.0 - p->theta * dt * o.di;
+                c[m] = -p->theta * dt * o.up;
+                if (m == 0) e_lo = -p->theta * dt * o.ex;
+                if (m == n - 1) e_hi = -p->theta * dt * o.ex;
             }
             orc_line_solve(n, a, b, c, e_lo, e_hi, rhs, x);
             for (int m = 0; m < n; ++m) Dd[base + (size_t)m * stride] = x[m];
@@ -507,13 +520,56 @@ static int sweep(const orc_problem* p, const mesh* M, int d, double t, double dt
 }
 
 /* ------------------------------------------------------------------------ */
-/* One Douglas step (section 5.1), backward time tau_n = n dt -> tau_{n+1}: */
-/*   D0 = dt (A0 + A1 + A2 + A3) U^n            at t_{n+1/2}, non-Dirichlet  */
-/*   D0 = g(t_{n+1}) - g(t_n)                  on Dirichlet nodes            */
-/*   (I - theta dt A1) D1 = D0, (I - theta dt A2) D2 = D1,                   */
-/*   (I - theta dt A3) D3 = D2,  U^{n+1} = U^n + D3.                         */
-/* Physical time t_n = T - n dt.                                             */
+/* One ADI step, backward time tau_n = n dt -> tau_{n+1}, physical time      */
+/* t_n = T - n dt.  Every operator is frozen at t_{n+1/2}, so F(V) = A V is   */
+/* linear within the step, with A = A0 + A1 + A2 + A3.                        */
+/*                                                                           */
+/* Douglas (section 5.1), in delta form D = Y - U^n:                         */
+/*   D0 = dt A U^n on non-Dirichlet nodes, g(t_{n+1}) - g(t_n) on Dirichlet   */
+/*   nodes; (I - theta dt A_j) D_j = D_{j-1}, j = 1, 2, 3; U^{n+1} = U^n + D3. */
+/* The three correction schemes take Y3 = U^n + D3 as a predictor and sweep  */
+/* once more from a corrected start:                                         */
+/*   CS:  Yt0 = Y0 + 1/2 dt (A0 Y3 - A0 U^n),                                */
+/*        Yt_j = Yt_{j-1} + theta dt (A_j Yt_j - A_j U^n),  U^{n+1} = Yt3;    */
+/*   MCS: Yh0 = Y0 + theta dt (A0 Y3 - A0 U^n),                              */
+/*        Yt0 = Yh0 + (1/2 - theta) dt (F(Y3) - F(U^n)),                     */
+/*        Yt_j = Yt_{j-1} + theta dt (A_j Yt_j - A_j U^n),  U^{n+1} = Yt3;    */
+/*   HV:  Yt0 = Y0 + 1/2 dt (F(Y3) - F(U^n)),                                */
+/*        Yt_j = Yt_{j-1} + theta dt (A_j Yt_j - A_j Y3),   U^{n+1} = Yt3.    */
+/* In delta form, E = Yt - U^n (CS, MCS) or E = Yt - Y3 (HV), the corrected   */
+/* start on non-Dirichlet nodes is                                           */
+/*   CS:  E0 = D0 + 1/2 dt A0 D3                                             */
+/*   MCS: E0 = D0 + theta dt A0 D3 + (1/2 - theta) dt A D3                   */
+/*   HV:  E0 = D0 + 1/2 dt A D3 - D3                                         */
+/* and every E_j solves (I - theta dt A_j) E_j = E_{j-1}.  On Dirichlet nodes */
+/* the solution takes g(t_{n+1}): E0 = g(t_{n+1}) - g(t_n) (CS, MCS) or 0     */
+/* (HV, whose Y3 already holds it).  U^{n+1} = U^n + E3 (CS, MCS) or         */
+/* U^n + D3 + E3 (HV).                                                       */
 /* ------------------------------------------------------------------------ */
+
+/* out = dt (A0 + A1 + A2 + A3) V on non-Dirichlet nodes, 0 on Dirichlet nodes */
+static int apply_all(const orc_problem* p, double t, double dt, const double* V, double* out, double* tmp,
+                     size_t npts)
+{
+    for (size_t q = 0; q < npts; ++q) out[q] = 0.0;
+    for (int d = 0; d < 4; ++d) {
+        int e = orc_apply(p, d, t, V, tmp);
+        if (e) return e;
+        for (size_t q = 0; q < npts; ++q) out[q] += tmp[q];
+    }
+    for (size_t q = 0; q < npts; ++q) out[q] = dt * out[q];
+    return 0;
+}
+
+/* the three line sweeps in place: (I - theta dt A_j) X_j = X_{j-1} */
+static int sweeps(const orc_problem* p, const mesh* M, double t, double dt, double* X)
+{
+    int err = sweep(p, M, 0, t, dt, X);
+    if (!err) err = sweep(p, M, 1, t, dt, X);
+    if (!err) err = sweep(p, M, 2, t, dt, X);
+    return err;
+}
+
 int orc_step(const orc_problem* p, int n, double* U)
 {
     mesh M;
@@ -524,15 +580,15 @@ int orc_step(const orc_problem* p, int n, double* U)
     double t_now = p->expiry - (double)n * dt;
     double t_next = p->expiry - (double)(n + 1) * dt;
     double t_half = p->expiry - ((double)n + 0.5) * dt;
-    double* Dd = (double*)malloc(sizeof(double) * npts * 2);
+    int corr = p->scheme != ORC_DOUGLAS;
+    double* Dd = (double*)malloc(sizeof(double) * npts * (corr ? 5 : 2));
     if (!Dd) { mesh_free(&M); return -2; }
     double* tmp = Dd + npts;
+    double* D0 = corr ? tmp + npts : NULL;   /* the explicit predictor, kept */
+    double* E = corr ? D0 + npts : NULL;     /* the corrected start, swept */
+    double* W = corr ? E + npts : NULL;      /* dt A0 D3 or dt A D3 */
     /* explicit predictor: sum of the four operators */
-    for (size_t q = 0; q < npts; ++q) Dd[q] = 0.0;
-    for (int d = 0; d < 4; ++d) {
-        orc_apply(p, d, t_half, U, tmp);
-        for (size_t q = 0; q < npts; ++q) Dd[q] += tmp[q];
-    }
+    int err = apply_all(p, t_half, 1.0, U, Dd, tmp, npts);
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < ny; ++k)
         for (int j = 0; j < nv; ++j)
@@ -543,11 +599,40 @@ int orc_step(const orc_problem* p, int n, double* U)
                 else
                     Dd[q] = dt * Dd[q];
             }
-    int err = sweep(p, &M, 0, t_half, dt, Dd);
-    if (!err) err = sweep(p, &M, 1, t_half, dt, Dd);
-    if (!err) err = sweep(p, &M, 2, t_half, dt, Dd);
-    if (!err)
+    if (corr)
+        for (size_t q = 0; q < npts; ++q) D0[q] = Dd[q];
+    if (!err) err = sweeps(p, &M, t_half, dt, Dd);   /* Dd = D3 */
+    if (!err && corr) {
+        /* corrected start E0 on non-Dirichlet nodes */
+        if (p->scheme == ORC_CS) {
+            err = orc_apply(p, 3, t_half, Dd, W);
+            for (size_t q = 0; q < npts && !err; ++q) E[q] = D0[q] + 0.5 * dt * W[q];
+        } else if (p->scheme == ORC_MCS) {
+            err = orc_apply(p, 3, t_half, Dd, W);
+            for (size_t q = 0; q < npts && !err; ++q) E[q] = D0[q] + p->theta * dt * W[q];
+            if (!err) err = apply_all(p, t_half, dt, Dd, W, tmp, npts);
+            for (size_t q = 0; q < npts && !err; ++q) E[q] = E[q] + (0.5 - p->theta) * W[q];
+        } else {
+            err = apply_all(p, t_half, dt, Dd, W, tmp, npts);
+            for (size_t q = 0; q < npts && !err; ++q) E[q] = D0[q] + 0.5 * W[q] - Dd[q];
+        }
+        /* Dirichlet nodes */
+        for (int k = 0; k < ny && !err; ++k)
+            for (int j = 0; j < nv; ++j)
+                for (int i = 0; i < nr; ++i) {
+                    size_t q = idx3(&M, i, j, k);
+                    if (is_dirichlet(p, &M, i, j, k)) E[q] = p->scheme == ORC_HV ? 0.0 : D0[q];
+                }
+        if (!err) err = sweeps(p, &M, t_half, dt, E);
+        if (!err) {
+            if (p->scheme == ORC_HV)
+                for (size_t q = 0; q < npts; ++q) U[q] = U[q] + Dd[q] + E[q];
+            else
+                for (size_t q = 0; q < npts; ++q) U[q] = U[q] + E[q];
+        }
+    } else if (!err) {
         for (size_t q = 0; q < npts; ++q) U[q] = U[q] + Dd[q];
+    }
     free(Dd);
     mesh_free(&M);
     return err;
