@@ -88,6 +88,27 @@ typedef struct {
     double expiry, pay, strike;
 } hjm_payoff;
 
+/* ADI scheme of a grid.  HJM_SCHEME_DOUGLAS is the paper's step (section
+   5.1): explicit predictor, then (I - theta dt A_d) sweeps along r, v, y.  The
+   other three add a correction stage for the mixed r-v derivative (which
+   Douglas treats explicitly, first order in time) and reach second order:
+   Craig-Sneyd (the paper mentions trying it, section 5.1), modified
+   Craig-Sneyd and Hundsdorfer-Verwer, as defined by in 't Hout and Welfert
+   (Appl. Numer. Math. 57, 2007).  Each runs the Douglas sweeps, forms a
+   corrected start from their result and sweeps once more: twice the work of
+   a Douglas step.  theta in (0, 1]: the paper uses 1/2; 1/3 is usual for
+   modified Craig-Sneyd and 1/2 + sqrt(3)/6 for Hundsdorfer-Verwer.  Every
+   operator is evaluated at t_{n+1/2}. */
+#define HJM_SCHEME_DOUGLAS 0
+#define HJM_SCHEME_CS      1
+#define HJM_SCHEME_MCS     2
+#define HJM_SCHEME_HV      3
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double theta;
+} hjm_scheme;
+
 typedef struct hjm_grid hjm_grid;
 typedef struct hjm_batch hjm_batch;
 
@@ -107,6 +128,20 @@ hjm_status hjm_workspace_bytes(const hjm_axis ax[3], int32_t n_steps, size_t* by
 hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff,
                            int32_t n_steps, void* d_workspace, size_t ws_bytes, void* hip_stream,
                            hjm_grid** out);
+
+/* The same with an explicit ADI scheme (hjm_grid_create is the Douglas
+   scheme with theta = 1/2).  The workspace of a correction scheme holds one
+   more nr*nv*ny array (hjm_scheme_workspace_bytes).  The correction schemes
+   run on the lane-split r solve and the stored-pivot y solve only: nr =
+   S * ROWS (S a power of two) with the r rows within the spike bound, and
+   ny = S * ROWS; other grids get HJM_EINVAL (before any device work), as do
+   an unknown kind or theta outside (0, 1].  hjm_adi_step then enqueues whole
+   steps of the chosen scheme. */
+hjm_status hjm_scheme_workspace_bytes(const hjm_axis ax[3], int32_t n_steps, const hjm_scheme* scheme,
+                                      size_t* bytes);
+hjm_status hjm_grid_create_scheme(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff,
+                                  const hjm_scheme* scheme, int32_t n_steps, void* d_workspace, size_t ws_bytes,
+                                  void* hip_stream, hjm_grid** out);
 
 /* Enqueue k more Douglas steps (section 5.1) on the grid's stream.
    HJM_ESTATE if that would go past n_steps. */
@@ -140,7 +175,8 @@ hjm_status hjm_grid_destroy(hjm_grid* g);
    the split or fused r solve (0 otherwise), plan[2..4] = the line-tile
    rows per thread of the r, v and y solves, plan[5] = rows per segment of the
    segmented v solve (0: the chained v solve), plan[6] = rows per segment of
-   the y solve on stored pivots (0: the per-step elimination), plan[7] = 0.  The
+   the y solve on stored pivots (0: the per-step elimination), plan[7] = the
+   ADI scheme (HJM_SCHEME_*).  The
    spike variants are chosen only where the r rows keep (|A| + |C|) / B
    bounded (section 5, tridiagonal systems), so every variant matches the
    sequential elimination to rounding. */

@@ -303,10 +303,10 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
 // over all lines and steps sits at a corner of their ranges.
 constexpr double kSpikeRho = 16.0;
 
-bool r_spike_ok(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps)
+bool r_spike_ok(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps, double theta = kTheta)
 {
     const Curve cv{m.f_level, m.f_slope, m.f_decay};
-    const double T = p.expiry, dt = T / n_steps, tdt = kTheta * dt;
+    const double T = p.expiry, dt = T / n_steps, tdt = theta * dt;
     double phi_lo = 1e300, phi_hi = -1e300;
     for (int n = 0; n < n_steps; ++n) {
         const double t = T - (n + 0.5) * dt;
@@ -393,23 +393,25 @@ size_t table_doubles(const hjm_axis ax[3], int n_steps)
 }
 
 struct SolveOffsets {
-    size_t U, D, YI, tables;
+    size_t U, D, YI, E, tables;
 };
 
-SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps)
+// corr: the Craig-Sneyd family's correction array E after the pivots
+SolveOffsets layout_solve(Layout& L, const hjm_axis ax[3], int n_steps, bool corr = false)
 {
     const size_t pts = (size_t)ax[0].n * ax[1].n * ax[2].n;
     SolveOffsets o;
     o.U = L.take(pts * 8);
     o.D = L.take(pts * 8);
     o.YI = L.take(pts * 8);
+    o.E = corr ? L.take(pts * 8) : 0;
     o.tables = L.take(table_doubles(ax, n_steps) * 8);
     return o;
 }
 
 // Fill the host tables of one solve: axis coefficient rows, step table.
 void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps, Plan& plan,
-                  std::vector<double>& out)
+                  std::vector<double>& out, double theta = kTheta)
 {
     const int nr = ax[0].n, nv = ax[1].n, ny = ax[2].n;
     out.assign(table_doubles(ax, n_steps), 0.0);
@@ -423,7 +425,7 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
     double* vg = gd + (size_t)(2 * ny + nr) * n_steps;
     const Mesh mr = make_mesh(ax[0]), mv = make_mesh(ax[1]), my = make_mesh(ax[2]);
     const double lam = m.lambda, eps = m.epsilon;
-    const double dt = p.expiry / n_steps, tdt = kTheta * dt;
+    const double dt = p.expiry / n_steps, tdt = theta * dt;
     const double hr1 = nr - 1.0, hv1 = nv - 1.0, hy1 = ny - 1.0;
     const double ih2r = hr1 * hr1, i2hr = 0.5 * hr1, ih2v = hv1 * hv1, i2hv = 0.5 * hv1, i2hy = 0.5 * hy1;
     const double i4hrhv = 0.25 * hr1 * hv1;
@@ -599,7 +601,7 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
 }
 
 void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps,
-               const Plan& pl, char* base, const SolveOffsets& o, int32_t* flag)
+               const Plan& pl, char* base, const SolveOffsets& o, int32_t* flag, double theta = kTheta)
 {
     std::memset(&d, 0, sizeof d);
     d.nr = ax[0].n; d.nv = ax[1].n; d.ny = ax[2].n;
@@ -613,7 +615,7 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.r_tiles = pl.r_tiles; d.v_tiles = pl.v_tiles; d.y_tiles = pl.y_tiles;
     d.r_pitch = pl.r_pitch;
     d.dt = p.expiry / n_steps;
-    d.tdt = kTheta * d.dt;
+    d.tdt = theta * d.dt;
     d.kappa = m.kappa;
     d.accrual = 1.0 + (p.pay - p.expiry) * p.strike;
     const double hr1 = ax[0].n - 1.0, hv1 = ax[1].n - 1.0, hy1 = ax[2].n - 1.0;
@@ -703,7 +705,10 @@ struct hjm_grid {
     hipStream_t stream = nullptr;
     char* base = nullptr;
     SolveDesc desc;
-    SolveDesc* d_desc = nullptr;
+    SolveDesc* d_desc = nullptr;  // [desc] or, for the Craig-Sneyd family, [stage 1, stage 2]
+    hjm_scheme scheme{HJM_SCHEME_DOUGLAS, 0, 0.5};
+    bool corr = false;            // a correction scheme (two sweep sequences per step)
+    SolveDesc desc2;              // its stage-2 descriptor
     Readout* d_rq = nullptr;
     double* d_out = nullptr;
     int32_t* d_flag = nullptr;
@@ -729,17 +734,39 @@ struct GridLayout {
     SolveOffsets s;
 };
 
-GridLayout grid_layout(const hjm_axis ax[3], int n_steps)
+GridLayout grid_layout(const hjm_axis ax[3], int n_steps, bool corr = false)
 {
     Layout L;
     GridLayout g;
-    g.desc = L.take(sizeof(SolveDesc));
+    g.desc = L.take(sizeof(SolveDesc) * (corr ? 2 : 1));
     g.rq = L.take(sizeof(Readout));
     g.out = L.take(sizeof(double));
     g.flag = L.take(sizeof(int32_t));
-    g.s = layout_solve(L, ax, n_steps);
+    g.s = layout_solve(L, ax, n_steps, corr);
     g.total = L.off;
     return g;
+}
+
+hjm_status validate_scheme(const hjm_scheme* sc)
+{
+    if (!sc) return fail(HJM_EINVAL, "null scheme");
+    if (sc->kind < HJM_SCHEME_DOUGLAS || sc->kind > HJM_SCHEME_HV) return fail(HJM_EINVAL, "unknown scheme %d", sc->kind);
+    if (!(sc->theta > 0.0 && sc->theta <= 1.0)) return fail(HJM_EINVAL, "theta must lie in (0, 1] (got %g)", sc->theta);
+    return HJM_OK;
+}
+
+// Stage-2 coefficients of the corrected start (see SolveDesc): CS a0 = 1/2;
+// MCS a0 = 1/2, a1 = 1/2 - theta; HV a0 = a1 = 1/2, b = -1 (relative to Y3).
+void scheme_stage2(SolveDesc& d2, const SolveDesc& d1, const hjm_scheme& sc, double* E)
+{
+    d2 = d1;
+    d2.stage = 2;
+    d2.D = E;
+    d2.D3 = d1.D;
+    d2.sc_a0 = 0.5;
+    d2.sc_a1 = sc.kind == HJM_SCHEME_MCS ? 0.5 - sc.theta : (sc.kind == HJM_SCHEME_HV ? 0.5 : 0.0);
+    d2.sc_b = sc.kind == HJM_SCHEME_HV ? -1.0 : 0.0;
+    d2.hv = sc.kind == HJM_SCHEME_HV;
 }
 
 }  // namespace
@@ -837,16 +864,48 @@ hjm_status hjm_workspace_bytes(const hjm_axis ax[3], int32_t n_steps, size_t* by
     return HJM_OK;
 }
 
+hjm_status hjm_scheme_workspace_bytes(const hjm_axis ax[3], int32_t n_steps, const hjm_scheme* scheme,
+                                      size_t* bytes)
+{
+    if (!ax || !bytes) return fail(HJM_EINVAL, "null argument");
+    hjm_status st = validate_scheme(scheme);
+    if (st) return st;
+    st = validate_axes(ax);
+    if (st) return st;
+    if (n_steps <= 0) return fail(HJM_EINVAL, "n_steps must be > 0");
+    *bytes = grid_layout(ax, n_steps, scheme->kind != HJM_SCHEME_DOUGLAS).total;
+    return HJM_OK;
+}
+
 hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff, int32_t n_steps,
                            void* d_workspace, size_t ws_bytes, void* hip_stream, hjm_grid** out)
+{
+    const hjm_scheme douglas{HJM_SCHEME_DOUGLAS, 0, 0.5};
+    return hjm_grid_create_scheme(ax, model, payoff, &douglas, n_steps, d_workspace, ws_bytes, hip_stream, out);
+}
+
+hjm_status hjm_grid_create_scheme(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff,
+                                  const hjm_scheme* scheme, int32_t n_steps, void* d_workspace, size_t ws_bytes,
+                                  void* hip_stream, hjm_grid** out)
 {
     if (!out) return fail(HJM_EINVAL, "null output handle");
     *out = nullptr;
     hjm_status st = validate_problem(ax, model, payoff, n_steps);
     if (st) return st;
+    st = validate_scheme(scheme);
+    if (st) return st;
+    const bool corr = scheme->kind != HJM_SCHEME_DOUGLAS;
+    int rows[3];
+    std::memcpy(rows, g_rows, sizeof rows);
+    const Plan plan = make_plan(ax[0].n, ax[1].n, ax[2].n, rows, r_spike_ok(ax, *model, *payoff, n_steps, scheme->theta));
+    if (corr && (!(plan.r_mode == R_FUSED || plan.r_mode == R_SPLIT) || !plan.yc_rows))
+        return fail(HJM_EINVAL,
+                    "the correction schemes run on the lane-split r solve and the stored-pivot y solve: nr = S*ROWS "
+                    "(S a power of two, rows within the spike bound) and ny = S*ROWS are needed (plan: r method %d, "
+                    "y rows %d)", plan.r_mode, plan.yc_rows);
     if (!d_workspace) return fail(HJM_EINVAL, "null workspace");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return fail(HJM_EINVAL, "workspace must be 256-byte aligned");
-    const GridLayout gl = grid_layout(ax, n_steps);
+    const GridLayout gl = grid_layout(ax, n_steps, corr);
     if (ws_bytes < gl.total) return fail(HJM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, gl.total);
     hjm_grid* g = new (std::nothrow) hjm_grid;
     if (!g) return fail(HJM_EINVAL, "host allocation failed");
@@ -854,19 +913,27 @@ hjm_status hjm_grid_create(const hjm_axis ax[3], const hjm_model* model, const h
     g->model = *model;
     g->payoff = *payoff;
     g->n_steps = n_steps;
-    std::memcpy(g->rows, g_rows, sizeof g->rows);
-    g->plan = make_plan(ax[0].n, ax[1].n, ax[2].n, g->rows, r_spike_ok(ax, *model, *payoff, n_steps));
+    std::memcpy(g->rows, rows, sizeof g->rows);
+    g->plan = plan;
+    g->scheme = *scheme;
+    g->corr = corr;
     g->stream = reinterpret_cast<hipStream_t>(hip_stream);
     g->base = reinterpret_cast<char*>(d_workspace);
     g->d_desc = reinterpret_cast<SolveDesc*>(g->base + gl.desc);
     g->d_rq = reinterpret_cast<Readout*>(g->base + gl.rq);
     g->d_out = reinterpret_cast<double*>(g->base + gl.out);
     g->d_flag = reinterpret_cast<int32_t*>(g->base + gl.flag);
-    build_tables(ax, *model, *payoff, n_steps, g->plan, g->tables);
-    fill_desc(g->desc, ax, *model, *payoff, n_steps, g->plan, g->base, gl.s, g->d_flag);
+    build_tables(ax, *model, *payoff, n_steps, g->plan, g->tables, scheme->theta);
+    fill_desc(g->desc, ax, *model, *payoff, n_steps, g->plan, g->base, gl.s, g->d_flag, scheme->theta);
+    if (corr) {
+        g->desc.stage = 1;
+        scheme_stage2(g->desc2, g->desc, *scheme, reinterpret_cast<double*>(g->base + gl.s.E));
+    }
     hipError_t e;
     if ((e = init_kernel_attributes()) ||
         (e = hipMemcpyAsync(g->d_desc, &g->desc, sizeof(SolveDesc), hipMemcpyHostToDevice, g->stream)) ||
+        (corr && (e = hipMemcpyAsync(g->d_desc + 1, &g->desc2, sizeof(SolveDesc), hipMemcpyHostToDevice,
+                                     g->stream))) ||
         (e = upload_tables(g->desc, g->tables, g->stream)) ||
         (e = launch_gd(g->d_desc, 1, (int64_t)(2 * ax[2].n + ax[0].n) * n_steps, g->stream)) ||
         (e = launch_terminal(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n * ax[2].n, g->stream)) ||
@@ -889,7 +956,12 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
     const bool split = p.r_mode == R_SPLIT;
     for (int32_t c = 0; c < k; ++c) {
         const int n = (int)g->step;
-        for (int pass = 0; pass < HJM_N_PASSES; ++pass) {
+        // one sweep sequence (Douglas), or two (the Craig-Sneyd family: the
+        // second on the stage-2 descriptor)
+        for (int q = 0; q < (g->corr ? 2 * HJM_N_PASSES : HJM_N_PASSES); ++q) {
+            const int pass = q % HJM_N_PASSES;
+            const bool st2 = q >= HJM_N_PASSES;
+            const SolveDesc* dd = g->d_desc + (st2 ? 1 : 0);
             if (pass == 1 && !split) continue;
             hipError_t e = hipSuccess;
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -908,15 +980,15 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
                 g->ev_pass[g->ev_used] = pass;
                 set_launch_events(e0, e1);
             }
-            if (pass == 0 && split) e = launch_exp(p.exp_J, g->d_desc, nullptr, p.exp_tiles, n, g->stream);
+            if (pass == 0 && split) e = launch_exp(p.exp_J, dd, nullptr, p.exp_tiles, n, g->stream, st2);
             else if (pass == 0 && p.r_mode == R_FUSED)
-                e = launch_exr(p.rs_rows, g->d_desc, nullptr, p.exr_tiles, n, p.exr_lds, g->stream);
-            else if (pass == 0) e = launch_xr(g->rows[0], g->d_desc, nullptr, p.r_tiles, n, p.r_lds, g->stream);
-            else if (pass == 1) e = launch_rs(p.rs_rows, g->d_desc, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
-            else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, g->d_desc, nullptr, p.vs_tiles, p.vs_S, g->stream);
-            else if (pass == 2) e = launch_v(g->rows[1], g->d_desc, nullptr, p.v_tiles, p.v_lds, g->stream);
-            else if (p.yc_rows) e = launch_yc(p.yc_rows, g->d_desc, nullptr, p.yc_tiles, p.yc_S, g->stream);
-            else e = launch_yu(g->rows[2], g->d_desc, nullptr, p.y_tiles, p.y_lds, g->stream);
+                e = launch_exr(p.rs_rows, dd, nullptr, p.exr_tiles, n, p.exr_lds, g->stream, st2);
+            else if (pass == 0) e = launch_xr(g->rows[0], dd, nullptr, p.r_tiles, n, p.r_lds, g->stream);
+            else if (pass == 1) e = launch_rs(p.rs_rows, dd, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
+            else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, dd, nullptr, p.vs_tiles, p.vs_S, g->stream);
+            else if (pass == 2) e = launch_v(g->rows[1], dd, nullptr, p.v_tiles, p.v_lds, g->stream);
+            else if (p.yc_rows) e = launch_yc(p.yc_rows, dd, nullptr, p.yc_tiles, p.yc_S, g->stream);
+            else e = launch_yu(g->rows[2], dd, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {
                 set_launch_events(nullptr, nullptr);  // a launch with no tiles records nothing
@@ -981,6 +1053,7 @@ hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[8])
     plan[4] = g->rows[2];
     plan[5] = g->plan.vs_rows;
     plan[6] = g->plan.yc_rows;
+    plan[7] = g->scheme.kind;
     return HJM_OK;
 }
 

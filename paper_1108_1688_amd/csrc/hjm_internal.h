@@ -63,6 +63,16 @@ struct SolveDesc {
     const double* gd;   // Dirichlet increments g(t_{n+1}) - g(t_n): (2 ny + nr) per step
     const double* vg;   // segmented v-solve constants, kVG * nv
     double* yinv;       // y-line reciprocal pivots 1 / den_k of (I - theta dt A3), nr*nv*ny (once per solve)
+    // ADI scheme stage.  0: the Douglas step.  The Craig-Sneyd family runs the
+    // Douglas sweeps as stage 1 (the y sweep leaves D3 in D, U unchanged), then
+    // stage 2 on a second descriptor whose D is the correction array E:
+    //   E0 = dt A U + dt (sc_a0 A0 + sc_a1 (A1 + A2 + A3)) D3 + sc_b D3
+    // on non-Dirichlet nodes (D3 read from the D3 pointer), the increment
+    // g(t_{n+1}) - g(t_n) on Dirichlet nodes when sc_b = 0 and 0 otherwise;
+    // the same sweeps; U += E3, plus D3 when hv
+    int32_t stage, hv;
+    double sc_a0, sc_a1, sc_b;
+    const double* D3;
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value
     int32_t* flag_pad;
 };
@@ -154,14 +164,15 @@ hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_
 hipError_t launch_yu(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks,
                      size_t lds_bytes, hipStream_t st);
 // J: v nodes per k_exp thread (4, 8 or 16)
-hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st);
+hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st,
+                      bool stage2 = false);
 hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, int nr_max,
                      hipStream_t st);
 // k_exr dynamic LDS (bytes) and table offset (doubles) for nr = S * rows
 // (rows >= 8: a pass's scratch, 8 doubles per lane, fits in its rows)
 void exr_lds(int nr, int rows, size_t* bytes, int* tab);
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
-                      hipStream_t st);
+                      hipStream_t st, bool stage2 = false);
 // rows per thread available to k_rs
 bool rs_rows_supported(int rows);
 hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);

@@ -883,11 +883,10 @@ __device__ __forceinline__ void wave_sync()
 // registers, one more LDS-pipe latency before the arithmetic; measured
 // faster inside the fused kernel, slower in the explicit kernel alone).  j0
 // must be wave-uniform (the v-table reads are scalar).
-template <int J, bool SHFL, class Put>
+template <int J, bool SHFL, bool STAGE2, class Put>
 __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k, int j0, int step, const Put& put)
 {
     const int nr = s.nr, nv = s.nv, ny = s.ny;
-    gcdouble* U = gp(s.U);
     gcdouble* rt = gp(s.rt);
     kcdouble* vt = kp(s.vt);
     gcdouble* yt = gp(s.yt);
@@ -895,7 +894,6 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
 
     const size_t sl = (size_t)nr;       // stride of j
     const size_t sy = (size_t)nr * nv;  // stride of k
-    gcdouble* col = U + (size_t)k * sy; // (k, j = 0, i = 0)
     const int im = max(i - 1, 0), ip = min(i + 1, nr - 1);
     // y stencil: two neighbours (offsets oa, ob) and the node itself
     const bool yhd = s.y_hi_dir && k == ny - 1;
@@ -903,53 +901,58 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
     if (k == 0) { oa = 1; ob = 2; }
     else if (k == ny - 1) { oa = -2; ob = -1; }
     if (yhd) { oa = 0; ob = 0; }
-    gcdouble* cola = col + (ptrdiff_t)oa * (ptrdiff_t)sy;  // plane k + oa
-    gcdouble* colb = col + (ptrdiff_t)ob * (ptrdiff_t)sy;
     const int dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
     auto jcl = [&](int jj) { return (size_t)min(max(jj, 0), nv - 1) * sl; };
     double cw[J + 4], lw[J + 2], rw[J + 2], ya[J], yb[J], ux[J];
+    // the windows of field F around the J nodes
+    auto load = [&](gcdouble* F) {
+        gcdouble* col = F + (size_t)k * sy;                          // (k, j = 0, i = 0)
+        gcdouble* cola = col + (ptrdiff_t)oa * (ptrdiff_t)sy;         // plane k + oa
+        gcdouble* colb = col + (ptrdiff_t)ob * (ptrdiff_t)sy;
 #pragma unroll
-    for (int m = 0; m < J + 4; ++m) cw[m] = col[jcl(j0 - 2 + m) + i];
+        for (int m = 0; m < J + 4; ++m) cw[m] = col[jcl(j0 - 2 + m) + i];
 #pragma unroll
-    for (int m = 0; m < J; ++m) {
-        ya[m] = cola[jcl(j0 + m) + i];
-        yb[m] = colb[jcl(j0 + m) + i];
-    }
-    if (SHFL) {
-        // the r faces clamp to the node itself
-        const int lane = (int)(threadIdx.x & 63);
-#pragma unroll
-        for (int m = 0; m < J + 2; ++m) {
-            const double lo = __shfl_up(cw[m + 1], 1);
-            const double hi = __shfl_down(cw[m + 1], 1);
-            lw[m] = i == 0 ? cw[m + 1] : lo;
-            rw[m] = i == nr - 1 ? cw[m + 1] : hi;
+        for (int m = 0; m < J; ++m) {
+            ya[m] = cola[jcl(j0 + m) + i];
+            yb[m] = colb[jcl(j0 + m) + i];
         }
-        if (lane == 0 && i > 0) {
+        if (SHFL) {
+            // the r faces clamp to the node itself
+            const int lane = (int)(threadIdx.x & 63);
 #pragma unroll
-            for (int m = 0; m < J + 2; ++m) lw[m] = col[jcl(j0 - 1 + m) + im];
+            for (int m = 0; m < J + 2; ++m) {
+                const double lo = __shfl_up(cw[m + 1], 1);
+                const double hi = __shfl_down(cw[m + 1], 1);
+                lw[m] = i == 0 ? cw[m + 1] : lo;
+                rw[m] = i == nr - 1 ? cw[m + 1] : hi;
+            }
+            if (lane == 0 && i > 0) {
+#pragma unroll
+                for (int m = 0; m < J + 2; ++m) lw[m] = col[jcl(j0 - 1 + m) + im];
+            }
+            if (lane == 63 && i < nr - 1) {
+#pragma unroll
+                for (int m = 0; m < J + 2; ++m) rw[m] = col[jcl(j0 - 1 + m) + ip];
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < J + 2; ++m) {
+                lw[m] = col[jcl(j0 - 1 + m) + im];
+                rw[m] = col[jcl(j0 - 1 + m) + ip];
+            }
         }
-        if (lane == 63 && i < nr - 1) {
+        if (dx != 0) {
+            // outflow r face rows reach two nodes in
 #pragma unroll
-            for (int m = 0; m < J + 2; ++m) rw[m] = col[jcl(j0 - 1 + m) + ip];
+            for (int m = 0; m < J; ++m) ux[m] = col[jcl(j0 + m) + (size_t)(i + dx)];
+        } else {
+            // interior rows: the extra entry has weight zero
+#pragma unroll
+            for (int m = 0; m < J; ++m) ux[m] = cw[m + 2];
         }
-    } else {
-#pragma unroll
-        for (int m = 0; m < J + 2; ++m) {
-            lw[m] = col[jcl(j0 - 1 + m) + im];
-            rw[m] = col[jcl(j0 - 1 + m) + ip];
-        }
-    }
-    if (dx != 0) {
-        // outflow r face rows reach two nodes in
-#pragma unroll
-        for (int m = 0; m < J; ++m) ux[m] = col[jcl(j0 + m) + (size_t)(i + dx)];
-    } else {
-        // interior rows: the extra entry has weight zero
-#pragma unroll
-        for (int m = 0; m < J; ++m) ux[m] = cw[m + 2];
-    }
+    };
 
+    load(gp(s.U));
     // per-column constants: A1 row pieces (affine in v), A3 coefficient, A0 factor
     const double c = stn[ST_PHI] + yt[YT_Y * ny + k];
     const double e = rt[RT_P * nr + i] * c + rt[RT_Q * nr + i];
@@ -964,16 +967,9 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
     if (k == 0) { wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
     else if (k == ny - 1) { wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
     const double w2 = yt[YT_W2 * ny + k];
-    // Dirichlet nodes: the increment does not depend on j
-    gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
-    const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
-    const bool dir = rlo || rhi || yhd;
-    const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
-    const double dt = s.dt;
-#pragma unroll
-    for (int m = 0; m < J; ++m) {
+    // (A1 + A2 + A3) and A0 of the loaded field at node j0 + m
+    auto stencil = [&](int m, double& a123, double& a0) {
         const int j = j0 + m;
-        if (j >= nv) break;  // wave-uniform
         const double v = vt[VT_V * nv + j];
         const double olo = mlo + alo * v, odi = mdi + adi * v, oup = mup + aup * v;
         const double a1 = olo * lw[m + 1] + odi * cw[m + 2] + oup * rw[m + 1] + mex * ux[m];
@@ -983,15 +979,50 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
         const double by = ryk * v - kyk;
         const double a3 = by * (wa * ya[m] + w2 * cw[m + 2] + wb * yb[m]);
         const double cross = (rw[m + 2] - rw[m]) - (lw[m + 2] - lw[m]);
-        const double a0 = rx * vt[VT_X * nv + j] * cross;
-        const double val = dt * (((a1 + a2) + a3) + a0);
-        put(m, dir ? gval : val);
+        a123 = (a1 + a2) + a3;
+        a0 = rx * vt[VT_X * nv + j] * cross;
+    };
+    // Dirichlet nodes: the increment does not depend on j
+    gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
+    const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
+    const bool dir = rlo || rhi || yhd;
+    const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
+    const double dt = s.dt;
+    if (!STAGE2) {
+#pragma unroll
+        for (int m = 0; m < J; ++m) {
+            if (j0 + m >= nv) break;  // wave-uniform
+            double a123, a0;
+            stencil(m, a123, a0);
+            put(m, dir ? gval : dt * (a123 + a0));
+        }
+    } else {
+        // corrected start of the Craig-Sneyd family:
+        // dt A U + dt (a0c A0 + a1c (A1 + A2 + A3)) D3 + bc D3
+        double su[J], s0[J];
+#pragma unroll
+        for (int m = 0; m < J; ++m) {
+            if (j0 + m >= nv) break;
+            stencil(m, su[m], s0[m]);
+        }
+        load(gp(s.D3));
+        const double a0c = s.sc_a0, a1c = s.sc_a1, bc = s.sc_b;
+        const double gdir = bc == 0.0 ? gval : 0.0;
+#pragma unroll
+        for (int m = 0; m < J; ++m) {
+            if (j0 + m >= nv) break;
+            double d123, d0;
+            stencil(m, d123, d0);
+            const double val = dt * ((su[m] + a1c * d123) + (s0[m] + a0c * d0)) + bc * cw[m + 2];
+            put(m, dir ? gdir : val);
+        }
     }
 }
 
-// Explicit predictor alone (split path).  Thread = one (i, k) column and J
-// consecutive v nodes.
-template <int J>
+// Explicit predictor alone (split path), or the corrected start of the
+// Craig-Sneyd family (STAGE2).  Thread = one (i, k) column and J consecutive
+// v nodes.
+template <int J, bool STAGE2>
 __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
                                                 int step)
 {
@@ -1009,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     // j is the same on every lane: keep it (and the v-table reads) scalar
     const int j0 = __builtin_amdgcn_readfirstlane(jc * J);
     gdouble* dcol = gp(s.D) + (size_t)k * nr * s.nv + (size_t)j0 * nr + i;
-    explicit_nodes<J, false>(s, i, k, j0, step, [&](int m, double x) { dcol[(size_t)m * nr] = x; });
+    explicit_nodes<J, false, STAGE2>(s, i, k, j0, step, [&](int m, double x) { dcol[(size_t)m * nr] = x; });
 }
 
 // The spike solve of one r line of nr = S * ROWS rows (S a power of two <=
@@ -1213,8 +1244,9 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     if (store && !ok) raise_flag(s);
 }
 
-// Explicit predictor and r sweep in one kernel (nr <= 256, nr = S * ROWS as
-// for k_rs, ROWS >= 8): the workgroup computes D0 on kExrJ consecutive v nodes of
+// Explicit predictor (or, STAGE2, the corrected start of the Craig-Sneyd
+// family) and r sweep in one kernel (nr <= 256, nr = S * ROWS as for k_rs,
+// ROWS >= 8): the workgroup computes D0 on kExrJ consecutive v nodes of
 // exr_P = 256 / nr whole y planes (thread = (i, plane)) into an LDS tile,
 // then solves the tile's exr_P * kExrJ r lines with the spike method, S lanes
 // per line, and writes D1.  D0 never goes to memory: 16 bytes per point less
@@ -1225,7 +1257,7 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
 // read its rows (pass p's scratch is its first 8 kBlock doubles, inside its
 // kBlock / S lines; the tile is sized to whole passes).  Three waves per SIMD
 // (at most 168 VGPRs; a few spill) measured faster than two without spills.
-template <int ROWS>
+template <int ROWS, bool STAGE2>
 __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
                                                 int step)
 {
@@ -1261,7 +1293,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
             ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
 #pragma unroll 1
             for (int jc = 0; jc < kExrJ; jc += 8)
-                explicit_nodes<8, true>(s, i, k, j0 + jc, step,
+                explicit_nodes<8, true, STAGE2>(s, i, k, j0 + jc, step,
                                   [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; });
         }
     }
@@ -1540,13 +1572,26 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
         if (S > 1) __syncthreads();
     }
     if (active) {
-        double u[ROWS];
+        if (s.stage == 1) {
+            // first sequence of the Craig-Sneyd family: D3 stays in D, U unchanged
 #pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm) u[mm] = U[off + (size_t)mm * sy];
+            for (int mm = 0; mm < ROWS; ++mm) D[off + (size_t)mm * sy] = d[mm];
+        } else {
+            double u[ROWS];
 #pragma unroll
-        for (int mm = 0; mm < ROWS; ++mm) U[off + (size_t)mm * sy] = u[mm] + d[mm];
+            for (int mm = 0; mm < ROWS; ++mm) u[mm] = U[off + (size_t)mm * sy];
+            if (s.hv) {
+                // Hundsdorfer-Verwer: the correction is relative to U + D3
+                gcdouble* D3 = gp(s.D3);
+#pragma unroll
+                for (int mm = 0; mm < ROWS; ++mm) u[mm] += D3[off + (size_t)mm * sy];
+            }
+#pragma unroll
+            for (int mm = 0; mm < ROWS; ++mm) U[off + (size_t)mm * sy] = u[mm] + d[mm];
+        }
     }
 }
+
 
 // Dirichlet increments g(t_{n+1}) - g(t_n) of every step (the Douglas D0 on
 // Dirichlet nodes): r_min face by k, r_max face by k, y_max face by i; zero
@@ -1642,8 +1687,9 @@ hipError_t init_kernel_attributes()
             (e = allow_lds(k_v<8>)) || (e = allow_lds(k_v<16>)) || (e = allow_lds(k_v<32>)) ||
             (e = allow_lds(k_yu<8>)) || (e = allow_lds(k_yu<16>)) || (e = allow_lds(k_yu<32>)) ||
             (e = allow_lds(k_rs<6>)) || (e = allow_lds(k_rs<8>)) || (e = allow_lds(k_rs<12>)) ||
-            (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_exr<8>)) || (e = allow_lds(k_exr<12>)) ||
-            (e = allow_lds(k_exr<16>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
+            (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_exr<8, false>)) || (e = allow_lds(k_exr<12, false>)) ||
+            (e = allow_lds(k_exr<16, false>)) || (e = allow_lds(k_exr<8, true>)) ||
+            (e = allow_lds(k_exr<12, true>)) || (e = allow_lds(k_exr<16, true>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
             (e = allow_lds(k_vs<32>)) || (e = allow_lds(k_yc<8>)) || (e = allow_lds(k_yc<16>)) ||
             (e = allow_lds(k_yc<32>)))
             return e;
@@ -1700,13 +1746,23 @@ hipError_t launch_v(int rows, const SolveDesc* d_desc, const int2* tasks, int n_
     return hipGetLastError();
 }
 
-hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st)
+hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, hipStream_t st,
+                      bool stage2)
 {
     if (n_tasks <= 0) return hipSuccess;
+    if (stage2) {
+        switch (J) {
+        case 4: HJM_LAUNCH((k_exp<4, true>), dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+        case 8: HJM_LAUNCH((k_exp<8, true>), dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+        case 16: HJM_LAUNCH((k_exp<16, true>), dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (J) {
-    case 4: HJM_LAUNCH(k_exp<4>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
-    case 8: HJM_LAUNCH(k_exp<8>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
-    case 16: HJM_LAUNCH(k_exp<16>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 4: HJM_LAUNCH((k_exp<4, false>), dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 8: HJM_LAUNCH((k_exp<8, false>), dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
+    case 16: HJM_LAUNCH((k_exp<16, false>), dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks, step); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1743,13 +1799,22 @@ void exr_lds(int nr, int rows, size_t* bytes, int* tab)
 }
 
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
-                      hipStream_t st)
+                      hipStream_t st, bool stage2)
 {
     if (n_tasks <= 0) return hipSuccess;
+    if (stage2) {
+        switch (rows) {
+        case 8: HJM_LAUNCH((k_exr<8, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        case 12: HJM_LAUNCH((k_exr<12, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        case 16: HJM_LAUNCH((k_exr<16, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (rows) {
-    case 8: HJM_LAUNCH(k_exr<8>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
-    case 12: HJM_LAUNCH(k_exr<12>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
-    case 16: HJM_LAUNCH(k_exr<16>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 8: HJM_LAUNCH((k_exr<8, false>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 12: HJM_LAUNCH((k_exr<12, false>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+    case 16: HJM_LAUNCH((k_exr<16, false>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

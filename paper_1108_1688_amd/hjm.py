@@ -22,6 +22,7 @@ BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
 N_PASSES = 4  # HJM_N_PASSES
 PASSES = ("explicit", "r", "v", "y+update")
 R_METHODS = ("spike", "chain", "split", "fused")
+SCHEMES = ("douglas", "cs", "mcs", "hv")  # HJM_SCHEME_*
 MLP_PARAMS = 199937  # HJM_MLP_PARAMS
 
 
@@ -48,6 +49,10 @@ class Payoff(C.Structure):
                 ("strike", C.c_double)]
 
 
+class Scheme(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("theta", C.c_double)]
+
+
 _lib = None
 
 
@@ -64,6 +69,8 @@ def lib():
     sig = {
         "hjm_workspace_bytes": (st, [P(Axis), i32, P(sz)]),
         "hjm_grid_create": (st, [P(Axis), P(Model), P(Payoff), i32, vp, sz, vp, P(vp)]),
+        "hjm_scheme_workspace_bytes": (st, [P(Axis), i32, P(Scheme), P(sz)]),
+        "hjm_grid_create_scheme": (st, [P(Axis), P(Model), P(Payoff), P(Scheme), i32, vp, sz, vp, P(vp)]),
         "hjm_adi_step": (st, [vp, i32]),
         "hjm_price": (st, [vp, d, d, P(d)]),
         "hjm_grid_solution": (st, [vp, P(vp), P(i64)]),
@@ -188,9 +195,15 @@ def _workspace(nbytes: int, device):
     return ws
 
 
+def make_scheme(spec) -> "Scheme":
+    """The spec's ADI scheme (Douglas with theta = 1/2 unless it says otherwise)."""
+    return Scheme(int(getattr(spec, "scheme", 0)), 0, float(getattr(spec, "theta", 0.5)))
+
+
 def workspace_bytes(spec) -> int:
     nbytes = C.c_size_t()
-    check(lib().hjm_workspace_bytes(make_axes(spec.axes), spec.n_steps, C.byref(nbytes)))
+    check(lib().hjm_scheme_workspace_bytes(make_axes(spec.axes), spec.n_steps, C.byref(make_scheme(spec)),
+                                           C.byref(nbytes)))
     return nbytes.value
 
 
@@ -210,8 +223,9 @@ class Grid:
         self._ax = make_axes(spec.axes)
         self._model = make_model(spec.model)
         self._payoff = make_payoff(spec.payoff)
+        self._scheme = make_scheme(spec)
         nbytes = C.c_size_t()
-        check(L.hjm_workspace_bytes(self._ax, spec.n_steps, C.byref(nbytes)))
+        check(L.hjm_scheme_workspace_bytes(self._ax, spec.n_steps, C.byref(self._scheme), C.byref(nbytes)))
         if workspace is not None:
             if workspace.dtype != torch.float64 or workspace.numel() * 8 < nbytes.value:
                 raise ValueError("workspace must be a float64 tensor of at least the required bytes")
@@ -221,9 +235,9 @@ class Grid:
         else:
             self.ws = _workspace(nbytes.value, self.device)
         h = C.c_void_p()
-        check(L.hjm_grid_create(self._ax, C.byref(self._model), C.byref(self._payoff), spec.n_steps,
-                                C.c_void_p(self.ws.data_ptr()), nbytes.value, _stream_handle(self.stream),
-                                C.byref(h)))
+        check(L.hjm_grid_create_scheme(self._ax, C.byref(self._model), C.byref(self._payoff),
+                                       C.byref(self._scheme), spec.n_steps, C.c_void_p(self.ws.data_ptr()),
+                                       nbytes.value, _stream_handle(self.stream), C.byref(h)))
         self._h = h
 
     def step(self, k: Optional[int] = None) -> "Grid":
@@ -265,7 +279,7 @@ class Grid:
         out = (C.c_int32 * 8)()
         check(lib().hjm_grid_plan(self._h, out))
         return {"r_method": R_METHODS[out[0]], "rs_rows": out[1], "line_tile": (out[2], out[3], out[4]),
-                "vs_rows": out[5], "yc_rows": out[6]}
+                "vs_rows": out[5], "yc_rows": out[6], "scheme": SCHEMES[out[7]]}
 
     def profile(self, enable: bool = True) -> None:
         """Bracket every pass launch with HIP events on the grid's stream."""
@@ -298,6 +312,8 @@ class Batch:
 
     def __init__(self, specs: Sequence, stream=None, device: Optional[str] = None):
         torch = _torch()
+        if any(getattr(sp, "scheme", 0) != 0 or getattr(sp, "theta", 0.5) != 0.5 for sp in specs):
+            raise ValueError("batches run the Douglas scheme with theta = 1/2; price other schemes with Grid")
         L = lib()
         self.specs = list(specs)
         n = len(self.specs)

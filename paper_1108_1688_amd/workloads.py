@@ -25,6 +25,9 @@ import numpy as np
 OUTFLOW = 0
 DIRICHLET = 1
 BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
+# ADI schemes: the paper's Douglas, Craig-Sneyd, modified Craig-Sneyd,
+# Hundsdorfer-Verwer (usual theta: 1/2, 1/2, 1/3, 1/2 + sqrt(3)/6)
+DOUGLAS, CS, MCS, HV = 0, 1, 2, 3
 
 LAMBDA = 0.15
 GAMMA = 0.9
@@ -75,6 +78,8 @@ class SolveSpec:
     n_steps: int
     r0: float
     v0: float = 1.0
+    scheme: int = 0      # ADI scheme: DOUGLAS (the paper's), CS, MCS or HV
+    theta: float = 0.5   # implicit weight of the line solves
 
     @property
     def shape(self):

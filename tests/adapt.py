@@ -9,4 +9,5 @@ def to_oracle(s: W.SolveSpec) -> O.Problem:
     return O.Problem(axes, kappa=m.kappa, theta_v=m.theta_v, lam=m.lam, gamma=m.gamma,
                      epsilon=m.epsilon, rho=m.rho, f_level=m.f_level, f_slope=m.f_slope,
                      f_decay=m.f_decay, kind=s.payoff.kind, expiry=s.payoff.expiry,
-                     pay=s.payoff.pay, strike=s.payoff.strike, n_steps=s.n_steps)
+                     pay=s.payoff.pay, strike=s.payoff.strike, n_steps=s.n_steps,
+                     scheme=s.scheme, theta=s.theta)

@@ -136,6 +136,30 @@ def test_line_tile_setting(L):
         hjm.set_line_tile(*old)
 
 
+def test_scheme_workspace_and_validation(L):
+    """A correction scheme needs one more grid-sized array; unknown schemes,
+    theta outside (0, 1] and grids without the lane-split r solve are
+    rejected on the host."""
+    from dataclasses import replace
+    s = W.config1()[1]
+    ax = hjm.make_axes(s.axes)
+    dbl = hjm.workspace_bytes(s)
+    cs = hjm.workspace_bytes(replace(s, scheme=W.CS))
+    assert cs - dbl >= s.points * 8 and cs - dbl < s.points * 8 + 512
+    nb = C.c_size_t()
+    for kind, theta in ((4, 0.5), (-1, 0.5), (W.CS, 0.0), (W.MCS, 1.5), (W.HV, float("nan"))):
+        st = L.hjm_scheme_workspace_bytes(ax, 10, C.byref(hjm.Scheme(kind, 0, theta)), C.byref(nb))
+        assert st == hjm.EINVAL, (kind, theta)
+    # nr = 40 has no power-of-two lane split: rejected before the workspace is touched
+    bad = replace(W.with_shape(s, 40, 24, 32, 10), scheme=W.CS)
+    h = C.c_void_p()
+    st = L.hjm_grid_create_scheme(hjm.make_axes(bad.axes), C.byref(hjm.make_model(bad.model)),
+                                  C.byref(hjm.make_payoff(bad.payoff)), C.byref(hjm.make_scheme(bad)), bad.n_steps,
+                                  C.c_void_p(256), 1 << 40, None, C.byref(h))
+    assert st == hjm.EINVAL and not h.value
+    assert "lane-split" in L.hjm_last_error().decode()
+
+
 def test_tuning_knobs(L):
     """Explicit chunk, r fusion and batch stream lanes: process-wide host
     settings, read back as set; invalid values rejected."""
