@@ -987,7 +987,9 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
             else if (pass == 1) e = launch_rs(p.rs_rows, dd, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
             else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, dd, nullptr, p.vs_tiles, p.vs_S, g->stream);
             else if (pass == 2) e = launch_v(g->rows[1], dd, nullptr, p.v_tiles, p.v_lds, g->stream);
-            else if (p.yc_rows) e = launch_yc(p.yc_rows, dd, nullptr, p.yc_tiles, p.yc_S, g->stream);
+            else if (p.yc_rows)
+                e = launch_yc(p.yc_rows, dd, nullptr, p.yc_tiles, p.yc_S, g->stream,
+                              !g->corr ? 0 : (!st2 ? 1 : (g->desc2.hv ? 2 : 0)));
             else e = launch_yu(g->rows[2], dd, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {

@@ -883,8 +883,122 @@ __device__ __forceinline__ void wave_sync()
 // registers, one more LDS-pipe latency before the arithmetic; measured
 // faster inside the fused kernel, slower in the explicit kernel alone).  j0
 // must be wave-uniform (the v-table reads are scalar).
-template <int J, bool SHFL, bool STAGE2, class Put>
+template <int J, bool SHFL, class Put>
 __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k, int j0, int step, const Put& put)
+{
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    gcdouble* U = gp(s.U);
+    gcdouble* rt = gp(s.rt);
+    kcdouble* vt = kp(s.vt);
+    gcdouble* yt = gp(s.yt);
+    gcdouble* stn = gp(s.st) + kStepStride * step;
+
+    const size_t sl = (size_t)nr;       // stride of j
+    const size_t sy = (size_t)nr * nv;  // stride of k
+    gcdouble* col = U + (size_t)k * sy; // (k, j = 0, i = 0)
+    const int im = max(i - 1, 0), ip = min(i + 1, nr - 1);
+    // y stencil: two neighbours (offsets oa, ob) and the node itself
+    const bool yhd = s.y_hi_dir && k == ny - 1;
+    int oa = -1, ob = 1;
+    if (k == 0) { oa = 1; ob = 2; }
+    else if (k == ny - 1) { oa = -2; ob = -1; }
+    if (yhd) { oa = 0; ob = 0; }
+    gcdouble* cola = col + (ptrdiff_t)oa * (ptrdiff_t)sy;  // plane k + oa
+    gcdouble* colb = col + (ptrdiff_t)ob * (ptrdiff_t)sy;
+    const int dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
+    auto jcl = [&](int jj) { return (size_t)min(max(jj, 0), nv - 1) * sl; };
+    double cw[J + 4], lw[J + 2], rw[J + 2], ya[J], yb[J], ux[J];
+#pragma unroll
+    for (int m = 0; m < J + 4; ++m) cw[m] = col[jcl(j0 - 2 + m) + i];
+#pragma unroll
+    for (int m = 0; m < J; ++m) {
+        ya[m] = cola[jcl(j0 + m) + i];
+        yb[m] = colb[jcl(j0 + m) + i];
+    }
+    if (SHFL) {
+        // the r faces clamp to the node itself
+        const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+        for (int m = 0; m < J + 2; ++m) {
+            const double lo = __shfl_up(cw[m + 1], 1);
+            const double hi = __shfl_down(cw[m + 1], 1);
+            lw[m] = i == 0 ? cw[m + 1] : lo;
+            rw[m] = i == nr - 1 ? cw[m + 1] : hi;
+        }
+        if (lane == 0 && i > 0) {
+#pragma unroll
+            for (int m = 0; m < J + 2; ++m) lw[m] = col[jcl(j0 - 1 + m) + im];
+        }
+        if (lane == 63 && i < nr - 1) {
+#pragma unroll
+            for (int m = 0; m < J + 2; ++m) rw[m] = col[jcl(j0 - 1 + m) + ip];
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < J + 2; ++m) {
+            lw[m] = col[jcl(j0 - 1 + m) + im];
+            rw[m] = col[jcl(j0 - 1 + m) + ip];
+        }
+    }
+    if (dx != 0) {
+        // outflow r face rows reach two nodes in
+#pragma unroll
+        for (int m = 0; m < J; ++m) ux[m] = col[jcl(j0 + m) + (size_t)(i + dx)];
+    } else {
+        // interior rows: the extra entry has weight zero
+#pragma unroll
+        for (int m = 0; m < J; ++m) ux[m] = cw[m + 2];
+    }
+
+    // per-column constants: A1 row pieces (affine in v), A3 coefficient, A0 factor
+    const double c = stn[ST_PHI] + yt[YT_Y * ny + k];
+    const double e = rt[RT_P * nr + i] * c + rt[RT_Q * nr + i];
+    const double mlo = rt[RT_MLO * nr + i] * e, alo = rt[RT_ALO * nr + i];
+    const double mdi = rt[RT_MDI * nr + i] * e - rt[RT_RR * nr + i], adi = rt[RT_ADI * nr + i];
+    const double mup = rt[RT_MUP * nr + i] * e, aup = rt[RT_AUP * nr + i];
+    const double mex = rt[RT_MEX * nr + i] * e;
+    const double ryk = rt[RT_Y * nr + i] * yt[YT_I * ny + k];
+    const double kyk = yt[YT_K * ny + k];
+    const double rx = rt[RT_X * nr + i];
+    double wa = yt[YT_W1 * ny + k], wb = yt[YT_W3 * ny + k];
+    if (k == 0) { wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
+    else if (k == ny - 1) { wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
+    const double w2 = yt[YT_W2 * ny + k];
+    // Dirichlet nodes: the increment does not depend on j
+    gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
+    const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
+    const bool dir = rlo || rhi || yhd;
+    const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
+    const double dt = s.dt;
+#pragma unroll
+    for (int m = 0; m < J; ++m) {
+        const int j = j0 + m;
+        if (j >= nv) break;  // wave-uniform
+        const double v = vt[VT_V * nv + j];
+        const double olo = mlo + alo * v, odi = mdi + adi * v, oup = mup + aup * v;
+        const double a1 = olo * lw[m + 1] + odi * cw[m + 2] + oup * rw[m + 1] + mex * ux[m];
+        const double a2 = vt[VT_O0 * nv + j] * cw[m] + vt[VT_O1 * nv + j] * cw[m + 1] +
+                          vt[VT_O2 * nv + j] * cw[m + 2] + vt[VT_O3 * nv + j] * cw[m + 3] +
+                          vt[VT_O4 * nv + j] * cw[m + 4];
+        const double by = ryk * v - kyk;
+        const double a3 = by * (wa * ya[m] + w2 * cw[m + 2] + wb * yb[m]);
+        const double cross = (rw[m + 2] - rw[m]) - (lw[m + 2] - lw[m]);
+        const double a0 = rx * vt[VT_X * nv + j] * cross;
+        const double val = dt * (((a1 + a2) + a3) + a0);
+        put(m, dir ? gval : val);
+    }
+}
+
+// The corrected start of the Craig-Sneyd family at the same J nodes, for
+// the second sweep sequence of a step (the descriptor's D is the correction
+// array):  E0 = dt A U + dt (a0 A0 + a1 (A1 + A2 + A3)) D3 + b D3 on
+// non-Dirichlet nodes, with (a0, a1, b) = (sc_a0, sc_a1, sc_b) and D3 the
+// first sequence's result; on Dirichlet nodes the increment g(t_{n+1}) -
+// g(t_n) when b = 0 (the correction is relative to U^n) and 0 otherwise (HV:
+// relative to U^n + D3, which already holds it).  The stencil of U, then the
+// same stencil of D3, each over windows loaded as the predictor loads them.
+template <int J, bool SHFL, class Put>
+__device__ __forceinline__ void corrected_start(const SolveDesc& s, int i, int k, int j0, int step, const Put& put)
 {
     const int nr = s.nr, nv = s.nv, ny = s.ny;
     gcdouble* rt = gp(s.rt);
@@ -988,17 +1102,7 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
     const bool dir = rlo || rhi || yhd;
     const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
     const double dt = s.dt;
-    if (!STAGE2) {
-#pragma unroll
-        for (int m = 0; m < J; ++m) {
-            if (j0 + m >= nv) break;  // wave-uniform
-            double a123, a0;
-            stencil(m, a123, a0);
-            put(m, dir ? gval : dt * (a123 + a0));
-        }
-    } else {
-        // corrected start of the Craig-Sneyd family:
-        // dt A U + dt (a0c A0 + a1c (A1 + A2 + A3)) D3 + bc D3
+    {
         double su[J], s0[J];
 #pragma unroll
         for (int m = 0; m < J; ++m) {
@@ -1040,7 +1144,11 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
     // j is the same on every lane: keep it (and the v-table reads) scalar
     const int j0 = __builtin_amdgcn_readfirstlane(jc * J);
     gdouble* dcol = gp(s.D) + (size_t)k * nr * s.nv + (size_t)j0 * nr + i;
-    explicit_nodes<J, false, STAGE2>(s, i, k, j0, step, [&](int m, double x) { dcol[(size_t)m * nr] = x; });
+    auto put = [&](int m, double x) { dcol[(size_t)m * nr] = x; };
+    if constexpr (STAGE2)
+        corrected_start<J, false>(s, i, k, j0, step, put);
+    else
+        explicit_nodes<J, false>(s, i, k, j0, step, put);
 }
 
 // The spike solve of one r line of nr = S * ROWS rows (S a power of two <=
@@ -1292,9 +1400,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
             const int g = i / ROWS;
             ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
 #pragma unroll 1
-            for (int jc = 0; jc < kExrJ; jc += 8)
-                explicit_nodes<8, true, STAGE2>(s, i, k, j0 + jc, step,
-                                  [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; });
+            for (int jc = 0; jc < kExrJ; jc += 8) {
+                auto put = [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; };
+                if constexpr (STAGE2)
+                    corrected_start<8, true>(s, i, k, j0 + jc, step, put);
+                else
+                    explicit_nodes<8, true>(s, i, k, j0 + jc, step, put);
+            }
         }
     }
     __syncthreads();
@@ -1459,7 +1571,7 @@ __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ d
 // FMA forward and one backward.  Then U^{n+1} = U^n + D3.  Workgroup = yc_S
 // waves; wave w holds rows [w ROWS, (w+1) ROWS) of 64 consecutive lines
 // (i, j), so row reads are contiguous and the y-table reads are wave-uniform.
-template <int ROWS>
+template <int ROWS, int MODE>
 __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
     extern __shared__ double lds_raw[];
@@ -1572,7 +1684,7 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
         if (S > 1) __syncthreads();
     }
     if (active) {
-        if (s.stage == 1) {
+        if constexpr (MODE == 1) {
             // first sequence of the Craig-Sneyd family: D3 stays in D, U unchanged
 #pragma unroll
             for (int mm = 0; mm < ROWS; ++mm) D[off + (size_t)mm * sy] = d[mm];
@@ -1580,7 +1692,7 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
             double u[ROWS];
 #pragma unroll
             for (int mm = 0; mm < ROWS; ++mm) u[mm] = U[off + (size_t)mm * sy];
-            if (s.hv) {
+            if constexpr (MODE == 2) {
                 // Hundsdorfer-Verwer: the correction is relative to U + D3
                 gcdouble* D3 = gp(s.D3);
 #pragma unroll
@@ -1657,6 +1769,14 @@ hipError_t allow_lds(K kernel)
                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
+template <int ROWS>
+hipError_t allow_yc()
+{
+    hipError_t e;
+    if ((e = allow_lds(k_yc<ROWS, 0>)) || (e = allow_lds(k_yc<ROWS, 1>))) return e;
+    return allow_lds(k_yc<ROWS, 2>);
+}
+
 }  // namespace
 
 // Timing events for the next sweep launch of this thread (profiling): the
@@ -1690,8 +1810,7 @@ hipError_t init_kernel_attributes()
             (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_exr<8, false>)) || (e = allow_lds(k_exr<12, false>)) ||
             (e = allow_lds(k_exr<16, false>)) || (e = allow_lds(k_exr<8, true>)) ||
             (e = allow_lds(k_exr<12, true>)) || (e = allow_lds(k_exr<16, true>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
-            (e = allow_lds(k_vs<32>)) || (e = allow_lds(k_yc<8>)) || (e = allow_lds(k_yc<16>)) ||
-            (e = allow_lds(k_yc<32>)))
+            (e = allow_lds(k_vs<32>)) || (e = allow_yc<8>()) || (e = allow_yc<16>()) || (e = allow_yc<32>()))
             return e;
         return hipSuccess;
     }();
@@ -1848,13 +1967,19 @@ hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines,
     return hipGetLastError();
 }
 
-hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st)
+hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st,
+                     int mode)
 {
     if (n_tasks <= 0) return hipSuccess;
     if (S_max < 1 || S_max > yc_max_segments(rows)) return hipErrorInvalidValue;
     // the exchange slots (2 per lane) and C inv of every row of the lines
     const size_t lds = (size_t)(2 + (size_t)S_max * rows) * 64 * 8;
-    HJM_DISPATCH_ROWS(rows, HJM_LAUNCH(k_yc<R>, dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
+    switch (mode) {
+    case 0: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 0>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
+    case 1: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 1>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
+    case 2: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 2>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
