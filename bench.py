@@ -149,6 +149,41 @@ def calibration(hjm, W, torch, stream, n_solves: int, tune: bool):
     return out
 
 
+def schemes_leg(hjm, W, torch, stream, reps: int = 3):
+    """The ADI schemes on the 1-year caplet of the 256x128x128 workload (40
+    steps): whole solves (set-up, steps, readout), per scheme; the correction
+    schemes sweep twice per step.  Also the price against a 4x finer time
+    grid of the same scheme, a measure of each scheme's time error."""
+    import math
+    from dataclasses import replace
+    base = W.config3()[0]
+    out = {"workload": "256x128x128 1-year ATM caplet, 40 steps (dt = 0.025); price error against 160 steps"}
+    for name, sc, th in (("douglas", W.DOUGLAS, 0.5), ("cs", W.CS, 0.5), ("mcs", W.MCS, 1.0 / 3.0),
+                         ("hv", W.HV, 0.5 + math.sqrt(3.0) / 6.0)):
+        spec = replace(base, scheme=sc, theta=th)
+        g = hjm.Grid(spec, stream=stream)
+        g.step()
+        p40 = g.price()
+        g.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g = hjm.Grid(spec, stream=stream)
+            g.step()
+            g.price()
+            g.close()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        g = hjm.Grid(replace(spec, n_steps=4 * spec.n_steps), stream=stream)
+        g.step()
+        p160 = g.price()
+        g.close()
+        out[name] = {"theta": th, "ms_per_solve": round(el * 1e3, 3),
+                     "point_steps_per_s": spec.points * spec.n_steps / el,
+                     "price": p40, "price_160_steps": p160, "rel_diff_vs_160_steps": abs(p40 - p160) / abs(p160)}
+    return out
+
+
 def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int, outside_frac: float):
     """Surrogate pricing: train on ADI prices (n_train_solves solves at 64^3,
     16 readouts each), then price n_query rows, a fraction outside the box
@@ -201,6 +236,7 @@ def main():
     ap.add_argument("--no-calibration", action="store_true", help="skip the batched calibration throughput")
     ap.add_argument("--calib-solves", type=int, default=512)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg of the calibration")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the ADI-schemes leg")
     ap.add_argument("--sur-solves", type=int, default=4096, help="ADI solves for the surrogate's training set")
     ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
@@ -356,6 +392,9 @@ def main():
             plain = out["calibration"]["plain_solves_per_s"]
             out["calibration"]["surrogate_speedup_vs_plain"] = out["calibration"]["surrogate"]["solves_per_s"] / plain
         log(f"calibration: {out['calibration']}")
+    if not args.no_schemes:
+        out["schemes"] = schemes_leg(hjm, W, torch, stream)
+        log(f"schemes: {out['schemes']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -1365,6 +1365,11 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
 // read its rows (pass p's scratch is its first 8 kBlock doubles, inside its
 // kBlock / S lines; the tile is sized to whole passes).  Three waves per SIMD
 // (at most 168 VGPRs; a few spill) measured faster than two without spills.
+// v nodes per explicit chunk of k_exr: 8; 4 for the corrected start, which
+// holds the stencil of U while it loads the windows of D3
+template <bool STAGE2>
+constexpr int kExrChunk = STAGE2 ? 4 : 8;
+
 template <int ROWS, bool STAGE2>
 __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
                                                 int step)
@@ -1400,12 +1405,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
             const int g = i / ROWS;
             ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
 #pragma unroll 1
-            for (int jc = 0; jc < kExrJ; jc += 8) {
+            for (int jc = 0; jc < kExrJ; jc += kExrChunk<STAGE2>) {
                 auto put = [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; };
                 if constexpr (STAGE2)
-                    corrected_start<8, true>(s, i, k, j0 + jc, step, put);
+                    corrected_start<kExrChunk<STAGE2>, true>(s, i, k, j0 + jc, step, put);
                 else
-                    explicit_nodes<8, true>(s, i, k, j0 + jc, step, put);
+                    explicit_nodes<kExrChunk<STAGE2>, true>(s, i, k, j0 + jc, step, put);
             }
         }
     }
