@@ -154,6 +154,12 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k);
    is outside the mesh. */
 hjm_status hjm_price(hjm_grid* g, double r0, double v0, double* out);
 
+/* As hjm_price, with the Greeks the paper plots (section 6): out[0] = C,
+   out[1] = rho = dC/dr and out[2] = vega = dC/dv at (r0, v0, y=0), the
+   derivatives of the same interpolant (in mesh coordinates, times the mesh
+   map's dx/dz). */
+hjm_status hjm_price_greeks(hjm_grid* g, double r0, double v0, double out[3]);
+
 /* Borrow the device grid U (nr*nv*ny doubles, inside the caller's workspace)
    and the number of steps taken so far.  Writing U and then calling
    hjm_grid_set_step restores a checkpoint. */
@@ -227,6 +233,10 @@ hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph);
 /* After hjm_batch_run: synchronise, check health, and read out the n prices
    at (r0[s], v0[s]) as hjm_price does. */
 hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, double* out);
+
+/* The same with the Greeks: out[3 s .. 3 s + 2] = (C, dC/dr, dC/dv) of solve
+   s, as hjm_price_greeks. */
+hjm_status hjm_batch_greeks(hjm_batch* b, const double* r0, const double* v0, double* out);
 
 /* Per-kernel timing of eager runs (hjm_batch_run with use_graph = 0): every
    launch of the first `steps` Douglas steps is bracketed by HIP events the

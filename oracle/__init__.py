@@ -89,6 +89,7 @@ def lib():
             "orc_run": (C.c_int, [P, C.c_int, C.c_int, dp]),
             "orc_bond_grid": (C.c_int, [P, d, dp]),
             "orc_readout": (d, [P, dp, d, d]),
+            "orc_greeks": (None, [P, dp, d, d, dp]),
             "orc_price": (C.c_int, [P, d, d, dp, dp]),
         }
         for name, (res, args) in sig.items():
@@ -273,6 +274,15 @@ def bond_grid(p: Problem, t: float) -> np.ndarray:
 def readout(p: Problem, U: np.ndarray, r0: float, v0: float) -> float:
     U = np.ascontiguousarray(U, dtype=np.float64)
     return lib().orc_readout(p.ref(), _dp(U), r0, v0)
+
+
+def greeks(p: Problem, U: np.ndarray, r0: float, v0: float) -> np.ndarray:
+    """(C, dC/dr, dC/dv) at (r0, v0, y_min): the readout's interpolant and its
+    derivatives (the rho and vega of section 6)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.empty(3)
+    lib().orc_greeks(p.ref(), _dp(U), r0, v0, _dp(out))
+    return out
 
 
 def price(p: Problem, r0: float, v0: float = 1.0):

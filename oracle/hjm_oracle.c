@@ -721,6 +721,69 @@ double orc_readout(const orc_problem* p, const double* U, double r0, double v0)
     return s;
 }
 
+/* The Greeks the paper plots (section 6): rho = dC/dr and vega = dC/dv at
+   (r0, v0) on the y = y_min plane, as the derivatives of the same tensor
+   4-point Lagrange interpolant.  In mesh coordinates x the derivative of the
+   basis function of node a is sum_{c != a} prod_{b != a, c} (x - x_b) /
+   prod_{b != a} (x_a - x_b); the chain rule multiplies it by dx/dz =
+   1 / ((c2 - c1) sqrt(alpha^2 + (z - K)^2)) of the sinh map.
+   out = (C, dC/dr, dC/dv). */
+static void lagrange4_d(double x, int n, double dw[4])
+{
+    double h = 1.0 / (double)(n - 1);
+    int m = (int)floor(x / h);
+    if (m < 0) m = 0;
+    if (m > n - 2) m = n - 2;
+    int s = m - 1;
+    if (s < 0) s = 0;
+    if (s > n - 4) s = n - 4;
+    for (int a = 0; a < 4; ++a) {
+        double xa = (double)(s + a) * h, den = 1.0, sum = 0.0;
+        for (int b = 0; b < 4; ++b)
+            if (b != a) den *= (xa - (double)(s + b) * h);
+        for (int c = 0; c < 4; ++c) {
+            if (c == a) continue;
+            double prod = 1.0;
+            for (int b = 0; b < 4; ++b)
+                if (b != a && b != c) prod *= (x - (double)(s + b) * h);
+            sum += prod;
+        }
+        dw[a] = sum / den;
+    }
+}
+
+static double axis_dxdz(double z, double zmin, double zmax, double K, double alpha)
+{
+    double c1 = asinh((zmin - K) / alpha), c2 = asinh((zmax - K) / alpha);
+    return 1.0 / ((c2 - c1) * sqrt(alpha * alpha + (z - K) * (z - K)));
+}
+
+void orc_greeks(const orc_problem* p, const double* U, double r0, double v0, double* out)
+{
+    int nr = p->n[0], nv = p->n[1];
+    double xr = orc_axis_x(r0, p->geom[0][0], p->geom[0][1], p->geom[0][2], p->geom[0][3]);
+    double xv = orc_axis_x(v0, p->geom[1][0], p->geom[1][1], p->geom[1][2], p->geom[1][3]);
+    int si, sj;
+    double wr[4], wv[4], dr[4], dv[4];
+    lagrange4(xr, nr, &si, wr);
+    lagrange4(xv, nv, &sj, wv);
+    lagrange4_d(xr, nr, dr);
+    lagrange4_d(xv, nv, dv);
+    double gr = axis_dxdz(r0, p->geom[0][0], p->geom[0][1], p->geom[0][2], p->geom[0][3]);
+    double gv = axis_dxdz(v0, p->geom[1][0], p->geom[1][1], p->geom[1][2], p->geom[1][3]);
+    double c = 0.0, cr = 0.0, cv = 0.0;
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a) {
+            double u = U[(size_t)(sj + b) * (size_t)nr + (size_t)(si + a)];
+            c += wv[b] * wr[a] * u;
+            cr += wv[b] * dr[a] * u;
+            cv += dv[b] * wr[a] * u;
+        }
+    out[0] = c;
+    out[1] = cr * gr;
+    out[2] = cv * gv;
+}
+
 /* Full solve from t = T to t = 0 and readout; U (nr*nv*ny) receives the
    final grid. */
 int orc_price(const orc_problem* p, double r0, double v0, double* U, double* price)

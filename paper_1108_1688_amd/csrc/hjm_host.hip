@@ -657,7 +657,8 @@ hipError_t upload_tables(const SolveDesc& d, const std::vector<double>& t, hipSt
 
 // 4-point Lagrange stencil in mesh coordinates (window centred on the
 // bracketing interval, clamped to the mesh).
-void lagrange4(double x, int n, int* start, double w[4])
+// dw receives the derivatives of the weights with respect to x.
+void lagrange4(double x, int n, int* start, double w[4], double dw[4])
 {
     const double h = 1.0 / (double)(n - 1);
     int m = (int)std::floor(x / h);
@@ -673,8 +674,26 @@ void lagrange4(double x, int n, int* start, double w[4])
             den *= (xa - xb);
         }
         w[a] = num / den;
+        // d/dx of prod_{b != a} (x - x_b): sum over the factor left out
+        double dnum = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            if (c == a) continue;
+            double pr = 1.0;
+            for (int b = 0; b < 4; ++b)
+                if (b != a && b != c) pr *= (x - (double)(s + b) * h);
+            dnum += pr;
+        }
+        dw[a] = dnum / den;
     }
     *start = s;
+}
+
+// dx/dz of the sinh mesh map x(z) = (asinh((z - K)/alpha) - c1) / (c2 - c1)
+double mesh_dxdz(const hjm_axis& a, double z)
+{
+    const double c1 = std::asinh((a.z_min - a.center) / a.alpha);
+    const double c2 = std::asinh((a.z_max - a.center) / a.alpha);
+    return 1.0 / ((c2 - c1) * std::sqrt(a.alpha * a.alpha + (z - a.center) * (z - a.center)));
 }
 
 hjm_status make_readout(const hjm_axis ax[3], double r0, double v0, int solve, Readout* R)
@@ -684,8 +703,13 @@ hjm_status make_readout(const hjm_axis ax[3], double r0, double v0, int solve, R
     if (v0 < ax[1].z_min || v0 > ax[1].z_max) return fail(HJM_EINVAL, "v0=%g outside the mesh", v0);
     std::memset(R, 0, sizeof *R);
     R->solve = solve;
-    lagrange4(mesh_x(ax[0], r0), ax[0].n, &R->i0, R->wr);
-    lagrange4(mesh_x(ax[1], v0), ax[1].n, &R->j0, R->wv);
+    lagrange4(mesh_x(ax[0], r0), ax[0].n, &R->i0, R->wr, R->dwr);
+    lagrange4(mesh_x(ax[1], v0), ax[1].n, &R->j0, R->wv, R->dwv);
+    const double sr = mesh_dxdz(ax[0], r0), sv = mesh_dxdz(ax[1], v0);
+    for (int a = 0; a < 4; ++a) {
+        R->dwr[a] *= sr;
+        R->dwv[a] *= sv;
+    }
     return HJM_OK;
 }
 
@@ -714,7 +738,7 @@ struct hjm_grid {
     int32_t* d_flag = nullptr;
     std::vector<double> tables;
     Readout rq;            // host copy of the last readout request
-    double out_host = 0.0;
+    double out_host[3] = {0.0, 0.0, 0.0};
     int32_t flag_host = 0;
     // per-pass timing
     bool profile = false;
@@ -740,7 +764,7 @@ GridLayout grid_layout(const hjm_axis ax[3], int n_steps, bool corr = false)
     GridLayout g;
     g.desc = L.take(sizeof(SolveDesc) * (corr ? 2 : 1));
     g.rq = L.take(sizeof(Readout));
-    g.out = L.take(sizeof(double));
+    g.out = L.take(sizeof(double) * 3);
     g.flag = L.take(sizeof(int32_t));
     g.s = layout_solve(L, ax, n_steps, corr);
     g.total = L.off;
@@ -1004,6 +1028,16 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
 
 hjm_status hjm_price(hjm_grid* g, double r0, double v0, double* out)
 {
+    if (!out) return fail(HJM_EINVAL, "null argument");
+    double three[3];
+    hjm_status st = hjm_price_greeks(g, r0, v0, three);
+    if (st) return st;
+    *out = three[0];
+    return HJM_OK;
+}
+
+hjm_status hjm_price_greeks(hjm_grid* g, double r0, double v0, double out[3])
+{
     if (!g || !out) return fail(HJM_EINVAL, "null argument");
     if (g->step != g->n_steps)
         return fail(HJM_ESTATE, "price needs all %d steps (taken %lld)", g->n_steps, (long long)g->step);
@@ -1013,12 +1047,12 @@ hjm_status hjm_price(hjm_grid* g, double r0, double v0, double* out)
     if ((e = hipMemcpyAsync(g->d_rq, &g->rq, sizeof g->rq, hipMemcpyHostToDevice, g->stream)) ||
         (e = launch_health(g->d_desc, 1, (int64_t)g->ax[0].n * g->ax[1].n * g->ax[2].n, g->stream)) ||
         (e = launch_readout(g->d_desc, g->d_rq, 1, g->d_out, g->stream)) ||
-        (e = hipMemcpyAsync(&g->out_host, g->d_out, sizeof(double), hipMemcpyDeviceToHost, g->stream)) ||
+        (e = hipMemcpyAsync(g->out_host, g->d_out, sizeof(double) * 3, hipMemcpyDeviceToHost, g->stream)) ||
         (e = hipMemcpyAsync(&g->flag_host, g->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream)) ||
         (e = hipStreamSynchronize(g->stream)))
         return hip_fail(e, "hjm_price");
     if (g->flag_host) return fail(HJM_ENUMERIC, "non-finite value or non-positive pivot in the solve");
-    *out = g->out_host;
+    for (int q = 0; q < 3; ++q) out[q] = g->out_host[q];
     return HJM_OK;
 }
 
@@ -1172,7 +1206,7 @@ BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
     b.desc = L.take(sizeof(SolveDesc) * n);
     b.tasks = L.take(sizeof(int2) * std::max<size_t>(nt, 1));
     b.rq = L.take(sizeof(Readout) * n);
-    b.out = L.take(sizeof(double) * n);
+    b.out = L.take(sizeof(double) * 3 * n);
     b.flags = L.take(sizeof(int32_t) * n);
     b.s.resize(n);
     for (int s = 0; s < n; ++s) b.s[s] = layout_solve(L, ax + 3 * s, n_steps[s]);
@@ -1440,6 +1474,16 @@ hjm_status hjm_batch_run(hjm_batch* b, int32_t use_graph)
 
 hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, double* out)
 {
+    if (!b || !out) return fail(HJM_EINVAL, "null argument");
+    std::vector<double> three(3 * (size_t)b->n);
+    hjm_status st = hjm_batch_greeks(b, r0, v0, three.data());
+    if (st) return st;
+    for (int s = 0; s < b->n; ++s) out[s] = three[3 * (size_t)s];
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_greeks(hjm_batch* b, const double* r0, const double* v0, double* out)
+{
     if (!b || !r0 || !v0 || !out) return fail(HJM_EINVAL, "null argument");
     if (!b->ran) return fail(HJM_ESTATE, "hjm_batch_run has not been called");
     b->rq.resize(b->n);
@@ -1452,11 +1496,11 @@ hjm_status hjm_batch_prices(hjm_batch* b, const double* r0, const double* v0, do
     if ((e = hipMemcpyAsync(b->d_rq, b->rq.data(), sizeof(Readout) * b->n, hipMemcpyHostToDevice, b->stream)) ||
         (e = launch_health(b->d_desc, b->n, b->max_points, b->stream)) ||
         (e = launch_readout(b->d_desc, b->d_rq, b->n, b->d_out, b->stream)) ||
-        (e = hipMemcpyAsync(out, b->d_out, sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream)) ||
+        (e = hipMemcpyAsync(out, b->d_out, sizeof(double) * 3 * b->n, hipMemcpyDeviceToHost, b->stream)) ||
         (e = hipMemcpyAsync(b->flags_host.data(), b->d_flags, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost,
                             b->stream)) ||
         (e = hipStreamSynchronize(b->stream)))
-        return hip_fail(e, "hjm_batch_prices");
+        return hip_fail(e, "hjm_batch_greeks");
     for (int s = 0; s < b->n; ++s)
         if (b->flags_host[s]) return fail(HJM_ENUMERIC, "solve %d: non-finite value or non-positive pivot", s);
     return HJM_OK;

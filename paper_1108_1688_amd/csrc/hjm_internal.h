@@ -138,12 +138,17 @@ enum { ST_PHI = 0, ST_AT, ST_GT, ST_HT, ST_AM, ST_GM, ST_HM };
 enum { KIND_BOND = 0, KIND_CAPLET = 1, KIND_FLOORLET = 2, KIND_FORWARD = 3 };
 
 // Readout request: 4x4 Lagrange stencil on the lowest y plane of one solve.
+// The kernel writes three values per request: the price (weights wr x wv),
+// d price / dr (dwr x wv) and d price / dv (wr x dwv), the derivative
+// weights being those of the interpolant in mesh coordinates times dx/dz.
 struct Readout {
     int32_t solve;
     int32_t i0, j0;
     int32_t pad;
     double wr[4];
     double wv[4];
+    double dwr[4];
+    double dwv[4];
 };
 
 // Record the next sweep launch of the calling thread between these two

@@ -1741,6 +1741,9 @@ __global__ __launch_bounds__(kBlock) void k_gd(const SolveDesc* __restrict__ des
     gp(const_cast<double*>(s.gd))[idx] = inc;
 }
 
+// Price and its r and v derivatives at (r0, v0) on the y_min plane: 4 x 4
+// Lagrange interpolation in mesh coordinates (section 6), differentiated for
+// the Greeks rho = dC/dr and vega = dC/dv the paper plots.
 __global__ void k_readout(const SolveDesc* __restrict__ descs, const Readout* __restrict__ rq, int n,
                           double* __restrict__ out)
 {
@@ -1749,11 +1752,17 @@ __global__ void k_readout(const SolveDesc* __restrict__ descs, const Readout* __
     const Readout R = rq[t];
     const SolveDesc& s = descs[R.solve];
     gcdouble* U = gp(s.U);
-    double acc = 0.0;
+    double acc = 0.0, acc_r = 0.0, acc_v = 0.0;
     for (int b = 0; b < 4; ++b)
-        for (int a = 0; a < 4; ++a)
-            acc += R.wv[b] * R.wr[a] * U[(size_t)(R.j0 + b) * s.nr + (R.i0 + a)];
-    out[t] = acc;
+        for (int a = 0; a < 4; ++a) {
+            const double u = U[(size_t)(R.j0 + b) * s.nr + (R.i0 + a)];
+            acc += R.wv[b] * R.wr[a] * u;
+            acc_r += R.wv[b] * R.dwr[a] * u;
+            acc_v += R.dwv[b] * R.wr[a] * u;
+        }
+    out[3 * t] = acc;
+    out[3 * t + 1] = acc_r;
+    out[3 * t + 2] = acc_v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_health(const SolveDesc* __restrict__ descs)

@@ -83,6 +83,8 @@ def lib():
         "hjm_batch_create": (st, [i32, P(Axis), P(Model), P(Payoff), P(i32), vp, sz, vp, P(vp)]),
         "hjm_batch_run": (st, [vp, i32]),
         "hjm_batch_prices": (st, [vp, P(d), P(d), P(d)]),
+        "hjm_batch_greeks": (st, [vp, P(d), P(d), P(d)]),
+        "hjm_price_greeks": (st, [vp, d, d, P(d)]),
         "hjm_batch_destroy": (st, [vp]),
         "hjm_batch_profile": (st, [vp, i32]),
         "hjm_batch_profile_read": (st, [vp, P(d), P(i64), P(i64)]),
@@ -254,6 +256,14 @@ class Grid:
         check(lib().hjm_price(self._h, float(r0), float(v0), C.byref(out)))
         return out.value
 
+    def greeks(self, r0: Optional[float] = None, v0: Optional[float] = None):
+        """(price, rho = dC/dr, vega = dC/dv) at (r0, v0, y = 0)."""
+        out = (C.c_double * 3)()
+        r0 = self.spec.r0 if r0 is None else r0
+        v0 = self.spec.v0 if v0 is None else v0
+        check(lib().hjm_price_greeks(self._h, float(r0), float(v0), out))
+        return tuple(out)
+
     @property
     def steps_taken(self) -> int:
         p, s = C.c_void_p(), C.c_int64()
@@ -360,6 +370,16 @@ class Batch:
         out = np.empty(n)
         dp = C.POINTER(C.c_double)
         check(lib().hjm_batch_prices(self._h, r0.ctypes.data_as(dp), v0.ctypes.data_as(dp), out.ctypes.data_as(dp)))
+        return out
+
+    def greeks(self, r0=None, v0=None) -> np.ndarray:
+        """(n, 3): price, rho = dC/dr and vega = dC/dv of every solve."""
+        n = len(self.specs)
+        r0 = np.array([sp.r0 for sp in self.specs] if r0 is None else r0, dtype=np.float64)
+        v0 = np.array([sp.v0 for sp in self.specs] if v0 is None else v0, dtype=np.float64)
+        out = np.empty((n, 3))
+        dp = C.POINTER(C.c_double)
+        check(lib().hjm_batch_greeks(self._h, r0.ctypes.data_as(dp), v0.ctypes.data_as(dp), out.ctypes.data_as(dp)))
         return out
 
     def close(self) -> None:

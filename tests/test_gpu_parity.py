@@ -259,3 +259,49 @@ def test_config3_ten_year_properties():
     closed = O.discount(p, T) - (1 + (TM - T) * K) * O.discount(p, TM)
     assert abs(prices[W.FORWARD] - closed) < 2e-5
     assert 0.0 < prices[W.CAPLET] < O.discount(p, T)
+
+
+def _readout_scale(p, U, r0, v0):
+    """sum |c| |U| of the readout's three linear forms sum c U (probed with
+    unit fields on the y_min plane): the size rounding is measured against."""
+    nr, nv = p.axes[0].n, p.axes[1].n
+    e = np.zeros(p.shape)
+    scale = np.zeros(3)
+    for j in range(nv):
+        for i in range(nr):
+            e[0, j, i] = 1.0
+            c = O.greeks(p, e, r0, v0)
+            e[0, j, i] = 0.0
+            scale += np.abs(c) * abs(U[0, j, i])
+    return scale
+
+
+@pytest.mark.parametrize("kind", [W.CAPLET, W.BOND, W.FLOORLET])
+def test_greeks_readout(kind):
+    """rho = dC/dr and vega = dC/dv at (r0, v0): the GPU readout of the GPU's
+    final grid equals the oracle's Greeks of that same grid to rounding
+    (1e-13 of sum |c U| over the interpolant's terms), and the oracle's Greeks
+    of its own grid within the grid's parity (1e-12 of the same sum)."""
+    s = _sloped((64, 48, 33), 12, kind=kind)
+    g = hjm.Grid(s)
+    g.step()
+    got = np.array(g.greeks())
+    Ug = g.solution().cpu().numpy().copy()
+    assert got[0] == g.price()
+    g.close()
+    p = to_oracle(s)
+    same = O.greeks(p, Ug, s.r0, s.v0)
+    scale = _readout_scale(p, Ug, s.r0, s.v0)
+    assert np.all(np.abs(got - same) <= 1e-13 * scale), (got, same, scale)
+    Uo, _ = oracle_grid(s)
+    ref = O.greeks(p, Uo, s.r0, s.v0)
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale), (got, ref, scale)
+    # off-centre points, through the batch
+    r0s, v0s = np.array([s.r0 * 0.7, s.r0 * 1.6]), np.array([0.4, 3.0])
+    b = hjm.Batch([s, s]).run()
+    gb = b.greeks(r0s, v0s)
+    b.close()
+    for q in range(2):
+        want = O.greeks(p, Ug, r0s[q], v0s[q])
+        sc = _readout_scale(p, Ug, r0s[q], v0s[q])
+        assert np.all(np.abs(gb[q] - want) <= 1e-13 * sc), (q, gb[q], want, sc)
