@@ -55,7 +55,7 @@ class _Problem(C.Structure):
         ("f_level", C.c_double), ("f_slope", C.c_double), ("f_decay", C.c_double),
         ("kind", C.c_int), ("expiry", C.c_double), ("pay", C.c_double),
         ("strike", C.c_double), ("n_steps", C.c_int),
-        ("scheme", C.c_int), ("theta", C.c_double),
+        ("scheme", C.c_int), ("theta", C.c_double), ("soften", C.c_int),
     ]
 
 
@@ -90,6 +90,8 @@ def lib():
             "orc_bond_grid": (C.c_int, [P, d, dp]),
             "orc_readout": (d, [P, dp, d, d]),
             "orc_greeks": (None, [P, dp, d, d, dp]),
+            "orc_gauss_legendre": (None, [C.c_int, dp, dp]),
+            "orc_payoff_cell": (d, [P, d, d, d, d]),
             "orc_price": (C.c_int, [P, d, d, dp, dp]),
         }
         for name, (res, args) in sig.items():
@@ -137,6 +139,7 @@ class Problem:
     n_steps: int = 50
     scheme: int = DOUGLAS
     theta: float = 0.5
+    soften: int = 0
     _c: _Problem = field(default=None, repr=False, compare=False)
 
     @property
@@ -161,6 +164,7 @@ class Problem:
         p.kind, p.expiry, p.pay, p.strike = self.kind, self.expiry, self.pay, self.strike
         p.n_steps = self.n_steps
         p.scheme, p.theta = self.scheme, self.theta
+        p.soften = self.soften
         self._c = p
         return p
 
@@ -274,6 +278,17 @@ def bond_grid(p: Problem, t: float) -> np.ndarray:
 def readout(p: Problem, U: np.ndarray, r0: float, v0: float) -> float:
     U = np.ascontiguousarray(U, dtype=np.float64)
     return lib().orc_readout(p.ref(), _dp(U), r0, v0)
+
+
+def gauss_legendre(n: int):
+    x, w = np.empty(n), np.empty(n)
+    lib().orc_gauss_legendre(n, _dp(x), _dp(w))
+    return x, w
+
+
+def payoff_cell(p: Problem, rlo: float, rhi: float, ylo: float, yhi: float) -> float:
+    """The terminal data averaged over [rlo, rhi] x [ylo, yhi] (section 7.2)."""
+    return lib().orc_payoff_cell(p.ref(), rlo, rhi, ylo, yhi)
 
 
 def greeks(p: Problem, U: np.ndarray, r0: float, v0: float) -> np.ndarray:

@@ -76,6 +76,7 @@ typedef struct {
     int n_steps;        /* N: dt = T / N */
     int scheme;         /* ORC_DOUGLAS (the paper's), ORC_CS, ORC_MCS, ORC_HV */
     double theta;       /* implicit weight of the line solves (the paper: 1/2) */
+    int soften;         /* terminal data averaged over each node's control element (section 7.2) */
 } orc_problem;
 
 #define ORC_OUTFLOW 0
@@ -639,14 +640,83 @@ int orc_step(const orc_problem* p, int n, double* U)
 }
 
 /* Terminal data on every node (independent of v), section 3.2. */
+/* Gauss-Legendre rule of n points on [-1, 1]: the roots of P_n, by Newton's
+   method from cos(pi (q + 3/4) / (n + 1/2)), with weights
+   2 / ((1 - x^2) P_n'(x)^2). */
+void orc_gauss_legendre(int n, double* x, double* w)
+{
+    for (int q = 0; q < n; ++q) {
+        double z = cos(acos(-1.0) * ((double)q + 0.75) / ((double)n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;   /* P_0, P_1; recurrence up to P_n */
+            for (int m = 2; m <= n; ++m) {
+                double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / (double)m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = (double)n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[q] = z;
+        w[q] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+#define ORC_SOFT_Q 16   /* Gauss-Legendre points across a control element in y */
+
+/* Section 7.2: the terminal data averaged over the control element
+   [rlo, rhi] x [ylo, yhi] of a node (it does not depend on v).  At t = T the
+   contract pays 1 - Delta p(T, T_M; r, y) (caplet: its positive part,
+   floorlet: the negative part's size, forward: all of it), where
+   Delta p = c e^{-G r - G^2 y / 2}, c = Delta P(0,T_M) / P(0,T) e^{G f(0,T)},
+   G = G(T_M - T).  For each y the
+   r-integral is closed form on either side of the kink
+   r* = (ln c - G^2 y / 2) / G; the y-average uses ORC_SOFT_Q Gauss-Legendre
+   points.  The bond pays 1 everywhere. */
+double orc_payoff_cell(const orc_problem* p, double rlo, double rhi, double ylo, double yhi)
+{
+    if (p->kind == 0) return 1.0;
+    double T = p->expiry, TM = p->pay;
+    double G = orc_G(p->kappa, TM - T);
+    double c = accrual(p) * orc_discount(p, TM) / orc_discount(p, T) * exp(G * orc_forward(p, T));
+    double x[ORC_SOFT_Q], w[ORC_SOFT_Q];
+    orc_gauss_legendre(ORC_SOFT_Q, x, w);
+    double ym = 0.5 * (ylo + yhi), hy = 0.5 * (yhi - ylo), sum = 0.0;
+    for (int q = 0; q < ORC_SOFT_Q; ++q) {
+        double y = ym + hy * x[q];
+        double cy = c * exp(-0.5 * G * G * y);        /* Delta p = cy e^{-G r} */
+        double rs = log(cy) / G;                     /* kink: 1 = cy e^{-G r*} */
+        double a = rlo, b = rhi, sign = 1.0;
+        if (p->kind == 1) { if (rs > a) a = rs; }            /* caplet: r > r* */
+        else if (p->kind == 2) { if (rs < b) b = rs; sign = -1.0; } /* floorlet: r < r* */
+        double I = 0.0;
+        if (b > a)  /* integral of sign (1 - cy e^{-G r}) over [a, b] */
+            I = sign * ((b - a) - cy * (exp(-G * a) - exp(-G * b)) / G);
+        sum += w[q] * I;
+    }
+    return 0.5 * sum / (rhi - rlo);
+}
+
 int orc_terminal(const orc_problem* p, double* U)
 {
     mesh M;
     if (mesh_build(p, &M)) return -2;
     for (int k = 0; k < M.ny; ++k)
-        for (int j = 0; j < M.nv; ++j)
-            for (int i = 0; i < M.nr; ++i)
-                U[idx3(&M, i, j, k)] = orc_payoff(p, M.r[i], M.y[k]);
+        for (int i = 0; i < M.nr; ++i) {
+            double u = orc_payoff(p, M.r[i], M.y[k]);
+            /* control element: halfway to the neighbouring nodes, cut at the
+               domain's ends; Dirichlet nodes keep the pointwise data */
+            if (p->soften && !is_dirichlet(p, &M, i, 0, k)) {
+                double rlo = i > 0 ? 0.5 * (M.r[i - 1] + M.r[i]) : M.r[0];
+                double rhi = i < M.nr - 1 ? 0.5 * (M.r[i] + M.r[i + 1]) : M.r[M.nr - 1];
+                double ylo = k > 0 ? 0.5 * (M.y[k - 1] + M.y[k]) : M.y[0];
+                double yhi = k < M.ny - 1 ? 0.5 * (M.y[k] + M.y[k + 1]) : M.y[M.ny - 1];
+                u = orc_payoff_cell(p, rlo, rhi, ylo, yhi);
+            }
+            for (int j = 0; j < M.nv; ++j) U[idx3(&M, i, j, k)] = u;
+        }
     mesh_free(&M);
     return 0;
 }
