@@ -81,10 +81,18 @@ typedef struct {
 } hjm_model;
 
 /* Contract: kind, expiry T > 0, payment T_M > T and strike K > 0 (caplet,
-   floorlet, forward; ignored for the bond). */
+   floorlet, forward; ignored for the bond).  soften replaces the terminal
+   data by their average over the node's control element (section 7.2): the
+   element is centred on the node in the mesh coordinates, [z(x - h/2),
+   z(x + h/2)] in r and in y (the payoff does not depend on v); closed form in
+   r across the payoff's kink, 16-point Gauss-Legendre in y.  0: pointwise
+   payoff (the paper's default); 1: every non-Dirichlet node; 2: only the
+   nodes whose element the caplet's or floorlet's kink crosses (the rest keep
+   the pointwise payoff, which is smooth there).  Dirichlet nodes always keep
+   the pointwise data. */
 typedef struct {
     int32_t kind;
-    int32_t reserved;
+    int32_t soften;
     double expiry, pay, strike;
 } hjm_payoff;
 

@@ -76,7 +76,8 @@ typedef struct {
     int n_steps;        /* N: dt = T / N */
     int scheme;         /* ORC_DOUGLAS (the paper's), ORC_CS, ORC_MCS, ORC_HV */
     double theta;       /* implicit weight of the line solves (the paper: 1/2) */
-    int soften;         /* terminal data averaged over each node's control element (section 7.2) */
+    int soften;         /* terminal data averaged over control elements (section 7.2):
+                           0 no, 1 every non-Dirichlet node, 2 the nodes whose element the kink crosses */
 } orc_problem;
 
 #define ORC_OUTFLOW 0
@@ -639,7 +640,6 @@ int orc_step(const orc_problem* p, int n, double* U)
     return err;
 }
 
-/* Terminal data on every node (independent of v), section 3.2. */
 /* Gauss-Legendre rule of n points on [-1, 1]: the roots of P_n, by Newton's
    method from cos(pi (q + 3/4) / (n + 1/2)), with weights
    2 / ((1 - x^2) P_n'(x)^2). */
@@ -692,28 +692,58 @@ double orc_payoff_cell(const orc_problem* p, double rlo, double rhi, double ylo,
         if (p->kind == 1) { if (rs > a) a = rs; }            /* caplet: r > r* */
         else if (p->kind == 2) { if (rs < b) b = rs; sign = -1.0; } /* floorlet: r < r* */
         double I = 0.0;
-        if (b > a)  /* integral of sign (1 - cy e^{-G r}) over [a, b] */
-            I = sign * ((b - a) - cy * (exp(-G * a) - exp(-G * b)) / G);
+        /* integral of sign (1 - cy e^{-G r}) over [a, b]; the exponential's
+           part is e^{-G a} (1 - e^{-G (b - a)}) / G, formed with expm1 so that
+           a short element loses no digits to the difference */
+        if (b > a)
+            I = sign * ((b - a) + cy * exp(-G * a) * expm1(-G * (b - a)) / G);
         sum += w[q] * I;
     }
     return 0.5 * sum / (rhi - rlo);
 }
 
+/* The mesh map at any x (also beyond [0, 1]): z = K + alpha sinh(c2 x + c1 (1 - x)). */
+static double axis_z(double x, double zmin, double zmax, double K, double alpha)
+{
+    double c1 = asinh((zmin - K) / alpha), c2 = asinh((zmax - K) / alpha);
+    return K + alpha * sinh(c2 * x + c1 * (1.0 - x));
+}
+
+/* Terminal data on every node (independent of v), section 3.2; softened
+   (section 7.2) where p->soften asks: the control element of node (i, k) is
+   centred on it in the mesh coordinates, [z(x_i - h/2), z(x_i + h/2)] in r
+   and in y (reaching beyond the domain at its ends), and the node takes the
+   payoff's average over it.  soften 2 averages only the elements the
+   payoff's kink crosses (where the pointwise data are not smooth).
+   Dirichlet nodes keep the pointwise data. */
 int orc_terminal(const orc_problem* p, double* U)
 {
     mesh M;
     if (mesh_build(p, &M)) return -2;
+    int kinked = p->kind == 1 || p->kind == 2;
+    double G = 0.0, c = 0.0;
+    if (kinked) {
+        G = orc_G(p->kappa, p->pay - p->expiry);
+        c = accrual(p) * orc_discount(p, p->pay) / orc_discount(p, p->expiry) * exp(G * orc_forward(p, p->expiry));
+    }
     for (int k = 0; k < M.ny; ++k)
         for (int i = 0; i < M.nr; ++i) {
             double u = orc_payoff(p, M.r[i], M.y[k]);
-            /* control element: halfway to the neighbouring nodes, cut at the
-               domain's ends; Dirichlet nodes keep the pointwise data */
             if (p->soften && !is_dirichlet(p, &M, i, 0, k)) {
-                double rlo = i > 0 ? 0.5 * (M.r[i - 1] + M.r[i]) : M.r[0];
-                double rhi = i < M.nr - 1 ? 0.5 * (M.r[i] + M.r[i + 1]) : M.r[M.nr - 1];
-                double ylo = k > 0 ? 0.5 * (M.y[k - 1] + M.y[k]) : M.y[0];
-                double yhi = k < M.ny - 1 ? 0.5 * (M.y[k] + M.y[k + 1]) : M.y[M.ny - 1];
-                u = orc_payoff_cell(p, rlo, rhi, ylo, yhi);
+                const double* gr = p->geom[0];
+                const double* gy = p->geom[2];
+                double hr = 1.0 / (double)(M.nr - 1), hy = 1.0 / (double)(M.ny - 1);
+                double rlo = axis_z(((double)i - 0.5) * hr, gr[0], gr[1], gr[2], gr[3]);
+                double rhi = axis_z(((double)i + 0.5) * hr, gr[0], gr[1], gr[2], gr[3]);
+                double ylo = axis_z(((double)k - 0.5) * hy, gy[0], gy[1], gy[2], gy[3]);
+                double yhi = axis_z(((double)k + 0.5) * hy, gy[0], gy[1], gy[2], gy[3]);
+                int take = p->soften == 1;
+                if (p->soften == 2 && kinked) {
+                    /* the kink r*(y) = (ln c - G^2 y / 2) / G falls with y */
+                    double rs_top = (log(c) - 0.5 * G * G * ylo) / G, rs_bot = (log(c) - 0.5 * G * G * yhi) / G;
+                    take = rs_top >= rlo && rs_bot <= rhi;
+                }
+                if (take) u = orc_payoff_cell(p, rlo, rhi, ylo, yhi);
             }
             for (int j = 0; j < M.nv; ++j) U[idx3(&M, i, j, k)] = u;
         }

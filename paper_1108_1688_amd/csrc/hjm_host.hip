@@ -83,6 +83,14 @@ Mesh make_mesh(const hjm_axis& a)
     return m;
 }
 
+// the mesh map at any x (also beyond [0, 1])
+double mesh_z(const hjm_axis& a, double x)
+{
+    const double c1 = std::asinh((a.z_min - a.center) / a.alpha);
+    const double c2 = std::asinh((a.z_max - a.center) / a.alpha);
+    return a.center + a.alpha * std::sinh(c2 * x + c1 * (1.0 - x));
+}
+
 double mesh_x(const hjm_axis& a, double z)
 {
     const double c1 = std::asinh((a.z_min - a.center) / a.alpha);
@@ -137,6 +145,7 @@ hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_
     if (m->gamma > 0.0 && ax[0].z_min < 0.0) return fail(HJM_EINVAL, "gamma > 0 needs r_min >= 0");
     if (m->f_decay < 0.0) return fail(HJM_EINVAL, "f_decay must be >= 0");
     if (p->kind < HJM_BOND || p->kind > HJM_FORWARD) return fail(HJM_EINVAL, "unknown payoff kind %d", p->kind);
+    if (p->soften < 0 || p->soften > 2) return fail(HJM_EINVAL, "soften must be 0, 1 or 2 (got %d)", p->soften);
     if (!(p->expiry > 0.0)) return fail(HJM_EINVAL, "expiry must be > 0");
     if (p->kind != HJM_BOND) {
         if (!(p->pay > p->expiry)) return fail(HJM_EINVAL, "payment date must be after expiry");
@@ -456,6 +465,8 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
         rt[RT_RR * nr + i] = dir ? 0.0 : r;
         rt[RT_X * nr + i] = (lo || hi) ? 0.0 : lam * rg / J;
         rt[RT_Y * nr + i] = lam * lam * rg * rg;
+        rt[RT_ELO * nr + i] = mesh_z(ax[0], (i - 0.5) / hr1);
+        rt[RT_EHI * nr + i] = mesh_z(ax[0], (i + 0.5) / hr1);
         // the same interior row with theta dt folded in (split path)
         rf[RF_P * nr + i] = tdt * rt[RT_P * nr + i];
         rf[RF_Q * nr + i] = tdt * rt[RT_Q * nr + i];
@@ -494,6 +505,8 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
         if (hi) { w[0] = i2hy; w[1] = -4.0 * i2hy; w[2] = 3.0 * i2hy; w[3] = 0.0; ma = 4.0; mb = -3.0; mc = 0.0; me = -1.0; }
         if (dir) { for (double& x : w) x = 0.0; ma = mb = mc = me = 0.0; }
         yt[YT_Y * ny + k] = y;
+        yt[YT_ELO * ny + k] = mesh_z(ax[2], (k - 0.5) / hy1);
+        yt[YT_EHI * ny + k] = mesh_z(ax[2], (k + 0.5) / hy1);
         yt[YT_I * ny + k] = yi;
         yt[YT_K * ny + k] = 2.0 * m.kappa * y * yi;
         for (int q = 0; q < 5; ++q) yt[(YT_W0 + q) * ny + k] = w[q];
@@ -610,6 +623,7 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.r_hi_dir = ax[0].hi_face == HJM_FACE_DIRICHLET;
     d.y_hi_dir = ax[2].hi_face == HJM_FACE_DIRICHLET;
     d.kind = p.kind;
+    d.soften = p.soften;
     d.r_S = pl.r_S; d.r_L = pl.r_L; d.v_S = pl.v_S; d.v_L = pl.v_L;
     d.y_S = pl.y_S; d.y_L = pl.y_L;
     d.r_tiles = pl.r_tiles; d.v_tiles = pl.v_tiles; d.y_tiles = pl.y_tiles;

@@ -71,6 +71,7 @@ struct SolveDesc {
     // g(t_{n+1}) - g(t_n) on Dirichlet nodes when sc_b = 0 and 0 otherwise;
     // the same sweeps; U += E3, plus D3 when hv
     int32_t stage, hv;
+    int32_t soften, pad5;  // terminal data averaged over control elements (section 7.2): 0, 1 all, 2 at the kink
     double sc_a0, sc_a1, sc_b;
     const double* D3;
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value
@@ -92,6 +93,7 @@ enum { RT_R = 0,   // r_i
        RT_RR,      // r_i, 0 on a Dirichlet row
        RT_X,       // lambda r^gamma / J_r, 0 on the r faces
        RT_Y,       // lambda^2 r^{2 gamma}
+       RT_ELO, RT_EHI,  // the node's control element [r(x_i - h/2), r(x_i + h/2)] (softening)
        kRT };
 // v-axis table rows (each nv long): the A2 row on offsets -2..+2 and the
 // v factor of the mixed term.
@@ -109,6 +111,7 @@ enum { YT_Y = 0,   // y_k
        YT_W0, YT_W1, YT_W2, YT_W3, YT_W4,
        YT_T1, YT_T2,
        YT_MA, YT_MB, YT_MC, YT_ME,
+       YT_ELO, YT_EHI,  // the node's control element in y (softening)
        kYT };
 // v-line factors: rows (each nv long) then scalars.  Forward sweep of row j:
 // d'_j = (d_j - VF_A[j] d'_{j-1}) * VF_INV[j]; back: x_j = d'_j - VF_C[j] x_{j+1}.

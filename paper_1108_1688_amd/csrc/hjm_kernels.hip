@@ -449,19 +449,98 @@ enum { LC_V = 0, LC_C, LC_O0, LC_O1, LC_O2, LC_O3, LC_O4, LC_VX, LC_PV, LC_K, LC
 // ---------------------------------------------------------------------------
 // Kernels.
 // ---------------------------------------------------------------------------
+// Gauss-Legendre rule of kSoftQ points on [-1, 1]: the roots of P_n by
+// Newton's method from cos(pi (q + 3/4) / (n + 1/2)), weights
+// 2 / ((1 - x^2) P_n'(x)^2).
+constexpr int kSoftQ = 16;
+__device__ void gauss_legendre(double (&x)[kSoftQ], double (&w)[kSoftQ])
+{
+    for (int q = 0; q < kSoftQ; ++q) {
+        double z = cos(3.14159265358979323846 * (q + 0.75) / (kSoftQ + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= kSoftQ; ++m) {
+                const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / (double)m;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = kSoftQ * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[q] = z;
+        w[q] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// The terminal data averaged over [rlo, rhi] x [ylo, yhi] (section 7.2).  At
+// t = T, Delta p(T, T_M; r, y) = c e^{-G r - G^2 y / 2} with c = Delta A_M
+// (the step table's bond factor at t = T) and G = G(T_M - T); for each y the
+// r-integral of the payoff is closed form on either side of the kink
+// r* = ln(c e^{-G^2 y / 2}) / G, and the y-average takes kSoftQ points.
+__device__ double payoff_cell(const SolveDesc& s, gcdouble* st0, const double (&x)[kSoftQ],
+                              const double (&w)[kSoftQ], double rlo, double rhi, double ylo, double yhi)
+{
+    if (s.kind == KIND_BOND) return 1.0;
+    const double G = st0[ST_GM];
+    const double c = s.accrual * st0[ST_AM];
+    const double ym = 0.5 * (ylo + yhi), hy = 0.5 * (yhi - ylo);
+    double sum = 0.0;
+    for (int q = 0; q < kSoftQ; ++q) {
+        const double y = ym + hy * x[q];
+        const double cy = c * exp(-0.5 * G * G * y);
+        const double rs = log(cy) / G;
+        double a = rlo, b = rhi, sign = 1.0;
+        if (s.kind == KIND_CAPLET) a = fmax(a, rs);
+        else if (s.kind == KIND_FLOORLET) { b = fmin(b, rs); sign = -1.0; }
+        // e^{-G a} (1 - e^{-G (b - a)}) / G through expm1: no cancellation on short elements
+        const double I = b > a ? sign * ((b - a) + cy * exp(-G * a) * expm1(-G * (b - a)) / G) : 0.0;
+        sum += w[q] * I;
+    }
+    return 0.5 * sum / (rhi - rlo);
+}
+
+// Terminal data U = payoff at t = T, pointwise or (soften) averaged over the
+// node's control element, centred on it in the mesh coordinates
+// ([z(x - h/2), z(x + h/2)] in r and y, from the tables): at every
+// non-Dirichlet node (soften 1) or where the payoff's kink crosses the element
+// (soften 2).  Thread = one (i, k) column, written to every j (lanes are
+// consecutive i: each store is contiguous).
 __global__ __launch_bounds__(kBlock) void k_terminal(const SolveDesc* __restrict__ descs)
 {
     const SolveDesc& s = descs[blockIdx.y];
     if (blockIdx.x == 0 && threadIdx.x == 0) *(__attribute__((address_space(1))) volatile int32_t*)s.flag = 0;
-    const int nr = s.nr, nv = s.nv;
-    const int64_t npts = (int64_t)nr * nv * s.ny;
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
     gcdouble* r = gp(s.rt) + RT_R * nr;
-    gcdouble* y = gp(s.yt) + YT_Y * s.ny;
+    gcdouble* y = gp(s.yt) + YT_Y * ny;
+    gcdouble* st0 = gp(s.st);
     gdouble* U = gp(s.U);
-    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < npts; p += (int64_t)gridDim.x * kBlock) {
+    double gx[kSoftQ], gw[kSoftQ];
+    if (s.soften) gauss_legendre(gx, gw);
+    const size_t sy = (size_t)nr * nv;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < (int64_t)nr * ny;
+         p += (int64_t)gridDim.x * kBlock) {
         const int i = (int)(p % nr);
-        const int k = (int)(p / ((int64_t)nr * nv));
-        U[p] = dirichlet_value(s, gp(s.st), r[i], y[k]);
+        const int k = (int)(p / nr);
+        const bool dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir) || (k == ny - 1 && s.y_hi_dir);
+        double u = dirichlet_value(s, st0, r[i], y[k]);
+        if (s.soften && !dir) {
+            gcdouble* rt = gp(s.rt);
+            gcdouble* yt = gp(s.yt);
+            const double rlo = rt[RT_ELO * nr + i], rhi = rt[RT_EHI * nr + i];
+            const double ylo = yt[YT_ELO * ny + k], yhi = yt[YT_EHI * ny + k];
+            bool take = s.soften == 1;
+            if (s.soften == 2 && (s.kind == KIND_CAPLET || s.kind == KIND_FLOORLET)) {
+                // the kink r*(y) = ln(c e^{-G^2 y / 2}) / G falls with y
+                const double G = st0[ST_GM], c = s.accrual * st0[ST_AM];
+                const double top = (log(c) - 0.5 * G * G * ylo) / G, bot = (log(c) - 0.5 * G * G * yhi) / G;
+                take = top >= rlo && bot <= rhi;
+            }
+            if (take) u = payoff_cell(s, st0, gx, gw, rlo, rhi, ylo, yhi);
+        }
+        gdouble* col = U + (size_t)k * sy + i;
+        for (int j = 0; j < nv; ++j) col[(size_t)j * nr] = u;
     }
 }
 

@@ -45,7 +45,7 @@ class Model(C.Structure):
 
 
 class Payoff(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("expiry", C.c_double), ("pay", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("soften", C.c_int32), ("expiry", C.c_double), ("pay", C.c_double),
                 ("strike", C.c_double)]
 
 
@@ -136,7 +136,7 @@ def make_model(m) -> Model:
 
 
 def make_payoff(p) -> Payoff:
-    return Payoff(p.kind, 0, p.expiry, p.pay, p.strike)
+    return Payoff(p.kind, int(getattr(p, "soften", 0)), p.expiry, p.pay, p.strike)
 
 
 def set_line_tile(r_rows: int, v_rows: int, y_rows: int) -> None:

@@ -68,6 +68,7 @@ class PayoffSpec:
     expiry: float
     pay: float
     strike: float
+    soften: int = 0   # 1: terminal data averaged over control elements (section 7.2)
 
 
 @dataclass(frozen=True)

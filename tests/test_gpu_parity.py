@@ -305,3 +305,30 @@ def test_greeks_readout(kind):
         want = O.greeks(p, Ug, r0s[q], v0s[q])
         sc = _readout_scale(p, Ug, r0s[q], v0s[q])
         assert np.all(np.abs(gb[q] - want) <= 1e-13 * sc), (q, gb[q], want, sc)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("kind", [W.CAPLET, W.FLOORLET, W.FORWARD, W.BOND])
+def test_softened_terminal_data(kind, mode):
+    """Section 7.2 softening: the GPU's terminal grid (control-element
+    averages, its own Gauss-Legendre rule; every node or only where the kink
+    crosses) equals the oracle's to 1e-13 of the grid's size, and the softened
+    solve keeps grid and price parity."""
+    from dataclasses import replace
+    s = _sloped((64, 24, 33), 10, kind=kind)
+    s = replace(s, payoff=replace(s.payoff, soften=mode))
+    g = hjm.Grid(s)
+    U0 = g.solution().cpu().numpy().copy()
+    g.close()
+    p = to_oracle(s)
+    T0 = O.terminal(p)
+    # the payoff is a difference of O(1) terms (1 and Delta p): rounding scales with 1
+    assert np.abs(U0 - T0).max() <= 1e-13 * max(np.abs(T0).max(), 1.0)
+    p.soften = 0
+    # the forward's payoff has no kink: mode 2 leaves it pointwise
+    changes = kind in (W.CAPLET, W.FLOORLET) or (kind == W.FORWARD and mode == 1)
+    assert np.array_equal(T0, O.terminal(p)) != changes
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)

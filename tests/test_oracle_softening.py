@@ -7,10 +7,17 @@ F2: each cell average equals a brute-force double integral of the pointwise
 payoff (scipy dblquad) over the same rectangle, on cells across the kink,
 in the money and out of the money, for caplet, floorlet, forward and bond,
 within the y rule's error (5e-9 relative).
-F3: the averaged terminal grid keeps the pointwise data on Dirichlet nodes,
-and the averages over a partition of a rectangle add up to the integral
-over it.
+F3: the softened terminal grid holds, at each node, the average over its
+element centred in the mesh coordinates (every non-Dirichlet node, or only
+where the kink crosses the element), keeps the pointwise data elsewhere, and
+averages over a partition of a rectangle add up to the integral over it.
+F4: on short elements (the r integral of e^{-G r} over an element of width
+1e-4..1e-2, where a difference of two exponentials would lose digits) the
+average equals a 40-digit evaluation of the same y rule to a few units in
+the last place of the payoff's O(1) terms.
 """
+import math
+
 import numpy as np
 import pytest
 from scipy import integrate
@@ -57,26 +64,86 @@ def test_cell_average_equals_double_integral(kind):
         assert abs(got - want) <= 5e-9 * max(abs(want), 1e-3), (kind, (rlo, rhi, ylo, yhi), got, want)
 
 
-def test_terminal_grid_softened():
+def _zmap(ax, x):
+    c1 = math.asinh((ax.z_min - ax.center) / ax.alpha)
+    c2 = math.asinh((ax.z_max - ax.center) / ax.alpha)
+    return ax.center + ax.alpha * math.sinh(c2 * x + c1 * (1.0 - x))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_terminal_grid_softened(mode):
+    """Every non-Dirichlet node (mode 1), or the nodes whose element the kink
+    crosses (mode 2), takes the average over its element [z(x - h/2),
+    z(x + h/2)] in r and y (the map written out here); Dirichlet nodes and,
+    in mode 2, nodes away from the kink keep the pointwise data."""
     s = W.with_shape(W.config1()[1], 24, 6, 12, 10)
     p = to_oracle(s)
     U0 = O.terminal(p)
-    p.soften = 1
+    p.soften = mode
     U1 = O.terminal(p)
-    r, _, _ = O.axis(p.axes[0])
-    y, _, _ = O.axis(p.axes[2])
-    # Dirichlet nodes (r_max, y_max) keep the pointwise payoff; v does not matter
+    ar, ay = p.axes[0], p.axes[2]
+    nr, ny = ar.n, ay.n
     assert np.array_equal(U1[:, :, -1], U0[:, :, -1]) and np.array_equal(U1[-1], U0[-1])
     assert np.all(U1 == U1[:, :1, :])
-    # the averages differ from the pointwise data near the kink only
-    d = np.abs(U1 - U0)[0, 0, :-1]
-    assert d.max() > 1e-5
-    # cells partition [r_0, r_mid] x [y_0, y_mid] away from the Dirichlet faces:
-    # sum of area x average = the integral over the union
-    ih, kh = 10, 6
-    rb = np.concatenate([[r[0]], 0.5 * (r[:-1] + r[1:])])
-    yb = np.concatenate([[y[0]], 0.5 * (y[:-1] + y[1:])])
-    total = sum((rb[i + 1] - rb[i]) * (yb[k + 1] - yb[k]) * U1[k, 0, i] for i in range(ih) for k in range(kh))
-    want, _ = integrate.dblquad(lambda yy, rr: O.payoff(p, rr, yy), rb[0], rb[ih], yb[0], yb[kh],
+    changed = 0
+    for k in range(ny - 1):
+        for i in range(nr - 1):
+            rlo, rhi = _zmap(ar, (i - 0.5) / (nr - 1)), _zmap(ar, (i + 0.5) / (nr - 1))
+            ylo, yhi = _zmap(ay, (k - 0.5) / (ny - 1)), _zmap(ay, (k + 0.5) / (ny - 1))
+            avg = O.payoff_cell(p, rlo, rhi, ylo, yhi)
+            crosses = min(O.payoff(p, rlo, ylo), O.payoff(p, rlo, yhi)) == 0.0 < max(O.payoff(p, rhi, ylo),
+                                                                                        O.payoff(p, rhi, yhi))
+            if mode == 1 or crosses:
+                # the map written out here may differ from the oracle's in the last bit
+                assert abs(U1[k, 0, i] - avg) <= 1e-12 * max(abs(avg), 1e-3), (k, i, U1[k, 0, i], avg)
+                changed += U1[k, 0, i] != U0[k, 0, i]
+            else:
+                assert U1[k, 0, i] == U0[k, 0, i], (k, i)
+    assert changed >= ny - 1
+
+
+def test_partition_of_averages_is_the_integral():
+    """Averages over elements that tile a rectangle add up, weighted by their
+    areas, to the payoff's integral over it."""
+    p = _problem(W.CAPLET)
+    ar, ay = p.axes[0], p.axes[2]
+    xr = np.linspace(0.2, 0.5, 13)
+    xy = np.linspace(0.0, 0.6, 7)
+    rb = [_zmap(ar, x) for x in xr]
+    yb = [_zmap(ay, x) for x in xy]
+    total = sum((rb[i + 1] - rb[i]) * (yb[k + 1] - yb[k]) * O.payoff_cell(p, rb[i], rb[i + 1], yb[k], yb[k + 1])
+                for i in range(len(rb) - 1) for k in range(len(yb) - 1))
+    want, _ = integrate.dblquad(lambda yy, rr: O.payoff(p, rr, yy), rb[0], rb[-1], yb[0], yb[-1],
                                 epsabs=1e-15, epsrel=1e-12)
     assert abs(total - want) <= 5e-9 * abs(want), (total, want)
+
+
+@pytest.mark.parametrize("kind", [W.CAPLET, W.FLOORLET, W.FORWARD])
+def test_short_elements_keep_their_digits(kind):
+    mp = pytest.importorskip("mpmath")
+    p = _problem(kind)
+    G = -math.expm1(-p.kappa * (p.pay - p.expiry)) / p.kappa
+    # c = Delta p(0,T_M)/p(0,T) e^{G f(0,T)}: the forward's pointwise payoff at r = 0, y = 0 is 1 - c
+    c = 1.0 - O.payoff(_problem(W.FORWARD), 0.0, 0.0)
+    xq, wq = O.gauss_legendre(16)
+    mp.mp.dps = 40
+    Gm, cm = mp.mpf(G), mp.mpf(c)
+    worst = 0.0
+    for rlo in (0.0, 0.02, 0.029, 0.031, 0.05):
+        for width in (1e-4, 1e-3, 1e-2):
+            rhi, ylo, yhi = rlo + width, 0.001, 0.003
+            got = O.payoff_cell(p, rlo, rhi, ylo, yhi)
+            ym, hy, S = (mp.mpf(ylo) + mp.mpf(yhi)) / 2, (mp.mpf(yhi) - mp.mpf(ylo)) / 2, mp.mpf(0)
+            for xk, wk in zip(xq, wq):
+                cy = cm * mp.exp(-Gm * Gm * (ym + hy * mp.mpf(xk)) / 2)
+                rs = mp.log(cy) / Gm
+                a, b, sg = mp.mpf(rlo), mp.mpf(rhi), 1
+                if kind == W.CAPLET:
+                    a = max(a, rs)
+                elif kind == W.FLOORLET:
+                    b, sg = min(b, rs), -1
+                if b > a:
+                    S += mp.mpf(wk) * sg * ((b - a) - cy * (mp.exp(-Gm * a) - mp.exp(-Gm * b)) / Gm)
+            want = float(S / 2 / (mp.mpf(rhi) - mp.mpf(rlo)))
+            worst = max(worst, abs(got - want))
+    assert worst <= 8 * np.finfo(float).eps, worst
