@@ -152,15 +152,17 @@ def calibration(hjm, W, torch, stream, n_solves: int, tune: bool):
 def schemes_leg(hjm, W, torch, stream, reps: int = 3):
     """The ADI schemes on the 1-year caplet of the 256x128x128 workload (40
     steps): whole solves (set-up, steps, readout), per scheme; the correction
-    schemes sweep twice per step.  Also the price against a 4x finer time
-    grid of the same scheme, a measure of each scheme's time error."""
+    schemes sweep twice per step, Douglas with q Huang subiterations q + 1
+    times.  Also the price against a 4x finer time grid of the same scheme, a
+    measure of each scheme's time error."""
     import math
     from dataclasses import replace
     base = W.config3()[0]
     out = {"workload": "256x128x128 1-year ATM caplet, 40 steps (dt = 0.025); price error against 160 steps"}
-    for name, sc, th in (("douglas", W.DOUGLAS, 0.5), ("cs", W.CS, 0.5), ("mcs", W.MCS, 1.0 / 3.0),
-                         ("hv", W.HV, 0.5 + math.sqrt(3.0) / 6.0)):
-        spec = replace(base, scheme=sc, theta=th)
+    for name, sc, th, q in (("douglas", W.DOUGLAS, 0.5, 0), ("cs", W.CS, 0.5, 0), ("mcs", W.MCS, 1.0 / 3.0, 0),
+                            ("hv", W.HV, 0.5 + math.sqrt(3.0) / 6.0, 0), ("huang2", W.HUANG, 0.5, 2),
+                            ("huang4", W.HUANG, 0.5, 4)):
+        spec = replace(base, scheme=sc, theta=th, af_iters=q)
         g = hjm.Grid(spec, stream=stream)
         g.step()
         p40 = g.price()
@@ -181,6 +183,62 @@ def schemes_leg(hjm, W, torch, stream, reps: int = 3):
         out[name] = {"theta": th, "ms_per_solve": round(el * 1e3, 3),
                      "point_steps_per_s": spec.points * spec.n_steps / el,
                      "price": p40, "price_160_steps": p160, "rel_diff_vs_160_steps": abs(p40 - p160) / abs(p160)}
+    return out
+
+
+def softening_leg(hjm, W, torch, stream):
+    """Section 7.2 softening on the 1-year ATM caplet (48^3 mesh centred on
+    the ATM strike, 100 steps), pointwise (mode 0), every node (1) and the
+    kink's elements only (2):
+    - smoothness in the strike: 41 strikes over +-2 r-node spacings on the
+      same mesh, priced as one batch; the RMS residual of a cubic fit of
+      price against strike (a smooth price leaves a residual near rounding;
+      the pointwise payoff's kink crossing nodes leaves wiggles);
+    - convergence: the price error at 16^3 .. 96^3 (100 steps) against 192^3
+      softened over the kink's elements;
+    - cost: grid set-up (tables, terminal data, pivots) at 256x128x128."""
+    from dataclasses import replace
+    cap = W.config1()[1]
+    k0 = cap.payoff.strike
+    base = W.with_shape(cap, 48, 48, 48, 100)
+    ax = base.axes[0]
+    import math
+    c1, c2 = math.asinh((ax.z_min - ax.center) / ax.alpha), math.asinh((ax.z_max - ax.center) / ax.alpha)
+    x0 = (math.asinh((k0 - ax.center) / ax.alpha) - c1) / (c2 - c1)
+    dr = ax.alpha * (c2 - c1) * math.cosh(c2 * x0 + c1 * (1 - x0)) / (ax.n - 1)
+    strikes = k0 + 2.0 * dr * np.linspace(-1.0, 1.0, 41)
+    out = {"workload": "1-year ATM caplet of the 32^3 case, 100 steps; strike sweep on the 48^3 mesh, "
+                       "convergence 16^3..96^3 against 192^3 (mode 2), set-up at 256x128x128",
+           "strike_sweep": {"strikes": 41, "span_bp": round(4e4 * dr, 2)}, "convergence": {}, "setup_ms": {}}
+    ref_spec = W.with_shape(replace(cap, payoff=replace(cap.payoff, soften=2)), 192, 192, 192, 100)
+    g = hjm.Grid(ref_spec, stream=stream).step()
+    ref = g.price()
+    g.close()
+    out["convergence"]["reference_192"] = ref
+    for mode in (0, 1, 2):
+        specs = [replace(base, payoff=replace(base.payoff, strike=float(k), soften=mode)) for k in strikes]
+        b = hjm.Batch(specs, stream=stream).run()
+        pr = b.prices()
+        b.close()
+        z = (strikes - k0) / dr
+        fit = np.polyval(np.polyfit(z, pr, 3), z)
+        out["strike_sweep"][f"mode{mode}_rms_cubic_residual_rel"] = float(np.sqrt(np.mean((pr - fit) ** 2)) / abs(pr).mean())
+        errs = {}
+        for n in (16, 24, 32, 48, 64, 96):
+            g = hjm.Grid(W.with_shape(replace(cap, payoff=replace(cap.payoff, soften=mode)), n, n, n, 100),
+                         stream=stream).step()
+            errs[str(n)] = abs(g.price() - ref) / abs(ref)
+            g.close()
+        out["convergence"][f"mode{mode}_rel_err"] = errs
+        big = replace(W.config3()[0], payoff=replace(W.config3()[0].payoff, soften=mode))
+        hjm.Grid(big, stream=stream).close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            g = hjm.Grid(big, stream=stream)
+            torch.cuda.synchronize()
+            g.close()
+        out["setup_ms"][f"mode{mode}"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
     return out
 
 
@@ -237,6 +295,7 @@ def main():
     ap.add_argument("--calib-solves", type=int, default=512)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg of the calibration")
     ap.add_argument("--no-schemes", action="store_true", help="skip the ADI-schemes leg")
+    ap.add_argument("--no-softening", action="store_true", help="skip the payoff-softening leg")
     ap.add_argument("--sur-solves", type=int, default=4096, help="ADI solves for the surrogate's training set")
     ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
@@ -395,6 +454,9 @@ def main():
     if not args.no_schemes:
         out["schemes"] = schemes_leg(hjm, W, torch, stream)
         log(f"schemes: {out['schemes']}")
+    if not args.no_softening:
+        out["softening"] = softening_leg(hjm, W, torch, stream)
+        log(f"softening: {out['softening']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -106,14 +106,25 @@ typedef struct {
    corrected start from their result and sweeps once more: twice the work of
    a Douglas step.  theta in (0, 1]: the paper uses 1/2; 1/3 is usual for
    modified Craig-Sneyd and 1/2 + sqrt(3)/6 for Hundsdorfer-Verwer.  Every
-   operator is evaluated at t_{n+1/2}. */
+   operator is evaluated at t_{n+1/2}.
+   HJM_SCHEME_HUANG is the Douglas step followed by af_iters (1..16)
+   subiterations of Huang's approximate-factorisation correction (section
+   5.1): each solves M (X_{m+1} - X_m) = D0 - (I - theta dt A) X_m with the
+   factored M = (I - theta dt A1)(I - theta dt A2)(I - theta dt A3), starting
+   from the Douglas increment X_1, so that the increment tends to that of the
+   unsplit theta scheme (I - theta dt A) X = D0 where the iteration
+   contracts; af_iters + 1 times the work of a Douglas step.  One
+   subiteration at theta = 1/2 is Hundsdorfer-Verwer at theta = 1/2.
+   af_iters is ignored by the other schemes. */
 #define HJM_SCHEME_DOUGLAS 0
 #define HJM_SCHEME_CS      1
 #define HJM_SCHEME_MCS     2
 #define HJM_SCHEME_HV      3
+#define HJM_SCHEME_HUANG   4
+#define HJM_MAX_AF_ITERS   16
 typedef struct {
     int32_t kind;
-    int32_t reserved;
+    int32_t af_iters;
     double theta;
 } hjm_scheme;
 

@@ -30,8 +30,9 @@ OUTFLOW = 0
 DIRICHLET = 1
 BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
 # ADI schemes: the paper's Douglas, Craig-Sneyd, modified Craig-Sneyd,
-# Hundsdorfer-Verwer
-DOUGLAS, CS, MCS, HV = 0, 1, 2, 3
+# Hundsdorfer-Verwer, and Douglas with Huang's approximate-factorisation
+# correction subiterations
+DOUGLAS, CS, MCS, HV, HUANG = 0, 1, 2, 3, 4
 
 
 def build(force: bool = False) -> str:
@@ -55,7 +56,7 @@ class _Problem(C.Structure):
         ("f_level", C.c_double), ("f_slope", C.c_double), ("f_decay", C.c_double),
         ("kind", C.c_int), ("expiry", C.c_double), ("pay", C.c_double),
         ("strike", C.c_double), ("n_steps", C.c_int),
-        ("scheme", C.c_int), ("theta", C.c_double), ("soften", C.c_int),
+        ("scheme", C.c_int), ("theta", C.c_double), ("soften", C.c_int), ("af_iters", C.c_int),
     ]
 
 
@@ -140,6 +141,7 @@ class Problem:
     scheme: int = DOUGLAS
     theta: float = 0.5
     soften: int = 0
+    af_iters: int = 0
     _c: _Problem = field(default=None, repr=False, compare=False)
 
     @property
@@ -165,6 +167,7 @@ class Problem:
         p.n_steps = self.n_steps
         p.scheme, p.theta = self.scheme, self.theta
         p.soften = self.soften
+        p.af_iters = self.af_iters
         self._c = p
         return p
 

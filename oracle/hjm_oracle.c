@@ -25,6 +25,9 @@
  *   - the Douglas ADI step of section 5.1 with theta = 1/2, and the three
  *     correction schemes of the same family (Craig-Sneyd, which the paper
  *     tried, modified Craig-Sneyd, Hundsdorfer-Verwer) with any theta;
+ *   - Huang's approximate-factorisation correction (section 5.1):
+ *     subiterations of the factored operator on the residual of the unsplit
+ *     theta scheme, starting from the Douglas increment;
  *   - the readout C(t=0; r0, v0, y=0) by 4-point Lagrange interpolation;
  *   - the Gaussian (gamma = 0, epsilon = 0) caplet closed form used as a pin.
  *
@@ -78,6 +81,7 @@ typedef struct {
     double theta;       /* implicit weight of the line solves (the paper: 1/2) */
     int soften;         /* terminal data averaged over control elements (section 7.2):
                            0 no, 1 every non-Dirichlet node, 2 the nodes whose element the kink crosses */
+    int af_iters;       /* ORC_HUANG: correction subiterations after the Douglas increment (>= 1) */
 } orc_problem;
 
 #define ORC_OUTFLOW 0
@@ -92,6 +96,9 @@ typedef struct {
 #define ORC_CS 1
 #define ORC_MCS 2
 #define ORC_HV 3
+/* Huang's approximate-factorisation correction (section 5.1 mentions trying
+   it; it removes the factorisation error of the Douglas step). */
+#define ORC_HUANG 4
 
 void orc_set_threads(int n)
 {
@@ -547,6 +554,16 @@ static int sweep(const orc_problem* p, const mesh* M, int d, double t, double dt
 /* the solution takes g(t_{n+1}): E0 = g(t_{n+1}) - g(t_n) (CS, MCS) or 0     */
 /* (HV, whose Y3 already holds it).  U^{n+1} = U^n + E3 (CS, MCS) or         */
 /* U^n + D3 + E3 (HV).                                                       */
+/*                                                                          */
+/* Huang's correction iterates towards the unsplit theta scheme             */
+/*   (I - theta dt A) X = D0,  U^{n+1} = U^n + X,                            */
+/* whose factored approximation M = (I - theta dt A1)(I - theta dt A2)       */
+/* (I - theta dt A3) the Douglas step solves instead: X_1 = M^{-1} D0 = D3,  */
+/* then for m = 1 .. q                                                       */
+/*   X_{m+1} = X_m + M^{-1} (D0 - (I - theta dt A) X_m)                      */
+/* (the residual is 0 on Dirichlet nodes, where X_m already holds the        */
+/* increment), and U^{n+1} = U^n + X_{q+1}.  As q grows X tends to the       */
+/* unsplit step wherever the iteration contracts.                            */
 /* ------------------------------------------------------------------------ */
 
 /* out = dt (A0 + A1 + A2 + A3) V on non-Dirichlet nodes, 0 on Dirichlet nodes */
@@ -574,6 +591,7 @@ static int sweeps(const orc_problem* p, const mesh* M, double t, double dt, doub
 
 int orc_step(const orc_problem* p, int n, double* U)
 {
+    if (p->scheme == ORC_HUANG && p->af_iters < 1) return -1;
     mesh M;
     if (mesh_build(p, &M)) return -2;
     int nr = M.nr, nv = M.nv, ny = M.ny;
@@ -604,7 +622,21 @@ int orc_step(const orc_problem* p, int n, double* U)
     if (corr)
         for (size_t q = 0; q < npts; ++q) D0[q] = Dd[q];
     if (!err) err = sweeps(p, &M, t_half, dt, Dd);   /* Dd = D3 */
-    if (!err && corr) {
+    if (!err && p->scheme == ORC_HUANG) {
+        /* Dd holds X_1; each pass sweeps the residual of the unsplit step */
+        for (int m = 0; m < p->af_iters && !err; ++m) {
+            err = apply_all(p, t_half, dt, Dd, W, tmp, npts);   /* W = dt A X_m */
+            for (int k = 0; k < ny && !err; ++k)
+                for (int j = 0; j < nv; ++j)
+                    for (int i = 0; i < nr; ++i) {
+                        size_t q = idx3(&M, i, j, k);
+                        E[q] = is_dirichlet(p, &M, i, j, k) ? 0.0 : D0[q] + p->theta * W[q] - Dd[q];
+                    }
+            if (!err) err = sweeps(p, &M, t_half, dt, E);
+            for (size_t q = 0; q < npts && !err; ++q) Dd[q] = Dd[q] + E[q];
+        }
+        for (size_t q = 0; q < npts && !err; ++q) U[q] = U[q] + Dd[q];
+    } else if (!err && corr) {
         /* corrected start E0 on non-Dirichlet nodes */
         if (p->scheme == ORC_CS) {
             err = orc_apply(p, 3, t_half, Dd, W);

@@ -788,23 +788,27 @@ GridLayout grid_layout(const hjm_axis ax[3], int n_steps, bool corr = false)
 hjm_status validate_scheme(const hjm_scheme* sc)
 {
     if (!sc) return fail(HJM_EINVAL, "null scheme");
-    if (sc->kind < HJM_SCHEME_DOUGLAS || sc->kind > HJM_SCHEME_HV) return fail(HJM_EINVAL, "unknown scheme %d", sc->kind);
+    if (sc->kind < HJM_SCHEME_DOUGLAS || sc->kind > HJM_SCHEME_HUANG) return fail(HJM_EINVAL, "unknown scheme %d", sc->kind);
+    if (sc->kind == HJM_SCHEME_HUANG && (sc->af_iters < 1 || sc->af_iters > HJM_MAX_AF_ITERS))
+        return fail(HJM_EINVAL, "af_iters must lie in [1, %d] (got %d)", HJM_MAX_AF_ITERS, sc->af_iters);
     if (!(sc->theta > 0.0 && sc->theta <= 1.0)) return fail(HJM_EINVAL, "theta must lie in (0, 1] (got %g)", sc->theta);
     return HJM_OK;
 }
 
 // Stage-2 coefficients of the corrected start (see SolveDesc): CS a0 = 1/2;
-// MCS a0 = 1/2, a1 = 1/2 - theta; HV a0 = a1 = 1/2, b = -1 (relative to Y3).
+// MCS a0 = 1/2, a1 = 1/2 - theta; HV a0 = a1 = 1/2, b = -1 (relative to Y3);
+// Huang a0 = a1 = theta, b = -1 (the residual of the unsplit theta step).
 void scheme_stage2(SolveDesc& d2, const SolveDesc& d1, const hjm_scheme& sc, double* E)
 {
+    const bool huang = sc.kind == HJM_SCHEME_HUANG;
     d2 = d1;
     d2.stage = 2;
     d2.D = E;
     d2.D3 = d1.D;
-    d2.sc_a0 = 0.5;
-    d2.sc_a1 = sc.kind == HJM_SCHEME_MCS ? 0.5 - sc.theta : (sc.kind == HJM_SCHEME_HV ? 0.5 : 0.0);
-    d2.sc_b = sc.kind == HJM_SCHEME_HV ? -1.0 : 0.0;
-    d2.hv = sc.kind == HJM_SCHEME_HV;
+    d2.sc_a0 = huang ? sc.theta : 0.5;
+    d2.sc_a1 = sc.kind == HJM_SCHEME_MCS ? 0.5 - sc.theta : (sc.kind == HJM_SCHEME_HV ? 0.5 : (huang ? sc.theta : 0.0));
+    d2.sc_b = sc.kind == HJM_SCHEME_HV || huang ? -1.0 : 0.0;
+    d2.hv = sc.kind == HJM_SCHEME_HV || huang;
 }
 
 }  // namespace
@@ -994,11 +998,13 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
     const bool split = p.r_mode == R_SPLIT;
     for (int32_t c = 0; c < k; ++c) {
         const int n = (int)g->step;
-        // one sweep sequence (Douglas), or two (the Craig-Sneyd family: the
-        // second on the stage-2 descriptor)
-        for (int q = 0; q < (g->corr ? 2 * HJM_N_PASSES : HJM_N_PASSES); ++q) {
+        // one sweep sequence (Douglas), two (the Craig-Sneyd family: the
+        // second on the stage-2 descriptor) or 1 + af_iters (Huang)
+        const int n_seq = !g->corr ? 1 : (g->scheme.kind == HJM_SCHEME_HUANG ? 1 + g->scheme.af_iters : 2);
+        for (int q = 0; q < n_seq * HJM_N_PASSES; ++q) {
             const int pass = q % HJM_N_PASSES;
             const bool st2 = q >= HJM_N_PASSES;
+            const bool last_seq = q >= (n_seq - 1) * HJM_N_PASSES;
             const SolveDesc* dd = g->d_desc + (st2 ? 1 : 0);
             if (pass == 1 && !split) continue;
             hipError_t e = hipSuccess;
@@ -1027,7 +1033,7 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
             else if (pass == 2) e = launch_v(g->rows[1], dd, nullptr, p.v_tiles, p.v_lds, g->stream);
             else if (p.yc_rows)
                 e = launch_yc(p.yc_rows, dd, nullptr, p.yc_tiles, p.yc_S, g->stream,
-                              !g->corr ? 0 : (!st2 ? 1 : (g->desc2.hv ? 2 : 0)));
+                              !g->corr ? 0 : (!st2 ? 1 : (!last_seq ? 3 : (g->desc2.hv ? 2 : 0))));
             else e = launch_yu(g->rows[2], dd, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {

@@ -69,11 +69,13 @@ struct SolveDesc {
     //   E0 = dt A U + dt (sc_a0 A0 + sc_a1 (A1 + A2 + A3)) D3 + sc_b D3
     // on non-Dirichlet nodes (D3 read from the D3 pointer), the increment
     // g(t_{n+1}) - g(t_n) on Dirichlet nodes when sc_b = 0 and 0 otherwise;
-    // the same sweeps; U += E3, plus D3 when hv
+    // the same sweeps; U += E3, plus D3 when hv.  Huang's correction runs the
+    // stage-2 sequence af_iters times with (sc_a0, sc_a1, sc_b) = (theta,
+    // theta, -1): each but the last adds E3 to D3 (D3 holds the iterate X_m)
     int32_t stage, hv;
     int32_t soften, pad5;  // terminal data averaged over control elements (section 7.2): 0, 1 all, 2 at the kink
     double sc_a0, sc_a1, sc_b;
-    const double* D3;
+    double* D3;
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value
     int32_t* flag_pad;
 };

@@ -452,26 +452,25 @@ enum { LC_V = 0, LC_C, LC_O0, LC_O1, LC_O2, LC_O3, LC_O4, LC_VX, LC_PV, LC_K, LC
 // Gauss-Legendre rule of kSoftQ points on [-1, 1]: the roots of P_n by
 // Newton's method from cos(pi (q + 3/4) / (n + 1/2)), weights
 // 2 / ((1 - x^2) P_n'(x)^2).
+// One root per call: the workgroup's first kSoftQ threads each find one.
 constexpr int kSoftQ = 16;
-__device__ void gauss_legendre(double (&x)[kSoftQ], double (&w)[kSoftQ])
+__device__ void gauss_legendre_root(int q, ldouble* x, ldouble* w)
 {
-    for (int q = 0; q < kSoftQ; ++q) {
-        double z = cos(3.14159265358979323846 * (q + 0.75) / (kSoftQ + 0.5)), dp = 1.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = z;
-            for (int m = 2; m <= kSoftQ; ++m) {
-                const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / (double)m;
-                p0 = p1;
-                p1 = p2;
-            }
-            dp = kSoftQ * (z * p1 - p0) / (z * z - 1.0);
-            const double dz = p1 / dp;
-            z -= dz;
-            if (fabs(dz) < 1e-16) break;
+    double z = cos(3.14159265358979323846 * (q + 0.75) / (kSoftQ + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int m = 2; m <= kSoftQ; ++m) {
+            const double p2 = ((2.0 * m - 1.0) * z * p1 - (m - 1.0) * p0) / (double)m;
+            p0 = p1;
+            p1 = p2;
         }
-        x[q] = z;
-        w[q] = 2.0 / ((1.0 - z * z) * dp * dp);
+        dp = kSoftQ * (z * p1 - p0) / (z * z - 1.0);
+        const double dz = p1 / dp;
+        z -= dz;
+        if (fabs(dz) < 1e-16) break;
     }
+    x[q] = z;
+    w[q] = 2.0 / ((1.0 - z * z) * dp * dp);
 }
 
 // The terminal data averaged over [rlo, rhi] x [ylo, yhi] (section 7.2).  At
@@ -479,8 +478,8 @@ __device__ void gauss_legendre(double (&x)[kSoftQ], double (&w)[kSoftQ])
 // (the step table's bond factor at t = T) and G = G(T_M - T); for each y the
 // r-integral of the payoff is closed form on either side of the kink
 // r* = ln(c e^{-G^2 y / 2}) / G, and the y-average takes kSoftQ points.
-__device__ double payoff_cell(const SolveDesc& s, gcdouble* st0, const double (&x)[kSoftQ],
-                              const double (&w)[kSoftQ], double rlo, double rhi, double ylo, double yhi)
+__device__ double payoff_cell(const SolveDesc& s, gcdouble* st0, const ldouble* x, const ldouble* w, double rlo,
+                              double rhi, double ylo, double yhi)
 {
     if (s.kind == KIND_BOND) return 1.0;
     const double G = st0[ST_GM];
@@ -516,8 +515,14 @@ __global__ __launch_bounds__(kBlock) void k_terminal(const SolveDesc* __restrict
     gcdouble* y = gp(s.yt) + YT_Y * ny;
     gcdouble* st0 = gp(s.st);
     gdouble* U = gp(s.U);
-    double gx[kSoftQ], gw[kSoftQ];
-    if (s.soften) gauss_legendre(gx, gw);
+    // the Gauss-Legendre rule, once per workgroup (s.soften is uniform here)
+    __shared__ double gl[2 * kSoftQ];
+    ldouble* gx = (ldouble*)gl;
+    ldouble* gw = gx + kSoftQ;
+    if (s.soften) {
+        if (threadIdx.x < kSoftQ) gauss_legendre_root(threadIdx.x, gx, gw);
+        __syncthreads();
+    }
     const size_t sy = (size_t)nr * nv;
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < (int64_t)nr * ny;
          p += (int64_t)gridDim.x * kBlock) {
@@ -1772,6 +1777,11 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
             // first sequence of the Craig-Sneyd family: D3 stays in D, U unchanged
 #pragma unroll
             for (int mm = 0; mm < ROWS; ++mm) D[off + (size_t)mm * sy] = d[mm];
+        } else if constexpr (MODE == 3) {
+            // an intermediate Huang subiteration: X_{m+1} = X_m + E3, U unchanged
+            gdouble* X = gp(s.D3);
+#pragma unroll
+            for (int mm = 0; mm < ROWS; ++mm) X[off + (size_t)mm * sy] = X[off + (size_t)mm * sy] + d[mm];
         } else {
             double u[ROWS];
 #pragma unroll
@@ -2071,6 +2081,7 @@ hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     case 0: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 0>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
     case 1: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 1>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
     case 2: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 2>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
+    case 3: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 3>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -22,7 +22,7 @@ BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
 N_PASSES = 4  # HJM_N_PASSES
 PASSES = ("explicit", "r", "v", "y+update")
 R_METHODS = ("spike", "chain", "split", "fused")
-SCHEMES = ("douglas", "cs", "mcs", "hv")  # HJM_SCHEME_*
+SCHEMES = ("douglas", "cs", "mcs", "hv", "huang")  # HJM_SCHEME_*
 MLP_PARAMS = 199937  # HJM_MLP_PARAMS
 
 
@@ -50,7 +50,7 @@ class Payoff(C.Structure):
 
 
 class Scheme(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("theta", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("af_iters", C.c_int32), ("theta", C.c_double)]
 
 
 _lib = None
@@ -199,7 +199,7 @@ def _workspace(nbytes: int, device):
 
 def make_scheme(spec) -> "Scheme":
     """The spec's ADI scheme (Douglas with theta = 1/2 unless it says otherwise)."""
-    return Scheme(int(getattr(spec, "scheme", 0)), 0, float(getattr(spec, "theta", 0.5)))
+    return Scheme(int(getattr(spec, "scheme", 0)), int(getattr(spec, "af_iters", 0)), float(getattr(spec, "theta", 0.5)))
 
 
 def workspace_bytes(spec) -> int:

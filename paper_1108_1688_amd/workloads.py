@@ -26,8 +26,10 @@ OUTFLOW = 0
 DIRICHLET = 1
 BOND, CAPLET, FLOORLET, FORWARD = 0, 1, 2, 3
 # ADI schemes: the paper's Douglas, Craig-Sneyd, modified Craig-Sneyd,
-# Hundsdorfer-Verwer (usual theta: 1/2, 1/2, 1/3, 1/2 + sqrt(3)/6)
-DOUGLAS, CS, MCS, HV = 0, 1, 2, 3
+# Hundsdorfer-Verwer (usual theta: 1/2, 1/2, 1/3, 1/2 + sqrt(3)/6), and
+# Douglas with Huang's approximate-factorisation correction (af_iters
+# subiterations)
+DOUGLAS, CS, MCS, HV, HUANG = 0, 1, 2, 3, 4
 
 LAMBDA = 0.15
 GAMMA = 0.9
@@ -79,8 +81,9 @@ class SolveSpec:
     n_steps: int
     r0: float
     v0: float = 1.0
-    scheme: int = 0      # ADI scheme: DOUGLAS (the paper's), CS, MCS or HV
+    scheme: int = 0      # ADI scheme: DOUGLAS (the paper's), CS, MCS, HV or HUANG
     theta: float = 0.5   # implicit weight of the line solves
+    af_iters: int = 0    # HUANG: correction subiterations after the Douglas increment
 
     @property
     def shape(self):

@@ -10,4 +10,5 @@ def to_oracle(s: W.SolveSpec) -> O.Problem:
                      epsilon=m.epsilon, rho=m.rho, f_level=m.f_level, f_slope=m.f_slope,
                      f_decay=m.f_decay, kind=s.payoff.kind, expiry=s.payoff.expiry,
                      pay=s.payoff.pay, strike=s.payoff.strike, n_steps=s.n_steps,
-                     scheme=s.scheme, theta=s.theta, soften=s.payoff.soften)
+                     scheme=s.scheme, theta=s.theta, soften=s.payoff.soften,
+                     af_iters=s.af_iters)

@@ -147,9 +147,13 @@ def test_scheme_workspace_and_validation(L):
     cs = hjm.workspace_bytes(replace(s, scheme=W.CS))
     assert cs - dbl >= s.points * 8 and cs - dbl < s.points * 8 + 512
     nb = C.c_size_t()
-    for kind, theta in ((4, 0.5), (-1, 0.5), (W.CS, 0.0), (W.MCS, 1.5), (W.HV, float("nan"))):
-        st = L.hjm_scheme_workspace_bytes(ax, 10, C.byref(hjm.Scheme(kind, 0, theta)), C.byref(nb))
-        assert st == hjm.EINVAL, (kind, theta)
+    for kind, iters, theta in ((5, 0, 0.5), (-1, 0, 0.5), (W.CS, 0, 0.0), (W.MCS, 0, 1.5), (W.HV, 0, float("nan")),
+                               (W.HUANG, 0, 0.5), (W.HUANG, 17, 0.5), (W.HUANG, -2, 0.5)):
+        st = L.hjm_scheme_workspace_bytes(ax, 10, C.byref(hjm.Scheme(kind, iters, theta)), C.byref(nb))
+        assert st == hjm.EINVAL, (kind, iters, theta)
+    # Huang's correction reuses the correction array: the same workspace at any af_iters
+    for q in (1, 16):
+        assert hjm.workspace_bytes(replace(s, scheme=W.HUANG, af_iters=q)) == cs
     # nr = 40 has no power-of-two lane split: rejected before the workspace is touched
     bad = replace(W.with_shape(s, 40, 24, 32, 10), scheme=W.CS)
     h = C.c_void_p()

@@ -1,5 +1,6 @@
 """GPU parity of the ADI schemes beyond the paper's Douglas step (Craig-Sneyd,
-modified Craig-Sneyd, Hundsdorfer-Verwer) and of Douglas with another theta,
+modified Craig-Sneyd, Hundsdorfer-Verwer, Douglas with Huang's
+approximate-factorisation correction) and of Douglas with another theta,
 against the CPU oracle on the same seeded inputs, through the C ABI.
 
 Bar: as for Douglas, max|dU| / max|U| <= 1e-12 over the whole grid and
@@ -35,18 +36,19 @@ def _need_gpu():
     hjm.set_r_fusion(fused)
 
 
-def _spec(shape, steps, scheme, theta, rho=-0.6, kind=W.CAPLET, gaussian=False):
+def _spec(shape, steps, scheme, theta, rho=-0.6, kind=W.CAPLET, gaussian=False, af_iters=0):
     from dataclasses import replace
     m = W.ModelSpec(kappa=0.08, epsilon=0.45, rho=rho, **W.CURVE_SLOPED)
     k = W.atm_strike(m, 2.0, 3.0)
     s = W.SolveSpec(W.default_axes(*shape, k), m, W.PayoffSpec(kind, 2.0, 3.0, k), steps, m.f_level)
     if gaussian:
         s = W.gaussian_variant(s)
-    return replace(s, scheme=scheme, theta=theta)
+    return replace(s, scheme=scheme, theta=theta, af_iters=af_iters)
 
 
 def _gpu(s):
-    print(f"[gpu] shape={s.shape} steps={s.n_steps} scheme={s.scheme} theta={s.theta}", flush=True)
+    print(f"[gpu] shape={s.shape} steps={s.n_steps} scheme={s.scheme} theta={s.theta} af_iters={s.af_iters}",
+          flush=True)
     g = hjm.Grid(s)
     plan = g.plan()
     g.step()
@@ -99,3 +101,23 @@ def test_scheme_rejected_where_unsupported():
     with pytest.raises(hjm.HjmError) as e:
         hjm.Grid(_spec((40, 24, 32), 1, W.CS, 0.5))
     assert e.value.status == hjm.EINVAL
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+@pytest.mark.parametrize("q,theta", [(1, 0.5), (2, 0.5), (5, 0.5), (3, 0.6)])
+def test_huang_parity(q, theta, path):
+    """Douglas plus q Huang subiterations: the intermediate sweeps accumulate
+    the iterate in place, the last adds it and its correction to U."""
+    hjm.set_r_fusion(path == "fused")
+    plan, err = _check(_spec((64, 24, 32), 8, W.HUANG, theta, af_iters=q))
+    assert plan["r_method"] == path and plan["scheme"] == "huang"
+    print(f"huang q={q} theta={theta} {path}: grid rel err {err:.2e}")
+
+
+def test_huang_one_subiteration_is_hv_on_gpu():
+    """One subiteration at theta = 1/2 is Hundsdorfer-Verwer at theta = 1/2:
+    on the GPU the two run the same kernels with the same coefficients, so
+    they agree bit for bit."""
+    Uh, ph, _ = _gpu(_spec((64, 24, 32), 6, W.HUANG, 0.5, af_iters=1))
+    Uv, pv, _ = _gpu(_spec((64, 24, 32), 6, W.HV, 0.5))
+    assert np.array_equal(Uh, Uv) and ph == pv

@@ -16,6 +16,16 @@ bit for bit.
 S3: with the mixed term present, one step of each of the three schemes
 differs from one step of unsplit Crank-Nicolson (dense solve) by O(dt^3),
 second-order accuracy, where Douglas differs by O(dt^2).
+
+Huang's approximate-factorisation correction (section 5.1):
+H1: with q subiterations the step equals the dense recursion
+X_1 = M^{-1} D0, X_{m+1} = X_m + M^{-1} (D0 - (I - theta dt A) X_m) (the
+residual zero on Dirichlet nodes), U^{n+1} = U^n + X_{q+1}.
+H2: the subiterations converge to the unsplit theta step (a dense solve of
+(I - theta dt A) X = D0): the distance falls geometrically with q and
+reaches rounding; at q = 0 it is the Douglas step's factorisation error.
+H3: one subiteration at theta = 1/2 is the Hundsdorfer-Verwer step at
+theta = 1/2 (to rounding).
 """
 import math
 
@@ -131,3 +141,65 @@ def test_local_error_against_unsplit_cn(scheme, theta, order):
     ratios = [errs[0] / errs[1], errs[1] / errs[2]]
     want = 2.0 ** order
     assert all(abs(r / want - 1.0) < 0.1 for r in ratios), (errs, ratios)
+
+
+def _huang_setup(theta=0.5, rho=-0.6):
+    p = _small_problem(6, 5, 5, rho=rho)
+    p.kind = W.CAPLET
+    n = 3
+    dt = p.expiry / p.n_steps
+    t_now, t_next, t_half = p.expiry - n * dt, p.expiry - (n + 1) * dt, p.expiry - (n + 0.5) * dt
+    rng = np.random.default_rng(5)
+    U0 = O.terminal(p) + 0.01 * rng.standard_normal(p.shape)
+    Ar, Av, Ay, Ax = _dense_ops(p, t_half)
+    A = Ar + Av + Ay + Ax
+    I = np.eye(A.shape[0])
+    M = (I - theta * dt * Ar) @ (I - theta * dt * Av) @ (I - theta * dt * Ay)
+    mask = _dirichlet_mask(p)
+    D0 = dt * A @ U0.ravel()
+    D0[mask] = (_g(p, t_next) - _g(p, t_now))[mask]
+    return p, n, U0, A, I, M, mask, D0, dt
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.7])
+@pytest.mark.parametrize("q", [1, 2, 5])
+def test_huang_subiterations_dense_recursion(q, theta):
+    p, n, U0, A, I, M, mask, D0, dt = _huang_setup(theta)
+    X = np.linalg.solve(M, D0)
+    for _ in range(q):
+        R = D0 - (I - theta * dt * A) @ X
+        R[mask] = 0.0
+        X = X + np.linalg.solve(M, R)
+    p.scheme, p.theta, p.af_iters = O.HUANG, theta, q
+    U1 = O.step(p, n, U0.copy())
+    assert np.abs((U1.ravel() - U0.ravel()) - X).max() <= 1e-12 * np.abs(X).max()
+
+
+def test_huang_converges_to_unsplit_step():
+    theta = 0.5
+    p, n, U0, A, I, M, mask, D0, dt = _huang_setup(theta)
+    # the unsplit step: (I - theta dt A) X = D0 off the Dirichlet nodes, X = D0 on them
+    K = I - theta * dt * A
+    K[mask] = I[mask]
+    X = np.linalg.solve(K, D0)
+    p.scheme, p.theta = O.DOUGLAS, theta
+    dist = [np.abs(O.step(p, n, U0.copy()).ravel() - U0.ravel() - X).max()]
+    p.scheme = O.HUANG
+    for q in range(1, 41):
+        p.af_iters = q
+        dist.append(np.abs(O.step(p, n, U0.copy()).ravel() - U0.ravel() - X).max())
+    scale = np.abs(X).max()
+    assert dist[0] > 1e-6 * scale          # the factorisation error of one Douglas step
+    assert all(b < a for a, b in zip(dist[:8], dist[1:9])), dist[:9]
+    assert dist[40] <= 1e-13 * scale, (dist[40], scale)
+
+
+def test_huang_one_subiteration_is_hv_at_half():
+    p = _small_problem(9, 8, 7, rho=-0.6)
+    p.scheme, p.theta = O.HV, 0.5
+    U_hv = O.run(p, 0, 6)
+    p.scheme, p.af_iters = O.HUANG, 1
+    U_h = O.run(p, 0, 6)
+    assert np.abs(U_h - U_hv).max() <= 1e-14 * np.abs(U_hv).max()
+    p.af_iters = 2
+    assert np.abs(O.run(p, 0, 6) - U_hv).max() > 1e-10 * np.abs(U_hv).max()
