@@ -18,7 +18,7 @@ import ctypes as C
 import os
 import subprocess
 from dataclasses import dataclass, field
-from typing import Sequence
+from typing import Optional, Sequence
 
 import numpy as np
 
@@ -57,6 +57,7 @@ class _Problem(C.Structure):
         ("kind", C.c_int), ("expiry", C.c_double), ("pay", C.c_double),
         ("strike", C.c_double), ("n_steps", C.c_int),
         ("scheme", C.c_int), ("theta", C.c_double), ("soften", C.c_int), ("af_iters", C.c_int),
+        ("curve_n", C.c_int), ("curve_t", C.POINTER(C.c_double)), ("curve_p", C.POINTER(C.c_double)),
     ]
 
 
@@ -142,7 +143,10 @@ class Problem:
     theta: float = 0.5
     soften: int = 0
     af_iters: int = 0
+    curve_t: Optional[Sequence[float]] = None   # discrete curve (section 6.1): maturities from 0
+    curve_p: Optional[Sequence[float]] = None   # and zero-coupon prices from 1
     _c: _Problem = field(default=None, repr=False, compare=False)
+    _knots: tuple = field(default=None, repr=False, compare=False)
 
     @property
     def shape(self):
@@ -168,6 +172,16 @@ class Problem:
         p.scheme, p.theta = self.scheme, self.theta
         p.soften = self.soften
         p.af_iters = self.af_iters
+        if self.curve_t is not None:
+            t = np.ascontiguousarray(self.curve_t, dtype=np.float64)
+            q = np.ascontiguousarray(self.curve_p, dtype=np.float64)
+            if not (2 <= len(t) <= 64 and len(q) == len(t) and t[0] == 0.0 and q[0] == 1.0
+                    and np.all(np.diff(t) > 0) and np.all(q > 0)):
+                raise ValueError("discrete curve: 2..64 knots from (0, 1), increasing maturities, prices > 0")
+            self._knots = (t, q)  # alive as long as the struct that points at them
+            p.curve_n = len(t)
+            p.curve_t = t.ctypes.data_as(C.POINTER(C.c_double))
+            p.curve_p = q.ctypes.data_as(C.POINTER(C.c_double))
         self._c = p
         return p
 

@@ -82,6 +82,9 @@ typedef struct {
     int soften;         /* terminal data averaged over control elements (section 7.2):
                            0 no, 1 every non-Dirichlet node, 2 the nodes whose element the kink crosses */
     int af_iters;       /* ORC_HUANG: correction subiterations after the Douglas increment (>= 1) */
+    int curve_n;        /* > 0: discrete curve of curve_n knots replaces f_level/f_slope/f_decay */
+    const double* curve_t;  /* maturities, curve_t[0] = 0 */
+    const double* curve_p;  /* zero-coupon prices P(0, t_i), curve_p[0] = 1 */
 } orc_problem;
 
 #define ORC_OUTFLOW 0
@@ -120,9 +123,69 @@ int orc_get_threads(void)
 
 /* ------------------------------------------------------------------------ */
 /* Section 2: the initial curve.  f(0,t) = a + b (1 - e^{-c t}).             */
+/* Section 6.1: a discrete zero-coupon curve, smoothed by a spline so that   */
+/* df(0,t)/dt is continuous.  Here S is the natural cubic spline of          */
+/* Y(t) = -ln P(0,t) through the knots (t_i, Y_i): a cubic on each interval, */
+/* S, S', S'' continuous at the knots, S'' = 0 at both ends; then            */
+/* f(0,t) = S'(t), df(0,t)/dt = S''(t), P(0,t) = exp(-S(t)).  Past the last  */
+/* knot S continues as its tangent line (the forward stays at its end value).*/
 /* ------------------------------------------------------------------------ */
+
+/* S(t), S'(t), S''(t) from the moments M_i = S''(t_i).  On [t_i, t_{i+1}],
+   h = t_{i+1} - t_i, a = (t_{i+1} - t) / h, b = (t - t_i) / h:
+     S   = a Y_i + b Y_{i+1} + h^2 ((a^3 - a) M_i + (b^3 - b) M_{i+1}) / 6,
+     S'  = (Y_{i+1} - Y_i) / h + h ((1 - 3 a^2) M_i + (3 b^2 - 1) M_{i+1}) / 6,
+     S'' = a M_i + b M_{i+1};
+   continuity of S' at the inner knots gives, for i = 1 .. n-2,
+     h_{i-1} M_{i-1} + 2 (h_{i-1} + h_i) M_i + h_i M_{i+1}
+       = 6 ((Y_{i+1} - Y_i) / h_i - (Y_i - Y_{i-1}) / h_{i-1}),
+   with M_0 = M_{n-1} = 0, solved here on every call (Gaussian elimination
+   of the tridiagonal system, which is diagonally dominant). */
+static void spline_eval(const orc_problem* p, double t, double* S, double* S1, double* S2)
+{
+    int n = p->curve_n;
+    double Y[64], M[64], lo[64], di[64], up[64], rhs[64];
+    for (int i = 0; i < n; ++i) { Y[i] = -log(p->curve_p[i]); M[i] = 0.0; }
+    for (int i = 1; i + 1 < n; ++i) {
+        double hl = p->curve_t[i] - p->curve_t[i - 1], hr = p->curve_t[i + 1] - p->curve_t[i];
+        lo[i] = hl;
+        di[i] = 2.0 * (hl + hr);
+        up[i] = hr;
+        rhs[i] = 6.0 * ((Y[i + 1] - Y[i]) / hr - (Y[i] - Y[i - 1]) / hl);
+    }
+    for (int i = 2; i + 1 < n; ++i) {      /* forward elimination */
+        double w = lo[i] / di[i - 1];
+        di[i] -= w * up[i - 1];
+        rhs[i] -= w * rhs[i - 1];
+    }
+    for (int i = n - 2; i >= 1; --i)       /* back substitution, M_{n-1} = 0 */
+        M[i] = (rhs[i] - up[i] * M[i + 1]) / di[i];
+    double tn = p->curve_t[n - 1];
+    if (t >= tn) {
+        /* the end: S(t_n) = Y_n, S'(t_n) from the last interval (b = 1, a = 0) */
+        double h = tn - p->curve_t[n - 2];
+        double s1 = (Y[n - 1] - Y[n - 2]) / h + h * (M[n - 2] + 2.0 * M[n - 1]) / 6.0;
+        *S = Y[n - 1] + s1 * (t - tn);
+        *S1 = s1;
+        *S2 = 0.0;
+        return;
+    }
+    int i = 0;
+    while (i + 2 < n && t >= p->curve_t[i + 1]) ++i;
+    double h = p->curve_t[i + 1] - p->curve_t[i];
+    double a = (p->curve_t[i + 1] - t) / h, b = (t - p->curve_t[i]) / h;
+    *S = a * Y[i] + b * Y[i + 1] + h * h * ((a * a * a - a) * M[i] + (b * b * b - b) * M[i + 1]) / 6.0;
+    *S1 = (Y[i + 1] - Y[i]) / h + h * ((1.0 - 3.0 * a * a) * M[i] + (3.0 * b * b - 1.0) * M[i + 1]) / 6.0;
+    *S2 = a * M[i] + b * M[i + 1];
+}
+
 double orc_forward(const orc_problem* p, double t)
 {
+    if (p->curve_n > 0) {
+        double S, S1, S2;
+        spline_eval(p, t, &S, &S1, &S2);
+        return S1;
+    }
     if (p->f_decay == 0.0) return p->f_level;
     return p->f_level + p->f_slope * (1.0 - exp(-p->f_decay * t));
 }
@@ -130,6 +193,11 @@ double orc_forward(const orc_problem* p, double t)
 /* d f(0,t) / dt, needed by the drift of r (eq. (1) coefficients). */
 double orc_forward_dt(const orc_problem* p, double t)
 {
+    if (p->curve_n > 0) {
+        double S, S1, S2;
+        spline_eval(p, t, &S, &S1, &S2);
+        return S2;
+    }
     if (p->f_decay == 0.0) return 0.0;
     return p->f_slope * p->f_decay * exp(-p->f_decay * t);
 }
@@ -138,7 +206,10 @@ double orc_forward_dt(const orc_problem* p, double t)
 double orc_discount(const orc_problem* p, double t)
 {
     double integral;
-    if (p->f_decay == 0.0) {
+    if (p->curve_n > 0) {
+        double S1, S2;
+        spline_eval(p, t, &integral, &S1, &S2);
+    } else if (p->f_decay == 0.0) {
         integral = p->f_level * t;
     } else {
         integral = p->f_level * t

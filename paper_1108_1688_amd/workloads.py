@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, replace
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -62,6 +62,10 @@ class ModelSpec:
     theta_v: float = THETA_V
     lam: float = LAMBDA
     gamma: float = GAMMA
+    # a discrete initial curve (section 6.1) replaces the parametric one when
+    # given: maturities (from 0) and zero-coupon prices (from 1)
+    curve_t: Optional[Tuple[float, ...]] = None
+    curve_p: Optional[Tuple[float, ...]] = None
 
 
 @dataclass(frozen=True)
@@ -117,6 +121,31 @@ def atm_strike(m: ModelSpec, expiry: float, pay: float) -> float:
 
 CURVE_SLOPED = dict(f_level=0.02, f_slope=0.01, f_decay=0.5)
 
+# Maturities (years) of the synthetic discrete zero-coupon curve that stands
+# in for the paper's market curve (figure 5, not available).
+CURVE_KNOTS = (0.0, 0.25, 0.5, 1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0, 10.0, 12.0, 15.0, 20.0)
+
+
+def discrete_curve(seed: int, knots: Tuple[float, ...] = CURVE_KNOTS) -> Tuple[Tuple[float, ...], Tuple[float, ...]]:
+    """Seeded discrete zero-coupon curve: zero rates z(t) = a + b (1 - e^{-t/3})
+    + h (t/2) e^{1 - t/2} with a ~ U[0.015, 0.03], b ~ U[0.005, 0.02] and a
+    hump h ~ U[0, 0.004] near 2 y; prices P = e^{-z t} quoted to 5 decimals
+    (the rounding makes the data discrete-valued, as market quotes are), and
+    P(0, 0) = 1.  Returns (maturities, prices)."""
+    rng = np.random.default_rng(seed)
+    a, b, h = rng.uniform(0.015, 0.03), rng.uniform(0.005, 0.02), rng.uniform(0.0, 0.004)
+    t = np.asarray(knots, dtype=np.float64)
+    z = a + b * (1.0 - np.exp(-t / 3.0)) + h * (t / 2.0) * np.exp(1.0 - t / 2.0)
+    P = np.round(np.exp(-z * t), 5)
+    P[0] = 1.0
+    return tuple(float(x) for x in t), tuple(float(x) for x in P)
+
+
+def knot_atm_strike(curve_t, curve_p, expiry: float, pay: float) -> float:
+    """The simple-compounded forward between two knots of a discrete curve."""
+    i, j = curve_t.index(expiry), curve_t.index(pay)
+    return (curve_p[i] / curve_p[j] - 1.0) / (pay - expiry)
+
 
 def _draw_model(rng: np.random.Generator, **curve) -> ModelSpec:
     kappa = float(rng.uniform(0.01, 0.2))
@@ -153,6 +182,25 @@ def config3() -> List[SolveSpec]:
         k = atm_strike(m, float(T), float(T + 1))
         out.append(SolveSpec(default_axes(256, 128, 128, k), m,
                              PayoffSpec(CAPLET, float(T), float(T + 1), k), 40 * T, m.f_level))
+    return out
+
+
+def config_discrete(n: Tuple[int, int, int] = (128, 64, 64), seed: int = 4) -> List[SolveSpec]:
+    """Caplets on the seeded discrete curve (section 6.1's second example):
+    ATM, expiring 1, 2 and 5 y, paid +1 y, 40 steps a year, on a 128x64x64
+    mesh; kappa ~ U[0.05, 0.2] (the r = 0 outflow face needs
+    f_t + kappa f > 0, and the spline's f_t dips below 0 where the curve
+    flattens), epsilon, rho as in the other configs.  r0 = the first knot
+    interval's average rate."""
+    rng = np.random.default_rng(seed)
+    ct, cp = discrete_curve(seed)
+    m = ModelSpec(kappa=float(rng.uniform(0.05, 0.2)), epsilon=float(rng.uniform(0.1, 0.6)),
+                  rho=float(rng.uniform(-0.8, 0.8)), f_level=0.0, curve_t=ct, curve_p=cp)
+    r0 = -math.log(cp[1]) / ct[1]
+    out = []
+    for T in (1.0, 2.0, 5.0):
+        k = knot_atm_strike(ct, cp, T, T + 1.0)
+        out.append(SolveSpec(default_axes(*n, k), m, PayoffSpec(CAPLET, T, T + 1.0, k), int(40 * T), r0))
     return out
 
 
@@ -236,6 +284,8 @@ def spec_line(s: SolveSpec) -> str:
     """One solve as the 37 numbers the hjm_run command-line runner reads:
     3 x (n z_min z_max center alpha lo_face hi_face), the model, the payoff,
     then n_steps r0 v0."""
+    if s.model.curve_t is not None:
+        raise ValueError("the runner's spec lines carry the parametric curve only")
     f = []
     for a in s.axes:
         f += [a.n, a.z_min, a.z_max, a.center, a.alpha, a.lo_face, a.hi_face]

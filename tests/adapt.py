@@ -11,4 +11,4 @@ def to_oracle(s: W.SolveSpec) -> O.Problem:
                      f_decay=m.f_decay, kind=s.payoff.kind, expiry=s.payoff.expiry,
                      pay=s.payoff.pay, strike=s.payoff.strike, n_steps=s.n_steps,
                      scheme=s.scheme, theta=s.theta, soften=s.payoff.soften,
-                     af_iters=s.af_iters)
+                     af_iters=s.af_iters, curve_t=m.curve_t, curve_p=m.curve_p)
