@@ -74,10 +74,26 @@ typedef struct {
    dv = theta_v (1 - v) dt + epsilon sqrt(v) dZ, dW dZ = rho dt, and the
    initial curve f(0,t) = f_level + f_slope (1 - exp(-f_decay t)).
    Requires kappa >= 0, theta_v >= 0, lambda >= 0, epsilon >= 0, |rho| <= 1,
-   gamma in [0,1] (gamma > 0 needs r_min >= 0), f_decay >= 0. */
+   gamma in [0,1] (gamma > 0 needs r_min >= 0), f_decay >= 0.
+
+   Discrete curve (section 6.1): with curve_n >= 2 the initial curve is
+   instead given by zero-coupon prices P(0, t_i) = curve_p[i] at maturities
+   curve_t[i] (host memory, read once by the create call and not kept),
+   smoothed by the natural cubic spline S of -ln P(0, t) through the knots:
+   f(0,t) = S'(t), df(0,t)/dt = S''(t) (continuous, as the paper asks), and
+   P(0,t) = exp(-S(t)); beyond the last knot the forward stays at its value
+   there.  Requires 2 <= curve_n <= HJM_MAX_CURVE_KNOTS, curve_t[0] = 0 and
+   curve_p[0] = 1, curve_t strictly increasing, every value finite and every
+   price > 0 (else HJM_EINVAL); f_level, f_slope and f_decay are then
+   ignored.  curve_n = 0 selects the parametric curve. */
+#define HJM_MAX_CURVE_KNOTS 64
 typedef struct {
     double kappa, theta_v, lambda, gamma, epsilon, rho;
     double f_level, f_slope, f_decay;
+    int32_t curve_n;
+    int32_t reserved;
+    const double* curve_t;
+    const double* curve_p;
 } hjm_model;
 
 /* Contract: kind, expiry T > 0, payment T_M > T and strike K > 0 (caplet,

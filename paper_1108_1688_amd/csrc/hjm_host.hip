@@ -44,13 +44,98 @@ bool finite(double x) { return std::isfinite(x); }
 // ---------------------------------------------------------------------------
 // Curve and bond factors (sections 2 and 3.1).
 // ---------------------------------------------------------------------------
+// The initial curve: parametric (section 2), or discrete zero-coupon prices
+// smoothed by the natural cubic spline S of -ln P(0,t) (section 6.1), held
+// per interval as S = k0 + k1 u + k2 u^2 + k3 u^3, u = t - t_i; past the last
+// knot S is continued linearly (constant forward, S'' = 0 as the natural end
+// condition has it there).
 struct Curve {
-    double a, b, c;
-    double f(double t) const { return c == 0.0 ? a : a + b * (1.0 - std::exp(-c * t)); }
-    double ft(double t) const { return c == 0.0 ? 0.0 : b * c * std::exp(-c * t); }
-    double integral(double t) const { return c == 0.0 ? a * t : a * t + b * (t - (1.0 - std::exp(-c * t)) / c); }
+    double a = 0.0, b = 0.0, c = 0.0;
+    std::vector<double> kt, k0, k1, k2, k3;
+    bool spline() const { return !kt.empty(); }
+    // interval of t (the last one covers t beyond the last knot: extrapolated)
+    int seg(double t) const
+    {
+        const int n = (int)kt.size();
+        const int i = (int)(std::upper_bound(kt.begin(), kt.end(), t) - kt.begin()) - 1;
+        return std::min(std::max(i, 0), n - 2);
+    }
+    double f(double t) const
+    {
+        if (!spline()) return c == 0.0 ? a : a + b * (1.0 - std::exp(-c * t));
+        if (t >= kt.back()) return end_slope();
+        const int i = seg(t);
+        const double u = t - kt[i];
+        return k1[i] + u * (2.0 * k2[i] + u * 3.0 * k3[i]);
+    }
+    double ft(double t) const
+    {
+        if (!spline()) return c == 0.0 ? 0.0 : b * c * std::exp(-c * t);
+        if (t >= kt.back()) return 0.0;
+        const int i = seg(t);
+        return 2.0 * k2[i] + 6.0 * k3[i] * (t - kt[i]);
+    }
+    double integral(double t) const
+    {
+        if (!spline()) return c == 0.0 ? a * t : a * t + b * (t - (1.0 - std::exp(-c * t)) / c);
+        const int n = (int)kt.size();
+        if (t >= kt.back()) {
+            const double h = kt[n - 1] - kt[n - 2];
+            const double end = k0[n - 2] + h * (k1[n - 2] + h * (k2[n - 2] + h * k3[n - 2]));
+            return end + end_slope() * (t - kt.back());
+        }
+        const int i = seg(t);
+        const double u = t - kt[i];
+        return k0[i] + u * (k1[i] + u * (k2[i] + u * k3[i]));
+    }
     double P(double t) const { return std::exp(-integral(t)); }
+    double end_slope() const
+    {
+        const int n = (int)kt.size();
+        const double h = kt[n - 1] - kt[n - 2];
+        return k1[n - 2] + h * (2.0 * k2[n - 2] + h * 3.0 * k3[n - 2]);
+    }
 };
+
+// Natural cubic spline through (t_i, -ln P_i): the second derivatives M_i at
+// the knots solve h_{i-1} M_{i-1} + 2 (h_{i-1} + h_i) M_i + h_i M_{i+1} =
+// 6 (d_i - d_{i-1}), d_i = (S_{i+1} - S_i) / h_i, with M_0 = M_{n-1} = 0
+// (diagonally dominant: elimination without pivoting).
+Curve make_curve(const hjm_model& m)
+{
+    Curve cv;
+    cv.a = m.f_level; cv.b = m.f_slope; cv.c = m.f_decay;
+    const int n = m.curve_n;
+    if (n < 2) return cv;
+    std::vector<double> S(n), h(n - 1), d(n - 1), M(n, 0.0);
+    for (int i = 0; i < n; ++i) S[i] = -std::log(m.curve_p[i]);
+    for (int i = 0; i + 1 < n; ++i) {
+        h[i] = m.curve_t[i + 1] - m.curve_t[i];
+        d[i] = (S[i + 1] - S[i]) / h[i];
+    }
+    if (n > 2) {
+        const int k = n - 2;  // unknowns M_1 .. M_{n-2}
+        std::vector<double> cp(k), rp(k);
+        for (int r = 0; r < k; ++r) {
+            const int i = r + 1;
+            const double lo = r > 0 ? h[i - 1] : 0.0, di = 2.0 * (h[i - 1] + h[i]), up = h[i];
+            const double rhs = 6.0 * (d[i] - d[i - 1]);
+            const double den = di - (r > 0 ? lo * cp[r - 1] : 0.0);
+            cp[r] = up / den;
+            rp[r] = (rhs - (r > 0 ? lo * rp[r - 1] : 0.0)) / den;
+        }
+        for (int r = k - 1; r >= 0; --r) M[r + 1] = rp[r] - (r + 1 < k ? cp[r] * M[r + 2] : 0.0);
+    }
+    cv.kt.assign(m.curve_t, m.curve_t + n);
+    cv.k0.resize(n - 1); cv.k1.resize(n - 1); cv.k2.resize(n - 1); cv.k3.resize(n - 1);
+    for (int i = 0; i + 1 < n; ++i) {
+        cv.k0[i] = S[i];
+        cv.k1[i] = d[i] - h[i] * (2.0 * M[i] + M[i + 1]) / 6.0;
+        cv.k2[i] = 0.5 * M[i];
+        cv.k3[i] = (M[i + 1] - M[i]) / (6.0 * h[i]);
+    }
+    return cv;
+}
 
 double Gfun(double kappa, double s) { return kappa == 0.0 ? s : -std::expm1(-kappa * s) / kappa; }
 
@@ -144,6 +229,20 @@ hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_
     if (m->gamma < 0.0 || m->gamma > 1.0) return fail(HJM_EINVAL, "gamma must be in [0, 1]");
     if (m->gamma > 0.0 && ax[0].z_min < 0.0) return fail(HJM_EINVAL, "gamma > 0 needs r_min >= 0");
     if (m->f_decay < 0.0) return fail(HJM_EINVAL, "f_decay must be >= 0");
+    if (m->curve_n != 0) {
+        const int n = m->curve_n;
+        if (n < 2 || n > HJM_MAX_CURVE_KNOTS)
+            return fail(HJM_EINVAL, "curve_n must be 0 or in [2, %d] (got %d)", HJM_MAX_CURVE_KNOTS, n);
+        if (!m->curve_t || !m->curve_p) return fail(HJM_EINVAL, "null discrete curve");
+        if (m->curve_t[0] != 0.0 || m->curve_p[0] != 1.0)
+            return fail(HJM_EINVAL, "a discrete curve starts at t = 0 with P = 1");
+        for (int i = 0; i < n; ++i) {
+            if (!finite(m->curve_t[i]) || !finite(m->curve_p[i]) || !(m->curve_p[i] > 0.0))
+                return fail(HJM_EINVAL, "discrete curve knot %d is not finite or its price is not > 0", i);
+            if (i > 0 && !(m->curve_t[i] > m->curve_t[i - 1]))
+                return fail(HJM_EINVAL, "discrete curve maturities must increase (knot %d)", i);
+        }
+    }
     if (p->kind < HJM_BOND || p->kind > HJM_FORWARD) return fail(HJM_EINVAL, "unknown payoff kind %d", p->kind);
     if (p->soften < 0 || p->soften > 2) return fail(HJM_EINVAL, "soften must be 0, 1 or 2 (got %d)", p->soften);
     if (!(p->expiry > 0.0)) return fail(HJM_EINVAL, "expiry must be > 0");
@@ -153,7 +252,7 @@ hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_
     }
     if (n_steps <= 0) return fail(HJM_EINVAL, "n_steps must be > 0");
     // Outflow faces: the drift must point out of the domain in backward time.
-    const Curve cv{m->f_level, m->f_slope, m->f_decay};
+    const Curve cv = make_curve(*m);
     const double T = p->expiry, dt = T / n_steps;
     const double r0 = ax[0].z_min, r1 = ax[0].z_max;
     const double v0 = ax[1].z_min, v1 = ax[1].z_max;
@@ -314,7 +413,7 @@ constexpr double kSpikeRho = 16.0;
 
 bool r_spike_ok(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p, int n_steps, double theta = kTheta)
 {
-    const Curve cv{m.f_level, m.f_slope, m.f_decay};
+    const Curve cv = make_curve(m);
     const double T = p.expiry, dt = T / n_steps, tdt = theta * dt;
     double phi_lo = 1e300, phi_hi = -1e300;
     for (int n = 0; n < n_steps; ++n) {
@@ -593,7 +692,7 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
             plan.vs_rows = plan.vs_S = plan.vs_tiles = 0;
         }
     }
-    const Curve cv{m.f_level, m.f_slope, m.f_decay};
+    const Curve cv = make_curve(m);
     const double T = p.expiry, TM = p.kind == HJM_BOND ? p.expiry : p.pay;
     const double PT = cv.P(T), PM = cv.P(TM);
     for (int n = 0; n <= n_steps; ++n) {
@@ -953,6 +1052,7 @@ hjm_status hjm_grid_create_scheme(const hjm_axis ax[3], const hjm_model* model, 
     if (!g) return fail(HJM_EINVAL, "host allocation failed");
     std::memcpy(g->ax, ax, sizeof g->ax);
     g->model = *model;
+    g->model.curve_t = g->model.curve_p = nullptr;  // the knots are not kept
     g->payoff = *payoff;
     g->n_steps = n_steps;
     std::memcpy(g->rows, rows, sizeof g->rows);

@@ -41,7 +41,8 @@ class Axis(C.Structure):
 class Model(C.Structure):
     _fields_ = [("kappa", C.c_double), ("theta_v", C.c_double), ("lam", C.c_double), ("gamma", C.c_double),
                 ("epsilon", C.c_double), ("rho", C.c_double), ("f_level", C.c_double), ("f_slope", C.c_double),
-                ("f_decay", C.c_double)]
+                ("f_decay", C.c_double), ("curve_n", C.c_int32), ("reserved", C.c_int32),
+                ("curve_t", C.POINTER(C.c_double)), ("curve_p", C.POINTER(C.c_double))]
 
 
 class Payoff(C.Structure):
@@ -132,7 +133,21 @@ def make_axes(spec_axes) -> "C.Array":
 
 
 def make_model(m) -> Model:
-    return Model(m.kappa, m.theta_v, m.lam, m.gamma, m.epsilon, m.rho, m.f_level, m.f_slope, m.f_decay)
+    """The model struct; a discrete curve (curve_t, curve_p) is copied into
+    arrays that the returned struct keeps alive (the library reads them once,
+    in the create call)."""
+    mod = Model(m.kappa, m.theta_v, m.lam, m.gamma, m.epsilon, m.rho, m.f_level, m.f_slope, m.f_decay)
+    ct, cp = getattr(m, "curve_t", None), getattr(m, "curve_p", None)
+    if ct is not None:
+        if cp is None or len(cp) != len(ct):
+            raise ValueError("curve_t and curve_p must have the same length")
+        t = (C.c_double * len(ct))(*[float(x) for x in ct])
+        p = (C.c_double * len(cp))(*[float(x) for x in cp])
+        mod.curve_n = len(ct)
+        mod.curve_t = C.cast(t, C.POINTER(C.c_double))
+        mod.curve_p = C.cast(p, C.POINTER(C.c_double))
+        mod._knots = (t, p)
+    return mod
 
 
 def make_payoff(p) -> Payoff:
@@ -335,7 +350,8 @@ class Batch:
                 x, y = self._ax[3 * s + a], sp.axes[a]
                 x.n, x.lo_face, x.hi_face = y.n, y.lo_face, y.hi_face
                 x.z_min, x.z_max, x.center, x.alpha = y.z_min, y.z_max, y.center, y.alpha
-        self._models = (Model * n)(*[make_model(sp.model) for sp in self.specs])
+        self._model_refs = [make_model(sp.model) for sp in self.specs]  # keeps discrete curves alive
+        self._models = (Model * n)(*self._model_refs)
         self._payoffs = (Payoff * n)(*[make_payoff(sp.payoff) for sp in self.specs])
         self._steps = (C.c_int32 * n)(*[sp.n_steps for sp in self.specs])
         nbytes = C.c_size_t()

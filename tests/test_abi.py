@@ -212,3 +212,32 @@ def test_batch_validation(L):
     pays[2].strike = 0.03
     st = L.hjm_batch_create(n, ax, models, pays, steps, C.c_void_p(0x100000), 100, None, C.byref(h))
     assert st == hjm.ENOMEM
+
+
+def test_discrete_curve_validation(L):
+    """Discrete curves are checked on the host before any device work: knot
+    count, the (0, 1) first knot, increasing maturities, positive finite
+    prices."""
+    from dataclasses import replace
+    s = W.config_discrete((24, 12, 12))[0]
+    ct, cp = list(s.model.curve_t), list(s.model.curve_p)
+    bad = [(ct[:1], cp[:1]),                                   # one knot
+           ([0.1] + ct[1:], cp),                               # first maturity not 0
+           (ct, [0.99] + cp[1:]),                              # first price not 1
+           (ct[:3] + [ct[2]] + ct[4:], cp),                    # maturities not increasing
+           (ct, cp[:5] + [0.0] + cp[6:]),                      # price 0
+           (ct, cp[:5] + [float("nan")] + cp[6:]),             # not finite
+           ([i * 0.5 for i in range(65)], [1.0] + [0.99] * 64)]  # too many knots
+    for t, p in bad:
+        sp = replace(s, model=replace(s.model, curve_t=tuple(t), curve_p=tuple(p)))
+        h = C.c_void_p()
+        st = L.hjm_grid_create_scheme(hjm.make_axes(sp.axes), C.byref(hjm.make_model(sp.model)),
+                                      C.byref(hjm.make_payoff(sp.payoff)), C.byref(hjm.make_scheme(sp)), sp.n_steps,
+                                      C.c_void_p(256), 1 << 40, None, C.byref(h))
+        assert st == hjm.EINVAL and not h.value, (t[:4], p[:6])
+    m = hjm.make_model(s.model)
+    m.curve_t = None
+    h = C.c_void_p()
+    st = L.hjm_grid_create_scheme(hjm.make_axes(s.axes), C.byref(m), C.byref(hjm.make_payoff(s.payoff)),
+                                  C.byref(hjm.make_scheme(s)), s.n_steps, C.c_void_p(256), 1 << 40, None, C.byref(h))
+    assert st == hjm.EINVAL and "null" in L.hjm_last_error().decode()

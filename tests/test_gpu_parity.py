@@ -332,3 +332,29 @@ def test_softened_terminal_data(kind, mode):
     Uo, po = oracle_grid(s)
     assert_grid(Ug, Uo)
     assert_price(pg, po)
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_discrete_curve_full_solve(which):
+    """Caplets on the seeded discrete curve (section 6.1): the host's spline
+    tables against the oracle's own spline, through whole solves."""
+    s = W.config_discrete((64, 24, 33))[which]
+    Ug, pg = gpu_grid(s)
+    Uo, po = oracle_grid(s)
+    assert_grid(Ug, Uo)
+    assert_price(pg, po)
+
+
+def test_discrete_curve_in_a_batch():
+    """A batch mixing discrete-curve and parametric solves prices each as its
+    single grid does, bit for bit, and the discrete ones as the oracle does."""
+    disc = W.config_discrete((48, 24, 32))[:2]
+    par = [W.with_shape(W.config2()[1], 48, 24, 32, 30)]
+    specs = [disc[0], par[0], disc[1]]
+    prices = hjm.Batch(specs).run().prices()
+    for sp, pb in zip(specs, prices):
+        g = hjm.Grid(sp).step()
+        assert pb == g.price()
+        g.close()
+    po, _ = O.price(to_oracle(disc[0]), disc[0].r0, disc[0].v0)
+    assert abs(prices[0] - po) <= REL * abs(po)
