@@ -242,6 +242,32 @@ def softening_leg(hjm, W, torch, stream):
     return out
 
 
+def discrete_curve_leg(hjm, W, torch, stream, reps: int = 3):
+    """Section 6.1's discrete curve: the three caplets of the discrete-curve
+    workload (128x64x64, 1, 2 and 5 y, 40 steps a year) as one batch, and the
+    same solves on the parametric sloped curve; the curve only changes host
+    tables, so the throughput should match."""
+    from dataclasses import replace
+    disc = W.config_discrete()
+    par = [replace(s, model=replace(s.model, curve_t=None, curve_p=None, **W.CURVE_SLOPED)) for s in disc]
+    out = {"workload": "3 caplets on a 128x64x64 mesh, 1/2/5 y, 40 steps a year, one batch"}
+    for name, specs in (("discrete", disc), ("parametric", par)):
+        b = hjm.Batch(specs, stream=stream)
+        b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        pr = b.prices()
+        b.close()
+        work = sum(s.points * s.n_steps for s in specs)
+        out[name] = {"ms_per_batch": round(el * 1e3, 3), "point_steps_per_s": work / el,
+                     "prices": [float(x) for x in pr]}
+    return out
+
+
 def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int, outside_frac: float):
     """Surrogate pricing: train on ADI prices (n_train_solves solves at 64^3,
     16 readouts each), then price n_query rows, a fraction outside the box
@@ -296,6 +322,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg of the calibration")
     ap.add_argument("--no-schemes", action="store_true", help="skip the ADI-schemes leg")
     ap.add_argument("--no-softening", action="store_true", help="skip the payoff-softening leg")
+    ap.add_argument("--no-curve", action="store_true", help="skip the discrete-curve leg")
     ap.add_argument("--sur-solves", type=int, default=4096, help="ADI solves for the surrogate's training set")
     ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
@@ -457,6 +484,9 @@ def main():
     if not args.no_softening:
         out["softening"] = softening_leg(hjm, W, torch, stream)
         log(f"softening: {out['softening']}")
+    if not args.no_curve:
+        out["discrete_curve"] = discrete_curve_leg(hjm, W, torch, stream)
+        log(f"discrete curve: {out['discrete_curve']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
