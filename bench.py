@@ -48,12 +48,12 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "f999c4fa0289032458c14706aaa3eed3d81465194e51a4705c5963d741726ed3"
-                      ":e7b0292e0911172aa4bc98822548d8a203ef94c5a8ffce6a029ba181dd94ec6e",
+    "sources_sha256": "79cda73a31d5ed5922f53199789f8668991793147d667fdceebf2d9ca8a0ce86"
+                      ":daba38f88d236dbd9b737bcf3ddb642738a6f031523fca6ba2a3208e91267698",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
-    "bytes_per_point": {"explicit+r": 19.049, "v": 15.978, "y+update": 32.050},
+    "bytes_per_point": {"explicit+r": 18.955, "v": 15.977, "y+update": 32.048},
 }
 
 
