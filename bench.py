@@ -268,6 +268,42 @@ def discrete_curve_leg(hjm, W, torch, stream, reps: int = 3):
     return out
 
 
+def multi_rhs_leg(hjm, W, torch, stream, reps: int = 5):
+    """Right-hand sides of one operator: config 2's three caplets (ATM and
+    +-100 bp on one 128x64x64 mesh, 5 y, 200 steps) plus the ATM floorlet, as
+    one batch with the shared operator (one set of tables and y pivots) and
+    without: batch set-up and a whole priced run."""
+    from dataclasses import replace
+    specs = W.config2()
+    specs = specs + [replace(specs[1], payoff=replace(specs[1].payoff, kind=W.FLOORLET))]
+    out = {"workload": "config 2: 3 caplet strikes + ATM floorlet, 128x64x64, 200 steps, one batch"}
+    old = hjm.get_batch_share()
+    try:
+        for name, on in (("shared", True), ("unshared", False)):
+            hjm.set_batch_share(on)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b = hjm.Batch(specs, stream=stream)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            b.run()
+            b.prices()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                b.run()
+                pr = b.prices()
+            el = (time.perf_counter() - t0) / reps
+            out[name] = {"operators": b.operators(), "setup_ms": round(t_setup * 1e3, 3),
+                         "ms_per_run": round(el * 1e3, 3),
+                         "point_steps_per_s": sum(s.points * s.n_steps for s in specs) / el,
+                         "prices": [float(x) for x in pr]}
+            b.close()
+    finally:
+        hjm.set_batch_share(old)
+    out["prices_bitwise_equal"] = out["shared"]["prices"] == out["unshared"]["prices"]
+    return out
+
+
 def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int, outside_frac: float):
     """Surrogate pricing: train on ADI prices (n_train_solves solves at 64^3,
     16 readouts each), then price n_query rows, a fraction outside the box
@@ -323,6 +359,7 @@ def main():
     ap.add_argument("--no-schemes", action="store_true", help="skip the ADI-schemes leg")
     ap.add_argument("--no-softening", action="store_true", help="skip the payoff-softening leg")
     ap.add_argument("--no-curve", action="store_true", help="skip the discrete-curve leg")
+    ap.add_argument("--no-multi-rhs", action="store_true", help="skip the shared-operator leg")
     ap.add_argument("--sur-solves", type=int, default=4096, help="ADI solves for the surrogate's training set")
     ap.add_argument("--sur-epochs", type=int, default=200)
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
@@ -487,6 +524,9 @@ def main():
     if not args.no_curve:
         out["discrete_curve"] = discrete_curve_leg(hjm, W, torch, stream)
         log(f"discrete curve: {out['discrete_curve']}")
+    if not args.no_multi_rhs:
+        out["multi_rhs"] = multi_rhs_leg(hjm, W, torch, stream)
+        log(f"multi-rhs: {out['multi_rhs']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -370,6 +370,23 @@ hjm_status hjm_get_r_fusion(int32_t* on);
 hjm_status hjm_set_batch_streams(int32_t n);
 hjm_status hjm_get_batch_streams(int32_t* n);
 
+/* Shared operators in batches created afterwards (on by default).  Solves
+   of a batch that differ only in their payoff (kind, strike, softening) with
+   the same axes, model (discrete curve included), expiry, payment date and
+   steps discretise one operator: several right-hand sides of one system
+   (the strikes of one caplet, a caplet and its floorlet).  With sharing on
+   they use the first such solve's coefficient tables and y-line pivots: the
+   host builds and uploads the tables once per operator, the pivot kernel
+   runs once per operator, and the y sweeps of the right-hand sides read one
+   pivot array, their line tiles interleaved so that the reads meet in cache.
+   Each solve keeps its own grid, terminal and Dirichlet data; every result
+   is bit-identical to the unshared batch.  Process-wide. */
+hjm_status hjm_set_batch_share(int32_t on);
+hjm_status hjm_get_batch_share(int32_t* on);
+
+/* The number of distinct operators of a batch (n when sharing is off). */
+hjm_status hjm_batch_operators(const hjm_batch* b, int32_t* n_operators);
+
 const char* hjm_status_str(hjm_status s);
 const char* hjm_last_error(void);
 

@@ -319,6 +319,7 @@ int g_exp_J = 8;      // v nodes per k_exp thread (4, 8 or 16)
 bool g_fuse_r = true;  // fuse the explicit predictor with the spike r solve where k_exr applies
 constexpr int kMaxBatchLanes = 8;
 int g_batch_lanes = 2;  // streams a batch spreads its solves over
+bool g_batch_share = true;  // solves of one operator share tables and y pivots
 
 // k_rs needs nr = S * ROWS with S a power of two <= 64 lanes; the preferred
 // rows per lane come first.
@@ -972,6 +973,19 @@ hjm_status hjm_get_batch_streams(int32_t* n)
     return HJM_OK;
 }
 
+hjm_status hjm_set_batch_share(int32_t on)
+{
+    g_batch_share = on != 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_batch_share(int32_t* on)
+{
+    if (!on) return fail(HJM_EINVAL, "null argument");
+    *on = g_batch_share ? 1 : 0;
+    return HJM_OK;
+}
+
 hjm_status hjm_get_r_fusion(int32_t* on)
 {
     if (!on) return fail(HJM_EINVAL, "null argument");
@@ -1273,6 +1287,8 @@ struct hjm_batch {
     int32_t* d_flags = nullptr;
     std::vector<SolveDesc> descs;
     std::vector<std::vector<double>> tables;
+    std::vector<int> owner;  // the solve whose tables and y pivots each solve uses (itself, unless shared)
+    int n_operators = 0;
     std::vector<LaunchGroup> groups;
     int max_steps = 0;
     int64_t max_points = 0, max_ylines = 0;
@@ -1315,6 +1331,39 @@ size_t task_bound(const hjm_axis* a)
     return (size_t)std::max(std::max(pb.r_tiles, pb.exp_tiles), pb.exr_tiles) + pb.rs_tiles +
            std::max(pb.v_tiles, pb.vs_tiles) +
            std::max(pb.y_tiles, pb.yc_tiles) + (size_t)pb.exp_tiles;
+}
+
+// Two solves discretise the same operator (the same coefficient tables and
+// y pivots) when they differ at most in the payoff's kind, strike and
+// softening: same axes, model (discrete curve values included), expiry,
+// bond-factor date and steps.
+bool same_operator(const hjm_axis* a, const hjm_model& m, const hjm_payoff& p, int ns, const hjm_axis* b,
+                   const hjm_model& q, const hjm_payoff& r, int nt)
+{
+    if (ns != nt) return false;
+    for (int d = 0; d < 3; ++d)
+        if (a[d].n != b[d].n || a[d].lo_face != b[d].lo_face || a[d].hi_face != b[d].hi_face ||
+            a[d].z_min != b[d].z_min || a[d].z_max != b[d].z_max || a[d].center != b[d].center ||
+            a[d].alpha != b[d].alpha)
+            return false;
+    if (m.kappa != q.kappa || m.theta_v != q.theta_v || m.lambda != q.lambda || m.gamma != q.gamma ||
+        m.epsilon != q.epsilon || m.rho != q.rho || m.curve_n != q.curve_n)
+        return false;
+    if (m.curve_n == 0 && (m.f_level != q.f_level || m.f_slope != q.f_slope || m.f_decay != q.f_decay)) return false;
+    for (int i = 0; i < m.curve_n; ++i)
+        if (m.curve_t[i] != q.curve_t[i] || m.curve_p[i] != q.curve_p[i]) return false;
+    const double pm = p.kind == HJM_BOND ? p.expiry : p.pay, rm = r.kind == HJM_BOND ? r.expiry : r.pay;
+    return p.expiry == r.expiry && pm == rm;
+}
+
+// A solve that shares another's operator reads that solve's tables and y
+// pivots; its own grid, Dirichlet increments and flag stay its own.
+void share_operator(SolveDesc& d, const SolveDesc& o)
+{
+    d.rt = o.rt; d.vt = o.vt; d.yt = o.yt; d.vf = o.vf;
+    d.st = o.st; d.rf = o.rf; d.vg = o.vg;
+    d.yinv = o.yinv;
+    d.ypiv_skip = 1;
 }
 
 BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
@@ -1453,19 +1502,35 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
     b->d_flags = reinterpret_cast<int32_t*>(b->base + bl.flags);
     b->descs.resize(n);
     b->tables.resize(n);
+    b->owner.resize(n);
     std::vector<Plan> plans(n);
     for (int s = 0; s < n; ++s) {
         const hjm_axis* a = ax + 3 * s;
-        plans[s] = make_plan(a[0].n, a[1].n, a[2].n, b->rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
-        build_tables(a, model[s], payoff[s], n_steps[s], plans[s], b->tables[s]);
+        int own = s;
+        for (int q = 0; g_batch_share && q < s && own == s; ++q)
+            if (b->owner[q] == q && same_operator(ax + 3 * q, model[q], payoff[q], n_steps[q], a, model[s], payoff[s],
+                                                  n_steps[s]))
+                own = q;
+        b->owner[s] = own;
+        if (own == s) {
+            plans[s] = make_plan(a[0].n, a[1].n, a[2].n, b->rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
+            build_tables(a, model[s], payoff[s], n_steps[s], plans[s], b->tables[s]);
+            b->n_operators += 1;
+        } else {
+            plans[s] = plans[own];
+        }
         fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], plans[s], b->base, bl.s[s], b->d_flags + s);
+        if (own != s) share_operator(b->descs[s], b->descs[own]);
         b->max_steps = std::max(b->max_steps, n_steps[s]);
         b->max_points = std::max<int64_t>(b->max_points, (int64_t)a[0].n * a[1].n * a[2].n);
         b->max_ylines = std::max<int64_t>(b->max_ylines, (int64_t)a[0].n * a[1].n);
     }
     std::vector<int> order(n);
     for (int s = 0; s < n; ++s) order[s] = s;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n_steps[a] > n_steps[c]; });
+    // longest first; the right-hand sides of one operator next to each other
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return n_steps[a] != n_steps[c] ? n_steps[a] > n_steps[c] : b->owner[a] < b->owner[c];
+    });
     // stream lanes: solves by decreasing work (points x steps) dealt to the
     // lanes in snake order, which balances the lanes' work
     b->n_lanes = std::max(1, std::min(g_batch_lanes, n));
@@ -1491,38 +1556,56 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
         b->groups.back().pts.assign(b->max_steps, 0);
         return b->groups.back();
     };
-    for (int lane = 0; lane < b->n_lanes; ++lane)
-    for (int kind = 0; kind < kGroupKinds; ++kind)
-        for (int s : order) {
-            if (lane_of[s] != lane) continue;
-            const Plan& pl = plans[s];
-            const int ns = n_steps[s];
-            int rows = 0, tiles = 0;
-            size_t lds = 0;
-            int aux = 0;
-            switch (kind) {
-            case G_XR:
-                if (pl.r_mode == R_SPIKE || pl.r_mode == R_CHAIN) { rows = b->rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; }
-                break;
-            case G_EXR: if (pl.r_mode == R_FUSED) { rows = pl.rs_rows; tiles = pl.exr_tiles; lds = pl.exr_lds; } break;
-            case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
-            case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
-            case G_V: if (!pl.vs_rows) { rows = b->rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
-            case G_VS: if (pl.vs_rows) { rows = pl.vs_rows; tiles = pl.vs_tiles; aux = pl.vs_S; } break;
-            case G_YU: if (!pl.yc_rows) { rows = b->rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
-            default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; aux = pl.yc_S; } break;
+    for (int lane = 0; lane < b->n_lanes; ++lane) {
+        std::vector<int> lane_order;
+        for (int s : order)
+            if (lane_of[s] == lane) lane_order.push_back(s);
+        for (int kind = 0; kind < kGroupKinds; ++kind)
+            for (size_t oi = 0; oi < lane_order.size(); ++oi) {
+                const int s = lane_order[oi];
+                const Plan& pl = plans[s];
+                const int ns = n_steps[s];
+                int rows = 0, tiles = 0;
+                size_t lds = 0;
+                int aux = 0;
+                switch (kind) {
+                case G_XR:
+                    if (pl.r_mode == R_SPIKE || pl.r_mode == R_CHAIN) { rows = b->rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; }
+                    break;
+                case G_EXR: if (pl.r_mode == R_FUSED) { rows = pl.rs_rows; tiles = pl.exr_tiles; lds = pl.exr_lds; } break;
+                case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
+                case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
+                case G_V: if (!pl.vs_rows) { rows = b->rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
+                case G_VS: if (pl.vs_rows) { rows = pl.vs_rows; tiles = pl.vs_tiles; aux = pl.vs_S; } break;
+                case G_YU: if (!pl.yc_rows) { rows = b->rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
+                default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; aux = pl.yc_S; } break;
+                }
+                if (!tiles) continue;
+                LaunchGroup& g = group(lane, kind, rows);
+                if (kind != G_YC) {
+                    for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(s, t));
+                } else if (oi == 0 || b->owner[lane_order[oi - 1]] != b->owner[s]) {
+                    // the right-hand sides of one operator (adjacent in the
+                    // lane's order, same plan) share the y pivots: their tiles
+                    // go in 8 at a time, each block for every right-hand side
+                    // in turn, so that tasks t, t + 8, ... (dealt to one XCD)
+                    // read one tile's pivots from that XCD's cache
+                    std::vector<int> rhs{s};
+                    for (size_t oj = oi + 1; oj < lane_order.size() && b->owner[lane_order[oj]] == b->owner[s]; ++oj)
+                        rhs.push_back(lane_order[oj]);
+                    for (int tb = 0; tb < tiles; tb += 8)
+                        for (int r : rhs)
+                            for (int x = tb; x < std::min(tiles, tb + 8); ++x) g.tasks.push_back(make_int2(r, x));
+                }
+                const int64_t pts = (int64_t)ax[3 * s].n * ax[3 * s + 1].n * ax[3 * s + 2].n;
+                for (int step = 0; step < ns; ++step) {
+                    g.cnt[step] += tiles;
+                    g.pts[step] += pts;
+                }
+                g.lds = std::max(g.lds, lds);
+                g.aux = std::max(g.aux, aux);
             }
-            if (!tiles) continue;
-            LaunchGroup& g = group(lane, kind, rows);
-            for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(s, t));
-            const int64_t pts = (int64_t)ax[3 * s].n * ax[3 * s + 1].n * ax[3 * s + 2].n;
-            for (int step = 0; step < ns; ++step) {
-                g.cnt[step] += tiles;
-                g.pts[step] += pts;
-            }
-            g.lds = std::max(g.lds, lds);
-            g.aux = std::max(g.aux, aux);
-        }
+    }
     std::vector<int2> all;
     for (LaunchGroup& g : b->groups) {
         g.off = all.size();
@@ -1544,7 +1627,7 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
         e = hipMemcpyAsync(b->d_tasks, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, b->stream);
     int64_t max_gd = 0;
     for (int s = 0; s < n && !e; ++s) {
-        e = upload_tables(b->descs[s], b->tables[s], b->stream);
+        if (b->owner[s] == s) e = upload_tables(b->descs[s], b->tables[s], b->stream);
         max_gd = std::max<int64_t>(max_gd, (int64_t)(2 * ax[3 * s + 2].n + ax[3 * s].n) * n_steps[s]);
     }
     if (!e) e = launch_gd(b->d_desc, n, max_gd, b->stream);
@@ -1555,6 +1638,13 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
         return hip_fail(e, "hjm_batch_create");
     }
     *out = b;
+    return HJM_OK;
+}
+
+hjm_status hjm_batch_operators(const hjm_batch* b, int32_t* n_operators)
+{
+    if (!b || !n_operators) return fail(HJM_EINVAL, "null argument");
+    *n_operators = b->n_operators;
     return HJM_OK;
 }
 

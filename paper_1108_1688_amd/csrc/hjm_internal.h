@@ -73,7 +73,8 @@ struct SolveDesc {
     // stage-2 sequence af_iters times with (sc_a0, sc_a1, sc_b) = (theta,
     // theta, -1): each but the last adds E3 to D3 (D3 holds the iterate X_m)
     int32_t stage, hv;
-    int32_t soften, pad5;  // terminal data averaged over control elements (section 7.2): 0, 1 all, 2 at the kink
+    int32_t soften;     // terminal data averaged over control elements (section 7.2): 0, 1 all, 2 at the kink
+    int32_t ypiv_skip;  // the y pivots belong to another solve of the batch (shared operator)
     double sc_a0, sc_a1, sc_b;
     double* D3;
     int32_t* flag;      // health flag: nonzero after a bad pivot or a non-finite value

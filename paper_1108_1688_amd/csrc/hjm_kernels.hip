@@ -1618,7 +1618,7 @@ __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ d
 {
     const SolveDesc& s = descs[blockIdx.y];
     const int nr = s.nr, nv = s.nv, ny = s.ny;
-    if (s.yc_S == 0) return;
+    if (s.yc_S == 0 || s.ypiv_skip) return;
     const int q = blockIdx.x * kBlock + threadIdx.x;  // q = j nr + i
     if (q >= nr * nv) return;
     const int j = q / nr;

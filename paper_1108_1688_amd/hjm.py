@@ -97,6 +97,9 @@ def lib():
         "hjm_get_r_fusion": (st, [P(i32)]),
         "hjm_set_batch_streams": (st, [i32]),
         "hjm_get_batch_streams": (st, [P(i32)]),
+        "hjm_set_batch_share": (st, [i32]),
+        "hjm_get_batch_share": (st, [P(i32)]),
+        "hjm_batch_operators": (st, [vp, P(i32)]),
         "hjm_mlp_workspace_bytes": (st, [i64, P(sz)]),
         "hjm_mlp_create": (st, [P(C.c_float), P(C.c_float), C.c_float, C.c_float, i64, vp, sz, vp, P(vp)]),
         "hjm_mlp_set_params": (st, [vp, P(C.c_float), i64]),
@@ -197,6 +200,19 @@ def get_batch_streams() -> int:
     n = C.c_int32()
     check(lib().hjm_get_batch_streams(C.byref(n)))
     return n.value
+
+
+def set_batch_share(on: bool) -> None:
+    """Whether batches created afterwards let solves of one operator (the
+    right-hand sides: payoffs on the same mesh, model, dates and steps)
+    share coefficient tables and y pivots."""
+    check(lib().hjm_set_batch_share(1 if on else 0))
+
+
+def get_batch_share() -> bool:
+    n = C.c_int32()
+    check(lib().hjm_get_batch_share(C.byref(n)))
+    return bool(n.value)
 
 
 def _torch():
@@ -387,6 +403,13 @@ class Batch:
         dp = C.POINTER(C.c_double)
         check(lib().hjm_batch_prices(self._h, r0.ctypes.data_as(dp), v0.ctypes.data_as(dp), out.ctypes.data_as(dp)))
         return out
+
+    def operators(self) -> int:
+        """Distinct operators among the batch's solves (its length when
+        sharing is off)."""
+        n = C.c_int32()
+        check(lib().hjm_batch_operators(self._h, C.byref(n)))
+        return n.value
 
     def greeks(self, r0=None, v0=None) -> np.ndarray:
         """(n, 3): price, rho = dC/dr and vega = dC/dv of every solve."""

@@ -187,6 +187,13 @@ def test_tuning_knobs(L):
                     hjm.set_batch_streams(bad)
         finally:
             hjm.set_batch_streams(old_n)
+        old_s = hjm.get_batch_share()
+        try:
+            for on in (False, True):
+                hjm.set_batch_share(on)
+                assert hjm.get_batch_share() is on
+        finally:
+            hjm.set_batch_share(old_s)
     finally:
         hjm.set_explicit_chunk(old_J)
         hjm.set_r_fusion(old_f)

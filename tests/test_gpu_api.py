@@ -176,3 +176,62 @@ def test_batch_stream_lanes_bitwise(lanes):
         hjm.set_batch_streams(old)
     for sp, p in list(zip(specs, ref))[::5]:
         assert p == hjm.Grid(sp).step().price()
+
+
+def _rhs_specs():
+    """Right-hand sides of one operator (config 2's three strikes and an ATM
+    floorlet on one 48x24x32 mesh, 30 steps), a solve on another model, and
+    two strikes on the discrete curve: three operators."""
+    from dataclasses import replace
+    base = W.with_shape(W.config2()[1], 48, 24, 32, 30)
+    k = base.payoff.strike
+    same = [replace(base, payoff=replace(base.payoff, strike=k + dk)) for dk in (-0.01, 0.0, 0.01)]
+    same.append(replace(base, payoff=replace(base.payoff, kind=W.FLOORLET)))
+    other = replace(base, model=replace(base.model, epsilon=base.model.epsilon * 0.5))
+    disc = W.with_shape(W.config_discrete()[0], 48, 24, 32, 30)
+    disc2 = replace(disc, payoff=replace(disc.payoff, strike=disc.payoff.strike + 0.005))
+    return [same[0], other, same[1], disc, same[2], disc2, same[3]]
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_shared_operator_batch_bitwise(lanes):
+    """Solves of one operator share tables and y pivots (one pivot kernel per
+    operator, y tiles interleaved across the right-hand sides): prices equal
+    the single grids' and the unshared batch's bit for bit."""
+    specs = _rhs_specs()
+    old_l, old_s = hjm.get_batch_streams(), hjm.get_batch_share()
+    try:
+        hjm.set_batch_streams(lanes)
+        hjm.set_batch_share(True)
+        b = hjm.Batch(specs).run()
+        shared, ops = b.prices(), b.operators()
+        b.close()
+        hjm.set_batch_share(False)
+        b = hjm.Batch(specs).run()
+        plain, ops_off = b.prices(), b.operators()
+        b.close()
+    finally:
+        hjm.set_batch_streams(old_l)
+        hjm.set_batch_share(old_s)
+    assert ops == 3 and ops_off == len(specs)
+    assert np.array_equal(shared, plain)
+    for sp, pb in zip(specs, shared):
+        g = hjm.Grid(sp).step()
+        assert pb == g.price()
+        g.close()
+    po, _ = O.price(to_oracle(specs[4]), specs[4].r0, specs[4].v0)
+    assert abs(shared[4] - po) <= 1e-12 * abs(po)
+
+
+def test_shared_operator_graph_replays():
+    specs = _rhs_specs()
+    st = torch.cuda.Stream()
+    eager = hjm.Batch(specs, stream=st).run(graph=False).prices()
+    b = hjm.Batch(specs, stream=st)
+    for rep in range(3):
+        b.run(graph=True)
+        assert np.array_equal(b.prices(), eager), rep
+        x = torch.randn(1000, device="cuda") * 2
+        torch.cuda.synchronize()
+        del x
+    b.close()
