@@ -235,3 +235,28 @@ def test_shared_operator_graph_replays():
         torch.cuda.synchronize()
         del x
     b.close()
+
+
+def test_config4_full_batch_sampled_against_oracle():
+    """The whole calibration workload as the bench times it (512 uneven
+    solves, one batch replayed from a HIP graph): every price finite and
+    between 0 and the discount factor, the graph replay equal to an eager run
+    bit for bit, and the eight cheapest solves equal to the oracle's to
+    1e-12."""
+    specs = W.config4()
+    st = torch.cuda.Stream()
+    b = hjm.Batch(specs, stream=st)
+    b.run(graph=True)
+    graph = b.prices()
+    b.run(graph=False)
+    eager = b.prices()
+    b.close()
+    assert np.array_equal(graph, eager)
+    assert np.all(np.isfinite(graph))
+    for sp, pg in zip(specs, graph):
+        assert 0.0 <= pg <= O.discount(to_oracle(sp), sp.payoff.expiry) * (1 + 1e-12), (sp.shape, pg)
+    cheap = sorted(range(len(specs)), key=lambda q: specs[q].points * specs[q].n_steps)[:8]
+    for q in cheap:
+        sp = specs[q]
+        po, _ = O.price(to_oracle(sp), sp.r0, sp.v0)
+        assert abs(graph[q] - po) <= 1e-12 * abs(po), (q, sp.shape, graph[q], po)
