@@ -48,14 +48,13 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "79cda73a31d5ed5922f53199789f8668991793147d667fdceebf2d9ca8a0ce86"
-                      ":daba38f88d236dbd9b737bcf3ddb642738a6f031523fca6ba2a3208e91267698",
+    "sources_sha256": "bd9f894d6ec229ece5872f886951073d56ddeac3984c014a44ae5211b36cb84b"
+                      ":fc04dde200c43ef1a85d6eb8c0ca29a6208a582cc80d6475abe83e1b4f0b5765",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
-    "bytes_per_point": {"explicit+r": 18.955, "v": 15.977, "y+update": 32.048},
+    "bytes_per_point": {"explicit+r": 19.023, "v": 15.978, "y+update": 32.050},
 }
-
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -367,7 +366,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=PROFILED_STEPS,
                     help="batch mode: time the launches of the first N Douglas steps (0: all)")
     ap.add_argument("--streams", type=int, default=None,
-                    help="stream lanes the batch spreads its solves over (library default 2)")
+                    help="stream lanes the batch spreads its solves over (library default 3)")
     ap.add_argument("--no-fusion", action="store_true",
                     help="keep the explicit predictor and the r sweep as two kernels")
     ap.add_argument("--mode", choices=("batch", "grids"), default="batch",

@@ -364,7 +364,7 @@ hjm_status hjm_get_explicit_chunk(int32_t* J);
 hjm_status hjm_set_r_fusion(int32_t on);
 hjm_status hjm_get_r_fusion(int32_t* on);
 
-/* Stream lanes of batches created afterwards (1..8, default 2; HJM_EINVAL
+/* Stream lanes of batches created afterwards (1..8, default 3; HJM_EINVAL
    otherwise).  More lanes overlap more kernels at fewer solves per launch.
    Process-wide. */
 hjm_status hjm_set_batch_streams(int32_t n);

@@ -318,7 +318,7 @@ int yc_rows_for(int ny, int preferred)
 int g_exp_J = 8;      // v nodes per k_exp thread (4, 8 or 16)
 bool g_fuse_r = true;  // fuse the explicit predictor with the spike r solve where k_exr applies
 constexpr int kMaxBatchLanes = 8;
-int g_batch_lanes = 2;  // streams a batch spreads its solves over
+int g_batch_lanes = 3;  // streams a batch spreads its solves over
 bool g_batch_share = true;  // solves of one operator share tables and y pivots
 
 // k_rs needs nr = S * ROWS with S a power of two <= 64 lanes; the preferred

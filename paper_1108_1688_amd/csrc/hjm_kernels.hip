@@ -1376,13 +1376,38 @@ __device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* 
 // Stage the split-path r row table into LDS, one block per segment:
 // [seg][kRF * ROWS + 1] (the odd pitch spreads the segments of a wave over
 // the LDS banks).  The caller synchronises the workgroup before reading it.
-template <int ROWS>
+// MAXIT > 0 bounds the thread's share (kRF nr <= MAXIT kBlock): its loads
+// are then all issued before the first LDS write, one memory latency instead
+// of one per element.
+template <int ROWS, int MAXIT = 0>
 __device__ __forceinline__ void stage_rf(const SolveDesc& s, ldouble* tab)
 {
+    if constexpr (MAXIT > 0) {
+        constexpr int TP = kRF * ROWS + 1;
+        const int n = kRF * s.nr;
+        gcdouble* rf = gp(s.rf);
+        double x[MAXIT];
+#pragma unroll
+        for (int q = 0; q < MAXIT; ++q) {
+            const int idx = (int)threadIdx.x + q * kBlock;
+            x[q] = idx < n ? rf[idx] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < MAXIT; ++q) {
+            const int idx = (int)threadIdx.x + q * kBlock;
+            if (idx < n) {
+                const int c6 = idx / s.nr;
+                const int i = idx - c6 * s.nr;
+                const int sg = i / ROWS;
+                tab[sg * TP + c6 * ROWS + (i - sg * ROWS)] = x[q];
+            }
+        }
+        // a table longer than the bound (never for the callers' shapes) goes on below
+    }
     constexpr int TP = kRF * ROWS + 1;
     const int nr = s.nr;
     gcdouble* rf = gp(s.rf);
-    for (int idx = (int)threadIdx.x; idx < kRF * nr; idx += kBlock) {
+    for (int idx = (int)threadIdx.x + MAXIT * kBlock; idx < kRF * nr; idx += kBlock) {
         const int c6 = idx / nr;
         const int i = idx - c6 * nr;
         const int sg = i / ROWS;
@@ -1479,7 +1504,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
     ldouble* tile = lds;
     constexpr int TP = kRF * ROWS + 1;
     ldouble* tab = lds + s.exr_tab;  // after the tile, rounded up to whole passes
-    stage_rf<ROWS>(s, tab);
+    stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
     {
         // explicit phase: thread (i, plane kk); planes past ny do nothing
         const int kk = t / nr;
