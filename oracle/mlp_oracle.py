@@ -15,6 +15,14 @@ Modes:
            numpy's order, not the GPU's): its distance from emulate measures
            how much the accumulation order alone moves the BF16 roundings.
 
+Caplet baseline (control variate of the network's target): the Gaussian
+(Hull-White) caplet price, the zero-coupon bond put of the textbook model,
+with the rate volatility frozen at lambda f(0,T)^gamma times the root of the
+variance factor's mean path v(t) = 1 + (v0 - 1) e^{-theta_v t} (the mean of
+the paper's section 3.1 variance process).  Written from the model's
+definitions; pinned against the solver oracle's Gaussian closed form (gamma =
+0, v0 = 1) and against quadrature of the variance integral.
+
 The loss is the mean squared error in network units, L = mean((y - t)^2); the
 optimiser is Adam (Kingma and Ba, "Adam: a method for stochastic
 optimization", Algorithm 1), with bias-corrected first and second moments.
@@ -141,3 +149,46 @@ def adam_step(p, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
     return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def _ndtr(z):
+    return 0.5 * (1.0 + erf(z / np.sqrt(2.0)))
+
+
+def caplet_baseline(x, lam, gam, theta_v, decay, tenor):
+    """Gaussian caplet price of each row (kappa, eps, rho, v0, level, slope,
+    strike offset, expiry): the curve f(0,t) = level + slope (1 - e^{-decay t}),
+    payment one tenor after expiry, strike = at-the-money (simple
+    compounding over the tenor) + offset.  Returns float64 prices."""
+    x = np.asarray(x, dtype=np.float64)
+    kap, v0, a, b, dk, T = x[:, 0], x[:, 3], x[:, 4], x[:, 5], x[:, 6], x[:, 7]
+    TM = T + tenor
+
+    def int_f(t):  # integral of f(0, s) over [0, t]
+        return a * t + b * (t - (1.0 - np.exp(-decay * t)) / decay)
+
+    PT, PM = np.exp(-int_f(T)), np.exp(-int_f(TM))
+    K = (PT / PM - 1.0) / tenor + dk
+    D = 1.0 + tenor * K
+    G = np.where(kap > 0, -np.expm1(-kap * tenor) / np.where(kap > 0, kap, 1.0), tenor)
+    fT = a + b * (1.0 - np.exp(-decay * T))
+    # variance of ln P(T, T_M) at expiry: lam^2 fT^(2 gam) G^2 int_0^T vbar(t) e^{-2 kap (T - t)} dt
+    I1 = np.where(kap > 0, -np.expm1(-2.0 * kap * T) / np.where(kap > 0, 2.0 * kap, 1.0), T)
+    d = 2.0 * kap - theta_v
+    # (e^{-theta_v T} - e^{-2 kap T}) / d without the cancellation near d = 0
+    I2 = np.exp(-2.0 * kap * T) * np.where(d != 0, np.expm1(d * T) / np.where(d != 0, d, 1.0), T)
+    var = lam ** 2 * fT ** (2.0 * gam) * G ** 2 * (I1 + (v0 - 1.0) * I2)
+    s = np.sqrt(var)
+    h = np.log(D * PM / PT) / s + 0.5 * s
+    return PT * _ndtr(s - h) - D * PM * _ndtr(-h)
+
+
+def baseline_target(x, price, scale, shift, consts):
+    """Network target of a price with the baseline: (ln(price / B) - shift) / scale."""
+    B = caplet_baseline(x, *consts)
+    return (np.log(np.asarray(price, dtype=np.float64) / B) - shift) / scale
+
+
+def baseline_price(x, y, scale, shift, consts):
+    """Price from the network output y: B exp(y scale + shift)."""
+    return caplet_baseline(x, *consts) * np.exp(np.asarray(y, dtype=np.float64) * scale + shift)

@@ -112,3 +112,77 @@ def test_emulated_forward_is_close_to_exact():
     ye, _ = M.forward(p, x, lo, hi, emulate=True)
     yx, _ = M.forward(p, x, lo, hi, emulate=False)
     assert np.abs(ye - yx).max() < 0.05 * np.abs(yx).max()
+
+
+# ---------------------------------------------------------------------------
+# Caplet baseline (the control variate of the surrogate's target)
+# ---------------------------------------------------------------------------
+import oracle as O  # noqa: E402
+from scipy import integrate  # noqa: E402
+
+_CONSTS = (0.15, 0.9, 0.25, 0.5, 1.0)  # lambda, gamma, theta_v, curve decay, tenor
+
+
+def _gaussian_oracle(x_row, lam_eff, decay=0.5, tenor=1.0):
+    """The solver oracle's Gaussian caplet (its own curve, bond and accrual
+    code) at the row's strike, with rate volatility lam_eff (gamma = 0)."""
+    kap, _, _, _, a, b, dk, T = (float(t) for t in x_row)
+    ax = O.Axis(5, 0.0, 1.0, 0.5, 1.0)
+    p = O.Problem([ax, ax, ax], kappa=kap, theta_v=0.25, lam=lam_eff, gamma=0.0, epsilon=0.0, rho=0.0,
+                  f_level=a, f_slope=b, f_decay=decay, kind=O.CAPLET, expiry=T, pay=T + tenor)
+    katm = (O.discount(p, T) / O.discount(p, T + tenor) - 1.0) / tenor
+    p.strike = katm + dk
+    return O.gaussian_caplet(p)
+
+
+def test_baseline_gaussian_limit_is_the_closed_form():
+    """gamma = 0 and v0 = 1 leave the Gaussian model itself: the baseline must
+    be the oracle's textbook caplet (bond put) price."""
+    x = M.np.asarray(__import__("paper_1108_1688_amd.workloads", fromlist=["x"]).surrogate_params(12, 7))
+    x[:, 3] = 1.0
+    x[0, 0] = 0.0  # kappa = 0: G(s) = s, variance factor T
+    got = M.caplet_baseline(x, 0.01, 0.0, 0.25, 0.5, 1.0)
+    want = np.array([_gaussian_oracle(r, 0.01) for r in x])
+    assert np.all(want > 0)
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+@pytest.mark.parametrize("kappa", [0.05, 0.125, 0.125 + 1e-9, 0.19])
+def test_baseline_variance_by_quadrature(kappa):
+    """The frozen-volatility variance lam^2 f(0,T)^(2 gamma) G^2 times the
+    integral of the variance factor's mean path against e^{-2 kappa (T - t)},
+    the integral done by quadrature (kappa = theta_v / 2 is the removable
+    singularity of the closed form): with it as an effective Gaussian
+    volatility the oracle's closed form must give the same price."""
+    lam, gam, thv, dec, ten = _CONSTS
+    for v0, T, a, b, dk in ((0.6, 2.5, 0.02, 0.01, 0.004), (1.4, 0.7, 0.035, 0.0, -0.008), (1.0, 4.0, 0.01, 0.02, 0.0)):
+        x = np.array([[kappa, 0.3, 0.1, v0, a, b, dk, T]])
+        integral, _ = integrate.quad(lambda t: (1.0 + (v0 - 1.0) * math.exp(-thv * t)) * math.exp(-2 * kappa * (T - t)),
+                                     0.0, T, epsabs=0, epsrel=1e-13)
+        fT = a + b * (1.0 - math.exp(-dec * T))
+        var_factor = -math.expm1(-2 * kappa * T) / (2 * kappa)
+        lam_eff = lam * fT ** gam * math.sqrt(integral / var_factor)
+        got = M.caplet_baseline(x, *_CONSTS)[0]
+        np.testing.assert_allclose(got, _gaussian_oracle(x[0], lam_eff), rtol=1e-10)
+
+
+def test_baseline_bounds_and_strike_order():
+    """Between intrinsic value and the expiry bond, decreasing in the strike."""
+    x = np.repeat(np.array([[0.1, 0.3, 0.0, 1.0, 0.02, 0.01, 0.0, 2.0]]), 9, axis=0)
+    x[:, 6] = np.linspace(-0.01, 0.01, 9)
+    B = M.caplet_baseline(x, *_CONSTS)
+    assert np.all(np.diff(B) < 0)
+    ax = O.Axis(5, 0.0, 1.0, 0.5, 1.0)
+    p = O.Problem([ax, ax, ax], kappa=0.1, theta_v=0.25, lam=0.15, gamma=0.9, epsilon=0.3, rho=0.0,
+                  f_level=0.02, f_slope=0.01, f_decay=0.5)
+    PT, PM = O.discount(p, 2.0), O.discount(p, 3.0)
+    K = (PT / PM - 1.0) + x[:, 6]
+    assert np.all(B >= np.maximum(PT - (1.0 + K) * PM, 0.0))
+    assert np.all(B < PT)
+
+
+def test_baseline_target_round_trip():
+    x = np.random.default_rng(3).random((7, 8)) * 0.0 + np.array([0.1, 0.3, 0.0, 1.0, 0.02, 0.01, 0.001, 1.5])
+    price = np.linspace(1e-4, 5e-3, 7)
+    t = M.baseline_target(x, price, 0.1, 0.0, _CONSTS)
+    np.testing.assert_allclose(M.baseline_price(x, t, 0.1, 0.0, _CONSTS), price, rtol=1e-13)
