@@ -349,6 +349,32 @@ hjm_status hjm_mlp_train_epoch(hjm_mlp* m, const float* d_x, const float* d_t, i
    the solver; d_in_box may be null).  Asynchronous. */
 hjm_status hjm_mlp_infer(hjm_mlp* m, const float* d_x, int64_t n, float* d_y, uint8_t* d_in_box);
 
+/* Gaussian caplet baseline: a control variate for the output.  Set, the
+   network's output y stands for ln(price / B(x)): hjm_mlp_infer reports
+   B(x) exp(y * out_scale + out_shift) instead of the affine map, and
+   hjm_mlp_targets forms (ln(price / B(x)) - out_shift) / out_scale.  B is the
+   caplet of the Gaussian special case of the model (section 3.1 with
+   gamma = 0, no stochastic variance: the textbook bond put), with the rate
+   volatility frozen at lambda f(0,T)^gamma times the root of the variance
+   factor's mean path 1 + (v0 - 1) e^{-theta_v t}; the row's curve is
+   f(0,t) = level + slope (1 - e^{-f_decay t}) (section 2), payment one tenor
+   after expiry, strike = at-the-money strike (simple compounding over the
+   tenor, as the accrual of section 3.2) + the row's offset.  Computed in
+   FP64 on the device.  Null b switches the baseline off (the default).
+   HJM_EINVAL unless lambda > 0, gamma in [0, 1], theta_v >= 0, f_decay > 0,
+   tenor > 0, all finite.  The output of rows outside the box is unspecified
+   (may be NaN where the baseline is undefined there). */
+typedef struct { double lambda, gamma, theta_v, f_decay, tenor; } hjm_mlp_baseline;
+hjm_status hjm_mlp_set_baseline(hjm_mlp* m, const hjm_mlp_baseline* b);
+
+/* Training targets in network units of n rows (0 <= n <= 2^31): d_t[r] =
+   (ln(d_price[r] / B(d_x[r])) - out_shift) / out_scale with the baseline,
+   (d_price[r] - out_shift) / out_scale without.  d_x n x 8 float32, d_price
+   n float64, d_t n float32, all device memory owned by the caller.  A price
+   <= 0 with the baseline gives NaN (drop such rows before training).
+   Asynchronous on the handle's stream. */
+hjm_status hjm_mlp_targets(hjm_mlp* m, const float* d_x, const double* d_price, int64_t n, float* d_t);
+
 hjm_status hjm_mlp_destroy(hjm_mlp* m);
 
 /* Nodes along v that one thread of the explicit-predictor kernel computes

@@ -52,6 +52,41 @@ __device__ __forceinline__ float gelu_d(float z)
     return Phi + z * phi;
 }
 
+// Gaussian caplet baseline (optional control variate of the output): with it
+// the network learns ln(price / B(x)) and reports B(x) exp(y scale + shift).
+// B is the textbook Gaussian (Hull-White) caplet, the zero-coupon bond put,
+// with the rate volatility frozen at lambda f(0,T)^gamma on the mean path
+// 1 + (v0 - 1) e^{-theta_v t} of the variance factor; the row's curve is
+// f(0,t) = level + slope (1 - e^{-decay t}), payment one tenor after expiry,
+// strike = at-the-money (simple compounding) + offset.  FP64 throughout.
+struct BaseK {
+    double lam, two_gam, theta_v, decay, tenor;
+    int on;
+};
+
+__device__ __forceinline__ double ncdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
+
+__device__ double caplet_baseline(const float* __restrict__ xr, const BaseK& b)
+{
+    const double kap = xr[0], v0 = xr[3], a = xr[4], sl = xr[5], dk = xr[6], T = xr[7];
+    const double c = b.decay, tau = b.tenor;
+    // integral of f(0, .) over [0, t]
+    const double iT = a * T + sl * (T + expm1(-c * T) / c);
+    const double iM = a * (T + tau) + sl * ((T + tau) + expm1(-c * (T + tau)) / c);
+    const double PT = exp(-iT), PM = exp(-iM);
+    const double D = 1.0 + tau * ((PT / PM - 1.0) / tau + dk);  // 1 + tau K
+    const double G = kap > 0.0 ? -expm1(-kap * tau) / kap : tau;
+    const double fT = a - sl * expm1(-c * T);
+    // integral over [0, T] of the mean variance path against e^{-2 kappa (T - t)}
+    const double I1 = kap > 0.0 ? -expm1(-2.0 * kap * T) / (2.0 * kap) : T;
+    const double d = 2.0 * kap - b.theta_v;
+    const double I2 = exp(-2.0 * kap * T) * (d != 0.0 ? expm1(d * T) / d : T);
+    const double var = b.lam * b.lam * pow(fT, b.two_gam) * G * G * (I1 + (v0 - 1.0) * I2);
+    const double sd = sqrt(var);
+    const double h = log(D * PM / PT) / sd + 0.5 * sd;
+    return PT * ncdf(sd - h) - D * PM * ncdf(-h);
+}
+
 __device__ __forceinline__ bf8 load8(const bf16_t* p)
 {
     // 16-byte aligned load of 8 BF16 values
@@ -139,7 +174,7 @@ __global__ __launch_bounds__(256) void k_fwd(const bf16_t* __restrict__ hin, con
 // map to price units.  One thread per sample.
 __global__ __launch_bounds__(256) void k_out(const bf16_t* __restrict__ h4, const bf16_t* __restrict__ w5,
                                              const float* __restrict__ b5, int64_t n, float scale, float shift,
-                                             float* __restrict__ y)
+                                             const float* __restrict__ x, BaseK base, float* __restrict__ y)
 {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
@@ -150,7 +185,27 @@ __global__ __launch_bounds__(256) void k_out(const bf16_t* __restrict__ h4, cons
 #pragma unroll
         for (int e = 0; e < 8; ++e) acc += (float)hv[e] * (float)wv[e];
     }
-    y[s] = (acc + b5[0]) * scale + shift;
+    if (base.on)
+        y[s] = (float)(caplet_baseline(x + s * kIn, base) * exp((double)(acc + b5[0]) * scale + shift));
+    else
+        y[s] = (acc + b5[0]) * scale + shift;
+}
+
+// Training targets in network units: (ln(price / B(x)) - shift) / scale with
+// the baseline, (price - shift) / scale without.  One thread per row.
+__global__ __launch_bounds__(256) void k_targets(const float* __restrict__ x, const double* __restrict__ price,
+                                                 int64_t n, float scale, float shift, BaseK base,
+                                                 float* __restrict__ t)
+{
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const double p = price[s];
+    if (base.on && !(p > 0.0)) {
+        t[s] = __builtin_nanf("");  // no logarithm: the row must be dropped
+        return;
+    }
+    const double y = base.on ? log(p / caplet_baseline(x + s * kIn, base)) : p;
+    t[s] = (float)((y - (double)shift) / (double)scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,6 +445,7 @@ struct hjm_mlp {
     int64_t max_batch = 0;
     float lo[kIn], hi[kIn];
     float scale = 1.0f, shift = 0.0f;
+    BaseK base{};  // off until hjm_mlp_set_baseline
     int64_t adam_t = 0;
     // device pointers (all inside the caller's workspace)
     float *p, *m, *v, *g, *box;
@@ -501,7 +557,9 @@ hjm_status gradients(hjm_mlp* h, const float* x, const float* t, int64_t n, doub
     hipStream_t st = h->stream;
     hipError_t e = forward(h, x, n, nullptr, true);
     if (e) return mhip(e, "mlp forward");
-    hipLaunchKernelGGL(k_out, dim3(blocks256(n)), dim3(256), 0, st, h->h4, h->w5, h->p + kOffB5, n, 1.0f, 0.0f, h->y);
+    // network units (the loss compares them with targets in the same units)
+    hipLaunchKernelGGL(k_out, dim3(blocks256(n)), dim3(256), 0, st, h->h4, h->w5, h->p + kOffB5, n, 1.0f, 0.0f,
+                       x, BaseK{}, h->y);
     hipLaunchKernelGGL(k_loss, dim3(blocks256(n)), dim3(256), 0, st, h->y, t, n, h->dy, h->lpart);
     const int64_t nb256 = (n + 255) / 256;
     hipLaunchKernelGGL(k_out_bwd, dim3((unsigned)nb256), dim3(256), 0, st, h->dy, h->h4, h->z4, h->w5, n, h->dz4,
@@ -687,11 +745,40 @@ hjm_status hjm_mlp_infer(hjm_mlp* h, const float* d_x, int64_t n, float* d_y, ui
         hipError_t e = forward(h, d_x + s0 * kIn, nb, d_in_box ? d_in_box + s0 : nullptr, false);
         if (!e) {
             hipLaunchKernelGGL(k_out, dim3(blocks256(nb)), dim3(256), 0, h->stream, h->h4, h->w5, h->p + kOffB5, nb,
-                               h->scale, h->shift, d_y + s0);
+                               h->scale, h->shift, d_x + s0 * kIn, h->base, d_y + s0);
             e = hipGetLastError();
         }
         if (e) return mhip(e, "hjm_mlp_infer");
     }
+    return HJM_OK;
+}
+
+hjm_status hjm_mlp_set_baseline(hjm_mlp* h, const hjm_mlp_baseline* b)
+{
+    if (!h) return mfail(HJM_EINVAL, "null handle");
+    if (!b) {
+        h->base = BaseK{};
+        return HJM_OK;
+    }
+    if (!(std::isfinite(b->lambda) && std::isfinite(b->gamma) && std::isfinite(b->theta_v) &&
+          std::isfinite(b->f_decay) && std::isfinite(b->tenor)))
+        return mfail(HJM_EINVAL, "baseline constants must be finite");
+    if (!(b->lambda > 0.0 && b->gamma >= 0.0 && b->gamma <= 1.0 && b->theta_v >= 0.0 && b->f_decay > 0.0 &&
+          b->tenor > 0.0))
+        return mfail(HJM_EINVAL, "baseline: need lambda > 0, gamma in [0, 1], theta_v >= 0, f_decay > 0, tenor > 0");
+    h->base = BaseK{b->lambda, 2.0 * b->gamma, b->theta_v, b->f_decay, b->tenor, 1};
+    return HJM_OK;
+}
+
+hjm_status hjm_mlp_targets(hjm_mlp* h, const float* d_x, const double* d_price, int64_t n, float* d_t)
+{
+    if (!h || !d_x || !d_price || !d_t) return mfail(HJM_EINVAL, "null argument");
+    if (n < 0 || n > ((int64_t)1 << 31)) return mfail(HJM_EINVAL, "n outside [0, 2^31]");
+    if (n == 0) return HJM_OK;
+    hipLaunchKernelGGL(k_targets, dim3(blocks256(n)), dim3(256), 0, h->stream, d_x, d_price, n, h->scale, h->shift,
+                       h->base, d_t);
+    hipError_t e = hipGetLastError();
+    if (e) return mhip(e, "hjm_mlp_targets");
     return HJM_OK;
 }
 

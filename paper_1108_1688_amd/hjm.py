@@ -50,6 +50,11 @@ class Payoff(C.Structure):
                 ("strike", C.c_double)]
 
 
+class MlpBaseline(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("gamma", C.c_double), ("theta_v", C.c_double), ("f_decay", C.c_double),
+                ("tenor", C.c_double)]
+
+
 class Scheme(C.Structure):
     _fields_ = [("kind", C.c_int32), ("af_iters", C.c_int32), ("theta", C.c_double)]
 
@@ -109,6 +114,8 @@ def lib():
         "hjm_mlp_adam": (st, [vp, C.c_float, C.c_float, C.c_float, C.c_float]),
         "hjm_mlp_train_epoch": (st, [vp, vp, vp, i64, i64, C.c_float, P(d)]),
         "hjm_mlp_infer": (st, [vp, vp, i64, vp, vp]),
+        "hjm_mlp_set_baseline": (st, [vp, vp]),
+        "hjm_mlp_targets": (st, [vp, vp, vp, i64, vp]),
         "hjm_mlp_destroy": (st, [vp]),
         "hjm_status_str": (C.c_char_p, [st]),
         "hjm_last_error": (C.c_char_p, []),
@@ -456,6 +463,7 @@ class Mlp:
                                self.out_shift, self.max_batch, C.c_void_p(self.ws.data_ptr()), nbytes.value,
                                _stream_handle(self.stream), C.byref(h)))
         self._h = h
+        self.baseline = None
 
     @staticmethod
     def _f32(a: np.ndarray):
@@ -499,6 +507,30 @@ class Mlp:
         check(lib().hjm_mlp_train_epoch(self._h, self._dev(x, 8), self._dev(t), x.shape[0], batch, lr,
                                         C.byref(loss)))
         return loss.value
+
+    def set_baseline(self, lam: float, gamma: float, theta_v: float, f_decay: float, tenor: float) -> None:
+        """Gaussian caplet baseline of the output (hjm_mlp_set_baseline)."""
+        b = MlpBaseline(lam, gamma, theta_v, f_decay, tenor)
+        check(lib().hjm_mlp_set_baseline(self._h, C.byref(b)))
+        self.baseline = (lam, gamma, theta_v, f_decay, tenor)
+
+    def clear_baseline(self) -> None:
+        check(lib().hjm_mlp_set_baseline(self._h, None))
+        self.baseline = None
+
+    def targets(self, x, price):
+        """Training targets (float32 device tensor) of prices (float64 device
+        tensor) at rows x, in network units (hjm_mlp_targets)."""
+        torch = _torch()
+        if price.dtype != torch.float64 or not price.is_cuda or not price.is_contiguous() or price.dim() != 1:
+            raise ValueError("expected a contiguous 1-D float64 CUDA tensor of prices")
+        n = x.shape[0]
+        if price.shape[0] != n:
+            raise ValueError("one price per row")
+        t = torch.empty(n, dtype=torch.float32, device=x.device)
+        check(lib().hjm_mlp_targets(self._h, self._dev(x, 8), C.c_void_p(price.data_ptr()), n,
+                                    C.c_void_p(t.data_ptr())))
+        return t
 
     def infer(self, x):
         """(prices, in_box) device tensors for the rows of x."""

@@ -10,7 +10,11 @@ arguments):
 
 Inputs per row: kappa, epsilon, rho, v0, curve level, curve slope, strike
 offset from the at-the-money strike, expiry (the caplet pays one year after
-expiry); the network predicts price / OUT_SCALE.
+expiry).  The network predicts ln(price / B) / OUT_SCALE, B the Gaussian
+caplet baseline of the library (a control variate computed on the device:
+the textbook Gaussian caplet at a frozen effective volatility), so that the
+squared-error loss weighs relative errors; make_mlp(baseline=False) gives
+the plain network that predicts price / PLAIN_SCALE.
 """
 from __future__ import annotations
 
@@ -24,7 +28,13 @@ import numpy as np
 from . import hjm
 from . import workloads as W
 
-OUT_SCALE = 1e-3  # network units: prices in units of 1e-3
+OUT_SCALE = 0.1     # network units with the baseline: 10 ln(price / B)
+PLAIN_SCALE = 1e-3  # network units without it: prices in units of 1e-3
+# the baseline's model constants: lambda, gamma, theta_v (section 3.3 values of
+# the solves), curve decay and tenor of the training rows
+BASELINE = (W.LAMBDA, W.GAMMA, W.THETA_V, W.SURROGATE_F_DECAY, W.SURROGATE_TENOR)
+FIT_PRICE_FLOOR = 1e-7  # rows priced below this are left out of the training (log target)
+SOFTEN = 0          # terminal data of the solves the network learns from and is judged against
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -42,7 +52,8 @@ def init_params(seed: int) -> np.ndarray:
     return p
 
 
-def training_set(n_solves: int, seed: int, n: int = W.SURROGATE_N, chunk: int = 256, stream=None):
+def training_set(n_solves: int, seed: int, n: int = W.SURROGATE_N, chunk: int = 256, stream=None,
+                 soften: int = SOFTEN):
     """Inputs (n_solves * 16, 8) float32 and ADI prices (float64): every solve
     is read out at the 16 values of W.SURROGATE_V0."""
     params = W.surrogate_params(n_solves, seed)
@@ -50,7 +61,7 @@ def training_set(n_solves: int, seed: int, n: int = W.SURROGATE_N, chunk: int = 
     v0s = np.array(W.SURROGATE_V0)
     for c0 in range(0, n_solves, chunk):
         rows = params[c0:c0 + chunk]
-        specs = [W.surrogate_solve(x, n) for x in rows]
+        specs = [W.surrogate_solve(x, n, soften) for x in rows]
         b = hjm.Batch(specs, stream=stream)
         b.run()
         r0 = np.array([s.r0 for s in specs])
@@ -64,12 +75,13 @@ def training_set(n_solves: int, seed: int, n: int = W.SURROGATE_N, chunk: int = 
     return np.concatenate(xs).astype(np.float32), np.concatenate(ps)
 
 
-def adi_prices(x: np.ndarray, n: int = W.SURROGATE_N, chunk: int = 256, stream=None) -> np.ndarray:
+def adi_prices(x: np.ndarray, n: int = W.SURROGATE_N, chunk: int = 256, stream=None,
+               soften: int = SOFTEN) -> np.ndarray:
     """Reference prices of arbitrary rows by the ADI solver (one solve per row)."""
     out = np.empty(len(x))
     for c0 in range(0, len(x), chunk):
         rows = x[c0:c0 + chunk]
-        specs = [W.surrogate_solve(r, n) for r in rows]
+        specs = [W.surrogate_solve(r, n, soften) for r in rows]
         b = hjm.Batch(specs, stream=stream)
         b.run()
         out[c0:c0 + chunk] = b.prices()
@@ -77,8 +89,12 @@ def adi_prices(x: np.ndarray, n: int = W.SURROGATE_N, chunk: int = 256, stream=N
     return out
 
 
-def make_mlp(max_batch: int = 65536, stream=None) -> hjm.Mlp:
-    return hjm.Mlp(W.SURROGATE_BOX_LO, W.SURROGATE_BOX_HI, OUT_SCALE, 0.0, max_batch=max_batch, stream=stream)
+def make_mlp(max_batch: int = 65536, stream=None, baseline: bool = True) -> hjm.Mlp:
+    if not baseline:
+        return hjm.Mlp(W.SURROGATE_BOX_LO, W.SURROGATE_BOX_HI, PLAIN_SCALE, 0.0, max_batch=max_batch, stream=stream)
+    m = hjm.Mlp(W.SURROGATE_BOX_LO, W.SURROGATE_BOX_HI, OUT_SCALE, 0.0, max_batch=max_batch, stream=stream)
+    m.set_baseline(*BASELINE)
+    return m
 
 
 @dataclass
@@ -89,13 +105,19 @@ class FitResult:
 
 def fit(mlp: hjm.Mlp, x: np.ndarray, prices: np.ndarray, epochs: int, batch: int = 1024, lr: float = 1e-3,
         lr_final: Optional[float] = None, seed: int = 0) -> FitResult:
-    """Train on (x, prices): per epoch the rows are shuffled (seeded) on the
-    host and one GPU pass over minibatches runs; the learning rate decays
+    """Train on (x, prices): the targets come from the library
+    (hjm_mlp_targets; with the baseline, rows priced at or below
+    FIT_PRICE_FLOOR are left out); per epoch the rows are shuffled (seeded) on
+    the host and one GPU pass over minibatches runs; the learning rate decays
     geometrically from lr to lr_final."""
     import torch
     dev = mlp.device
+    if mlp.baseline is not None:
+        keep = np.asarray(prices) > FIT_PRICE_FLOOR
+        x, prices = np.asarray(x)[keep], np.asarray(prices)[keep]
     xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
-    td = torch.from_numpy((prices / OUT_SCALE).astype(np.float32)).to(dev)
+    pd = torch.from_numpy(np.ascontiguousarray(prices, dtype=np.float64)).to(dev)
+    td = mlp.targets(xd, pd)
     rng = np.random.default_rng(seed)
     losses = []
     t0 = time.perf_counter()
@@ -116,7 +138,7 @@ class Priced:
     n_fallback: int
 
 
-def price(mlp: hjm.Mlp, x: np.ndarray, n: int = W.SURROGATE_N, stream=None) -> Priced:
+def price(mlp: hjm.Mlp, x: np.ndarray, n: int = W.SURROGATE_N, stream=None, soften: int = SOFTEN) -> Priced:
     """Surrogate prices inside the training box, ADI prices outside it."""
     import torch
     xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(mlp.device)
@@ -125,5 +147,5 @@ def price(mlp: hjm.Mlp, x: np.ndarray, n: int = W.SURROGATE_N, stream=None) -> P
     inside = inb.cpu().numpy().astype(bool)
     outside = np.nonzero(~inside)[0]
     if len(outside):
-        out[outside] = adi_prices(x[outside].astype(np.float64), n=n, stream=stream)
+        out[outside] = adi_prices(x[outside].astype(np.float64), n=n, stream=stream, soften=soften)
     return Priced(out, inside, len(outside))

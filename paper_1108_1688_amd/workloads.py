@@ -226,16 +226,19 @@ SURROGATE_BOX_LO = np.array([0.01, 0.1, -0.8, 0.5, 0.01, 0.0, -0.01, 0.5])
 SURROGATE_BOX_HI = np.array([0.2, 0.6, 0.8, 1.5, 0.04, 0.02, 0.01, 5.0])
 SURROGATE_DT = 0.025
 SURROGATE_N = 64
+SURROGATE_F_DECAY = 0.5   # f(0,t) = level + slope (1 - exp(-SURROGATE_F_DECAY t))
+SURROGATE_TENOR = 1.0     # the caplet pays one tenor after expiry
 SURROGATE_V0 = tuple(0.5 + (1.5 - 0.5) * (q + 0.5) / 16.0 for q in range(16))
 
 
-def surrogate_solve(x: np.ndarray, n: int = SURROGATE_N) -> SolveSpec:
-    """One caplet solve from a surrogate input row (v0 is read out, not solved for)."""
+def surrogate_solve(x: np.ndarray, n: int = SURROGATE_N, soften: int = 0) -> SolveSpec:
+    """One caplet solve from a surrogate input row (v0 is read out, not solved for);
+    soften selects the terminal data (0 pointwise, 1 or 2 control-element averages)."""
     kappa, eps, rho, v0, lvl, slope, dk, T = (float(t) for t in x)
-    m = ModelSpec(kappa=kappa, epsilon=eps, rho=rho, f_level=lvl, f_slope=slope, f_decay=0.5)
-    k = atm_strike(m, T, T + 1.0) + dk
+    m = ModelSpec(kappa=kappa, epsilon=eps, rho=rho, f_level=lvl, f_slope=slope, f_decay=SURROGATE_F_DECAY)
+    k = atm_strike(m, T, T + SURROGATE_TENOR) + dk
     N = max(1, int(round(T / SURROGATE_DT)))
-    return SolveSpec(default_axes(n, n, n, k), m, PayoffSpec(CAPLET, T, T + 1.0, k), N, lvl, v0)
+    return SolveSpec(default_axes(n, n, n, k), m, PayoffSpec(CAPLET, T, T + SURROGATE_TENOR, k, soften), N, lvl, v0)
 
 
 def surrogate_params(n_solves: int, seed: int) -> np.ndarray:

@@ -61,16 +61,16 @@ def _dev(a):
 def test_forward_and_box_flags_match_oracle():
     p = _params(1)
     x = _rows(300, 2, outside=40)  # 300: a ragged tail of the 64-row tiles
-    m = S.make_mlp(max_batch=128)   # several passes of max_batch rows
+    m = S.make_mlp(max_batch=128, baseline=False)   # several passes of max_batch rows
     m.set_params(p)
     y, inb = m.infer(_dev(x))
     y = y.cpu().numpy().astype(np.float64)
     yo, c = M.forward(p.astype(np.float64), x, LO, HI, emulate=True)
-    yo = yo * S.OUT_SCALE
+    yo = yo * S.PLAIN_SCALE
     assert np.array_equal(inb.cpu().numpy().astype(bool), c["inside"])
     assert c["inside"].sum() == 260
     y32, _ = M.forward(p.astype(np.float64), x, LO, HI, emulate="emulate32")
-    y32 = y32 * S.OUT_SCALE
+    y32 = y32 * S.PLAIN_SCALE
     scale = np.abs(yo).mean()
     err = np.abs(y - yo) / scale
     ref = np.abs(y32 - yo) / scale
@@ -78,6 +78,48 @@ def test_forward_and_box_flags_match_oracle():
           f"oracle fp32-vs-fp64 sums: max {ref.max():.2e} rms {np.sqrt(np.mean(ref**2)):.2e}")
     assert err.max() <= 3 * ref.max() + 1e-5
     assert np.sqrt(np.mean(err ** 2)) <= 3 * np.sqrt(np.mean(ref ** 2)) + 1e-5
+
+
+def test_baseline_output_and_targets_match_oracle():
+    """With the Gaussian caplet baseline: the reported price is B exp(0.1 y)
+    with y the network (same bar as the plain forward, on the recovered y),
+    and the targets are 10 ln(price / B), both against the oracle's own
+    baseline; a non-positive price gives NaN; invalid constants are refused."""
+    p = _params(1)
+    x = _rows(300, 2)
+    x64 = x.astype(np.float64)
+    m = S.make_mlp(max_batch=128)
+    m.set_params(p)
+    y, inb = m.infer(_dev(x))
+    assert inb.cpu().numpy().all()
+    y = y.cpu().numpy().astype(np.float64)
+    yo, _ = M.forward(p.astype(np.float64), x, LO, HI, emulate=True)
+    y32, _ = M.forward(p.astype(np.float64), x, LO, HI, emulate="emulate32")
+    B = M.caplet_baseline(x64, *S.BASELINE)
+    assert np.all(B > 0) and np.all(np.isfinite(y)) and np.all(y > 0)
+    yb = np.log(y / B) / S.OUT_SCALE  # the GPU's network output, recovered
+    scale = np.abs(yo).mean()
+    err = np.abs(yb - yo) / scale
+    ref = np.abs(y32 - yo) / scale
+    print(f"baseline forward err / mean |y|: max {err.max():.2e}; oracle fp32-vs-fp64 sums: max {ref.max():.2e}")
+    # the price is stored as float32: 6e-8 relative, 6e-7 in network units
+    assert err.max() <= 3 * ref.max() + 1e-5 + 1e-6 / scale
+    price = B * np.exp(np.random.default_rng(9).uniform(-1.0, 2.0, len(x)))
+    price[:3] = (0.0, -1e-6, 1.0)
+    t = m.targets(_dev(x), torch.from_numpy(price).cuda()).cpu().numpy().astype(np.float64)
+    to = M.baseline_target(x64[3:], price[3:], S.OUT_SCALE, 0.0, S.BASELINE)
+    assert np.isnan(t[0]) and np.isnan(t[1])
+    np.testing.assert_allclose(t[3:], to, rtol=1e-6, atol=1e-5)
+    np.testing.assert_allclose(np.exp(-S.OUT_SCALE * t[2]), B[2], rtol=1e-6)
+    with pytest.raises(hjm.HjmError):
+        m.set_baseline(0.15, 1.5, 0.25, 0.5, 1.0)
+    with pytest.raises(hjm.HjmError):
+        m.set_baseline(0.15, 0.9, 0.25, 0.0, 1.0)
+    # without the baseline the targets are the scaled prices
+    m.clear_baseline()
+    t = m.targets(_dev(x[3:]), torch.from_numpy(price[3:]).cuda()).cpu().numpy()
+    np.testing.assert_allclose(t, (price[3:] / S.OUT_SCALE).astype(np.float32), rtol=1e-6)
+    m.close()
 
 
 def test_gradients_and_loss_match_oracle():
