@@ -303,6 +303,9 @@ def multi_rhs_leg(hjm, W, torch, stream, reps: int = 5):
     return out
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
+
+
 def _rel_errors(pred, ref):
     err = np.abs(pred - ref)
     big = ref > 1e-4
@@ -310,6 +313,33 @@ def _rel_errors(pred, ref):
     return {"rows": int(len(ref)), "rms_abs": float(np.sqrt(np.mean(err ** 2))),
             "median_rel": float(np.median(rel)), "p95_rel": float(np.percentile(rel, 95)),
             "max_rel": float(rel.max()), "rel_rows": "prices above 1e-4"}
+
+
+def surrogate_mfma(torch, S, m, x_in, reps: int = 20):
+    """The network's matrix-core figures: in-box inference alone (no solver
+    fallback) timed with HIP events on the network's stream, and the
+    training epochs' rate; algorithmic FLOPs 2 (8*256 + 3*256*256 + 256) per
+    row forward (the first layer's zero padding to 32 inputs not counted),
+    three times that per row trained (forward, input and weight gradients)."""
+    xd = torch.from_numpy(np.ascontiguousarray(x_in, dtype=np.float32)).to(m.device)
+    n = xd.shape[0]
+    m.infer(xd)
+    torch.cuda.synchronize(m.device)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(m.stream):
+        e0.record()
+        for _ in range(reps):
+            m.infer(xd)
+        e1.record()
+    torch.cuda.synchronize(m.device)
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    fwd = 2.0 * (8 * 256 + 3 * 256 * 256 + 256)
+    tflops = fwd * n / (us * 1e-6) / 1e12
+    return {"infer_rows": n, "infer_us": round(us, 2), "flop_per_row_forward": fwd,
+            "infer_TFLOPs": round(tflops, 2), "peak_TFLOPs": MFMA_BF16_PEAK_TFLOPS,
+            "infer_frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4),
+            "note": "BF16 MFMA with FP32 accumulation; dense peak"}
 
 
 def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int, outside_frac: float):
@@ -338,6 +368,7 @@ def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int,
     t0 = time.perf_counter()
     pr = S.price(m, xq)
     el = time.perf_counter() - t0
+    mfma = surrogate_mfma(torch, S, m, xq[n_out:])
     # error against ADI on in-box rows (validation solves read out at v0)
     nv = 512
     xv = xq[n_out:n_out + nv].astype(np.float64)
@@ -355,7 +386,10 @@ def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int,
             "final_train_mse_net_units": fitres.losses[-1],
             "query_rows": n_query, "fallback_rows": pr.n_fallback,
             "solves_per_s": n_query / el,
+            "mfma": mfma,
             "error_vs_adi": _rel_errors(pr.prices[n_out:n_out + nv], ref),
+            "train_TFLOPs": round(3 * 2.0 * (8 * 256 + 3 * 256 * 256 + 256) * len(x) * epochs
+                                  / fitres.seconds / 1e12, 3),
             "plain_price_target_error_vs_adi": _rel_errors(plain, ref),
             "plain_price_target_train_s": round(fitp.seconds, 2),
             "adi_64_error_vs_adi_128": _rel_errors(ref, ref128)}

@@ -93,6 +93,12 @@ __device__ __forceinline__ bf8 load8(const bf16_t* p)
     return *reinterpret_cast<const bf8*>(p);
 }
 
+// one input mapped to [-1, 1] over its box side, rounded to BF16
+__device__ __forceinline__ bf16_t norm_in(float v, float lo, float hi)
+{
+    return f2bf(2.0f * (v - lo) / (hi - lo) - 1.0f);
+}
+
 // ---------------------------------------------------------------------------
 // Input: normalise to [-1, 1] over the box, flag rows outside it, pad to 32.
 // ---------------------------------------------------------------------------
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(256) void k_input(const float* __restrict__ x, int6
     for (int c = 0; c < kIn; ++c) {
         const float v = x[s * kIn + c];
         inside = inside && v >= lo[c] && v <= hi[c];
-        row[c] = f2bf(2.0f * (v - lo[c]) / (hi[c] - lo[c]) - 1.0f);
+        row[c] = norm_in(v, lo[c], hi[c]);
     }
     for (int c = 0; c < KIN; ++c) xp[s * KIN + c] = row[c];
     if (in_box) in_box[s] = inside ? 1 : 0;
@@ -206,6 +212,124 @@ __global__ __launch_bounds__(256) void k_targets(const float* __restrict__ x, co
     }
     const double y = base.on ? log(p / caplet_baseline(x + s * kIn, base)) : p;
     t[s] = (float)((y - (double)shift) / (double)scale);
+}
+
+// ---------------------------------------------------------------------------
+// Inference in one kernel.  A workgroup takes 64 rows through the input map,
+// the four hidden layers and the output layer; the rows' activations stay in
+// LDS (BF16, 64 x 256, rows padded by 16 bytes so that the fragment reads of
+// a wave spread over the banks), so HBM sees only the inputs, the weights
+// (from L2 after the first workgroups) and the prices.  Each layer is the
+// k_fwd tiling (wave w: features [64 w, 64 w + 64) of all 64 rows, 4 x 4 MFMA
+// tiles, k in steps of 32) with its A operand read from LDS, then bias, GELU
+// and BF16 rounding as k_fwd; the output is k_out's sum.  Same operations in
+// the same order as k_input, k_fwd and k_out: the same results.
+// ---------------------------------------------------------------------------
+constexpr int kXP = KIN + 8;  // LDS row pitch of the input tile (BF16 values)
+constexpr int kHP = H + 8;    // LDS row pitch of the activation tile
+
+// acc = A W^T over K for the wave's 64 features; A is the LDS tile (pitch ap)
+template <int K>
+__device__ __forceinline__ void tile_layer(const bf16_t* __restrict__ a_lds, int ap, const bf16_t* __restrict__ w,
+                                           int f0, int r, int kq, f4 (&acc)[4][4])
+{
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf8 av[4], bv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = load8(w + (int64_t)(f0 + c * 16 + r) * K + k0 + kq);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = *reinterpret_cast<const bf8*>(a_lds + (a * 16 + r) * ap + k0 + kq);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[c], acc[a][c], 0, 0, 0);
+    }
+}
+
+// H tile = BF16(GELU(acc + b)) for the wave's features
+__device__ __forceinline__ void tile_gelu(bf16_t* __restrict__ h_lds, const float* __restrict__ b, int f0, int r,
+                                          int lane, const f4 (&acc)[4][4])
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int f = f0 + c * 16 + r;
+        const float bias = b[f];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = a * 16 + (lane >> 4) * 4 + v;
+                h_lds[row * kHP + f] = f2bf(gelu(acc[a][c][v] + bias));
+            }
+    }
+}
+
+__global__ __launch_bounds__(256, 4) void k_infer(const float* __restrict__ x, int64_t n, const float* __restrict__ box,
+                                               const bf16_t* __restrict__ w1, const bf16_t* __restrict__ w2,
+                                               const bf16_t* __restrict__ w3, const bf16_t* __restrict__ w4,
+                                               const bf16_t* __restrict__ w5, const float* __restrict__ p,
+                                               float scale, float shift, BaseK base, float* __restrict__ y,
+                                               uint8_t* __restrict__ in_box)
+{
+    __shared__ __attribute__((aligned(16))) bf16_t xs[64 * kXP];
+    __shared__ __attribute__((aligned(16))) bf16_t hs[64 * kHP];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int64_t s0 = (int64_t)blockIdx.x * 64;
+    if (t < 64) {
+        // row s0 + t; tail rows repeat the last sample (never stored)
+        const bool live = s0 + t < n;
+        const int64_t s = live ? s0 + t : n - 1;
+        bool inside = true;
+#pragma unroll
+        for (int c = 0; c < KIN; ++c) {
+            bf16_t q = 0;
+            if (c < kIn) {
+                const float v = x[s * kIn + c];
+                inside = inside && v >= box[c] && v <= box[kIn + c];
+                q = norm_in(v, box[c], box[kIn + c]);
+            }
+            xs[t * kXP + c] = q;
+        }
+        if (in_box && live) in_box[s] = inside ? 1 : 0;
+    }
+    __syncthreads();
+    const int r = lane & 15;
+    const int kq = (lane >> 4) * 8;
+    const int f0 = wave * 64;
+    f4 acc[4][4];
+    tile_layer<KIN>(xs, kXP, w1, f0, r, kq, acc);
+    tile_gelu(hs, p + kOffB1, f0, r, lane, acc);
+    __syncthreads();
+    const bf16_t* ws[3] = {w2, w3, w4};
+    const int64_t bo[3] = {kOffB2, kOffB3, kOffB4};
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+        tile_layer<H>(hs, kHP, ws[l], f0, r, kq, acc);
+        __syncthreads();  // every wave has read the layer's inputs
+        tile_gelu(hs, p + bo[l], f0, r, lane, acc);
+        __syncthreads();
+    }
+    if (t < 64 && s0 + t < n) {
+        const int64_t s = s0 + t;
+        float a = 0.0f;
+        for (int f = 0; f < H; f += 8) {
+            const bf8 hv = *reinterpret_cast<const bf8*>(hs + t * kHP + f);
+            const bf8 wv = load8(w5 + f);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a += (float)hv[e] * (float)wv[e];
+        }
+        if (base.on)
+            y[s] = (float)(caplet_baseline(x + s * kIn, base) * exp((double)(a + p[kOffB5]) * scale + shift));
+        else
+            y[s] = (a + p[kOffB5]) * scale + shift;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -742,12 +866,10 @@ hjm_status hjm_mlp_infer(hjm_mlp* h, const float* d_x, int64_t n, float* d_y, ui
     if (n < 0) return mfail(HJM_EINVAL, "negative n");
     for (int64_t s0 = 0; s0 < n; s0 += h->max_batch) {
         const int64_t nb = std::min(h->max_batch, n - s0);
-        hipError_t e = forward(h, d_x + s0 * kIn, nb, d_in_box ? d_in_box + s0 : nullptr, false);
-        if (!e) {
-            hipLaunchKernelGGL(k_out, dim3(blocks256(nb)), dim3(256), 0, h->stream, h->h4, h->w5, h->p + kOffB5, nb,
-                               h->scale, h->shift, d_x + s0 * kIn, h->base, d_y + s0);
-            e = hipGetLastError();
-        }
+        hipLaunchKernelGGL(k_infer, dim3((unsigned)((nb + 63) / 64)), dim3(256), 0, h->stream, d_x + s0 * kIn, nb,
+                           h->box, h->w1, h->w2, h->w3, h->w4, h->w5, h->p, h->scale, h->shift, h->base, d_y + s0,
+                           d_in_box ? d_in_box + s0 : nullptr);
+        hipError_t e = hipGetLastError();
         if (e) return mhip(e, "hjm_mlp_infer");
     }
     return HJM_OK;

@@ -149,3 +149,36 @@ def price(mlp: hjm.Mlp, x: np.ndarray, n: int = W.SURROGATE_N, stream=None, soft
     if len(outside):
         out[outside] = adi_prices(x[outside].astype(np.float64), n=n, stream=stream, soften=soften)
     return Priced(out, inside, len(outside))
+
+
+def main(argv=None) -> None:
+    """Train a surrogate on a small ADI set, then run in-box inference
+    repeatedly and print the times (a short run to trace with a profiler)."""
+    import argparse
+    import torch
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--train-solves", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--infer-rows", type=int, default=65536)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args(argv)
+    x, prices = training_set(a.train_solves, seed=21)
+    m = make_mlp(max_batch=max(a.infer_rows, 1024))
+    m.set_params(init_params(22))
+    fr = fit(m, x, prices, epochs=a.epochs, batch=1024, lr=2e-3, lr_final=1e-4, seed=23)
+    print(f"surrogate: {len(x)} rows, {a.epochs} epochs in {fr.seconds:.2f} s, final loss {fr.losses[-1]:.3e}",
+          flush=True)
+    xq = torch.from_numpy(W.surrogate_params(a.infer_rows, seed=24).astype(np.float32)).to(m.device)
+    m.infer(xq)
+    torch.cuda.synchronize(m.device)
+    t0 = time.perf_counter()
+    for _ in range(a.reps):
+        m.infer(xq)
+    torch.cuda.synchronize(m.device)
+    el = (time.perf_counter() - t0) / a.reps
+    print(f"surrogate: inference of {a.infer_rows} rows in {el * 1e6:.1f} us per pass", flush=True)
+    m.close()
+
+
+if __name__ == "__main__":
+    main()
