@@ -123,16 +123,18 @@ __global__ __launch_bounds__(256) void k_input(const float* __restrict__ x, int6
 // ---------------------------------------------------------------------------
 // Forward layer: Z = Hin W^T + b (FP32), Hout = BF16(GELU(Z)).
 // Hin is n x K (BF16, row-major), W is 256 x K (BF16, row-major).  A
-// workgroup of 4 waves takes 64 samples; wave w computes features
-// [64 w, 64 w + 64) for all 64 samples: 4 x 4 MFMA tiles of 16 x 16.
+// workgroup is one wave: 64 samples (blockIdx.x) and features
+// [64 w, 64 w + 64), w = blockIdx.y: 4 x 4 MFMA tiles of 16 x 16.  One wave
+// per workgroup keeps four times as many compute units busy on the small
+// training batches as a workgroup holding all four feature blocks would.
 // ---------------------------------------------------------------------------
 template <int K>
-__global__ __launch_bounds__(256) void k_fwd(const bf16_t* __restrict__ hin, const bf16_t* __restrict__ w,
-                                             const float* __restrict__ b, int64_t n, float* __restrict__ z,
-                                             bf16_t* __restrict__ hout)
+__global__ __launch_bounds__(64) void k_fwd(const bf16_t* __restrict__ hin, const bf16_t* __restrict__ w,
+                                            const float* __restrict__ b, int64_t n, float* __restrict__ z,
+                                            bf16_t* __restrict__ hout)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
+    const int wave = blockIdx.y;
     const int64_t s0 = (int64_t)blockIdx.x * 64;
     const int f0 = wave * 64;
     const int r = lane & 15;
@@ -358,17 +360,19 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
 }
 
 // Output layer backward: dZ4 = BF16(dy w5 GELU'(Z4)), and per-block partials
-// of dw5 = sum_s dy H4 and db5 = sum_s dy (block = 256 samples).
+// of dw5 = sum_s dy H4 and db5 = sum_s dy (block = kOutSub samples: many
+// blocks, short serial loops).
+constexpr int kOutSub = 16;
 __global__ __launch_bounds__(256) void k_out_bwd(const float* __restrict__ dy, const bf16_t* __restrict__ h4,
                                                  const float* __restrict__ z4, const bf16_t* __restrict__ w5,
                                                  int64_t n, bf16_t* __restrict__ dz4, float* __restrict__ part)
 {
-    // thread = feature f; loop over the block's 256 samples
+    // thread = feature f; loop over the block's samples
     const int f = threadIdx.x;
-    const int64_t s0 = (int64_t)blockIdx.x * 256;
+    const int64_t s0 = (int64_t)blockIdx.x * kOutSub;
     const float wf = bf2f(w5[f]);
     float gw = 0.0f, gb = 0.0f;
-    for (int q = 0; q < 256; ++q) {
+    for (int q = 0; q < kOutSub; ++q) {
         const int64_t s = s0 + q;
         if (s >= n) break;
         const float d = dy[s];
@@ -382,13 +386,14 @@ __global__ __launch_bounds__(256) void k_out_bwd(const float* __restrict__ dy, c
 
 // dH = dZ W (n x 256 times 256 x K) with dZ_prev = BF16(dH GELU'(Z_prev)).
 // wt is W^T (K x 256, BF16 row-major), so B = W^T^T reads rows of wt.
-// Same tiling as k_fwd with K = 256 features of the output side.
-__global__ __launch_bounds__(256) void k_bwd_dh(const bf16_t* __restrict__ dz, const bf16_t* __restrict__ wt,
-                                                const float* __restrict__ zprev, int64_t n,
-                                                bf16_t* __restrict__ dzprev)
+// Same tiling as k_fwd (one wave per workgroup, blockIdx.y the column
+// block) with K = 256 features of the output side.
+__global__ __launch_bounds__(64) void k_bwd_dh(const bf16_t* __restrict__ dz, const bf16_t* __restrict__ wt,
+                                               const float* __restrict__ zprev, int64_t n,
+                                               bf16_t* __restrict__ dzprev)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
+    const int wave = blockIdx.y;
     const int64_t s0 = (int64_t)blockIdx.x * 64;
     const int f0 = wave * 64;  // output column block (input features of the layer)
     const int r = lane & 15;
@@ -656,13 +661,14 @@ hipError_t forward(hjm_mlp* h, const float* x, int64_t n, uint8_t* in_box, bool 
     hipStream_t st = h->stream;
     const unsigned gb = (unsigned)((n + 63) / 64);
     hipLaunchKernelGGL(k_input, dim3(blocks256(n)), dim3(256), 0, st, x, n, h->box, h->box + kIn, h->xp, in_box);
-    hipLaunchKernelGGL(k_fwd<KIN>, dim3(gb), dim3(256), 0, st, h->xp, h->w1, h->p + kOffB1, n,
+    const dim3 grid(gb, H / 64);  // (64-sample tile, feature block)
+    hipLaunchKernelGGL(k_fwd<KIN>, grid, dim3(64), 0, st, h->xp, h->w1, h->p + kOffB1, n,
                        keep_z ? h->z1 : nullptr, h->h1);
-    hipLaunchKernelGGL(k_fwd<H>, dim3(gb), dim3(256), 0, st, h->h1, h->w2, h->p + kOffB2, n,
+    hipLaunchKernelGGL(k_fwd<H>, grid, dim3(64), 0, st, h->h1, h->w2, h->p + kOffB2, n,
                        keep_z ? h->z2 : nullptr, h->h2);
-    hipLaunchKernelGGL(k_fwd<H>, dim3(gb), dim3(256), 0, st, h->h2, h->w3, h->p + kOffB3, n,
+    hipLaunchKernelGGL(k_fwd<H>, grid, dim3(64), 0, st, h->h2, h->w3, h->p + kOffB3, n,
                        keep_z ? h->z3 : nullptr, h->h3);
-    hipLaunchKernelGGL(k_fwd<H>, dim3(gb), dim3(256), 0, st, h->h3, h->w4, h->p + kOffB4, n,
+    hipLaunchKernelGGL(k_fwd<H>, grid, dim3(64), 0, st, h->h3, h->w4, h->p + kOffB4, n,
                        keep_z ? h->z4 : nullptr, h->h4);
     return hipGetLastError();
 }
@@ -685,11 +691,12 @@ hjm_status gradients(hjm_mlp* h, const float* x, const float* t, int64_t n, doub
     hipLaunchKernelGGL(k_out, dim3(blocks256(n)), dim3(256), 0, st, h->h4, h->w5, h->p + kOffB5, n, 1.0f, 0.0f,
                        x, BaseK{}, h->y);
     hipLaunchKernelGGL(k_loss, dim3(blocks256(n)), dim3(256), 0, st, h->y, t, n, h->dy, h->lpart);
-    const int64_t nb256 = (n + 255) / 256;
-    hipLaunchKernelGGL(k_out_bwd, dim3((unsigned)nb256), dim3(256), 0, st, h->dy, h->h4, h->z4, h->w5, n, h->dz4,
+    // (n / 16) (H + 1) partials fit the ceil(n / 256) (H H + H + 1) floats of part
+    const int64_t nsub = (n + kOutSub - 1) / kOutSub;
+    hipLaunchKernelGGL(k_out_bwd, dim3((unsigned)nsub), dim3(256), 0, st, h->dy, h->h4, h->z4, h->w5, n, h->dz4,
                        h->part);
     // dw5, db5
-    hipLaunchKernelGGL(k_sum, dim3(blocks256(H + 1)), dim3(256), 0, st, h->part, (int)nb256, (int64_t)(H + 1),
+    hipLaunchKernelGGL(k_sum, dim3(blocks256(H + 1)), dim3(256), 0, st, h->part, (int)nsub, (int64_t)(H + 1),
                        h->g + kOffW5);
     const unsigned gb = (unsigned)((n + 63) / 64);
     const int64_t ch = chunks_of(n);
@@ -713,7 +720,7 @@ hjm_status gradients(hjm_mlp* h, const float* x, const float* t, int64_t n, doub
         }
         hipLaunchKernelGGL(k_sum, dim3(blocks256(H)), dim3(256), 0, st, h->bpart, (int)ch, (int64_t)H, h->g + ly.offB);
         if (ly.wt)
-            hipLaunchKernelGGL(k_bwd_dh, dim3(gb), dim3(256), 0, st, ly.dz, ly.wt, ly.zprev, n, ly.dzprev);
+            hipLaunchKernelGGL(k_bwd_dh, dim3(gb, H / 64), dim3(64), 0, st, ly.dz, ly.wt, ly.zprev, n, ly.dzprev);
     }
     if ((e = hipGetLastError())) return mhip(e, "mlp backward");
     if (sse) {
