@@ -306,6 +306,27 @@ def multi_rhs_leg(hjm, W, torch, stream, reps: int = 5):
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix-core peak
 
 
+def stream_copy_gbs(torch, mib: int = 1024, reps: int = 20) -> float:
+    """Streaming-copy bandwidth of the device (read + write bytes per second)
+    from torch's device-to-device copy of mib MiB, timed with HIP events: the
+    practical HBM ceiling the passes' GB/s are also compared with."""
+    n = mib * (1 << 20) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2.0 * mib * (1 << 20) / s / 1e9
+
+
 def _rel_errors(pred, ref):
     err = np.abs(pred - ref)
     big = ref > 1e-4
@@ -530,6 +551,9 @@ def main():
         ok = traffic_ok and b is not None
         passes[name]["traffic_bytes_per_point"] = b if ok else None
         passes[name]["traffic_bytes"] = round(b * passes[name]["points_per_launch"]) if ok else None
+    copy_gbs = stream_copy_gbs(torch)
+    for name in passes:
+        passes[name]["frac_of_copy"] = round(passes[name]["GB/s"] / copy_gbs, 4)
     dom = max(range(npass), key=lambda q: pass_ms[q])
     dname = names[dom]
     achieved = passes[dname]["GB/s"]
@@ -538,7 +562,10 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": passes[dname]["traffic_bytes"],
                 "traffic_unit": "HBM bytes per launch (measured bytes per point x points per launch)",
                 "bytes_per_point": PASS_BYTES[dname], "points_per_launch": passes[dname]["points_per_launch"],
-                "douglas_step_GBs": round(step_gbs, 1), "passes": passes}
+                "douglas_step_GBs": round(step_gbs, 1),
+                "stream_copy_GBs": round(copy_gbs, 1),
+                "stream_copy_note": "torch device-to-device copy of 1 GiB, read + write bytes, HIP events",
+                "passes": passes}
     log(f"prices (1..10y): {[round(p, 8) for p in prices]}")
     log(f"{value / 1e9:.2f} G pt-steps/s, {ms_per_step:.2f} ms per bench step; passes {passes}")
 
