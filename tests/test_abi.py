@@ -117,6 +117,9 @@ def test_null_handles(L):
     assert L.hjm_grid_plan(None, (C.c_int32 * 8)()) == hjm.EINVAL
     assert L.hjm_grid_profile_read(None, (C.c_double * hjm.N_PASSES)(), (C.c_int64 * hjm.N_PASSES)()) == hjm.EINVAL
     assert L.hjm_grid_destroy(None) == hjm.OK
+    b = hjm.MlpBaseline(0.15, 0.9, 0.25, 0.5, 1.0)
+    assert L.hjm_mlp_set_baseline(None, C.byref(b)) == hjm.EINVAL
+    assert L.hjm_mlp_targets(None, None, None, 1, None) == hjm.EINVAL
 
 
 def test_pass_count_matches_header():
