@@ -241,6 +241,16 @@ def surrogate_solve(x: np.ndarray, n: int = SURROGATE_N, soften: int = 0) -> Sol
     return SolveSpec(default_axes(n, n, n, k), m, PayoffSpec(CAPLET, T, T + SURROGATE_TENOR, k, soften), N, lvl, v0)
 
 
+def surrogate_readouts(n_solves: int, readouts: int, seed: int) -> np.ndarray:
+    """v0 values (n_solves, readouts) at which each training solve is read out:
+    the 16-point grid SURROGATE_V0 for every solve when readouts = 16, else
+    seeded uniform draws in the box's v0 range."""
+    if readouts == len(SURROGATE_V0):
+        return np.tile(np.array(SURROGATE_V0), (n_solves, 1))
+    rng = np.random.default_rng(seed)
+    return SURROGATE_BOX_LO[3] + (SURROGATE_BOX_HI[3] - SURROGATE_BOX_LO[3]) * rng.random((n_solves, readouts))
+
+
 def surrogate_params(n_solves: int, seed: int) -> np.ndarray:
     """Uniform draws in the surrogate box, one row per solve (column 3, v0, is overwritten
     by the readout grid of SURROGATE_V0 when the training set is built)."""
