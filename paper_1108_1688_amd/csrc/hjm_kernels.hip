@@ -953,6 +953,23 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Neighbouring lanes' values by one DPP move per 32-bit half (wave_shr:1,
+// wave_shl:1: lane l reads lane l - 1, resp. l + 1, across the whole wave):
+// VALU moves, no LDS-pipe round trip.  Lane 0 (resp. 63) keeps its own
+// value; the callers overwrite those lanes.
+__device__ __forceinline__ double from_lane_below(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_lane_above(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x130, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // Explicit predictor D0 = dt (A1 + A2 + A3 + A0) U^n (eq. (discreta) with the
 // centred stencils of eq. (esquema), one-sided rows on outflow faces), and the
 // Dirichlet increment on Dirichlet nodes, at the J nodes (i, j0 + m, k),
@@ -962,11 +979,11 @@ __device__ __forceinline__ void wave_sync()
 // window u(i, j0-2 .. j0+J+1) and the two y neighbours; the outflow extra
 // entry (two nodes in) only on the r faces, where its weight is not zero.
 // The neighbouring columns u(i -+ 1, j0-1 .. j0+J) are loaded too (SHFL
-// false) or taken from the neighbouring lanes' v windows by cross-lane
-// permutes, the wave's edge lanes loading theirs (SHFL true: fewer loads and
-// registers, one more LDS-pipe latency before the arithmetic; measured
-// faster inside the fused kernel, slower in the explicit kernel alone).  j0
-// must be wave-uniform (the v-table reads are scalar).
+// false) or taken from the neighbouring lanes' v windows by DPP moves across
+// the wave, the wave's edge lanes loading theirs (SHFL true: fewer loads and
+// registers; measured faster inside the fused kernel, slower in the
+// explicit kernel alone).  j0 must be wave-uniform (the v-table reads are
+// scalar).
 template <int J, bool SHFL, class Put>
 __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k, int j0, int step, const Put& put)
 {
@@ -1004,8 +1021,8 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
         const int lane = (int)(threadIdx.x & 63);
 #pragma unroll
         for (int m = 0; m < J + 2; ++m) {
-            const double lo = __shfl_up(cw[m + 1], 1);
-            const double hi = __shfl_down(cw[m + 1], 1);
+            const double lo = from_lane_below(cw[m + 1]);
+            const double hi = from_lane_above(cw[m + 1]);
             lw[m] = i == 0 ? cw[m + 1] : lo;
             rw[m] = i == nr - 1 ? cw[m + 1] : hi;
         }
@@ -1119,8 +1136,8 @@ __device__ __forceinline__ void corrected_start(const SolveDesc& s, int i, int k
             const int lane = (int)(threadIdx.x & 63);
 #pragma unroll
             for (int m = 0; m < J + 2; ++m) {
-                const double lo = __shfl_up(cw[m + 1], 1);
-                const double hi = __shfl_down(cw[m + 1], 1);
+                const double lo = from_lane_below(cw[m + 1]);
+                const double hi = from_lane_above(cw[m + 1]);
                 lw[m] = i == 0 ? cw[m + 1] : lo;
                 rw[m] = i == nr - 1 ? cw[m + 1] : hi;
             }
