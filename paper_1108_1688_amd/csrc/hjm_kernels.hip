@@ -1399,6 +1399,22 @@ __device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* 
 template <int ROWS, int MAXIT = 0>
 __device__ __forceinline__ void stage_rf(const SolveDesc& s, ldouble* tab)
 {
+    if constexpr (MAXIT >= kRF) {
+        if (s.nr == kBlock) {
+            // one r node per thread: its kRF rows, no division by nr
+            constexpr int TP = kRF * ROWS + 1;
+            gcdouble* rf = gp(s.rf);
+            const int i = (int)threadIdx.x;
+            const int sg = i / ROWS;
+            const int mm = i - sg * ROWS;
+            double x[kRF];
+#pragma unroll
+            for (int c6 = 0; c6 < kRF; ++c6) x[c6] = rf[c6 * kBlock + i];
+#pragma unroll
+            for (int c6 = 0; c6 < kRF; ++c6) tab[sg * TP + c6 * ROWS + mm] = x[c6];
+            return;
+        }
+    }
     if constexpr (MAXIT > 0) {
         constexpr int TP = kRF * ROWS + 1;
         const int n = kRF * s.nr;
