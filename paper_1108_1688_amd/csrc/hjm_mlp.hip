@@ -178,11 +178,10 @@ __global__ __launch_bounds__(64) void k_fwd(const bf16_t* __restrict__ hin, cons
     }
 }
 
-// Output layer: y = H4 . w5 + b5 (BF16 operands, FP32 sum), then the affine
-// map to price units.  One thread per sample.
+// Output layer of the training pass: y = H4 . w5 + b5 (BF16 operands, FP32
+// sum) in network units.  One thread per sample.
 __global__ __launch_bounds__(256) void k_out(const bf16_t* __restrict__ h4, const bf16_t* __restrict__ w5,
-                                             const float* __restrict__ b5, int64_t n, float scale, float shift,
-                                             const float* __restrict__ x, BaseK base, float* __restrict__ y)
+                                             const float* __restrict__ b5, int64_t n, float* __restrict__ y)
 {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
@@ -193,10 +192,7 @@ __global__ __launch_bounds__(256) void k_out(const bf16_t* __restrict__ h4, cons
 #pragma unroll
         for (int e = 0; e < 8; ++e) acc += (float)hv[e] * (float)wv[e];
     }
-    if (base.on)
-        y[s] = (float)(caplet_baseline(x + s * kIn, base) * exp((double)(acc + b5[0]) * scale + shift));
-    else
-        y[s] = (acc + b5[0]) * scale + shift;
+    y[s] = acc + b5[0];
 }
 
 // Training targets in network units: (ln(price / B(x)) - shift) / scale with
@@ -655,7 +651,8 @@ size_t mlp_layout(hjm_mlp* h, char* base, int64_t nb)
 
 unsigned blocks256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// forward from raw inputs; z arrays kept when training
+// training forward pass from raw inputs (inference runs k_infer instead);
+// z arrays kept for the backward pass when keep_z
 hipError_t forward(hjm_mlp* h, const float* x, int64_t n, uint8_t* in_box, bool keep_z)
 {
     hipStream_t st = h->stream;
@@ -688,8 +685,7 @@ hjm_status gradients(hjm_mlp* h, const float* x, const float* t, int64_t n, doub
     hipError_t e = forward(h, x, n, nullptr, true);
     if (e) return mhip(e, "mlp forward");
     // network units (the loss compares them with targets in the same units)
-    hipLaunchKernelGGL(k_out, dim3(blocks256(n)), dim3(256), 0, st, h->h4, h->w5, h->p + kOffB5, n, 1.0f, 0.0f,
-                       x, BaseK{}, h->y);
+    hipLaunchKernelGGL(k_out, dim3(blocks256(n)), dim3(256), 0, st, h->h4, h->w5, h->p + kOffB5, n, h->y);
     hipLaunchKernelGGL(k_loss, dim3(blocks256(n)), dim3(256), 0, st, h->y, t, n, h->dy, h->lpart);
     // (n / 16) (H + 1) partials fit the ceil(n / 256) (H H + H + 1) floats of part
     const int64_t nsub = (n + kOutSub - 1) / kOutSub;
