@@ -454,8 +454,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the sharded design is described in DESIGN.md and is not built", flush=True)
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "sharding the solves over several GPUs is not implemented", flush=True)
         sys.exit(2)
 
     import torch
