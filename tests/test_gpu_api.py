@@ -237,12 +237,42 @@ def test_shared_operator_graph_replays():
     b.close()
 
 
-def test_config4_full_batch_sampled_against_oracle():
+def config4_oracle_subset(specs, n=32):
+    """Solves of the calibration workload to check against the oracle: for
+    each axis and each of its sizes {32, 48, 64, 96} the cheapest solve with
+    that size, the cheapest and the longest of the 200-step-class solves, the
+    cheapest and the longest 96^3 solves, then the cheapest others up to n."""
+    cost = [sp.points * sp.n_steps for sp in specs]
+    chosen = []
+
+    def add(q):
+        if q not in chosen:
+            chosen.append(q)
+
+    for ax in range(3):
+        for size in (32, 48, 64, 96):
+            add(min((q for q in range(len(specs)) if specs[q].axes[ax].n == size), key=lambda q: cost[q]))
+    longest = max(sp.n_steps for sp in specs)
+    steps_max = [q for q in range(len(specs)) if specs[q].n_steps == longest]
+    add(min(steps_max, key=lambda q: cost[q]))
+    add(max(steps_max, key=lambda q: cost[q]))
+    cubes = [q for q in range(len(specs)) if specs[q].points == 96 ** 3]
+    add(min(cubes, key=lambda q: cost[q]))
+    add(max(cubes, key=lambda q: cost[q]))
+    for q in sorted(range(len(specs)), key=lambda q: cost[q]):
+        if len(chosen) >= n:
+            break
+        add(q)
+    return chosen
+
+
+def test_config4_full_batch_against_single_grids_and_oracle():
     """The whole calibration workload as the bench times it (512 uneven
-    solves, one batch replayed from a HIP graph): every price finite and
-    between 0 and the discount factor, the graph replay equal to an eager run
-    bit for bit, and the eight cheapest solves equal to the oracle's to
-    1e-12."""
+    solves, one batch replayed from a HIP graph): the graph replay equals an
+    eager run bit for bit; every price equals its own single-grid solve
+    (hjm_grid_create + hjm_adi_step + hjm_price) bit for bit and lies between 0
+    and the discount factor; 32 solves covering every size on every axis, the
+    longest step counts and the largest grids equal the oracle's to 1e-12."""
     specs = W.config4()
     st = torch.cuda.Stream()
     b = hjm.Batch(specs, stream=st)
@@ -253,10 +283,24 @@ def test_config4_full_batch_sampled_against_oracle():
     b.close()
     assert np.array_equal(graph, eager)
     assert np.all(np.isfinite(graph))
-    for sp, pg in zip(specs, graph):
+    methods = {}
+    for q, (sp, pg) in enumerate(zip(specs, graph)):
         assert 0.0 <= pg <= O.discount(to_oracle(sp), sp.payoff.expiry) * (1 + 1e-12), (sp.shape, pg)
-    cheap = sorted(range(len(specs)), key=lambda q: specs[q].points * specs[q].n_steps)[:8]
-    for q in cheap:
+        g = hjm.Grid(sp, stream=st)
+        plan = g.plan()
+        g.step()
+        single = g.price()
+        g.close()
+        assert single == pg, (q, sp.shape, single, pg)
+        methods[q] = (plan["r_method"], plan["vs_rows"] > 0, plan["yc_rows"] > 0)
+    subset = config4_oracle_subset(specs)
+    print(f"config4 plans: {sorted(set(methods.values()))}; oracle subset plans: "
+          f"{sorted(set(methods[q] for q in subset))}", flush=True)
+    worst = 0.0
+    for q in subset:
         sp = specs[q]
         po, _ = O.price(to_oracle(sp), sp.r0, sp.v0)
-        assert abs(graph[q] - po) <= 1e-12 * abs(po), (q, sp.shape, graph[q], po)
+        err = abs(graph[q] - po) / abs(po)
+        worst = max(worst, err)
+        assert err <= 1e-12, (q, sp.shape, sp.n_steps, graph[q], po)
+    print(f"config4 oracle subset: {len(subset)} solves, worst price rel err {worst:.2e}", flush=True)

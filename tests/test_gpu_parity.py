@@ -9,9 +9,11 @@ itself a cancellation, such as the linear forward payoff at the money), and
 the whole grid within max|dU| / max|U| <= 1e-12.  Shapes span
 several tiles and segments with ragged tails; every line-tile setting is used;
 the full-size 256x128x128 grid is checked element-wise after the first steps
-in the launch configuration the benchmark times, a full 256x128x128 solve
-(the 1-year caplet) is checked end to end, and the 10-year solve through
-properties that hold at any size.
+in the launch configuration the benchmark times, full 256x128x128 solves
+(the 1-, 5- and 10-year caplets: 40, 200 and 400 Douglas steps, the last
+the longest rounding accumulation of any workload) are checked end to end on
+every node, and the 10-year solve also through properties that hold at any
+size.
 """
 import numpy as np
 import pytest
@@ -82,6 +84,7 @@ def assert_price(pg, po, tol=REL):
     assert abs(pg - po) <= tol * scale, (pg, float(po), abs(pg - po) / scale)
     if po.__class__ is OraclePrice and po > 0 and po.scale <= abs(po) * (1 + 1e-12):
         assert abs(pg - po) <= tol * abs(po)
+    return abs(pg - po) / scale
 
 
 @pytest.mark.parametrize("which", [0, 1], ids=["bond", "caplet"])
@@ -240,6 +243,25 @@ def test_config3_one_year_caplet_full_solve():
     err = assert_grid(Ug, Uo)
     assert_price(pg, po)
     print(f"config3 1y grid rel err {err:.2e}, price rel err {abs(pg - po) / po:.2e}")
+
+
+@pytest.mark.parametrize("which", [4, 9], ids=["5y-200-steps", "10y-400-steps"])
+def test_config3_long_solves_against_oracle(which):
+    """The 5- and 10-year caplets of the 256x128x128 workload, whole solves
+    (200 and 400 Douglas steps) in the benchmark's launch configuration, on
+    every node and at the readout against the oracle run on the host's
+    cores.  Rounding accumulates over the steps (section 5.1: each step adds
+    a few ulps per node), so the 400-step solve sets the budget of the 1e-12
+    bar; the margins are printed."""
+    s = W.config3()[which]
+    assert s.n_steps == 40 * (which + 1) and s.shape == (128, 128, 256)
+    Ug, pg = gpu_grid(s)
+    assert PLANS == ["fused", True, True]
+    Uo, po = oracle_grid(s)
+    err = assert_grid(Ug, Uo)
+    perr = assert_price(pg, po)
+    print(f"config3 {s.payoff.expiry:g}y ({s.n_steps} steps) grid rel err {err:.2e}, "
+          f"price {pg!r} vs {po!r} rel err {perr:.2e}", flush=True)
 
 
 def test_config3_ten_year_properties():
