@@ -141,10 +141,16 @@ int orc_get_threads(void)
        = 6 ((Y_{i+1} - Y_i) / h_i - (Y_i - Y_{i-1}) / h_{i-1}),
    with M_0 = M_{n-1} = 0, solved here on every call (Gaussian elimination
    of the tridiagonal system, which is diagonally dominant). */
+#define ORC_MAX_KNOTS 64
 static void spline_eval(const orc_problem* p, double t, double* S, double* S1, double* S2)
 {
     int n = p->curve_n;
-    double Y[64], M[64], lo[64], di[64], up[64], rhs[64];
+    double Y[ORC_MAX_KNOTS], M[ORC_MAX_KNOTS], lo[ORC_MAX_KNOTS], di[ORC_MAX_KNOTS], up[ORC_MAX_KNOTS],
+        rhs[ORC_MAX_KNOTS];
+    if (n < 2 || n > ORC_MAX_KNOTS) {  /* no such curve: every value is NaN */
+        *S = *S1 = *S2 = NAN;
+        return;
+    }
     for (int i = 0; i < n; ++i) { Y[i] = -log(p->curve_p[i]); M[i] = 0.0; }
     for (int i = 1; i + 1 < n; ++i) {
         double hl = p->curve_t[i] - p->curve_t[i - 1], hr = p->curve_t[i + 1] - p->curve_t[i];

@@ -610,8 +610,10 @@ int64_t chunks_of(int64_t n) { return (n + kChunk - 1) / kChunk; }
 size_t mlp_layout(hjm_mlp* h, char* base, int64_t nb)
 {
     MlpLayout L;
-    auto F = [&](size_t count) { return reinterpret_cast<float*>(base + L.take(count * 4)); };
-    auto B = [&](size_t count) { return reinterpret_cast<bf16_t*>(base + L.take(count * 2)); };
+    // addresses from integers: sizing (base null) forms no pointer from a null one
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(base);
+    auto F = [&](size_t count) { return reinterpret_cast<float*>(b0 + L.take(count * 4)); };
+    auto B = [&](size_t count) { return reinterpret_cast<bf16_t*>(b0 + L.take(count * 2)); };
     const int64_t ch = chunks_of(nb);
     const size_t rows = (size_t)((nb + 63) / 64 * 64);
     float* p = F(kParams);
