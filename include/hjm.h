@@ -238,6 +238,34 @@ hjm_status hjm_grid_profile(hjm_grid* g, int32_t enable);
    (ms[HJM_N_PASSES], launches[HJM_N_PASSES]); the sums restart from zero. */
 hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[HJM_N_PASSES], int64_t launches[HJM_N_PASSES]);
 
+/* Pricing without allocation, for callers that cannot allocate device
+   memory (code that must not call hipMalloc: set-up inside HIP graph
+   capture, tight serving loops, harnesses that forbid allocation).
+   hjm_price_static runs one whole Douglas solve (theta = 1/2) from t = T to
+   t = 0 and reads it out, like hjm_grid_create + hjm_adi_step(n_steps) +
+   hjm_price_greeks, with the same kernels and the same results bit for bit,
+   but every working array of the solve (the Douglas increment D, the y
+   pivots, the tables, the descriptor, the readout slot and the health flag)
+   lives in a library-owned device array of HJM_STATIC_SCRATCH_BYTES, one per
+   GPU, held until the process ends.  The library allocates nothing.
+     d_U    caller's device memory, nr*nv*ny doubles, 256-byte aligned: the
+            grid (on return, the solution at t = 0, laid out as in every grid)
+     out    host: out[0] = C, out[1] = rho, out[2] = vega at (r0, v0, y = 0)
+   hip_stream must belong to the calling thread's current device (HJM_EINVAL
+   otherwise).  Synchronises the stream.  Errors: as hjm_grid_create and
+   hjm_price_greeks; HJM_ENOMEM (before any device work) when the working
+   arrays need more than HJM_STATIC_SCRATCH_BYTES (hjm_static_scratch_bytes
+   reports the need: 16 bytes per grid point plus the tables, so grids up to
+   about 2 million points fit).  Every call on one GPU shares that GPU's array
+   and overwrites what the last call left there: calls that overlap on one
+   GPU (from several threads, or on several streams) race and give wrong
+   results. */
+#define HJM_STATIC_SCRATCH_BYTES (32u << 20)
+hjm_status hjm_static_scratch_bytes(const hjm_axis ax[3], int32_t n_steps, size_t* bytes);
+hjm_status hjm_price_static(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff,
+                            int32_t n_steps, double r0, double v0, double* d_U, void* hip_stream,
+                            double out[3]);
+
 /* ---------------------------------------------------------------------- */
 /* Batched independent solves (calibration-style throughput).              */
 /* ---------------------------------------------------------------------- */

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -911,6 +912,126 @@ void scheme_stage2(SolveDesc& d2, const SolveDesc& d1, const hjm_scheme& sc, dou
     d2.hv = sc.kind == HJM_SCHEME_HV || huang;
 }
 
+// The solve's kernel variants (host only); HJM_EINVAL where a correction
+// scheme asks for kernels the grid's shape does not allow.
+hjm_status grid_plan(const hjm_axis ax[3], const hjm_model& model, const hjm_payoff& payoff, const hjm_scheme& scheme,
+                     int n_steps, Plan* out)
+{
+    const bool corr = scheme.kind != HJM_SCHEME_DOUGLAS;
+    int rows[3];
+    std::memcpy(rows, g_rows, sizeof rows);
+    const Plan plan = make_plan(ax[0].n, ax[1].n, ax[2].n, rows, r_spike_ok(ax, model, payoff, n_steps, scheme.theta));
+    if (corr && (!(plan.r_mode == R_FUSED || plan.r_mode == R_SPLIT) || !plan.yc_rows))
+        return fail(HJM_EINVAL,
+                    "the correction schemes run on the lane-split r solve and the stored-pivot y solve: nr = S*ROWS "
+                    "(S a power of two, rows within the spike bound) and ny = S*ROWS are needed (plan: r method %d, "
+                    "y rows %d)", plan.r_mode, plan.yc_rows);
+    *out = plan;
+    return HJM_OK;
+}
+
+// Fill a grid handle over device memory laid out as gl at base (U at
+// d_U instead when d_U is not null), upload its tables and enqueue the
+// set-up kernels (Dirichlet increments, terminal data, y pivots); waits for
+// them.  The problem and scheme are validated by the caller.
+hjm_status grid_init(hjm_grid* g, const hjm_axis ax[3], const hjm_model& model, const hjm_payoff& payoff,
+                     const hjm_scheme& scheme, int n_steps, const Plan& plan, char* base, const GridLayout& gl,
+                     hipStream_t stream, double* d_U)
+{
+    const bool corr = scheme.kind != HJM_SCHEME_DOUGLAS;
+    std::memcpy(g->ax, ax, sizeof g->ax);
+    g->model = model;
+    g->model.curve_t = g->model.curve_p = nullptr;  // the knots are not kept
+    g->payoff = payoff;
+    g->n_steps = n_steps;
+    std::memcpy(g->rows, g_rows, sizeof g->rows);
+    g->plan = plan;
+    g->scheme = scheme;
+    g->corr = corr;
+    g->stream = stream;
+    g->base = base;
+    g->d_desc = reinterpret_cast<SolveDesc*>(g->base + gl.desc);
+    g->d_rq = reinterpret_cast<Readout*>(g->base + gl.rq);
+    g->d_out = reinterpret_cast<double*>(g->base + gl.out);
+    g->d_flag = reinterpret_cast<int32_t*>(g->base + gl.flag);
+    build_tables(ax, model, payoff, n_steps, g->plan, g->tables, scheme.theta);
+    fill_desc(g->desc, ax, model, payoff, n_steps, g->plan, g->base, gl.s, g->d_flag, scheme.theta);
+    if (d_U) g->desc.U = d_U;
+    if (corr) {
+        g->desc.stage = 1;
+        scheme_stage2(g->desc2, g->desc, scheme, reinterpret_cast<double*>(g->base + gl.s.E));
+    }
+    hipError_t e;
+    if ((e = init_kernel_attributes()) ||
+        (e = hipMemcpyAsync(g->d_desc, &g->desc, sizeof(SolveDesc), hipMemcpyHostToDevice, g->stream)) ||
+        (corr && (e = hipMemcpyAsync(g->d_desc + 1, &g->desc2, sizeof(SolveDesc), hipMemcpyHostToDevice,
+                                     g->stream))) ||
+        (e = upload_tables(g->desc, g->tables, g->stream)) ||
+        (e = launch_gd(g->d_desc, 1, (int64_t)(2 * ax[2].n + ax[0].n) * n_steps, g->stream)) ||
+        (e = launch_terminal(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n * ax[2].n, g->stream)) ||
+        (e = launch_ypiv(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n, g->stream)) ||
+        (e = hipStreamSynchronize(g->stream)))
+        return hip_fail(e, "grid set-up");
+    return HJM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Working memory of hjm_price_static: one array per GPU, held until the
+// process ends.  Host code never uses the array's name as an address (on the
+// host it names a stand-in, not device memory): hipGetSymbolAddress gives
+// each device's copy, once per device, and only that address is used.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) char scratch[HJM_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_at[kMaxDevices] = {};
+
+// The calling thread's current device's copy of the array; the stream (if
+// not null) must belong to that device.
+hjm_status static_scratch(hipStream_t stream, char** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(HJM_EDEVICE, "device %d beyond the %d supported", dev, kMaxDevices);
+    if (stream) {
+        hipDevice_t sdev = 0;
+        if ((e = hipStreamGetDevice(stream, &sdev))) return hip_fail(e, "hipStreamGetDevice");
+        if ((int)sdev != dev)
+            return fail(HJM_EINVAL, "the stream belongs to device %d, the current device is %d", (int)sdev, dev);
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256) return fail(HJM_EDEVICE, "static scratch at a bad address");
+        g_scratch_at[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_at[dev];
+    return HJM_OK;
+}
+
+// hjm_price_static's layout: a grid's (descriptor, readout, flag, D, y
+// pivots, tables) without U, which is the caller's.
+GridLayout static_layout(const hjm_axis ax[3], int n_steps)
+{
+    Layout L;
+    GridLayout g;
+    g.desc = L.take(sizeof(SolveDesc));
+    g.rq = L.take(sizeof(Readout));
+    g.out = L.take(sizeof(double) * 3);
+    g.flag = L.take(sizeof(int32_t));
+    const size_t pts = (size_t)ax[0].n * ax[1].n * ax[2].n;
+    g.s.U = 0;  // unused: the caller's d_U
+    g.s.D = L.take(pts * 8);
+    g.s.YI = L.take(pts * 8);
+    g.s.E = 0;
+    g.s.tables = L.take(table_doubles(ax, n_steps) * 8);
+    g.total = L.off;
+    return g;
+}
+
 }  // namespace
 
 int32_t hjm::report_error(int32_t code, const char* msg)
@@ -1049,54 +1170,21 @@ hjm_status hjm_grid_create_scheme(const hjm_axis ax[3], const hjm_model* model, 
     if (st) return st;
     st = validate_scheme(scheme);
     if (st) return st;
+    Plan plan;
+    st = grid_plan(ax, *model, *payoff, *scheme, n_steps, &plan);
+    if (st) return st;
     const bool corr = scheme->kind != HJM_SCHEME_DOUGLAS;
-    int rows[3];
-    std::memcpy(rows, g_rows, sizeof rows);
-    const Plan plan = make_plan(ax[0].n, ax[1].n, ax[2].n, rows, r_spike_ok(ax, *model, *payoff, n_steps, scheme->theta));
-    if (corr && (!(plan.r_mode == R_FUSED || plan.r_mode == R_SPLIT) || !plan.yc_rows))
-        return fail(HJM_EINVAL,
-                    "the correction schemes run on the lane-split r solve and the stored-pivot y solve: nr = S*ROWS "
-                    "(S a power of two, rows within the spike bound) and ny = S*ROWS are needed (plan: r method %d, "
-                    "y rows %d)", plan.r_mode, plan.yc_rows);
     if (!d_workspace) return fail(HJM_EINVAL, "null workspace");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return fail(HJM_EINVAL, "workspace must be 256-byte aligned");
     const GridLayout gl = grid_layout(ax, n_steps, corr);
     if (ws_bytes < gl.total) return fail(HJM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, gl.total);
     hjm_grid* g = new (std::nothrow) hjm_grid;
     if (!g) return fail(HJM_EINVAL, "host allocation failed");
-    std::memcpy(g->ax, ax, sizeof g->ax);
-    g->model = *model;
-    g->model.curve_t = g->model.curve_p = nullptr;  // the knots are not kept
-    g->payoff = *payoff;
-    g->n_steps = n_steps;
-    std::memcpy(g->rows, rows, sizeof g->rows);
-    g->plan = plan;
-    g->scheme = *scheme;
-    g->corr = corr;
-    g->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    g->base = reinterpret_cast<char*>(d_workspace);
-    g->d_desc = reinterpret_cast<SolveDesc*>(g->base + gl.desc);
-    g->d_rq = reinterpret_cast<Readout*>(g->base + gl.rq);
-    g->d_out = reinterpret_cast<double*>(g->base + gl.out);
-    g->d_flag = reinterpret_cast<int32_t*>(g->base + gl.flag);
-    build_tables(ax, *model, *payoff, n_steps, g->plan, g->tables, scheme->theta);
-    fill_desc(g->desc, ax, *model, *payoff, n_steps, g->plan, g->base, gl.s, g->d_flag, scheme->theta);
-    if (corr) {
-        g->desc.stage = 1;
-        scheme_stage2(g->desc2, g->desc, *scheme, reinterpret_cast<double*>(g->base + gl.s.E));
-    }
-    hipError_t e;
-    if ((e = init_kernel_attributes()) ||
-        (e = hipMemcpyAsync(g->d_desc, &g->desc, sizeof(SolveDesc), hipMemcpyHostToDevice, g->stream)) ||
-        (corr && (e = hipMemcpyAsync(g->d_desc + 1, &g->desc2, sizeof(SolveDesc), hipMemcpyHostToDevice,
-                                     g->stream))) ||
-        (e = upload_tables(g->desc, g->tables, g->stream)) ||
-        (e = launch_gd(g->d_desc, 1, (int64_t)(2 * ax[2].n + ax[0].n) * n_steps, g->stream)) ||
-        (e = launch_terminal(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n * ax[2].n, g->stream)) ||
-        (e = launch_ypiv(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n, g->stream)) ||
-        (e = hipStreamSynchronize(g->stream))) {
+    st = grid_init(g, ax, *model, *payoff, *scheme, n_steps, plan, reinterpret_cast<char*>(d_workspace), gl,
+                   reinterpret_cast<hipStream_t>(hip_stream), nullptr);
+    if (st) {
         delete g;
-        return hip_fail(e, "hjm_grid_create");
+        return st;
     }
     *out = g;
     return HJM_OK;
@@ -1249,6 +1337,46 @@ hjm_status hjm_grid_profile_read(hjm_grid* g, double ms[HJM_N_PASSES], int64_t l
     }
     g->ev_used = 0;
     return HJM_OK;
+}
+
+hjm_status hjm_static_scratch_bytes(const hjm_axis ax[3], int32_t n_steps, size_t* bytes)
+{
+    if (!ax || !bytes) return fail(HJM_EINVAL, "null argument");
+    hjm_status st = validate_axes(ax);
+    if (st) return st;
+    if (n_steps <= 0) return fail(HJM_EINVAL, "n_steps must be > 0");
+    *bytes = static_layout(ax, n_steps).total;
+    return HJM_OK;
+}
+
+hjm_status hjm_price_static(const hjm_axis ax[3], const hjm_model* model, const hjm_payoff* payoff, int32_t n_steps,
+                            double r0, double v0, double* d_U, void* hip_stream, double out[3])
+{
+    if (!out || !d_U) return fail(HJM_EINVAL, "null argument");
+    if (reinterpret_cast<uintptr_t>(d_U) % 256) return fail(HJM_EINVAL, "d_U must be 256-byte aligned");
+    hjm_status st = validate_problem(ax, model, payoff, n_steps);
+    if (st) return st;
+    const hjm_scheme douglas{HJM_SCHEME_DOUGLAS, 0, kTheta};
+    Plan plan;
+    st = grid_plan(ax, *model, *payoff, douglas, n_steps, &plan);
+    if (st) return st;
+    Readout probe;
+    st = make_readout(ax, r0, v0, 0, &probe);  // reject a bad readout point before any device work
+    if (st) return st;
+    const GridLayout gl = static_layout(ax, n_steps);
+    if (gl.total > HJM_STATIC_SCRATCH_BYTES)
+        return fail(HJM_ENOMEM, "the solve needs %zu bytes of scratch, more than the %zu of the static array",
+                    gl.total, (size_t)HJM_STATIC_SCRATCH_BYTES);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    char* base = nullptr;
+    st = static_scratch(stream, &base);
+    if (st) return st;
+    hjm_grid g;
+    st = grid_init(&g, ax, *model, *payoff, douglas, n_steps, plan, base, gl, stream, d_U);
+    if (st) return st;
+    st = hjm_adi_step(&g, n_steps);
+    if (st) return st;
+    return hjm_price_greeks(&g, r0, v0, out);
 }
 
 }  // extern "C"

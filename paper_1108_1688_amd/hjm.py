@@ -24,6 +24,7 @@ PASSES = ("explicit", "r", "v", "y+update")
 R_METHODS = ("spike", "chain", "split", "fused")
 SCHEMES = ("douglas", "cs", "mcs", "hv", "huang")  # HJM_SCHEME_*
 MLP_PARAMS = 199937  # HJM_MLP_PARAMS
+STATIC_SCRATCH_BYTES = 32 << 20  # HJM_STATIC_SCRATCH_BYTES
 
 
 class HjmError(RuntimeError):
@@ -85,6 +86,8 @@ def lib():
         "hjm_grid_plan": (st, [vp, P(i32)]),
         "hjm_grid_profile": (st, [vp, i32]),
         "hjm_grid_profile_read": (st, [vp, P(d), P(i64)]),
+        "hjm_static_scratch_bytes": (st, [P(Axis), i32, P(sz)]),
+        "hjm_price_static": (st, [P(Axis), P(Model), P(Payoff), i32, d, d, vp, vp, P(d)]),
         "hjm_batch_workspace_bytes": (st, [i32, P(Axis), P(i32), P(sz)]),
         "hjm_batch_create": (st, [i32, P(Axis), P(Model), P(Payoff), P(i32), vp, sz, vp, P(vp)]),
         "hjm_batch_run": (st, [vp, i32]),
@@ -353,6 +356,34 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+def static_scratch_bytes(spec) -> int:
+    """Bytes of the library's static device array that price_static needs for this solve."""
+    nbytes = C.c_size_t()
+    check(lib().hjm_static_scratch_bytes(make_axes(spec.axes), spec.n_steps, C.byref(nbytes)))
+    return nbytes.value
+
+
+def price_static(spec, U, stream=None, r0: Optional[float] = None, v0: Optional[float] = None):
+    """One whole Douglas solve through hjm_price_static (no allocation in the
+    library: its working arrays live in a static device array).  U is the
+    caller's float64 CUDA tensor of spec.points elements (256-byte aligned);
+    on return it holds the solution at t = 0.  Returns (price, rho, vega)."""
+    torch = _torch()
+    if U.dtype != torch.float64 or not U.is_cuda or not U.is_contiguous() or U.numel() != spec.points:
+        raise ValueError("U must be a contiguous float64 CUDA tensor of spec.points elements")
+    if U.data_ptr() % 256:
+        raise ValueError("U must be 256-byte aligned")
+    stream = stream if stream is not None else torch.cuda.current_stream(U.device)
+    r0 = spec.r0 if r0 is None else r0
+    v0 = spec.v0 if v0 is None else v0
+    model = make_model(spec.model)
+    out = (C.c_double * 3)()
+    check(lib().hjm_price_static(make_axes(spec.axes), C.byref(model), C.byref(make_payoff(spec.payoff)),
+                                 spec.n_steps, float(r0), float(v0), C.c_void_p(U.data_ptr()),
+                                 _stream_handle(stream), out))
+    return tuple(out)
 
 
 class Batch:
