@@ -325,6 +325,21 @@ hjm_status hjm_batch_destroy(hjm_batch* b);
 hjm_status hjm_set_line_tile(int32_t r_rows, int32_t v_rows, int32_t y_rows);
 hjm_status hjm_get_line_tile(int32_t* r_rows, int32_t* v_rows, int32_t* y_rows);
 
+/* Per-shape line tiles (the autotuner's choices): the preferred rows per
+   thread (8, 16 or 32; 0 removes the override) of the line solves along
+   `axis` (0 r, 1 v, 2 y) on grids with n nodes on that axis and `lines`
+   such lines (the product of the other two node counts; 0: any count), in
+   place of hjm_set_line_tile's value there.  A solve takes the override of
+   its exact line shape, else the one for its line length, else the global
+   value.  Handles created afterwards use them; inside a batch each solve
+   takes its own shape's rows (solves that end up with different kernel
+   variants launch in separate groups).  Every setting gives the same prices
+   to rounding (the plans keep every variant within rounding of the
+   sequential elimination). */
+hjm_status hjm_set_axis_tile(int32_t axis, int32_t n, int64_t lines, int32_t rows);
+hjm_status hjm_get_axis_tile(int32_t axis, int32_t n, int64_t lines, int32_t* rows);
+hjm_status hjm_clear_axis_tiles(void);
+
 /* ---------------------------------------------------------------------- */
 /* Learned surrogate (caplet prices inside a box of model inputs).          */
 /* ---------------------------------------------------------------------- */
@@ -417,6 +432,15 @@ hjm_status hjm_get_explicit_chunk(int32_t* J);
    16 more bytes of memory traffic per grid point and step.  Process-wide. */
 hjm_status hjm_set_r_fusion(int32_t on);
 hjm_status hjm_get_r_fusion(int32_t* on);
+
+/* How the fused explicit + r kernel reads the explicit predictor's
+   neighbours (eq. (esquema) stencils): on (default), each workgroup stages
+   its tile's v window of U in LDS and reads the r neighbours and mixed-term
+   corners there; off, every thread loads its own neighbours (lane moves for
+   the r neighbours).  Same values either way.  For handles created
+   afterwards; grids of 4 GiB or more always take the second form. */
+hjm_status hjm_set_exr_window(int32_t on);
+hjm_status hjm_get_exr_window(int32_t* on);
 
 /* Stream lanes of batches created afterwards (1..8, default 3; HJM_EINVAL
    otherwise).  More lanes overlap more kernels at fewer solves per launch.

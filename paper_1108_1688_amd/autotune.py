@@ -1,17 +1,20 @@
-"""Autotuner for the line-solve tiles and the explicit-kernel chunk.
+"""Autotuner for the line-solve tiles, per line shape.
 
-The Douglas step is four kernels (explicit predictor, r, v and y sweeps) and
-each one's speed depends on one setting only: the rows per thread of its own
-line solve (r, v, y) or, for the explicit predictor, the v nodes per thread
-(on grids whose r lines are solved inside the explicit kernel, the r rows).
-The library times each kernel launch with HIP events, so a few runs along the
-diagonal of the settings give every kernel's time for every candidate value,
-and each kernel gets its own best value.
+A Douglas step runs one kernel per direction (the explicit predictor fused
+with the r sweep, then the v and y sweeps), and each kernel's speed depends
+on the rows per thread of its own line solve and on the shape of its lines:
+the line length n (the node count along its axis) and the number of lines
+(the product of the other two node counts).  The library times each kernel
+launch with HIP events, so timing every candidate value on every axis at
+once (the settings (8, 8, 8), (16, 16, 16), (32, 32, 32)) gives each
+kernel's time for each of its candidates on each grid shape; for every line
+shape (axis, n, lines) the candidate with the least time, weighted by the
+work (grid points times steps) of the solves that have that line shape,
+wins.  The choices go to the library as per-shape overrides
+(hjm_set_axis_tile), so that one batch runs each shape on its own best tiles.
 
-Timings are taken on representative solves (the largest by grid points times
-steps) and weighted by the work each stands for; results are cached in a JSON
-file keyed by the library build and the shapes, so a later process can reuse
-them without timing again.
+Results are cached in a JSON file keyed by the device, the library build and
+each line shape, so a later process reuses them without timing again.
 """
 from __future__ import annotations
 
@@ -23,43 +26,54 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 from . import hjm
 
-# (r rows, v rows, y rows, explicit chunk) along the diagonal: every kernel
-# sees each of its candidate values once
-DIAGONAL: Tuple[Tuple[int, int, int, int], ...] = ((8, 8, 8, 4), (16, 16, 16, 8), (32, 32, 32, 16))
+CANDIDATES: Tuple[int, ...] = (8, 16, 32)
+AXES = ("r", "v", "y")
+# the pass of each axis's line solve in the per-pass timing (on grids whose
+# r lines are solved inside the explicit kernel, pass 0 holds both)
+PASS_OF_AXIS = {0: (0, 1), 1: (2,), 2: (3,)}
+
+LineShape = Tuple[int, int, int]  # (axis, nodes per line, lines)
+
+
+def line_shapes(shape: Tuple[int, int, int]) -> List[LineShape]:
+    """The three line shapes of an nr x nv x ny grid."""
+    nr, nv, ny = shape
+    return [(0, nr, nv * ny), (1, nv, nr * ny), (2, ny, nr * nv)]
 
 
 @dataclass
 class Tuning:
-    setting: Tuple[int, int, int, int]        # (r, v, y, explicit chunk)
-    per_pass_us: Dict[str, float]             # per Douglas step, for the chosen setting
-    runs: List[dict] = field(default_factory=list)
+    choice: Dict[LineShape, int]                          # rows per thread of every line shape
+    us: Dict[LineShape, Dict[int, float]]                 # weighted kernel time per candidate
+    default_rows: Tuple[int, int, int] = (16, 16, 16)
     cached: bool = False
+    timed_grids: int = 0
 
     def apply(self) -> None:
-        r, v, y, J = self.setting
-        hjm.set_line_tile(r, v, y)
-        hjm.set_explicit_chunk(J)
+        """Install the choices as the library's per-shape overrides."""
+        for (axis, n, lines), rows in self.choice.items():
+            hjm.set_axis_tile(axis, n, lines, rows)
+
+    def summary(self) -> dict:
+        """Chosen rows per line shape ("r:96x9216" -> 16) and how many
+        shapes differ from the default."""
+        out = {f"{AXES[a]}:{n}x{lines}": rows for (a, n, lines), rows in sorted(self.choice.items())}
+        differ = sum(1 for (a, _, _), rows in self.choice.items() if rows != self.default_rows[a])
+        return {"per_line_shape": out, "line_shapes": len(self.choice), "differ_from_default": differ}
 
 
-def choose(runs: Sequence[dict], split: bool) -> Tuple[Tuple[int, int, int, int], Dict[str, float]]:
-    """Pick each kernel's best value from diagonal runs.  A run is
-    {"setting": (r, v, y, J), "us": [explicit, r, v, y]} with per-step
-    microseconds (weighted over the representative solves).  When the r lines
-    are solved inside the explicit kernel (split False), the explicit pass
-    follows the r rows and the chunk is irrelevant."""
-    def best(pass_idx, knob):
-        run = min(runs, key=lambda x: x["us"][pass_idx])
-        return run["setting"][knob], run["us"][pass_idx]
+def choose(times: Dict[LineShape, Dict[int, float]]) -> Dict[LineShape, int]:
+    """Each line shape's candidate with the least weighted time."""
+    return {key: min(per, key=per.get) for key, per in times.items() if per}
 
-    if split:
-        J, t0 = best(0, 3)
-        r, t1 = best(1, 0)
-    else:
-        r, t0 = best(0, 0)
-        J, t1 = hjm.get_explicit_chunk(), 0.0
-    v, t2 = best(2, 1)
-    y, t3 = best(3, 2)
-    return (r, v, y, J), dict(zip(hjm.PASSES, (t0, t1, t2, t3)))
+
+def _device_id() -> str:
+    try:
+        import torch
+        p = torch.cuda.get_device_properties(0)
+        return getattr(p, "gcnArchName", p.name).split(":")[0]
+    except Exception:
+        return "unknown"
 
 
 def _lib_id() -> str:
@@ -67,14 +81,14 @@ def _lib_id() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _cache_key(specs: Sequence) -> str:
-    shapes = sorted({(s.axes[0].n, s.axes[1].n, s.axes[2].n) for s in specs})
-    return _lib_id() + ":" + ";".join("x".join(map(str, sh)) for sh in shapes)
+def _key_str(dev: str, lib: str, key: LineShape) -> str:
+    a, n, lines = key
+    return f"{dev}:{lib}:{AXES[a]}:{n}:{lines}"
 
 
-def representatives(specs: Sequence, k: int = 3) -> List[Tuple[object, float]]:
-    """Up to k solves of distinct shapes with the most work, each with the
-    share of the total point-steps of its shape."""
+def shapes_by_work(specs: Sequence) -> Dict[Tuple[int, int, int], Tuple[object, float]]:
+    """Each distinct grid shape of specs: a solve of that shape (the one with
+    the most steps) and the shape's share of all point-steps."""
     work: Dict[tuple, float] = {}
     pick: Dict[tuple, object] = {}
     for s in specs:
@@ -82,62 +96,64 @@ def representatives(specs: Sequence, k: int = 3) -> List[Tuple[object, float]]:
         work[sh] = work.get(sh, 0.0) + s.points * s.n_steps
         if sh not in pick or s.n_steps > pick[sh].n_steps:
             pick[sh] = s
-    top = sorted(work, key=work.get, reverse=True)[:k]
     total = sum(work.values())
-    return [(pick[sh], work[sh] / total) for sh in top]
+    return {sh: (pick[sh], work[sh] / total) for sh in work}
+
+
+def time_shapes(shapes: Dict[tuple, Tuple[object, float]], steps: int) -> Dict[LineShape, Dict[int, float]]:
+    """Per line shape and candidate: the weighted per-launch microseconds of
+    that axis's kernel, from `steps` event-timed Douglas steps of one grid of
+    every shape under each candidate setting (after one untimed step)."""
+    times: Dict[LineShape, Dict[int, float]] = {}
+    for rows in CANDIDATES:
+        hjm.clear_axis_tiles()
+        hjm.set_line_tile(rows, rows, rows)
+        for sh, (spec, weight) in shapes.items():
+            n = min(steps + 1, spec.n_steps)
+            g = hjm.Grid(spec)
+            g.step(1)
+            g.profile(True)
+            g.profile_read()
+            g.step(n - 1)
+            ms, cnt = g.profile_read()
+            g.close()
+            for key in line_shapes(sh):
+                us = sum(1e3 * ms[q] / cnt[q] for q in PASS_OF_AXIS[key[0]] if cnt[q])
+                times.setdefault(key, {})
+                times[key][rows] = times[key].get(rows, 0.0) + weight * us
+    return times
 
 
 def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bool = True) -> Tuning:
-    """Time the diagonal settings on representative solves and choose each
-    kernel's best value.  Restores the previous settings unless apply."""
+    """Choose the rows per thread of every line shape of specs (timing what
+    the cache does not hold) and, if apply, install them as overrides; the
+    global line tile is left as it was."""
     specs = list(specs)
-    key = _cache_key(specs)
+    shapes = shapes_by_work(specs)
+    keys = sorted({k for sh in shapes for k in line_shapes(sh)})
+    dev, lib = _device_id(), _lib_id()
+    old_tile = hjm.get_line_tile()
+    stored = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
-            stored = json.load(f).get(key)
-        if stored:
-            t = Tuning(tuple(stored["setting"]), stored["per_pass_us"], stored.get("runs", []), cached=True)
-            if apply:
-                t.apply()
-            return t
-    old_tile, old_J = hjm.get_line_tile(), hjm.get_explicit_chunk()
-    reps = representatives(specs)
-    runs = []
-    split = True
-    try:
-        for setting in DIAGONAL:
-            r, v, y, J = setting
-            hjm.set_line_tile(r, v, y)
-            hjm.set_explicit_chunk(J)
-            us = [0.0] * hjm.N_PASSES
-            for spec, weight in reps:
-                n = min(steps + 1, spec.n_steps)
-                g = hjm.Grid(spec)
-                split = split and g.plan()["r_method"] == "split"
-                g.step(1)  # warm-up
-                g.profile(True)
-                g.profile_read()
-                g.step(n - 1)
-                ms, cnt = g.profile_read()
-                g.close()
-                for q in range(hjm.N_PASSES):
-                    if cnt[q]:
-                        us[q] += weight * 1e3 * ms[q] / cnt[q]
-            runs.append({"setting": setting, "us": us})
-    finally:
-        hjm.set_line_tile(*old_tile)
-        hjm.set_explicit_chunk(old_J)
-    setting, per_pass = choose(runs, split)
-    result = Tuning(setting, per_pass, runs)
-    if cache:
-        data = {}
-        if os.path.exists(cache):
-            with open(cache) as f:
-                data = json.load(f)
-        data[key] = {"setting": list(setting), "per_pass_us": per_pass, "runs": runs}
-        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
-        with open(cache, "w") as f:
-            json.dump(data, f, indent=1)
+            stored = json.load(f)
+    if all(_key_str(dev, lib, k) in stored for k in keys):
+        t = Tuning({k: stored[_key_str(dev, lib, k)]["rows"] for k in keys},
+                   {k: {int(c): v for c, v in stored[_key_str(dev, lib, k)]["us"].items()} for k in keys},
+                   old_tile, cached=True)
+    else:
+        try:
+            times = time_shapes(shapes, steps)
+        finally:
+            hjm.clear_axis_tiles()
+            hjm.set_line_tile(*old_tile)
+        t = Tuning(choose(times), times, old_tile, timed_grids=len(shapes) * len(CANDIDATES))
+        if cache:
+            for k in keys:
+                stored[_key_str(dev, lib, k)] = {"rows": t.choice[k], "us": {str(c): v for c, v in t.us[k].items()}}
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(stored, f, indent=1)
     if apply:
-        result.apply()
-    return result
+        t.apply()
+    return t

@@ -9,9 +9,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using namespace hjm;
@@ -283,6 +285,7 @@ hjm_status validate_problem(const hjm_axis ax[3], const hjm_model* m, const hjm_
 // Line-solve tiling.
 // ---------------------------------------------------------------------------
 struct Plan {
+    int rows[3];  // preferred rows per thread of the r, v, y line solves
     bool r_spike;
     int r_mode;  // R_SPIKE / R_CHAIN (k_xr), R_SPLIT (k_exp + k_rs) or R_FUSED (k_exr)
     int r_S, r_L, r_pitch, v_S, v_L, y_S, y_L;
@@ -291,6 +294,7 @@ struct Plan {
     int rs_rows, rs_S, rs_log2S, rs_L, rs_tiles;
     int exp_J, exp_cb, exp_tiles;
     int exr_P, exr_tiles, exr_tab;      // fused explicit + r solve
+    bool exr_win;                       // its explicit phase from an LDS window
     size_t exr_lds;
     int vs_rows, vs_S, vs_tiles;        // segmented v solve (0: chained k_v)
     int yc_rows, yc_S, yc_L, yc_tiles;  // y solve on stored pivots (0: k_yu)
@@ -316,8 +320,27 @@ int yc_rows_for(int ny, int preferred)
     return 0;
 }
 
+// Overrides of the preferred rows by line shape: (axis, nodes per line,
+// lines; 0 lines: any count): the autotuner's per-shape choices.
+std::map<std::tuple<int, int, int64_t>, int> g_axis_rows;
+
+// The preferred rows of a solve on an nr x nv x ny grid: the override for
+// its exact line shape, else for its line length, else the global setting.
+void plan_rows(int nr, int nv, int ny, int rows[3])
+{
+    const int n[3] = {nr, nv, ny};
+    const int64_t lines[3] = {(int64_t)nv * ny, (int64_t)nr * ny, (int64_t)nr * nv};
+    for (int a = 0; a < 3; ++a) {
+        rows[a] = g_rows[a];
+        auto it = g_axis_rows.find(std::make_tuple(a, n[a], lines[a]));
+        if (it == g_axis_rows.end()) it = g_axis_rows.find(std::make_tuple(a, n[a], (int64_t)0));
+        if (it != g_axis_rows.end()) rows[a] = it->second;
+    }
+}
+
 int g_exp_J = 8;      // v nodes per k_exp thread (4, 8 or 16)
 bool g_fuse_r = true;  // fuse the explicit predictor with the spike r solve where k_exr applies
+bool g_exr_window = true;  // the fused kernel's explicit phase reads its neighbours from an LDS window
 constexpr int kMaxBatchLanes = 8;
 int g_batch_lanes = 3;  // streams a batch spreads its solves over
 bool g_batch_share = true;  // solves of one operator share tables and y pivots
@@ -342,6 +365,7 @@ constexpr int kLCDoubles = 16;  // per-line constants of the explicit phase
 Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
 {
     Plan p;
+    std::memcpy(p.rows, rows, sizeof p.rows);
     p.r_spike = r_spike;
     p.r_S = (nr + rows[0] - 1) / rows[0];
     p.r_pitch = (nr + 4) | 1;  // two zero pads per side, odd: conflict-free strided LDS access
@@ -393,6 +417,9 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     }
     p.exr_P = p.exr_tiles = p.exr_tab = 0;
     p.exr_lds = 0;
+    // the window variant addresses the grid as one buffer of < 4 GiB
+    // the window variant addresses the grid as one buffer of < 4 GiB
+    p.exr_win = g_exr_window && (uint64_t)nr * nv * ny * 8 < (1ull << 32);
     if (p.rs_rows >= 8 && nr <= kExrMaxNr) {
         p.exr_P = kBlock / nr;
         p.exr_tiles = ((ny + p.exr_P - 1) / p.exr_P) * ((nv + kExrJ - 1) / kExrJ);
@@ -919,7 +946,7 @@ hjm_status grid_plan(const hjm_axis ax[3], const hjm_model& model, const hjm_pay
 {
     const bool corr = scheme.kind != HJM_SCHEME_DOUGLAS;
     int rows[3];
-    std::memcpy(rows, g_rows, sizeof rows);
+    plan_rows(ax[0].n, ax[1].n, ax[2].n, rows);
     const Plan plan = make_plan(ax[0].n, ax[1].n, ax[2].n, rows, r_spike_ok(ax, model, payoff, n_steps, scheme.theta));
     if (corr && (!(plan.r_mode == R_FUSED || plan.r_mode == R_SPLIT) || !plan.yc_rows))
         return fail(HJM_EINVAL,
@@ -944,7 +971,7 @@ hjm_status grid_init(hjm_grid* g, const hjm_axis ax[3], const hjm_model& model, 
     g->model.curve_t = g->model.curve_p = nullptr;  // the knots are not kept
     g->payoff = payoff;
     g->n_steps = n_steps;
-    std::memcpy(g->rows, g_rows, sizeof g->rows);
+    std::memcpy(g->rows, plan.rows, sizeof g->rows);
     g->plan = plan;
     g->scheme = scheme;
     g->corr = corr;
@@ -1067,6 +1094,33 @@ hjm_status hjm_set_line_tile(int32_t r_rows, int32_t v_rows, int32_t y_rows)
     return HJM_OK;
 }
 
+hjm_status hjm_set_axis_tile(int32_t axis, int32_t n, int64_t lines, int32_t rows)
+{
+    if (axis < 0 || axis > 2) return fail(HJM_EINVAL, "axis must be 0 (r), 1 (v) or 2 (y) (got %d)", axis);
+    if (n < 5 || n > kMaxNodes) return fail(HJM_EINVAL, "node count %d outside [5, %d]", n, kMaxNodes);
+    if (lines < 0) return fail(HJM_EINVAL, "negative line count");
+    if (rows != 0 && rows != 8 && rows != 16 && rows != 32)
+        return fail(HJM_EINVAL, "line tile rows must be 0 (no override), 8, 16 or 32 (got %d)", rows);
+    const auto key = std::make_tuple((int)axis, (int)n, (int64_t)lines);
+    if (rows) g_axis_rows[key] = rows;
+    else g_axis_rows.erase(key);
+    return HJM_OK;
+}
+
+hjm_status hjm_get_axis_tile(int32_t axis, int32_t n, int64_t lines, int32_t* rows)
+{
+    if (!rows) return fail(HJM_EINVAL, "null argument");
+    auto it = g_axis_rows.find(std::make_tuple((int)axis, (int)n, (int64_t)lines));
+    *rows = it == g_axis_rows.end() ? 0 : it->second;
+    return HJM_OK;
+}
+
+hjm_status hjm_clear_axis_tiles(void)
+{
+    g_axis_rows.clear();
+    return HJM_OK;
+}
+
 hjm_status hjm_set_explicit_chunk(int32_t J)
 {
     if (J != 4 && J != 8 && J != 16) return fail(HJM_EINVAL, "explicit chunk must be 4, 8 or 16 (got %d)", J);
@@ -1077,6 +1131,19 @@ hjm_status hjm_set_explicit_chunk(int32_t J)
 hjm_status hjm_set_r_fusion(int32_t on)
 {
     g_fuse_r = on != 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_set_exr_window(int32_t on)
+{
+    g_exr_window = on != 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_exr_window(int32_t* on)
+{
+    if (!on) return fail(HJM_EINVAL, "null argument");
+    *on = g_exr_window ? 1 : 0;
     return HJM_OK;
 }
 
@@ -1228,7 +1295,7 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
             }
             if (pass == 0 && split) e = launch_exp(p.exp_J, dd, nullptr, p.exp_tiles, n, g->stream, st2);
             else if (pass == 0 && p.r_mode == R_FUSED)
-                e = launch_exr(p.rs_rows, dd, nullptr, p.exr_tiles, n, p.exr_lds, g->stream, st2);
+                e = launch_exr(p.rs_rows, dd, nullptr, p.exr_tiles, n, p.exr_lds, g->stream, st2, p.exr_win);
             else if (pass == 0) e = launch_xr(g->rows[0], dd, nullptr, p.r_tiles, n, p.r_lds, g->stream);
             else if (pass == 1) e = launch_rs(p.rs_rows, dd, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
             else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, dd, nullptr, p.vs_tiles, p.vs_S, g->stream);
@@ -1517,7 +1584,7 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step, hipS
     const int2* t = b->d_tasks + g.off;
     switch (g.kind) {
     case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, st);
-    case G_EXR: return launch_exr(g.rows, b->d_desc, t, nt, step, g.lds, st);
+    case G_EXR: return launch_exr(g.rows & 0xff, b->d_desc, t, nt, step, g.lds, st, false, (g.rows >> 8) != 0);
     case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, st);
     case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, st);
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, st);
@@ -1641,7 +1708,9 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
                 own = q;
         b->owner[s] = own;
         if (own == s) {
-            plans[s] = make_plan(a[0].n, a[1].n, a[2].n, b->rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
+            int rows[3];
+            plan_rows(a[0].n, a[1].n, a[2].n, rows);
+            plans[s] = make_plan(a[0].n, a[1].n, a[2].n, rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
             build_tables(a, model[s], payoff[s], n_steps[s], plans[s], b->tables[s]);
             b->n_operators += 1;
         } else {
@@ -1698,14 +1767,17 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
                 int aux = 0;
                 switch (kind) {
                 case G_XR:
-                    if (pl.r_mode == R_SPIKE || pl.r_mode == R_CHAIN) { rows = b->rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; }
+                    if (pl.r_mode == R_SPIKE || pl.r_mode == R_CHAIN) { rows = pl.rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; }
                     break;
-                case G_EXR: if (pl.r_mode == R_FUSED) { rows = pl.rs_rows; tiles = pl.exr_tiles; lds = pl.exr_lds; } break;
+                case G_EXR:
+                    // rows, plus 256 for the window variant (its own group)
+                    if (pl.r_mode == R_FUSED) { rows = pl.rs_rows + (pl.exr_win ? 256 : 0); tiles = pl.exr_tiles; lds = pl.exr_lds; }
+                    break;
                 case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
                 case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
-                case G_V: if (!pl.vs_rows) { rows = b->rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
+                case G_V: if (!pl.vs_rows) { rows = pl.rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
                 case G_VS: if (pl.vs_rows) { rows = pl.vs_rows; tiles = pl.vs_tiles; aux = pl.vs_S; } break;
-                case G_YU: if (!pl.yc_rows) { rows = b->rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
+                case G_YU: if (!pl.yc_rows) { rows = pl.rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
                 default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; aux = pl.yc_S; } break;
                 }
                 if (!tiles) continue;

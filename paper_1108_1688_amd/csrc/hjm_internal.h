@@ -180,10 +180,14 @@ hipError_t launch_exp(int J, const SolveDesc* d_desc, const int2* tasks, int n_t
 hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, int nr_max,
                      hipStream_t st);
 // k_exr dynamic LDS (bytes) and table offset (doubles) for nr = S * rows
-// (rows >= 8: a pass's scratch, 8 doubles per lane, fits in its rows)
+// (rows >= 8: a pass's scratch, 8 doubles per lane, fits in its rows); the
+// same for both explicit phases
 void exr_lds(int nr, int rows, size_t* bytes, int* tab);
+// window: the explicit phase reads its neighbours from an LDS window of its
+// tile (else each thread loads its own).  The predictor only: the corrected
+// start keeps the per-lane loads.
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
-                      hipStream_t st, bool stage2 = false);
+                      hipStream_t st, bool stage2 = false, bool window = false);
 // rows per thread available to k_rs
 bool rs_rows_supported(int rows);
 hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);

@@ -49,6 +49,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "hjm_internal.h"
 
 namespace hjm {
@@ -1494,69 +1496,213 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     if (store && !ok) raise_flag(s);
 }
 
-// Explicit predictor (or, STAGE2, the corrected start of the Craig-Sneyd
-// family) and r sweep in one kernel (nr <= 256, nr = S * ROWS as for k_rs,
-// ROWS >= 8): the workgroup computes D0 on kExrJ consecutive v nodes of
-// exr_P = 256 / nr whole y planes (thread = (i, plane)) into an LDS tile,
-// then solves the tile's exr_P * kExrJ r lines with the spike method, S lanes
-// per line, and writes D1.  D0 never goes to memory: 16 bytes per point less
-// than the split pair.  Tile layout: line (plane kk, node jj) at
-// (kk kExrJ + jj) S (ROWS + 1), its segment g at g (ROWS + 1) (the pad spreads
-// a wave's segments over the banks).  The lanes of pass p reuse their own
-// lines' part of the tile as the reduced-system scratch once every lane has
-// read its rows (pass p's scratch is its first 8 kBlock doubles, inside its
-// kBlock / S lines; the tile is sized to whole passes).  Three waves per SIMD
-// (at most 168 VGPRs; a few spill) measured faster than two without spills.
-// v nodes per explicit chunk of k_exr: 8; 4 for the corrected start, which
-// holds the stencil of U while it loads the windows of D3
-template <bool STAGE2>
-constexpr int kExrChunk = STAGE2 ? 4 : 8;
+// A solve's grid as a raw buffer: a load names a per-lane byte offset
+// (one VGPR, the same for every load of a thread) and a wave-uniform byte
+// offset (an SGPR, formed by scalar arithmetic), so loads cost no vector
+// address arithmetic.  The host keeps the grid under 4 GiB for this path.
+struct GridBuf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ GridBuf(const double* base, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)bytes, 0x00020000))
+    {
+    }
+    __device__ __forceinline__ double operator()(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    }
+};
 
-template <int ROWS, bool STAGE2>
-__global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
-                                                int step)
+// Per-column constants of the explicit predictor at (i, plane k): the A1
+// row pieces (affine in v), the A3 coefficient and weights, the A0 factor,
+// and the Dirichlet increment of the column's Dirichlet nodes (as
+// explicit_nodes forms them).
+struct ExpColumn {
+    double mlo, alo, mdi, adi, mup, aup, mex, ryk, kyk, rx, wa, wb, w2, gval, dt;
+    bool dir, yhd;
+    int dx;  // outflow r face rows reach two nodes in (+2 at r_min, -2 at r_max)
+    __device__ __forceinline__ ExpColumn(const SolveDesc& s, int i, int k, int step)
+    {
+        const int nr = s.nr, ny = s.ny;
+        gcdouble* rt = gp(s.rt);
+        gcdouble* yt = gp(s.yt);
+        gcdouble* stn = gp(s.st) + kStepStride * step;
+        const double c = stn[ST_PHI] + yt[YT_Y * ny + k];
+        const double e = rt[RT_P * nr + i] * c + rt[RT_Q * nr + i];
+        mlo = rt[RT_MLO * nr + i] * e;
+        alo = rt[RT_ALO * nr + i];
+        mdi = rt[RT_MDI * nr + i] * e - rt[RT_RR * nr + i];
+        adi = rt[RT_ADI * nr + i];
+        mup = rt[RT_MUP * nr + i] * e;
+        aup = rt[RT_AUP * nr + i];
+        mex = rt[RT_MEX * nr + i] * e;
+        ryk = rt[RT_Y * nr + i] * yt[YT_I * ny + k];
+        kyk = yt[YT_K * ny + k];
+        rx = rt[RT_X * nr + i];
+        wa = yt[YT_W1 * ny + k];
+        wb = yt[YT_W3 * ny + k];
+        if (k == 0) { wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
+        else if (k == ny - 1) { wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
+        w2 = yt[YT_W2 * ny + k];
+        yhd = s.y_hi_dir && k == ny - 1;
+        gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
+        const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
+        dir = rlo || rhi || yhd;
+        gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
+        dt = s.dt;
+        dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
+    }
+};
+
+// D0 at (i, j0 + m, k), m < J, j0 + m < nv, from the LDS window (wcol: this
+// thread's column of the window, J + 4 rows at pitch nr holding v nodes
+// j0 - 2 .. j0 + J + 1; the neighbouring columns beside it), the tile's
+// v-table values in LDS (vtc: kVT rows of J, row r node m = vt[r][j0 + m];
+// every lane reads the same address, a broadcast) and the y neighbours ya,
+// yb (planes k + oa, k + ob): the arithmetic of explicit_nodes, so the same
+// values.  Nothing here waits on a scalar load: the v-table values come
+// from LDS, whose reads return in order.  The nodes go in chunks of CH, each
+// reading its window rows (the column itself too) only when it starts, so
+// the registers hold one chunk's neighbours, not the whole window.
+template <int J>
+__device__ __forceinline__ void window_nodes(const SolveDesc& s, const ldouble* wcol, const ldouble* vtc,
+                                             const ExpColumn& q, const double (&ya)[J], const double (&yb)[J],
+                                             int j0, double (&out)[J])
 {
-    extern __shared__ double lds_raw[];
-    ldouble* lds = (ldouble*)lds_raw;
-    const int bi = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int2 tk = tasks ? tasks[bi] : make_int2(0, bi);
-    const SolveDesc& s = descs[tk.x];
-    if (step >= s.n_steps) return;  // whole workgroup: uniform
+    const int nr = s.nr, nv = s.nv;
+    constexpr int CH = 4;
+#pragma unroll
+    for (int m0 = 0; m0 < J; m0 += CH) {
+        __builtin_amdgcn_sched_barrier(0);
+        double col[CH + 4];
+#pragma unroll
+        for (int c = 0; c < CH + 4; ++c) col[c] = wcol[(size_t)(m0 + c) * nr];
+#pragma unroll
+        for (int mm = 0; mm < CH; ++mm) {
+            const int m = m0 + mm;
+            const int j = j0 + m;
+            if (j >= nv) break;  // wave-uniform
+            // window rows m + 1 .. m + 3 hold v nodes j - 1 .. j + 1
+            const ldouble* w0 = wcol + (size_t)(m + 2) * nr;
+            const double lw0 = w0[-1], rw0 = w0[1];
+            const double lwm = w0[-1 - nr], rwm = w0[1 - nr];
+            const double lwp = w0[nr - 1], rwp = w0[nr + 1];
+            const double* cw5 = col + mm;  // u(i, j - 2 .. j + 2)
+            const double ux = q.dx != 0 ? w0[q.dx] : cw5[2];
+            const double v = vtc[VT_V * J + m];
+            const double olo = q.mlo + q.alo * v, odi = q.mdi + q.adi * v, oup = q.mup + q.aup * v;
+            const double a1 = olo * lw0 + odi * cw5[2] + oup * rw0 + q.mex * ux;
+            const double a2 = vtc[VT_O0 * J + m] * cw5[0] + vtc[VT_O1 * J + m] * cw5[1] +
+                              vtc[VT_O2 * J + m] * cw5[2] + vtc[VT_O3 * J + m] * cw5[3] +
+                              vtc[VT_O4 * J + m] * cw5[4];
+            const double by = q.ryk * v - q.kyk;
+            const double a3 = by * (q.wa * ya[m] + q.w2 * cw5[2] + q.wb * yb[m]);
+            const double cross = (rwp - rwm) - (lwp - lwm);
+            const double a0 = q.rx * vtc[VT_X * J + m] * cross;
+            const double val = q.dt * (((a1 + a2) + a3) + a0);
+            out[m] = q.dir ? q.gval : val;
+        }
+    }
+}
+
+// The window's guard doubles (two before it, two after its rows of P planes:
+// finite, so that i -+ 1 and i -+ 2 stay inside; their weights are zero where
+// they leave a row).
+__device__ __forceinline__ void window_guards(ldouble* win, int P, int WR, int nr)
+{
+    const int t = (int)threadIdx.x;
+    if (t < 2) {
+        win[t - 2] = 0.0;
+        win[(size_t)P * WR * nr + t] = 0.0;
+    }
+}
+
+// Explicit predictor of the fused kernel from an LDS window.  Thread
+// (i, plane kk) loads its column u(i, j0-2 .. j0+J+1) of plane k and its J y
+// neighbours of planes k+oa, k+ob straight into registers, all at once (v
+// rows past the faces clamp to the face row, scalar arithmetic); the columns
+// go to the window win (per plane J + 4 rows of nr, row pitch nr); after a
+// barrier every neighbour is an LDS read at a fixed offset from the thread's
+// column (window_nodes).  out[m] receives D0 at (i, j0 + m, k) for
+// j0 + m < nv.  UK: every wave lies inside one plane (nr a multiple of 64),
+// so k, the y offsets and the y-table reads are wave-uniform.  Every thread
+// of the workgroup calls it (one barrier inside).
+template <int J, bool UK>
+__device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win, ldouble* vtc, int P, int k0, int j0,
+                                                int step, double (&out)[J])
+{
+    constexpr int WR = J + 4;
     const int nr = s.nr, nv = s.nv, ny = s.ny;
-    const int P = s.exr_P;
+    const int t = (int)threadIdx.x;
+    const int kk = t / nr;
+    const int i = t - kk * nr;
+    const bool act = kk < P && k0 + kk < ny;
+    int k = min(k0 + kk, ny - 1);
+    if (UK) k = __builtin_amdgcn_readfirstlane(k);
+    const bool yhd = s.y_hi_dir && k == ny - 1;
+    int oa = -1, ob = 1;
+    if (k == 0) { oa = 1; ob = 2; }
+    else if (k == ny - 1) { oa = -2; ob = -1; }
+    if (yhd) { oa = 0; ob = 0; }
+    const uint32_t sl = (uint32_t)nr * 8u;
+    const uint32_t sy = (uint32_t)nv * sl;
+    const GridBuf U(s.U, sy * (uint32_t)ny);
+    // per-lane byte offsets: the column of plane k and of the two y neighbours
+    const uint32_t vo = (uint32_t)(UK ? i : k * nr * nv + i) * 8u;
+    const uint32_t po = UK ? (uint32_t)k * sy : 0u;
+    const uint32_t voa = UK ? vo : vo + (uint32_t)(oa * (int)sy);
+    const uint32_t vob = UK ? vo : vo + (uint32_t)(ob * (int)sy);
+    const uint32_t poa = UK ? (uint32_t)(k + oa) * sy : 0u;
+    const uint32_t pob = UK ? (uint32_t)(k + ob) * sy : 0u;
+    auto row = [&](int j) { return (uint32_t)min(max(j, 0), nv - 1) * sl; };
+    double cw[WR], ya[J], yb[J];
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < WR; ++m) cw[m] = U(vo, po + row(j0 - 2 + m));
+#pragma unroll
+        for (int m = 0; m < J; ++m) {
+            ya[m] = U(voa, poa + row(j0 + m));
+            yb[m] = U(vob, pob + row(j0 + m));
+        }
+    }
+    // the tile's v-table values (kVT rows of J; v nodes past nv repeat the
+    // last one, whose results are not stored) by vector loads, into LDS
+    double vv = 0.0;
+    if (t < kVT * J) {
+        const int r = t / J;
+        vv = gp(s.vt)[(size_t)r * nv + min(j0 + (t - r * J), nv - 1)];
+    }
+    const ExpColumn q(s, i, k, step);
+    ldouble* wcol = win + (size_t)kk * WR * nr + i;
+    window_guards(win, P, WR, nr);
+    if (t < kVT * J) vtc[t] = vv;
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < WR; ++m) wcol[(size_t)m * nr] = cw[m];
+    }
+    __syncthreads();
+    if (!act) return;
+    window_nodes<J>(s, wcol, vtc, q, ya, yb, j0, out);
+}
+
+// The r lines of a fused tile (P planes from k0 x kExrJ v nodes from j0,
+// D0 in the tile: line (plane kk, node jj) at (kk kExrJ + jj) LP, segment g
+// at g (ROWS + 1)) by the spike method, S = rs_S lanes per line, and D1 to
+// memory.  The lanes of pass p reuse their own lines' part of the tile as the
+// reduced-system scratch once every lane has read its rows (pass p's scratch
+// is its first 8 kBlock doubles, inside its kBlock / S lines; the tile is
+// sized to whole passes).  Every thread calls it, after a barrier that
+// follows the tile's writes.
+template <int ROWS>
+__device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, const ldouble* tab, int P, int k0,
+                                           int j0, int step)
+{
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
     const int S = s.rs_S;
     const int log2S = s.rs_log2S;
     constexpr int SP = ROWS + 1;
-    const int LP = S * SP;
-    const int nvb = (nv + kExrJ - 1) / kExrJ;
-    const int kb = tk.y / nvb;
-    const int jb = tk.y - kb * nvb;
-    const int k0 = kb * P;
-    const int j0 = __builtin_amdgcn_readfirstlane(jb * kExrJ);
-    const int t = threadIdx.x;
-    ldouble* tile = lds;
     constexpr int TP = kRF * ROWS + 1;
-    ldouble* tab = lds + s.exr_tab;  // after the tile, rounded up to whole passes
-    stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
-    {
-        // explicit phase: thread (i, plane kk); planes past ny do nothing
-        const int kk = t / nr;
-        const int i = t - kk * nr;
-        const int k = k0 + kk;
-        if (kk < P && k < ny) {
-            const int g = i / ROWS;
-            ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
-#pragma unroll 1
-            for (int jc = 0; jc < kExrJ; jc += kExrChunk<STAGE2>) {
-                auto put = [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; };
-                if constexpr (STAGE2)
-                    corrected_start<kExrChunk<STAGE2>, true>(s, i, k, j0 + jc, step, put);
-                else
-                    explicit_nodes<kExrChunk<STAGE2>, true>(s, i, k, j0 + jc, step, put);
-            }
-        }
-    }
-    __syncthreads();
+    const int LP = S * SP;
+    const int t = (int)threadIdx.x;
     const double phi = gp(s.st)[kStepStride * step + ST_PHI];
     const int L = P * kExrJ;
     for (int base = 0; base < L * S; base += kBlock) {  // uniform trip count
@@ -1589,6 +1735,128 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
         }
         // the next pass reads only its own lines' rows, which this pass's
         // scratch does not reach: no barrier needed here
+    }
+}
+
+// Explicit predictor (or, STAGE2, the corrected start of the Craig-Sneyd
+// family) and r sweep in one kernel (nr <= 256, nr = S * ROWS as for k_rs,
+// ROWS >= 8): the workgroup computes D0 on kExrJ consecutive v nodes of
+// exr_P = 256 / nr whole y planes (thread = (i, plane)) into an LDS tile,
+// then solves the tile's exr_P * kExrJ r lines with the spike method, S lanes
+// per line, and writes D1.  D0 never goes to memory: 16 bytes per point less
+// than the split pair.  Tile layout: line (plane kk, node jj) at
+// (kk kExrJ + jj) S (ROWS + 1), its segment g at g (ROWS + 1) (the pad spreads
+// a wave's segments over the banks).  The lanes of pass p reuse their own
+// lines' part of the tile as the reduced-system scratch once every lane has
+// read its rows (pass p's scratch is its first 8 kBlock doubles, inside its
+// kBlock / S lines; the tile is sized to whole passes).  Three waves per SIMD
+// (at most 168 VGPRs; a few spill) measured faster than two without spills.
+// v nodes per explicit chunk of k_exr: 8; 4 for the corrected start, which
+// holds the stencil of U while it loads the windows of D3
+template <bool STAGE2>
+constexpr int kExrChunk = STAGE2 ? 4 : 8;
+
+template <int ROWS, bool STAGE2, bool WIN = false>
+__global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
+                                                int step)
+{
+    extern __shared__ double lds_raw[];
+    ldouble* lds = (ldouble*)lds_raw;
+    const int bi = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int2 tk = tasks ? tasks[bi] : make_int2(0, bi);
+    const SolveDesc& s = descs[tk.x];
+    if (step >= s.n_steps) return;  // whole workgroup: uniform
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int P = s.exr_P;
+    const int S = s.rs_S;
+    constexpr int SP = ROWS + 1;
+    const int LP = S * SP;
+    const int nvb = (nv + kExrJ - 1) / kExrJ;
+    const int kb = tk.y / nvb;
+    const int jb = tk.y - kb * nvb;
+    const int k0 = kb * P;
+    const int j0 = __builtin_amdgcn_readfirstlane(jb * kExrJ);
+    const int t = threadIdx.x;
+    ldouble* tile = lds;
+    ldouble* tab = lds + s.exr_tab;  // after the tile, rounded up to whole passes
+    stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
+    if constexpr (WIN && !STAGE2) {
+        // explicit phase from the LDS window (it shares the LDS of the tile,
+        // which is written once every thread has finished reading it)
+        double out[kExrJ];
+        // the v-table cache after the row table
+        ldouble* vtc = tab + (size_t)S * (kRF * ROWS + 1);
+        if (nr % 64 == 0)
+            explicit_window<kExrJ, true>(s, tile + 2, vtc, P, k0, j0, step, out);
+        else
+            explicit_window<kExrJ, false>(s, tile + 2, vtc, P, k0, j0, step, out);
+        const int kk = t / nr;
+        const int i = t - kk * nr;
+        __syncthreads();
+        if (kk < P && k0 + kk < ny) {
+            const int g = i / ROWS;
+            ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
+#pragma unroll
+            for (int m = 0; m < kExrJ; ++m)
+                if (j0 + m < nv) dst[(size_t)m * LP] = out[m];
+        }
+    } else {
+        // explicit phase: thread (i, plane kk); planes past ny do nothing
+        const int kk = t / nr;
+        const int i = t - kk * nr;
+        const int k = k0 + kk;
+        if (kk < P && k < ny) {
+            const int g = i / ROWS;
+            ldouble* dst = tile + (size_t)kk * kExrJ * LP + g * SP + (i - g * ROWS);
+#pragma unroll 1
+            for (int jc = 0; jc < kExrJ; jc += kExrChunk<STAGE2>) {
+                auto put = [&](int m, double x) { dst[(size_t)(jc + m) * LP] = x; };
+                if constexpr (STAGE2)
+                    corrected_start<kExrChunk<STAGE2>, true>(s, i, k, j0 + jc, step, put);
+                else
+                    explicit_nodes<kExrChunk<STAGE2>, true>(s, i, k, j0 + jc, step, put);
+            }
+        }
+    }
+    __syncthreads();
+    if constexpr (WIN && !STAGE2) {
+        solve_tile<ROWS>(s, tile, tab, P, k0, j0, step);
+    } else {
+        // the same passes as solve_tile, written out here: inlined as one
+        // function the per-lane-load variants keep fewer registers spilled
+        const int log2S = s.rs_log2S;
+        constexpr int TP = kRF * ROWS + 1;
+        const double phi = gp(s.st)[kStepStride * step + ST_PHI];
+        const int L = P * kExrJ;
+        for (int base = 0; base < L * S; base += kBlock) {  // uniform trip count
+            const int u = base + t;
+            const int ln = u >> log2S;
+            const int seg = u & (S - 1);
+            const int kk = ln / kExrJ;
+            const int jj = ln - kk * kExrJ;
+            const int k = min(k0 + kk, ny - 1);
+            const int j = min(j0 + jj, nv - 1);
+            const bool active = ln < L && k0 + kk < ny && j0 + jj < nv;
+            double d[ROWS];
+            const ldouble* src = tile + (size_t)min(ln, L - 1) * LP + seg * SP;
+#pragma unroll
+            for (int mm = 0; mm < ROWS; ++mm) d[mm] = src[mm];
+            __syncthreads();  // every lane of the pass has read its rows: the scratch may overwrite them
+            // Dirichlet y_max lines keep D0 (wave-uniform: a wave's lines share the plane)
+            const bool ydir = s.y_hi_dir && k == ny - 1;
+            bool ok = true;
+            if (!ydir) {
+                const double v = gp(s.vt)[VT_V * nv + j];
+                const double c = phi + gp(s.yt)[YT_Y * ny + k];
+                ok = spike_r_lane<ROWS>(s, tab + seg * TP, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
+            }
+            if (active) {
+                gdouble* line = gp(s.D) + ((size_t)k * nv + j) * nr + (size_t)seg * ROWS;
+#pragma unroll
+                for (int mm = 0; mm < ROWS; ++mm) line[mm] = d[mm];
+                if (!ok) raise_flag(s);
+            }
+        }
     }
 }
 
@@ -1969,7 +2237,9 @@ hipError_t init_kernel_attributes()
             (e = allow_lds(k_yu<8>)) || (e = allow_lds(k_yu<16>)) || (e = allow_lds(k_yu<32>)) ||
             (e = allow_lds(k_rs<6>)) || (e = allow_lds(k_rs<8>)) || (e = allow_lds(k_rs<12>)) ||
             (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_exr<8, false>)) || (e = allow_lds(k_exr<12, false>)) ||
-            (e = allow_lds(k_exr<16, false>)) || (e = allow_lds(k_exr<8, true>)) ||
+            (e = allow_lds(k_exr<16, false>)) || (e = allow_lds(k_exr<8, false, true>)) ||
+            (e = allow_lds(k_exr<12, false, true>)) || (e = allow_lds(k_exr<16, false, true>)) ||
+            (e = allow_lds(k_exr<8, true>)) ||
             (e = allow_lds(k_exr<12, true>)) || (e = allow_lds(k_exr<16, true>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
             (e = allow_lds(k_vs<32>)) || (e = allow_yc<8>()) || (e = allow_yc<16>()) || (e = allow_yc<32>()))
             return e;
@@ -2073,15 +2343,28 @@ void exr_lds(int nr, int rows, size_t* bytes, int* tab)
     const int P = kBlock / nr;
     const int lanes = P * kExrJ * S;
     const int passes = (lanes + kBlock - 1) / kBlock;
-    const int tile = passes * kBlock * (rows + 1);  // whole passes: the last pass's scratch stays inside
+    // whole passes: the last pass's scratch stays inside; at least the
+    // window variant's explicit window (J + 4 rows of nr per plane, two
+    // guard doubles each side), which the tile overwrites after it
+    const int tile = std::max(passes * kBlock * (rows + 1), P * (kExrJ + 4) * nr + 4);
     *tab = tile;
-    *bytes = ((size_t)tile + (size_t)S * (kRF * rows + 1)) * 8;
+    // the row table, then the window variant's v-table cache (kVT x kExrJ)
+    *bytes = ((size_t)tile + (size_t)S * (kRF * rows + 1) + (size_t)kVT * kExrJ) * 8;
 }
 
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
-                      hipStream_t st, bool stage2)
+                      hipStream_t st, bool stage2, bool window)
 {
     if (n_tasks <= 0) return hipSuccess;
+    if (window && !stage2) {
+        switch (rows) {
+        case 8: HJM_LAUNCH((k_exr<8, false, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        case 12: HJM_LAUNCH((k_exr<12, false, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        case 16: HJM_LAUNCH((k_exr<16, false, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (stage2) {
         switch (rows) {
         case 8: HJM_LAUNCH((k_exr<8, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;

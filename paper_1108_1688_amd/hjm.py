@@ -99,10 +99,15 @@ def lib():
         "hjm_batch_profile_read": (st, [vp, P(d), P(i64), P(i64)]),
         "hjm_set_line_tile": (st, [i32, i32, i32]),
         "hjm_get_line_tile": (st, [P(i32), P(i32), P(i32)]),
+        "hjm_set_axis_tile": (st, [i32, i32, i64, i32]),
+        "hjm_get_axis_tile": (st, [i32, i32, i64, P(i32)]),
+        "hjm_clear_axis_tiles": (st, []),
         "hjm_set_explicit_chunk": (st, [i32]),
         "hjm_get_explicit_chunk": (st, [P(i32)]),
         "hjm_set_r_fusion": (st, [i32]),
         "hjm_get_r_fusion": (st, [P(i32)]),
+        "hjm_set_exr_window": (st, [i32]),
+        "hjm_get_exr_window": (st, [P(i32)]),
         "hjm_set_batch_streams": (st, [i32]),
         "hjm_get_batch_streams": (st, [P(i32)]),
         "hjm_set_batch_share": (st, [i32]),
@@ -178,6 +183,24 @@ def get_line_tile():
     return r.value, v.value, y.value
 
 
+def set_axis_tile(axis: int, n: int, lines: int, rows: int) -> None:
+    """Preferred rows per thread (8, 16, 32; 0 clears) of the line solves
+    along axis (0 r, 1 v, 2 y) on grids with n nodes there and `lines` such
+    lines (0: any count), for handles created afterwards (overrides
+    set_line_tile for that shape)."""
+    check(lib().hjm_set_axis_tile(int(axis), int(n), int(lines), int(rows)))
+
+
+def get_axis_tile(axis: int, n: int, lines: int = 0) -> int:
+    r = C.c_int32()
+    check(lib().hjm_get_axis_tile(int(axis), int(n), int(lines), C.byref(r)))
+    return r.value
+
+
+def clear_axis_tiles() -> None:
+    check(lib().hjm_clear_axis_tiles())
+
+
 def set_explicit_chunk(J: int) -> None:
     """v nodes per thread of the explicit-predictor kernel (4, 8 or 16) for handles created afterwards."""
     check(lib().hjm_set_explicit_chunk(J))
@@ -198,6 +221,18 @@ def set_r_fusion(on: bool) -> None:
 def get_r_fusion() -> bool:
     on = C.c_int32()
     check(lib().hjm_get_r_fusion(C.byref(on)))
+    return bool(on.value)
+
+
+def set_exr_window(on: bool) -> None:
+    """Explicit phase of the fused kernel from an LDS window (default) or
+    from per-thread neighbour loads, for handles created afterwards."""
+    check(lib().hjm_set_exr_window(1 if on else 0))
+
+
+def get_exr_window() -> bool:
+    on = C.c_int32()
+    check(lib().hjm_get_exr_window(C.byref(on)))
     return bool(on.value)
 
 

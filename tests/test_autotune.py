@@ -1,45 +1,55 @@
-"""Autotuner: selection logic (host only) and, on a GPU, a tuned solve."""
+"""Autotuner: selection logic (host only) and, on a GPU, per-shape tiles
+that a batch applies, with the tuned solves against the oracle."""
 import numpy as np
 import pytest
 
 from paper_1108_1688_amd import workloads as W
 
 
-def test_choose_takes_each_kernels_best_value():
+def test_line_shapes_of_a_grid():
     from paper_1108_1688_amd import autotune as A
-    runs = [{"setting": (8, 8, 8, 4), "us": [30.0, 50.0, 20.0, 40.0]},
-            {"setting": (16, 16, 16, 8), "us": [25.0, 35.0, 22.0, 33.0]},
-            {"setting": (32, 32, 32, 16), "us": [28.0, 36.0, 18.0, 35.0]}]
-    setting, per = A.choose(runs, split=True)
-    assert setting == (16, 32, 16, 8)
-    assert per == {"explicit": 25.0, "r": 35.0, "v": 18.0, "y+update": 33.0}
+    assert A.line_shapes((96, 48, 32)) == [(0, 96, 48 * 32), (1, 48, 96 * 32), (2, 32, 96 * 48)]
 
 
-def test_choose_fused_r_follows_the_explicit_pass():
+def test_choose_takes_each_line_shapes_fastest_candidate():
     from paper_1108_1688_amd import autotune as A
-    from paper_1108_1688_amd import hjm
-    runs = [{"setting": (8, 8, 8, 4), "us": [90.0, 0.0, 20.0, 40.0]},
-            {"setting": (16, 16, 16, 8), "us": [80.0, 0.0, 22.0, 33.0]},
-            {"setting": (32, 32, 32, 16), "us": [95.0, 0.0, 18.0, 35.0]}]
-    setting, _ = A.choose(runs, split=False)
-    assert setting[:3] == (16, 32, 16) and setting[3] == hjm.get_explicit_chunk()
+    times = {(0, 96, 1536): {8: 30.0, 16: 25.0, 32: 28.0},
+             (1, 48, 3072): {8: 20.0, 16: 22.0, 32: 18.0},
+             (2, 32, 4608): {8: 9.0, 16: 11.0, 32: 10.0}}
+    assert A.choose(times) == {(0, 96, 1536): 16, (1, 48, 3072): 32, (2, 32, 4608): 8}
 
 
-def test_representatives_weights_sum_to_one_and_prefer_big_work():
+def test_shapes_by_work_weights_sum_to_one():
     from paper_1108_1688_amd import autotune as A
     specs = W.config4(64)
-    reps = A.representatives(specs, k=3)
-    assert len(reps) == 3
-    work = {}
-    for s in specs:
-        sh = s.shape
-        work[sh] = work.get(sh, 0) + s.points * s.n_steps
-    top = sorted(work.values(), reverse=True)[:3]
-    assert np.allclose([w for _, w in reps], [t / sum(work.values()) for t in top])
+    shapes = A.shapes_by_work(specs)
+    total = sum(s.points * s.n_steps for s in specs)
+    assert abs(sum(w for _, w in shapes.values()) - 1.0) < 1e-12
+    for sh, (spec, w) in shapes.items():
+        assert spec.shape[::-1] == sh
+        mine = sum(s.points * s.n_steps for s in specs if s.shape[::-1] == sh)
+        assert abs(w - mine / total) < 1e-12
+        assert spec.n_steps == max(s.n_steps for s in specs if s.shape[::-1] == sh)
+
+
+def test_axis_tile_overrides_round_trip_and_refusals():
+    from paper_1108_1688_amd import hjm
+    hjm.clear_axis_tiles()
+    hjm.set_axis_tile(1, 48, 0, 32)
+    hjm.set_axis_tile(2, 96, 96 * 64, 8)
+    assert hjm.get_axis_tile(1, 48) == 32 and hjm.get_axis_tile(2, 96, 96 * 64) == 8
+    assert hjm.get_axis_tile(2, 96) == 0
+    for bad in ((3, 48, 0, 16), (0, 4, 0, 16), (0, 48, 0, 12), (0, 48, -1, 16)):
+        with pytest.raises(hjm.HjmError):
+            hjm.set_axis_tile(*bad)
+    hjm.set_axis_tile(1, 48, 0, 0)
+    assert hjm.get_axis_tile(1, 48) == 0
+    hjm.clear_axis_tiles()
+    assert hjm.get_axis_tile(2, 96, 96 * 64) == 0
 
 
 @pytest.mark.gpu
-def test_tuned_solve_matches_oracle(tmp_path):
+def test_tuned_batch_matches_oracle_and_untuned(tmp_path):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -47,25 +57,32 @@ def test_tuned_solve_matches_oracle(tmp_path):
     from adapt import to_oracle
     from paper_1108_1688_amd import autotune as A
     from paper_1108_1688_amd import hjm
-    old = hjm.get_line_tile(), hjm.get_explicit_chunk()
+    old = hjm.get_line_tile()
+    base = W.config2()[1]
+    specs = [W.with_shape(base, 64, 48, 32, 30), W.with_shape(base, 96, 32, 64, 24),
+             W.with_shape(base, 32, 64, 48, 20)]
     try:
-        s = W.with_shape(W.config2()[1], 64, 48, 32, 30)
+        hjm.clear_axis_tiles()
+        untuned = hjm.Batch(specs).run().prices()
         cache = str(tmp_path / "tune.json")
-        t = A.tune([s], steps=3, cache=cache)
-        assert len(t.runs) == len(A.DIAGONAL) and not t.cached
-        assert (hjm.get_line_tile() + (hjm.get_explicit_chunk(),)) == t.setting
-        again = A.tune([s], cache=cache)
-        assert again.cached and again.setting == t.setting
-        g = hjm.Grid(s)
-        g.step()
-        pg = g.price()
-        Ug = g.solution().cpu().numpy().copy()
-        g.close()
-        p = to_oracle(s)
-        Uo = O.run(p, 0, s.n_steps)
-        assert np.abs(Ug - Uo).max() <= 1e-12 * np.abs(Uo).max()
-        po = O.readout(p, Uo, s.r0, s.v0)
-        assert abs(pg - po) <= 1e-12 * abs(po)
+        t = A.tune(specs, steps=3, cache=cache)
+        assert not t.cached and t.timed_grids == 3 * len(A.CANDIDATES)
+        assert len(t.choice) == 9
+        assert tuple(hjm.get_line_tile()) == tuple(old)
+        for (axis, n, lines), rows in t.choice.items():
+            assert hjm.get_axis_tile(axis, n, lines) == rows
+        print(f"tuned: {t.summary()}")
+        again = A.tune(specs, cache=cache)
+        assert again.cached and again.choice == t.choice
+        tuned = hjm.Batch(specs).run().prices()
+        for sp, pb, pu in zip(specs, tuned, untuned):
+            g = hjm.Grid(sp)
+            g.step()
+            assert g.price() == pb
+            g.close()
+            po, _ = O.price(to_oracle(sp), sp.r0, sp.v0)
+            assert abs(pb - po) <= 1e-12 * abs(po)
+            assert abs(pu - po) <= 1e-12 * abs(po)
     finally:
-        hjm.set_line_tile(*old[0])
-        hjm.set_explicit_chunk(old[1])
+        hjm.clear_axis_tiles()
+        hjm.set_line_tile(*old)

@@ -10,8 +10,10 @@ size of that effect is measured, not assumed: the oracle's float32-sum
 variant (emulate32) differs from its float64-sum variant by the same
 mechanism, and the GPU must stay within three times that distance (plus
 1e-5 of the output scale); a wrong layout or index would miss it by orders
-of magnitude.  Gradient tensors agree to 1e-2 in relative L2 norm; box flags
-are compared exactly (both sides compare the same float32 values).
+of magnitude.  Gradient tensors agree per tensor in relative L2 norm within
+four times the same spread of the oracle's gradients (the GPU also sums the
+backward products in float32), plus 2e-5; box flags are compared exactly
+(both sides compare the same float32 values).
 """
 import math
 
@@ -132,12 +134,17 @@ def test_gradients_and_loss_match_oracle():
     sse = m.gradients(_dev(x), _dev(t))
     g = m.grads().astype(np.float64)
     so, go = M.loss_and_grads(p.astype(np.float64), x, t, LO, HI, emulate=True)
-    assert abs(sse - so) <= 1e-4 * so
-    G, Go = M.unpack(g), M.unpack(go)
+    s32, g32 = M.loss_and_grads(p.astype(np.float64), x, t, LO, HI, emulate="emulate32")
+    assert abs(sse - so) <= 3 * abs(s32 - so) + 1e-6 * so
+    G, Go, G32 = M.unpack(g), M.unpack(go), M.unpack(g32)
     for name, _ in M.SHAPES:
-        rel = np.linalg.norm(G[name] - Go[name]) / max(np.linalg.norm(Go[name]), 1e-30)
-        print(f"{name}: rel L2 err {rel:.2e}")
-        assert rel <= 1e-2, name
+        norm = max(np.linalg.norm(Go[name]), 1e-30)
+        rel = np.linalg.norm(G[name] - Go[name]) / norm
+        # the oracle's own spread between float32 and float64 layer sums (the
+        # GPU also sums the backward products in float32, hence 4x)
+        spread = np.linalg.norm(G32[name] - Go[name]) / norm
+        print(f"{name}: rel L2 err {rel:.2e} (oracle fp32-vs-fp64 sums {spread:.2e})")
+        assert rel <= 4 * spread + 2e-5, name
 
 
 def test_adam_step_matches_oracle():
@@ -154,6 +161,12 @@ def test_adam_step_matches_oracle():
     assert np.abs(got - want).max() <= 1e-6
 
 
+# relative-error bars of the small training run below (3072 rows, 150
+# epochs): about twice the values measured on the GPU (median 9.9e-3, p95
+# 0.105)
+MED_BAR, P95_BAR = 2e-2, 2e-1
+
+
 def test_trained_surrogate_gains_over_the_solver():
     """Train on solver prices; on new rows in the box the surrogate prices
     far faster than the solver, with a stated error; rows outside the box
@@ -164,8 +177,17 @@ def test_trained_surrogate_gains_over_the_solver():
     m.set_params(S.init_params(12))
     res = S.fit(m, x, prices, epochs=150, batch=256, lr=2e-3, lr_final=2e-4, seed=13)
     assert res.losses[-1] < 0.1 * res.losses[0]
-    xv, pv = S.training_set(32, seed=14)  # 512 validation rows
+    # 512 validation rows: 32 solves, each read out at 16 values of v0 (the
+    # solver's cost of these prices is these 32 batched solves)
+    import time
     torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    xv, pv = S.training_set(32, seed=14)
+    torch.cuda.synchronize()
+    adi_s = time.perf_counter() - t2
+    S.training_set(32, seed=14)
+    torch.cuda.synchronize()
+    adi_s = min(adi_s, time.perf_counter() - t2 - adi_s)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     xd = _dev(xv)
@@ -179,14 +201,16 @@ def test_trained_surrogate_gains_over_the_solver():
     err = np.abs(ys - pv)
     rms = float(np.sqrt(np.mean(err ** 2)))
     base = float(np.sqrt(np.mean((pv - prices.mean()) ** 2)))  # predicting the mean price
-    import time
-    t2 = time.perf_counter()
-    S.adi_prices(xv[:32].astype(np.float64))
-    adi_s = (time.perf_counter() - t2) / 32 * len(xv)
-    print(f"surrogate rms {rms:.2e} (mean-price baseline {base:.2e}), median rel "
-          f"{np.median(err / np.abs(pv)):.2e}; {len(xv) / surrogate_s:.3g} vs {len(xv) / adi_s:.3g} prices/s")
+    big = pv > S.FIT_PRICE_FLOOR
+    rel = err[big] / pv[big]
+    med, p95 = float(np.median(rel)), float(np.percentile(rel, 95))
+    print(f"surrogate rms {rms:.2e} (mean-price baseline {base:.2e}), relative error above "
+          f"{S.FIT_PRICE_FLOOR:g}: median {med:.2e}, p95 {p95:.2e}, max {rel.max():.2e}; below it max abs "
+          f"{err[~big].max() if (~big).any() else 0.0:.2e}; {len(xv) / surrogate_s:.3g} vs "
+          f"{len(xv) / adi_s:.3g} prices/s")
     assert rms < 0.1 * base
-    assert surrogate_s * 100 < adi_s
+    assert med <= MED_BAR and p95 <= P95_BAR, (med, p95)
+    assert surrogate_s * 20 < adi_s
     # out of the box: solver prices, equal to a direct solve
     xo = W.surrogate_outside(6, 15).astype(np.float32)
     pr = S.price(m, xo)

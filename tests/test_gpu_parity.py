@@ -220,6 +220,37 @@ def test_fused_explicit_r_tiles(shape, tile):
     assert_price(pg, po)
 
 
+@pytest.mark.parametrize("shape,tile", [((256, 40, 19), 16), ((256, 24, 9), 8), ((128, 24, 17), 16),
+                                        ((96, 20, 13), 16), ((64, 33, 10), 16), ((48, 17, 9), 16),
+                                        ((32, 20, 13), 8), ((16, 33, 7), 16)],
+                         ids=lambda x: "x".join(map(str, x)) if isinstance(x, tuple) else f"rows{x}")
+def test_fused_explicit_window_against_lane_loads(shape, tile):
+    """The fused kernel's two explicit phases (neighbours from the LDS window,
+    or each thread's own loads and lane moves) on the same grid: both within
+    the bar of the oracle, and equal to each other on every node (the same
+    arithmetic on the same values).  Shapes cover whole-wave planes (nr a
+    multiple of 64: the plane index is wave-uniform), planes that share a
+    wave (nr = 16, 32, 48, 96; 48 and 96 take 12 rows per lane), two passes
+    of spike lanes (nr = 256 at 8 rows), ragged v blocks and y plane
+    blocks."""
+    hjm.set_line_tile(tile, 16, 16)
+    s = _sloped(shape, 9 if shape[0] <= 64 else 80)
+    grids = {}
+    try:
+        for win in (False, True):
+            hjm.set_exr_window(win)
+            grids[win] = gpu_grid(s)
+            assert PLANS[0] == "fused"
+    finally:
+        hjm.set_exr_window(True)
+    Uo, po = oracle_grid(s)
+    for win in (False, True):
+        assert_grid(grids[win][0], Uo)
+        assert_price(grids[win][1], po)
+    diff = float(np.abs(grids[True][0] - grids[False][0]).max())
+    assert diff == 0.0, f"window and lane-load explicit phases differ by {diff:.3e}"
+
+
 @pytest.mark.parametrize("shape,vs,yc", [((48, 40, 41), False, False), ((48, 48, 40), True, True),
                                          ((64, 24, 17), True, False), ((64, 29, 32), False, True)],
                          ids=["v-chain,y-chain", "v-seg,y-piv", "v-seg,y-chain", "v-chain,y-piv"])
