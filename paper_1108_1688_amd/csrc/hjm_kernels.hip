@@ -50,6 +50,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "hjm_internal.h"
 
@@ -972,6 +973,100 @@ __device__ __forceinline__ double from_lane_above(double x)
     return __hiloint2double(hi, lo);
 }
 
+// The value of the lane OFF below (row_shr) or above (row_shl) inside the
+// calling lane's row of 16 lanes, one DPP move per 32-bit half; a lane whose
+// source lies outside its row keeps its own value (the callers select).
+template <int OFF>
+__device__ __forceinline__ double row_below(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x110 + OFF, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x110 + OFF, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int OFF>
+__device__ __forceinline__ double row_above(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x100 + OFF, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x100 + OFF, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The spike method's reduced system for lines of S <= 16 segments, each
+// segment in one lane (seg = lane mod S; a line's lanes lie inside one row of
+// 16 lanes), by parallel scans across the line's lanes instead of one lane's
+// serial sweep.  Segment s knows the first- and last-row values of its three
+// local solutions: F_s = yF - vF L_{s-1} - wF F_{s+1}, L_s = yL - vL L_{s-1} -
+// wL F_{s+1} (F, L: the segment's first and last unknowns).  Forward
+// elimination gives L_s = alp_s + bet_s F_{s+1} and F_s = gam_s + del_s F_{s+1},
+// with the pivot den_s = 1 + vF bet_{s-1}; with alp = a / z, bet = b / z
+// (z_s = den_s z_{s-1}, z_{-1} = 1, a = b = 0) that recurrence is linear,
+// (a, b, z)_s = M_s (a, b, z)_{s-1} with
+//   M_s = [[-vL, yL vF - vL yF, yL], [0, vL wF - wL vF, -wL], [0, vF, 1]],
+// so an inclusive scan of the products M_s ... M_0 (log2 S steps of row
+// shifts) gives every (a, b, z)_s at once.  Then gam_s = (yF z_{s-1} -
+// vF a_{s-1}) / z_s, del_s = -wF z_{s-1} / z_s, and the backward recurrence
+// F_s = gam_s + del_s F_{s+1} (F_S = 0) is a suffix scan of affine maps.
+// Returns the coupling values XL = L_{s-1} and XR = F_{s+1} of this lane's
+// segment (0 at the line's ends); false after a non-positive pivot.
+__device__ __forceinline__ bool reduced_scan(int seg, int S, double yF, double vF, double wF, double yL, double vL,
+                                             double wL, double& XL, double& XR)
+{
+    // this segment's transfer matrix, [[x, r0, r1], [0, b00, b01], [0, b10, b11]]
+    double x = -vL, r0 = yL * vF - vL * yF, r1 = yL, b00 = vL * wF - wL * vF, b01 = -wL, b10 = vF, b11 = 1.0;
+    auto fwd = [&](auto off_c) {
+        constexpr int OFF = decltype(off_c)::value;
+        if (S <= OFF) return;  // wave-uniform
+        const double qx = row_below<OFF>(x), q0 = row_below<OFF>(r0), q1 = row_below<OFF>(r1);
+        const double c00 = row_below<OFF>(b00), c01 = row_below<OFF>(b01);
+        const double c10 = row_below<OFF>(b10), c11 = row_below<OFF>(b11);
+        if (seg >= OFF) {
+            const double nr0 = x * q0 + r0 * c00 + r1 * c10;
+            const double nr1 = x * q1 + r0 * c01 + r1 * c11;
+            const double n00 = b00 * c00 + b01 * c10, n01 = b00 * c01 + b01 * c11;
+            const double n10 = b10 * c00 + b11 * c10, n11 = b10 * c01 + b11 * c11;
+            x = x * qx;
+            r0 = nr0; r1 = nr1;
+            b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+        }
+    };
+    fwd(std::integral_constant<int, 1>());
+    fwd(std::integral_constant<int, 2>());
+    fwd(std::integral_constant<int, 4>());
+    fwd(std::integral_constant<int, 8>());
+    // (a, b, z) of this segment and of the previous one
+    const double a = r1, b = b01, z = b11;
+    double ap = row_below<1>(a), zp = row_below<1>(z);
+    if (seg == 0) { ap = 0.0; zp = 1.0; }
+    const bool ok = z > 0.0;
+    const double iz = rcp_nr(z);
+    double del = -wF * zp * iz;
+    double gam = (yF * zp - vF * ap) * iz;
+    const double alp = a * iz, bet = b * iz;
+    // F_s = gam_s + del_s F_{s+1}: compose the affine maps toward the line's end
+    auto bwd = [&](auto off_c) {
+        constexpr int OFF = decltype(off_c)::value;
+        if (S <= OFF) return;  // wave-uniform
+        const double qd = row_above<OFF>(del), qg = row_above<OFF>(gam);
+        if (seg + OFF < S) {
+            gam = del * qg + gam;
+            del = del * qd;
+        }
+    };
+    bwd(std::integral_constant<int, 1>());
+    bwd(std::integral_constant<int, 2>());
+    bwd(std::integral_constant<int, 4>());
+    bwd(std::integral_constant<int, 8>());
+    const double F = gam;
+    double Fn = row_above<1>(F);
+    if (seg == S - 1) Fn = 0.0;
+    const double L = alp + bet * Fn;
+    double Lp = row_below<1>(L);
+    if (seg == 0) Lp = 0.0;
+    XL = Lp;
+    XR = Fn;
+    return ok;
+}
+
 // Explicit predictor D0 = dt (A1 + A2 + A3 + A0) U^n (eq. (discreta) with the
 // centred stencils of eq. (esquema), one-sided rows on outflow faces), and the
 // Dirichlet increment on Dirichlet nodes, at the J nodes (i, j0 + m, k),
@@ -1341,6 +1436,9 @@ __device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* 
             vv = vp[mm] - cp[mm] * vv;
             w = -cp[mm] * w;
         }
+        if (S <= 16) {
+            ok = reduced_scan(seg, S, y, vv, w, d[ROWS - 1], vp[ROWS - 1], cp[ROWS - 1], XL, XR) && ok;
+        } else {
         my[0] = y; my[1] = vv; my[2] = w;
         my[3] = d[ROWS - 1]; my[4] = vp[ROWS - 1]; my[5] = cp[ROWS - 1];
         wave_sync();
@@ -1378,6 +1476,7 @@ __device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* 
         wave_sync();
         XL = my[7];
         XR = my[6];
+        }
     }
     // back substitution with the coupling values
     double x = d[ROWS - 1] - XL * vp[ROWS - 1] - XR * cp[ROWS - 1];
@@ -1624,11 +1723,12 @@ __device__ __forceinline__ void window_guards(ldouble* win, int P, int WR, int n
 // barrier every neighbour is an LDS read at a fixed offset from the thread's
 // column (window_nodes).  out[m] receives D0 at (i, j0 + m, k) for
 // j0 + m < nv.  UK: every wave lies inside one plane (nr a multiple of 64),
-// so k, the y offsets and the y-table reads are wave-uniform.  Every thread
-// of the workgroup calls it (one barrier inside).
-template <int J, bool UK>
+// so k, the y offsets and the y-table reads are wave-uniform.  stage() runs
+// once the grid loads are issued (the caller's own staging into LDS).  Every
+// thread of the workgroup calls it (one barrier inside).
+template <int J, bool UK, class Stage>
 __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win, ldouble* vtc, int P, int k0, int j0,
-                                                int step, double (&out)[J])
+                                                int step, double (&out)[J], const Stage& stage)
 {
     constexpr int WR = J + 4;
     const int nr = s.nr, nv = s.nv, ny = s.ny;
@@ -1664,6 +1764,9 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
             yb[m] = U(vob, pob + row(j0 + m));
         }
     }
+    // the caller's staging (its loads queue behind the grid's, so that one
+    // memory round trip covers both)
+    stage();
     // the tile's v-table values (kVT rows of J; v nodes past nv repeat the
     // last one, whose results are not stored) by vector loads, into LDS
     double vv = 0.0;
@@ -1779,6 +1882,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
     const int t = threadIdx.x;
     ldouble* tile = lds;
     ldouble* tab = lds + s.exr_tab;  // after the tile, rounded up to whole passes
+    auto stage_table = [&]() {};
     stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
     if constexpr (WIN && !STAGE2) {
         // explicit phase from the LDS window (it shares the LDS of the tile,
@@ -1787,9 +1891,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
         // the v-table cache after the row table
         ldouble* vtc = tab + (size_t)S * (kRF * ROWS + 1);
         if (nr % 64 == 0)
-            explicit_window<kExrJ, true>(s, tile + 2, vtc, P, k0, j0, step, out);
+            explicit_window<kExrJ, true>(s, tile + 2, vtc, P, k0, j0, step, out, stage_table);
         else
-            explicit_window<kExrJ, false>(s, tile + 2, vtc, P, k0, j0, step, out);
+            explicit_window<kExrJ, false>(s, tile + 2, vtc, P, k0, j0, step, out, stage_table);
         const int kk = t / nr;
         const int i = t - kk * nr;
         __syncthreads();
