@@ -1349,6 +1349,40 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
         explicit_nodes<J, false>(s, i, k, j0, step, put);
 }
 
+// The r-axis table entries of the two face rows (0 and nr - 1) that
+// RowRFull reads, staged in LDS once per workgroup so that the spike solve's
+// first and last lanes take them from there: kFace doubles, row 0 then row
+// nr - 1, each in the order of kFaceRows.  Every thread calls it; the caller
+// synchronises the workgroup before reading.
+constexpr int kFaceRows[] = {RT_P, RT_Q, RT_MLO, RT_ALO, RT_MDI, RT_ADI, RT_RR, RT_MUP, RT_AUP, RT_MEX};
+constexpr int kFaceN = 10;
+constexpr int kFace = 2 * kFaceN;
+__device__ __forceinline__ void stage_face(const SolveDesc& s, ldouble* face)
+{
+    const int t = (int)threadIdx.x;
+    if (t < kFace) {
+        const int w = t / kFaceN;
+        face[t] = gp(s.rt)[(size_t)kFaceRows[t - w * kFaceN] * s.nr + (w ? s.nr - 1 : 0)];
+    }
+}
+
+// Face row w (0: row 0, 1: row nr - 1) of (I - theta dt A1) on a line with
+// variance v and c = f_t + kappa f + y, from the staged entries (as RowRFull).
+__device__ __forceinline__ void face_row(const ldouble* face, int w, double v, double c, double tdt, double& A,
+                                         double& B, double& C, double& E)
+{
+    const ldouble* f = face + w * kFaceN;
+    const double e = f[0] * c + f[1];
+    const double olo = f[2] * e + f[3] * v;
+    const double odi = f[4] * e + f[5] * v - f[6];
+    const double oup = f[7] * e + f[8] * v;
+    const double oex = f[9] * e;
+    A = -tdt * olo;
+    B = 1.0 - tdt * odi;
+    C = -tdt * oup;
+    E = -tdt * oex;
+}
+
 // The spike solve of one r line of nr = S * ROWS rows (S a power of two <=
 // 64) by S consecutive lanes of a wavefront: this lane holds rows
 // [seg ROWS, (seg + 1) ROWS) in d (right-hand side in, solution out).  tseg
@@ -1361,10 +1395,9 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
 // last.  Accurate when the rows are diagonally dominant (the host selects
 // this path only then).  Returns false after a non-positive pivot.
 template <int ROWS>
-__device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* tseg, ldouble* my, int seg, int S,
-                                             double v, double c, double (&d)[ROWS])
+__device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* tseg, const ldouble* face, ldouble* my,
+                                             int seg, int S, double v, double c, double (&d)[ROWS])
 {
-    const int nr = s.nr;
     auto coef = [&](int mm, double& A, double& B, double& C) {
         const ldouble* tb = tseg + mm;
         const double e = tb[RF_P * ROWS] * c + tb[RF_Q * ROWS];
@@ -1379,9 +1412,8 @@ __device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* 
     double fb0 = 1.0, fc0 = 0.0, fe0 = 0.0, fd0 = 0.0, b1 = 0.0, c1 = 0.0, d1 = 0.0;
     double fal = 0.0, fbl = 1.0, fel = 0.0, fdl = 0.0, a2 = 0.0, b2 = 0.0, d2 = 0.0;
     if (first) {
-        RowRFull full{gp(s.rt), nr, v, c, s.tdt};
         double A0, B0, C0, E0, A1, B1, C1;
-        full(0, A0, B0, C0, E0);
+        face_row(face, 0, v, c, s.tdt, A0, B0, C0, E0);
         coef(1, A1, B1, C1);
         const double f = A1 / B0;
         fb0 = B0; fc0 = C0; fe0 = E0; fd0 = d[0];
@@ -1391,9 +1423,8 @@ __device__ __forceinline__ bool spike_r_lane(const SolveDesc& s, const ldouble* 
         ok = ok && B0 > 0.0;
     }
     if (last) {
-        RowRFull full{gp(s.rt), nr, v, c, s.tdt};
         double Al, Bl, Cl, El, A2, B2, C2;
-        full(nr - 1, Al, Bl, Cl, El);
+        face_row(face, 1, v, c, s.tdt, Al, Bl, Cl, El);
         coef(ROWS - 2, A2, B2, C2);
         const double f = C2 / Bl;
         fal = Al; fbl = Bl; fel = El; fdl = d[ROWS - 1];
@@ -1585,9 +1616,11 @@ __global__ __launch_bounds__(kBlock) void k_rs(const SolveDesc* __restrict__ des
     constexpr int TP = kRF * ROWS + 1;
     ldouble* tab = lds;
     ldouble* red = lds + (size_t)TP * S;  // 8 doubles per thread
+    ldouble* face = red + (size_t)kBlock * 8;
     stage_rf<ROWS>(s, tab);
+    stage_face(s, face);
     __syncthreads();
-    const bool ok = spike_r_lane<ROWS>(s, tab + seg * TP, red + t * 8, seg, S, v, c, d);
+    const bool ok = spike_r_lane<ROWS>(s, tab + seg * TP, face, red + t * 8, seg, S, v, c, d);
     if (store) {
 #pragma unroll
         for (int mm = 0; mm < ROWS; ++mm) line[mm] = d[mm];
@@ -1653,8 +1686,10 @@ struct ExpColumn {
 };
 
 // D0 at (i, j0 + m, k), m < J, j0 + m < nv, from the LDS window (wcol: this
-// thread's column of the window, J + 4 rows at pitch nr holding v nodes
-// j0 - 2 .. j0 + J + 1; the neighbouring columns beside it), the tile's
+// thread's column of the window, J + 2 rows at pitch nr holding v nodes
+// j0 - 1 .. j0 + J; the neighbouring columns beside it; ulo, uhi: this
+// column's v nodes j0 - 2 and j0 + J + 1, which only the v stencil of the
+// thread's own column reads), the tile's
 // v-table values in LDS (vtc: kVT rows of J, row r node m = vt[r][j0 + m];
 // every lane reads the same address, a broadcast) and the y neighbours ya,
 // yb (planes k + oa, k + ob): the arithmetic of explicit_nodes, so the same
@@ -1665,23 +1700,28 @@ struct ExpColumn {
 template <int J>
 __device__ __forceinline__ void window_nodes(const SolveDesc& s, const ldouble* wcol, const ldouble* vtc,
                                              const ExpColumn& q, const double (&ya)[J], const double (&yb)[J],
-                                             int j0, double (&out)[J])
+                                             double ulo, double uhi, int j0, double (&out)[J])
 {
     const int nr = s.nr, nv = s.nv;
     constexpr int CH = 4;
 #pragma unroll
     for (int m0 = 0; m0 < J; m0 += CH) {
         __builtin_amdgcn_sched_barrier(0);
+        // u(i, j0 + m0 - 2 .. j0 + m0 + CH + 1): window rows m0 - 1 .. m0 + CH,
+        // the two beyond the window from registers
         double col[CH + 4];
 #pragma unroll
-        for (int c = 0; c < CH + 4; ++c) col[c] = wcol[(size_t)(m0 + c) * nr];
+        for (int c = 0; c < CH + 4; ++c) {
+            const int r = m0 - 1 + c;
+            col[c] = r < 0 ? ulo : (r > J + 1 ? uhi : wcol[(size_t)r * nr]);
+        }
 #pragma unroll
         for (int mm = 0; mm < CH; ++mm) {
             const int m = m0 + mm;
             const int j = j0 + m;
             if (j >= nv) break;  // wave-uniform
-            // window rows m + 1 .. m + 3 hold v nodes j - 1 .. j + 1
-            const ldouble* w0 = wcol + (size_t)(m + 2) * nr;
+            // window rows m .. m + 2 hold v nodes j - 1 .. j + 1
+            const ldouble* w0 = wcol + (size_t)(m + 1) * nr;
             const double lw0 = w0[-1], rw0 = w0[1];
             const double lwm = w0[-1 - nr], rwm = w0[1 - nr];
             const double lwp = w0[nr - 1], rwp = w0[nr + 1];
@@ -1718,10 +1758,10 @@ __device__ __forceinline__ void window_guards(ldouble* win, int P, int WR, int n
 // Explicit predictor of the fused kernel from an LDS window.  Thread
 // (i, plane kk) loads its column u(i, j0-2 .. j0+J+1) of plane k and its J y
 // neighbours of planes k+oa, k+ob straight into registers, all at once (v
-// rows past the faces clamp to the face row, scalar arithmetic); the columns
-// go to the window win (per plane J + 4 rows of nr, row pitch nr); after a
-// barrier every neighbour is an LDS read at a fixed offset from the thread's
-// column (window_nodes).  out[m] receives D0 at (i, j0 + m, k) for
+// rows past the faces clamp to the face row, scalar arithmetic); the columns'
+// v nodes j0-1 .. j0+J go to the window win (per plane J + 2 rows of nr, row
+// pitch nr); after a barrier every neighbour is an LDS read at a fixed offset
+// from the thread's column (window_nodes).  out[m] receives D0 at (i, j0 + m, k) for
 // j0 + m < nv.  UK: every wave lies inside one plane (nr a multiple of 64),
 // so k, the y offsets and the y-table reads are wave-uniform.  stage() runs
 // once the grid loads are issued (the caller's own staging into LDS).  Every
@@ -1730,7 +1770,8 @@ template <int J, bool UK, class Stage>
 __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win, ldouble* vtc, int P, int k0, int j0,
                                                 int step, double (&out)[J], const Stage& stage)
 {
-    constexpr int WR = J + 4;
+    constexpr int WR = J + 4;   // the column's v nodes j0 - 2 .. j0 + J + 1
+    constexpr int WL = J + 2;   // the window's rows: v nodes j0 - 1 .. j0 + J
     const int nr = s.nr, nv = s.nv, ny = s.ny;
     const int t = (int)threadIdx.x;
     const int kk = t / nr;
@@ -1775,16 +1816,16 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
         vv = gp(s.vt)[(size_t)r * nv + min(j0 + (t - r * J), nv - 1)];
     }
     const ExpColumn q(s, i, k, step);
-    ldouble* wcol = win + (size_t)kk * WR * nr + i;
-    window_guards(win, P, WR, nr);
+    ldouble* wcol = win + (size_t)kk * WL * nr + i;
+    window_guards(win, P, WL, nr);
     if (t < kVT * J) vtc[t] = vv;
     if (act) {
 #pragma unroll
-        for (int m = 0; m < WR; ++m) wcol[(size_t)m * nr] = cw[m];
+        for (int m = 0; m < WL; ++m) wcol[(size_t)m * nr] = cw[m + 1];
     }
     __syncthreads();
     if (!act) return;
-    window_nodes<J>(s, wcol, vtc, q, ya, yb, j0, out);
+    window_nodes<J>(s, wcol, vtc, q, ya, yb, cw[0], cw[WR - 1], j0, out);
 }
 
 // The r lines of a fused tile (P planes from k0 x kExrJ v nodes from j0,
@@ -1796,8 +1837,8 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
 // sized to whole passes).  Every thread calls it, after a barrier that
 // follows the tile's writes.
 template <int ROWS>
-__device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, const ldouble* tab, int P, int k0,
-                                           int j0, int step)
+__device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, const ldouble* tab, const ldouble* face,
+                                           int P, int k0, int j0, int step)
 {
     const int nr = s.nr, nv = s.nv, ny = s.ny;
     const int S = s.rs_S;
@@ -1828,7 +1869,7 @@ __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, co
         if (!ydir) {
             const double v = gp(s.vt)[VT_V * nv + j];
             const double c = phi + gp(s.yt)[YT_Y * ny + k];
-            ok = spike_r_lane<ROWS>(s, tab + seg * TP, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
+            ok = spike_r_lane<ROWS>(s, tab + seg * TP, face, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
         }
         if (active) {
             gdouble* line = gp(s.D) + ((size_t)k * nv + j) * nr + (size_t)seg * ROWS;
@@ -1884,6 +1925,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
     ldouble* tab = lds + s.exr_tab;  // after the tile, rounded up to whole passes
     auto stage_table = [&]() {};
     stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
+    // after the row table and the window variant's v-table cache
+    ldouble* face = tab + (size_t)S * (kRF * ROWS + 1) + (size_t)kVT * kExrJ;
+    stage_face(s, face);
     if constexpr (WIN && !STAGE2) {
         // explicit phase from the LDS window (it shares the LDS of the tile,
         // which is written once every thread has finished reading it)
@@ -1924,7 +1968,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
     }
     __syncthreads();
     if constexpr (WIN && !STAGE2) {
-        solve_tile<ROWS>(s, tile, tab, P, k0, j0, step);
+        solve_tile<ROWS>(s, tile, tab, face, P, k0, j0, step);
     } else {
         // the same passes as solve_tile, written out here: inlined as one
         // function the per-lane-load variants keep fewer registers spilled
@@ -1952,7 +1996,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
             if (!ydir) {
                 const double v = gp(s.vt)[VT_V * nv + j];
                 const double c = phi + gp(s.yt)[YT_Y * ny + k];
-                ok = spike_r_lane<ROWS>(s, tab + seg * TP, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
+                ok = spike_r_lane<ROWS>(s, tab + seg * TP, face, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
             }
             if (active) {
                 gdouble* line = gp(s.D) + ((size_t)k * nv + j) * nr + (size_t)seg * ROWS;
@@ -2430,7 +2474,8 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     if (n_tasks <= 0) return hipSuccess;
     // row table (kRF * ROWS + 1 per segment, at most nr_max / ROWS + 1
     // segments) and 8 doubles per thread for the reduced systems
-    const size_t lds = ((size_t)kRF * nr_max + (size_t)(nr_max / rows + 1) * (kRF + 1)) * 8 + (size_t)kBlock * 8 * 8;
+    const size_t lds = ((size_t)kRF * nr_max + (size_t)(nr_max / rows + 1) * (kRF + 1)) * 8 + (size_t)kBlock * 8 * 8 +
+                       (size_t)kFace * 8;
     switch (rows) {
     case 6: HJM_LAUNCH(k_rs<6>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
     case 8: HJM_LAUNCH(k_rs<8>, dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
@@ -2448,12 +2493,13 @@ void exr_lds(int nr, int rows, size_t* bytes, int* tab)
     const int lanes = P * kExrJ * S;
     const int passes = (lanes + kBlock - 1) / kBlock;
     // whole passes: the last pass's scratch stays inside; at least the
-    // window variant's explicit window (J + 4 rows of nr per plane, two
+    // window variant's explicit window (J + 2 rows of nr per plane, two
     // guard doubles each side), which the tile overwrites after it
-    const int tile = std::max(passes * kBlock * (rows + 1), P * (kExrJ + 4) * nr + 4);
+    const int tile = std::max(passes * kBlock * (rows + 1), P * (kExrJ + 2) * nr + 4);
     *tab = tile;
-    // the row table, then the window variant's v-table cache (kVT x kExrJ)
-    *bytes = ((size_t)tile + (size_t)S * (kRF * rows + 1) + (size_t)kVT * kExrJ) * 8;
+    // the row table, the window variant's v-table cache (kVT x kExrJ) and the
+    // face rows' table entries
+    *bytes = ((size_t)tile + (size_t)S * (kRF * rows + 1) + (size_t)kVT * kExrJ + (size_t)kFace) * 8;
 }
 
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
