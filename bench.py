@@ -48,12 +48,13 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "df1e0d356aa436ce857c065aae9647206be84d248b60670fad2a4764a003557e"
-                      ":fc04dde200c43ef1a85d6eb8c0ca29a6208a582cc80d6475abe83e1b4f0b5765",
+    "sources_sha256": "c78034718aa530f98d6966f527270b5883584289f1cd9b9e4d830dba854e683e"
+                      ":0102d6ef5584efcef198435b521715106074929b541b031ae1e4443b1cafbbdb",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
-    "bytes_per_point": {"explicit+r": 18.440, "v": 15.977, "y+update": 32.048},
+    "exr_window": True,
+    "bytes_per_point": {"explicit+r": 18.402, "v": 15.978, "y+update": 32.050},
 }
 
 def log(*a):
@@ -417,7 +418,7 @@ def surrogate_mfma(torch, S, m, x_in, reps: int = 20):
 
 
 def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int, outside_frac: float,
-                  readouts: int = 16):
+                  readouts: int = 16, lr=(1e-3, 1e-5)):
     """Surrogate pricing: train on ADI prices (n_train_solves solves at 64^3,
     `readouts` v0 readouts each), then price n_query rows, a fraction outside
     the box (priced by ADI), and state the surrogate's error against ADI on
@@ -432,7 +433,7 @@ def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int,
     t_data = time.perf_counter() - t0
     m = S.make_mlp(max_batch=65536)
     m.set_params(S.init_params(22))
-    fitres = S.fit(m, x, prices, epochs=epochs, batch=1024, lr=2e-3, lr_final=1e-4, seed=23)
+    fitres = S.fit(m, x, prices, epochs=epochs, batch=1024, lr=lr[0], lr_final=lr[1], seed=23)
     # queries: fresh rows in the box plus a fraction pushed outside it
     n_out = int(round(outside_frac * n_query))
     xq = W.surrogate_params(n_query, seed=24)
@@ -477,14 +478,14 @@ def surrogate_leg(hjm, W, torch, n_train_solves: int, epochs: int, n_query: int,
     m.close()
     mp = S.make_mlp(max_batch=65536, baseline=False)
     mp.set_params(S.init_params(22))
-    fitp = S.fit(mp, x, prices, epochs=epochs, batch=1024, lr=2e-3, lr_final=1e-4, seed=23)
+    fitp = S.fit(mp, x, prices, epochs=epochs, batch=1024, lr=lr[0], lr_final=lr[1], seed=23)
     plain = S.price(mp, xv.astype(np.float32)).prices
     mp.close()
     sur = pr.prices[n_out:n_out + nv]
     low = ref <= 1e-4
     return {"train_rows": int(len(x)), "train_rows_fitted": int((prices > S.FIT_PRICE_FLOOR).sum()),
             "fit_price_floor": S.FIT_PRICE_FLOOR, "train_solves": n_train_solves,
-            "readouts_per_solve": readouts, "epochs": epochs,
+            "readouts_per_solve": readouts, "epochs": epochs, "lr": list(lr),
             "target": "10 ln(price / Gaussian caplet baseline)",
             "train_data_s": round(t_data, 2), "train_s": round(fitres.seconds, 2),
             "final_train_mse_net_units": fitres.losses[-1],
@@ -523,9 +524,10 @@ def main():
     ap.add_argument("--no-softening", action="store_true", help="skip the payoff-softening leg")
     ap.add_argument("--no-curve", action="store_true", help="skip the discrete-curve leg")
     ap.add_argument("--no-multi-rhs", action="store_true", help="skip the shared-operator leg")
-    ap.add_argument("--sur-solves", type=int, default=16384, help="ADI solves for the surrogate's training set")
+    ap.add_argument("--sur-solves", type=int, default=65536, help="ADI solves for the surrogate's training set")
     ap.add_argument("--sur-readouts", type=int, default=4, help="v0 readouts per training solve")
-    ap.add_argument("--sur-epochs", type=int, default=200)
+    ap.add_argument("--sur-epochs", type=int, default=400)
+    ap.add_argument("--sur-lr", type=str, default="1e-3,1e-5", help="learning rate, first and last epoch")
     ap.add_argument("--tile", type=str, default=None, help="rows per thread r,v,y (e.g. 16,16,16)")
     ap.add_argument("--exp-chunk", type=int, default=None, help="v nodes per explicit-kernel thread (4, 8, 16)")
     ap.add_argument("--profile-steps", type=int, default=PROFILED_STEPS,
@@ -639,7 +641,8 @@ def main():
     traffic_ok = (kernel_sources_sha256() == MEASURED_TRAFFIC["sources_sha256"]
                   and tuple(hjm.get_line_tile()) == MEASURED_TRAFFIC["line_tile"]
                   and hjm.get_explicit_chunk() == MEASURED_TRAFFIC["explicit_chunk"]
-                  and hjm.get_r_fusion() == MEASURED_TRAFFIC["r_fusion"])
+                  and hjm.get_r_fusion() == MEASURED_TRAFFIC["r_fusion"]
+                  and hjm.get_exr_window() == MEASURED_TRAFFIC["exr_window"])
     for name in passes:
         b = MEASURED_TRAFFIC["bytes_per_point"].get(name)
         ok = traffic_ok and b is not None
@@ -681,7 +684,8 @@ def main():
         out["calibration"] = calibration(hjm, W, torch, stream, args.calib_solves, tune=True)
         if not args.no_surrogate:
             out["calibration"]["surrogate"] = surrogate_leg(hjm, W, torch, args.sur_solves, args.sur_epochs,
-                                                            65536, 0.01, readouts=args.sur_readouts)
+                                                            65536, 0.01, readouts=args.sur_readouts,
+                                                            lr=tuple(float(v) for v in args.sur_lr.split(",")))
         log(f"calibration: {out['calibration']}")
     if not args.no_schemes:
         out["schemes"] = schemes_leg(hjm, W, torch, stream)
