@@ -48,13 +48,14 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "c78034718aa530f98d6966f527270b5883584289f1cd9b9e4d830dba854e683e"
-                      ":0102d6ef5584efcef198435b521715106074929b541b031ae1e4443b1cafbbdb",
+    "sources_sha256": "35bf7e94538d96303da2198a87b714b7a15025ff4a6d9f03f8c9ec8a49f42bec"
+                      ":161829d532aefc8a2b772d8867dda011d3a4a38de9c838c263ec446dcc49c327",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
     "exr_window": True,
-    "bytes_per_point": {"explicit+r": 18.402, "v": 15.978, "y+update": 32.050},
+    "y_minors": True,
+    "bytes_per_point": {"explicit+r": 18.430, "v": 15.978, "y+update": 24.071},
 }
 
 def log(*a):
@@ -642,7 +643,8 @@ def main():
                   and tuple(hjm.get_line_tile()) == MEASURED_TRAFFIC["line_tile"]
                   and hjm.get_explicit_chunk() == MEASURED_TRAFFIC["explicit_chunk"]
                   and hjm.get_r_fusion() == MEASURED_TRAFFIC["r_fusion"]
-                  and hjm.get_exr_window() == MEASURED_TRAFFIC["exr_window"])
+                  and hjm.get_exr_window() == MEASURED_TRAFFIC["exr_window"]
+                  and hjm.get_y_minors() == MEASURED_TRAFFIC["y_minors"])
     for name in passes:
         b = MEASURED_TRAFFIC["bytes_per_point"].get(name)
         ok = traffic_ok and b is not None

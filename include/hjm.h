@@ -442,6 +442,20 @@ hjm_status hjm_get_r_fusion(int32_t* on);
 hjm_status hjm_set_exr_window(int32_t on);
 hjm_status hjm_get_exr_window(int32_t* on);
 
+/* Where the y sweep on reciprocal pivots (plan[6] > 0) takes its pivots
+   1/den_k of the Thomas elimination of (I - theta dt A3) (section 7.1; the y
+   operator does not change from step to step): on (default), the sweep forms
+   them every step from the minors of the line matrix, den_k = th_k / th_{k-1}
+   with th_k = B_k th_{k-1} - A_k C_{k-1} th_{k-2}, which needs no stored
+   array (8 bytes per grid point less traffic per step); off, a set-up kernel
+   stores them once per solve (den_k = B_k - A_k C_{k-1} / den_{k-1}) and
+   every step reads them.  The two agree to rounding (about 1e-15 relative),
+   not bit for bit.  A non-positive pivot raises the health flag either way.
+   Grids of the correction schemes always store the pivots.  For handles
+   created afterwards.  Process-wide. */
+hjm_status hjm_set_y_minors(int32_t on);
+hjm_status hjm_get_y_minors(int32_t* on);
+
 /* Stream lanes of batches created afterwards (1..8, default 3; HJM_EINVAL
    otherwise).  More lanes overlap more kernels at fewer solves per launch.
    Process-wide. */

@@ -297,7 +297,8 @@ struct Plan {
     bool exr_win;                       // its explicit phase from an LDS window
     size_t exr_lds;
     int vs_rows, vs_S, vs_tiles;        // segmented v solve (0: chained k_v)
-    int yc_rows, yc_S, yc_L, yc_tiles;  // y solve on stored pivots (0: k_yu)
+    int yc_rows, yc_S, yc_L, yc_tiles;  // y solve on reciprocal pivots (0: k_yu)
+    bool y_minors;                      // those pivots formed in k_yc each step (else stored by k_ypiv)
 };
 
 // Segmented v solve: nv = S * ROWS with S <= 4 waves; preferred rows first.
@@ -341,6 +342,7 @@ void plan_rows(int nr, int nv, int ny, int rows[3])
 int g_exp_J = 8;      // v nodes per k_exp thread (4, 8 or 16)
 bool g_fuse_r = true;  // fuse the explicit predictor with the spike r solve where k_exr applies
 bool g_exr_window = true;  // the fused kernel's explicit phase reads its neighbours from an LDS window
+bool g_y_minors = true;    // k_yc forms the y pivots from the minors recurrence (no stored pivot array)
 constexpr int kMaxBatchLanes = 8;
 int g_batch_lanes = 3;  // streams a batch spreads its solves over
 bool g_batch_share = true;  // solves of one operator share tables and y pivots
@@ -408,6 +410,7 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     p.yc_S = p.yc_rows ? ny / p.yc_rows : 0;
     p.yc_L = p.yc_rows ? 64 : 0;
     p.yc_tiles = p.yc_rows ? (nr * nv + p.yc_L - 1) / p.yc_L : 0;
+    p.y_minors = p.yc_rows && g_y_minors;
     if (p.rs_rows) {
         p.r_mode = R_SPLIT;
         p.rs_S = nr / p.rs_rows;
@@ -417,7 +420,6 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     }
     p.exr_P = p.exr_tiles = p.exr_tab = 0;
     p.exr_lds = 0;
-    // the window variant addresses the grid as one buffer of < 4 GiB
     // the window variant addresses the grid as one buffer of < 4 GiB
     p.exr_win = g_exr_window && (uint64_t)nr * nv * ny * 8 < (1ull << 32);
     if (p.rs_rows >= 8 && nr <= kExrMaxNr) {
@@ -784,6 +786,7 @@ void fill_desc(SolveDesc& d, const hjm_axis ax[3], const hjm_model& m, const hjm
     d.yinv = reinterpret_cast<double*>(base + o.YI);
     d.vs_S = pl.vs_S; d.vs_tiles = pl.vs_tiles;
     d.yc_S = pl.yc_S; d.yc_L = pl.yc_L; d.yc_tiles = pl.yc_tiles;
+    d.ypiv_skip = pl.y_minors ? 1 : 0;  // k_yc forms its own pivots: nothing to store
 }
 
 // Upload a solve's host tables, all but the Dirichlet increments (gd), which
@@ -973,6 +976,9 @@ hjm_status grid_init(hjm_grid* g, const hjm_axis ax[3], const hjm_model& model, 
     g->n_steps = n_steps;
     std::memcpy(g->rows, plan.rows, sizeof g->rows);
     g->plan = plan;
+    // the correction schemes keep the stored pivots: their other sweep modes
+    // would run at lower occupancy with the pivots formed in the kernel
+    if (corr) g->plan.y_minors = false;
     g->scheme = scheme;
     g->corr = corr;
     g->stream = stream;
@@ -996,7 +1002,7 @@ hjm_status grid_init(hjm_grid* g, const hjm_axis ax[3], const hjm_model& model, 
         (e = upload_tables(g->desc, g->tables, g->stream)) ||
         (e = launch_gd(g->d_desc, 1, (int64_t)(2 * ax[2].n + ax[0].n) * n_steps, g->stream)) ||
         (e = launch_terminal(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n * ax[2].n, g->stream)) ||
-        (e = launch_ypiv(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n, g->stream)) ||
+        (!g->plan.y_minors && (e = launch_ypiv(g->d_desc, 1, (int64_t)ax[0].n * ax[1].n, g->stream))) ||
         (e = hipStreamSynchronize(g->stream)))
         return hip_fail(e, "grid set-up");
     return HJM_OK;
@@ -1144,6 +1150,19 @@ hjm_status hjm_get_exr_window(int32_t* on)
 {
     if (!on) return fail(HJM_EINVAL, "null argument");
     *on = g_exr_window ? 1 : 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_set_y_minors(int32_t on)
+{
+    g_y_minors = on != 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_y_minors(int32_t* on)
+{
+    if (!on) return fail(HJM_EINVAL, "null argument");
+    *on = g_y_minors ? 1 : 0;
     return HJM_OK;
 }
 
@@ -1302,7 +1321,7 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
             else if (pass == 2) e = launch_v(g->rows[1], dd, nullptr, p.v_tiles, p.v_lds, g->stream);
             else if (p.yc_rows)
                 e = launch_yc(p.yc_rows, dd, nullptr, p.yc_tiles, p.yc_S, g->stream,
-                              !g->corr ? 0 : (!st2 ? 1 : (!last_seq ? 3 : (g->desc2.hv ? 2 : 0))));
+                              !g->corr ? 0 : (!st2 ? 1 : (!last_seq ? 3 : (g->desc2.hv ? 2 : 0))), p.y_minors);
             else e = launch_yu(g->rows[2], dd, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {
@@ -1590,7 +1609,7 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step, hipS
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, st);
     case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
     case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, st);
-    default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, st);
+    default: return launch_yc(g.rows & 0xff, b->d_desc, t, nt, g.aux, st, 0, (g.rows >> 8) != 0);
     }
 }
 
@@ -1778,7 +1797,8 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
                 case G_V: if (!pl.vs_rows) { rows = pl.rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
                 case G_VS: if (pl.vs_rows) { rows = pl.vs_rows; tiles = pl.vs_tiles; aux = pl.vs_S; } break;
                 case G_YU: if (!pl.yc_rows) { rows = pl.rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
-                default: if (pl.yc_rows) { rows = pl.yc_rows; tiles = pl.yc_tiles; aux = pl.yc_S; } break;
+                // rows, plus 256 for pivots formed in the kernel (its own group)
+                default: if (pl.yc_rows) { rows = pl.yc_rows + (pl.y_minors ? 256 : 0); tiles = pl.yc_tiles; aux = pl.yc_S; } break;
                 }
                 if (!tiles) continue;
                 LaunchGroup& g = group(lane, kind, rows);
@@ -1831,7 +1851,9 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
         max_gd = std::max<int64_t>(max_gd, (int64_t)(2 * ax[3 * s + 2].n + ax[3 * s].n) * n_steps[s]);
     }
     if (!e) e = launch_gd(b->d_desc, n, max_gd, b->stream);
-    if (!e) e = launch_ypiv(b->d_desc, n, b->max_ylines, b->stream);
+    bool stored_pivots = false;
+    for (int s = 0; s < n; ++s) stored_pivots = stored_pivots || (plans[s].yc_rows && !plans[s].y_minors);
+    if (!e && stored_pivots) e = launch_ypiv(b->d_desc, n, b->max_ylines, b->stream);
     if (!e) e = hipStreamSynchronize(b->stream);
     if (e) {
         delete b;

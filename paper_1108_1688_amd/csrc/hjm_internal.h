@@ -196,9 +196,12 @@ hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
 hipError_t launch_gd(const SolveDesc* d_desc, int n_solves, int64_t max_entries, hipStream_t st);
 hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines, hipStream_t st);
 // mode 0: U += D3 (Douglas; the last sequence of CS and MCS); 1: D3 stays in
-// D (the first sequence of the Craig-Sneyd family); 2: U += D3 + E3 (HV's last)
+// D (the first sequence of the Craig-Sneyd family); 2: U += D3 + E3 (HV's
+// last); 3: D3 += E3 (an intermediate Huang subiteration).  minors: the
+// reciprocal pivots are formed in the kernel from the minors recurrence, else
+// read from the array k_ypiv wrote
 hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st,
-                     int mode = 0);
+                     int mode = 0, bool minors = false);
 // k_yc holds 4 ROWS-long arrays per thread: workgroups of at most 128 / ROWS
 // waves keep them in registers
 constexpr int yc_max_segments(int rows) { return 128 / rows; }

@@ -2128,13 +2128,36 @@ __global__ __launch_bounds__(kBlock) void k_ypiv(const SolveDesc* __restrict__ d
     if (!ok && !line_dir) raise_flag(s);
 }
 
-// y sweep + update on the stored reciprocal pivots: Thomas in row order,
-// segments of ROWS rows chained through LDS (segment s runs once segment s-1
-// has handed over d' of its last row); the only serial work per row is one
-// FMA forward and one backward.  Then U^{n+1} = U^n + D3.  Workgroup = yc_S
-// waves; wave w holds rows [w ROWS, (w+1) ROWS) of 64 consecutive lines
-// (i, j), so row reads are contiguous and the y-table reads are wave-uniform.
-template <int ROWS, int MODE>
+// Exact rescaling by a power of two (no rounding): the minors recurrence is
+// homogeneous, so a common factor of its two carried values changes no ratio.
+__device__ __forceinline__ int pow2_exponent(double x)
+{
+    return __builtin_amdgcn_frexp_exp(x);
+}
+
+// y sweep + update: Thomas in row order, segments of ROWS rows chained
+// through LDS (segment s runs once segment s-1 has handed over d' of its last
+// row); the only serial work per row is one FMA forward and one backward.
+// Then U^{n+1} = U^n + D3.  Workgroup = yc_S waves; wave w holds rows
+// [w ROWS, (w+1) ROWS) of 64 consecutive lines (i, j), so row reads are
+// contiguous and the y-table reads are wave-uniform.
+//
+// The reciprocal pivots 1 / den_k either come from the array k_ypiv wrote
+// (MINORS false) or are formed here each step (MINORS true), which saves
+// reading one grid-sized array per step.  Thomas's pivots are ratios of
+// consecutive leading minors of the line matrix, den_k = th_k / th_{k-1}, and
+// the minors obey the linear recurrence th_k = B_k th_{k-1} - A_k C_{k-1}
+// th_{k-2} (th_{-1} = 1, th_{-2} = 0): no division on its chain.  Every
+// segment first carries the basis (1, 0), (0, 1) of (th_{b-1}, th_{b-2})
+// through its rows (a 2x2 transfer, in parallel over segments); segment s then
+// composes the transfers of segments 0 .. s-1 into its own start values and
+// replays its rows, 1 / den_k = th_{k-1} / th_k off the chain.  On these
+// lines the off-diagonal product A_k C_{k-1} is negative except where the y
+// drift changes sign (and small there), so the minors are sums of positive
+// terms: as accurate as the pivots of the division recurrence.  Both carried
+// values are rescaled by a power of two every 8 rows (exact), so the minors
+// never overflow.
+template <int ROWS, int MODE, bool MINORS>
 __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
     extern __shared__ double lds_raw[];
@@ -2158,7 +2181,6 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
     const size_t off = (size_t)qc + (size_t)sg * ROWS * sy;
     gdouble* D = gp(s.D);
     gdouble* U = gp(s.U);
-    gcdouble* YI = gp(s.yinv);
     kcdouble* yt = kp(s.yt);
     const bool first = sg == 0;
     const bool last = sg == S - 1;
@@ -2170,26 +2192,32 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
 #pragma unroll
     for (int mm = 0; mm < ROWS; ++mm) {
         d[mm] = D[off + (size_t)mm * sy];
-        iv[mm] = YI[off + (size_t)mm * sy];
+        if constexpr (!MINORS) iv[mm] = gp(s.yinv)[off + (size_t)mm * sy];
     }
     // C inv goes to LDS (it is needed only by the backward chain), [row][lane]
     ldouble* cpl = lds + 128 + (size_t)sg * ROWS * 64 + l;
     const double qv = gp(s.rt)[RT_Y * nr + i] * gp(s.vt)[VT_V * nv + j];
-    auto row = [&](int kk, double& A, double& B, double& C, double& E) {
-        const double a = yt[YT_T1 * ny + kk] * qv + yt[YT_T2 * ny + kk];
-        A = yt[YT_MA * ny + kk] * a;
-        B = 1.0 + yt[YT_MB * ny + kk] * a;
-        C = yt[YT_MC * ny + kk] * a;
-        E = yt[YT_ME * ny + kk] * a;
+    // the row entries from the tables; yq and the table pointer are passed
+    // in, so that a pass that recomputes them (MINORS: the transfer, then
+    // the replay) can hide the repeat from the compiler, which would
+    // otherwise keep every row's entries live between the passes
+    auto row_of = [&](kcdouble* ytab, double yq, int kk, double& A, double& B, double& C, double& E) {
+        const double a = ytab[YT_T1 * ny + kk] * yq + ytab[YT_T2 * ny + kk];
+        A = ytab[YT_MA * ny + kk] * a;
+        B = 1.0 + ytab[YT_MB * ny + kk] * a;
+        C = ytab[YT_MC * ny + kk] * a;
+        E = ytab[YT_ME * ny + kk] * a;
     };
+    auto row = [&](int kk, double& A, double& B, double& C, double& E) { row_of(yt, qv, kk, A, B, C, E); };
     double d0 = 0.0, B0 = 1.0, C0 = 0.0, E0 = 0.0, dl = 0.0, Al = 0.0, Bl = 1.0, El = 0.0;
-    double c1m = 0.0, a2m = 0.0;
+    double c1m = 0.0, a2m = 0.0, b1m = 1.0, b2m = 1.0;
     if (first) {
         double A0, A1, B1, C1, E1;
         row(0, A0, B0, C0, E0);
         row(1, A1, B1, C1, E1);
         const double f = A1 / B0;
         c1m = C1 - f * E0;
+        b1m = B1 - f * C0;
         d0 = d[0];
         if (work) d[1] = d[1] - f * d0;
     }
@@ -2199,25 +2227,118 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
         row(ny - 2, A2, B2, C2, E2);
         const double f = C2 / Bl;
         a2m = A2 - f * El;
+        b2m = B2 - f * Al;
         dl = d[ROWS - 1];
         if (work) d[ROWS - 2] = d[ROWS - 2] - f * dl;
     }
-    // with inv_k = 1 / den_k the recurrences are d'_k = inv_k d_k +
-    // (-A_k inv_k) d'_{k-1} and x_k = d'_k - (C_k inv_k) x_{k+1}; rows 0 and
-    // n-1 are identity rows (lines on a Dirichlet r face keep D)
+    // row mm of the segment with the face rows folded in: rows 0 and n-1 are
+    // identity rows, row 1 lost its A and row n-2 its C
+    auto frow_of = [&](kcdouble* ytab, double yq, int mm, double& A, double& B, double& C) {
+        double E;
+        row_of(ytab, yq, sg * ROWS + mm, A, B, C, E);
+        if (mm == 0) { A = first ? 0.0 : A; B = first ? 1.0 : B; C = first ? 0.0 : C; }
+        if (mm == 1) { A = first ? 0.0 : A; B = first ? b1m : B; C = first ? c1m : C; }
+        if (mm == ROWS - 2) { A = last ? a2m : A; B = last ? b2m : B; C = last ? 0.0 : C; }
+        if (mm == ROWS - 1) { A = last ? 0.0 : A; B = last ? 1.0 : B; C = last ? 0.0 : C; }
+    };
+    auto frow = [&](int mm, double& A, double& B, double& C) { frow_of(yt, qv, mm, A, B, C); };
+    bool ok = true;
+    if constexpr (MINORS) {
+        // C of the row before the segment (no fold reaches it: ROWS >= 8)
+        double cb = 0.0;
+        if (!first) {
+            double A, B, E;
+            row(sg * ROWS - 1, A, B, cb, E);
+        }
+        // the segment's transfer: (th_{b+R-1}, th_{b+R-2}) = u th_{b-1} + w th_{b-2}
+        double u0 = 1.0, u1 = 0.0, w0 = 0.0, w1 = 1.0, cprev = cb;
 #pragma unroll
-    for (int mm = 0; mm < ROWS; ++mm) {
-        const int kk = sg * ROWS + mm;
-        double A, B, C, E;
-        row(kk, A, B, C, E);
-        if (mm == 0) { A = first ? 0.0 : A; C = first ? 0.0 : C; }
-        if (mm == 1) { A = first ? 0.0 : A; C = first ? c1m : C; }
-        if (mm == ROWS - 2) { A = last ? a2m : A; C = last ? 0.0 : C; }
-        if (mm == ROWS - 1) { A = last ? 0.0 : A; C = last ? 0.0 : C; }
-        const double inv = iv[mm];
-        if (seg < S) cpl[mm * 64] = C * inv;  // waves past S (batches) share segment 0's rows: no write
-        al[mm] = work ? -A * inv : 0.0;
-        d[mm] = work ? d[mm] * inv : d[mm];
+        for (int mm = 0; mm < ROWS; ++mm) {
+            double A, B, C;
+            frow(mm, A, B, C);
+            const double P = A * cprev;
+            cprev = C;
+            const double nu = B * u0 - P * u1;
+            const double nw = B * w0 - P * w1;
+            u1 = u0; u0 = nu;
+            w1 = w0; w0 = nw;
+            if (mm % 8 == 7) {
+                const int e = -pow2_exponent(fabs(u0) + fabs(w0));
+                u0 = __builtin_ldexp(u0, e); u1 = __builtin_ldexp(u1, e);
+                w0 = __builtin_ldexp(w0, e); w1 = __builtin_ldexp(w1, e);
+            }
+        }
+        // start values of segment sg: the transfers of the segments before it
+        // applied to (th_{-1}, th_{-2}) = (1, 0); the transfers sit where the
+        // C inv rows go, read by every later segment before any is written
+        double t1 = 1.0, t2 = 0.0;
+        if (S > 1) {
+            ldouble* tr = lds + 128 + l;
+            if (seg < S - 1) {
+                tr[(seg * 4 + 0) * 64] = u0; tr[(seg * 4 + 1) * 64] = u1;
+                tr[(seg * 4 + 2) * 64] = w0; tr[(seg * 4 + 3) * 64] = w1;
+            }
+            __syncthreads();
+            for (int qq = 0; qq < sg; ++qq) {
+                const double x = tr[(qq * 4 + 0) * 64] * t1 + tr[(qq * 4 + 2) * 64] * t2;
+                const double y = tr[(qq * 4 + 1) * 64] * t1 + tr[(qq * 4 + 3) * 64] * t2;
+                const int e = -pow2_exponent(x);
+                t1 = __builtin_ldexp(x, e);
+                t2 = __builtin_ldexp(y, e);
+            }
+            __syncthreads();
+        }
+        ok = t1 > 0.0;
+        if (first) ok = ok && B0 > 0.0;
+        if (last) ok = ok && Bl > 0.0;
+        // replay, 1 / den_k = th_{k-1} / th_k (identity rows: exactly 1), and
+        // the sweep's coefficients from it at once; the rows' entries are
+        // formed again (cheaper than holding them since the transfer)
+        double qv2 = qv;
+        kcdouble* yt2 = yt;
+        asm volatile("" : "+v"(qv2), "+s"(yt2));
+        cprev = cb;
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            // rows in groups of 4: the scheduler would otherwise run the whole
+            // minors chain ahead and hold every row's values for the divisions
+            if (mm % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+            double A, B, C;
+            frow_of(yt2, qv2, mm, A, B, C);
+            const double P = A * cprev;
+            cprev = C;
+            const double t0 = B * t1 - P * t2;
+            ok = ok && t0 > 0.0;
+            const bool ident = (mm == 0 && first) || (mm == ROWS - 1 && last);
+            const double inv = ident ? 1.0 : t1 * rcp_nr(t0);
+            t2 = t1;
+            t1 = t0;
+            if (mm % 8 == 7) {
+                const int e = -pow2_exponent(t1);
+                t1 = __builtin_ldexp(t1, e);
+                t2 = __builtin_ldexp(t2, e);
+            }
+            al[mm] = work ? -A * inv : 0.0;
+            d[mm] = work ? d[mm] * inv : d[mm];
+            // formed here, not sunk into the sweep's branches (which would keep
+            // every row's A and inv live until then)
+            asm volatile("" : "+v"(al[mm]), "+v"(d[mm]));
+            if (seg < S) cpl[mm * 64] = C * inv;  // waves past S (batches) share segment 0's rows: no write
+        }
+        if (!ok && work) raise_flag(s);
+    } else {
+        // with inv_k = 1 / den_k the recurrences are d'_k = inv_k d_k +
+        // (-A_k inv_k) d'_{k-1} and x_k = d'_k - (C_k inv_k) x_{k+1}; rows 0
+        // and n-1 are identity rows (lines on a Dirichlet r face keep D)
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            double A, B, C;
+            frow(mm, A, B, C);
+            const double inv = iv[mm];
+            if (seg < S) cpl[mm * 64] = C * inv;  // waves past S (batches) share segment 0's rows: no write
+            al[mm] = work ? -A * inv : 0.0;
+            d[mm] = work ? d[mm] * inv : d[mm];
+        }
     }
     ldouble* xch = lds + 2 * l;
     for (int stage = 0; stage < S; ++stage) {
@@ -2350,8 +2471,13 @@ template <int ROWS>
 hipError_t allow_yc()
 {
     hipError_t e;
-    if ((e = allow_lds(k_yc<ROWS, 0>)) || (e = allow_lds(k_yc<ROWS, 1>))) return e;
-    return allow_lds(k_yc<ROWS, 2>);
+    if ((e = allow_lds(k_yc<ROWS, 0, false>)) || (e = allow_lds(k_yc<ROWS, 1, false>)) ||
+        (e = allow_lds(k_yc<ROWS, 2, false>)) || (e = allow_lds(k_yc<ROWS, 3, false>)))
+        return e;
+    if ((e = allow_lds(k_yc<ROWS, 0, true>)) || (e = allow_lds(k_yc<ROWS, 1, true>)) ||
+        (e = allow_lds(k_yc<ROWS, 2, true>)) || (e = allow_lds(k_yc<ROWS, 3, true>)))
+        return e;
+    return hipSuccess;
 }
 
 }  // namespace
@@ -2562,17 +2688,21 @@ hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines,
 }
 
 hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st,
-                     int mode)
+                     int mode, bool minors)
 {
     if (n_tasks <= 0) return hipSuccess;
     if (S_max < 1 || S_max > yc_max_segments(rows)) return hipErrorInvalidValue;
     // the exchange slots (2 per lane) and C inv of every row of the lines
     const size_t lds = (size_t)(2 + (size_t)S_max * rows) * 64 * 8;
     switch (mode) {
-    case 0: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 0>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
-    case 1: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 1>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
-    case 2: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 2>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
-    case 3: HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 3>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) break;
+#define HJM_YC(M)                                                                                                       \
+    if (minors) HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, M, true>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) \
+    else HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, M, false>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
+    case 0: HJM_YC(0) break;
+    case 1: HJM_YC(1) break;
+    case 2: HJM_YC(2) break;
+    case 3: HJM_YC(3) break;
+#undef HJM_YC
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -108,6 +108,8 @@ def lib():
         "hjm_get_r_fusion": (st, [P(i32)]),
         "hjm_set_exr_window": (st, [i32]),
         "hjm_get_exr_window": (st, [P(i32)]),
+        "hjm_set_y_minors": (st, [i32]),
+        "hjm_get_y_minors": (st, [P(i32)]),
         "hjm_set_batch_streams": (st, [i32]),
         "hjm_get_batch_streams": (st, [P(i32)]),
         "hjm_set_batch_share": (st, [i32]),
@@ -233,6 +235,18 @@ def set_exr_window(on: bool) -> None:
 def get_exr_window() -> bool:
     on = C.c_int32()
     check(lib().hjm_get_exr_window(C.byref(on)))
+    return bool(on.value)
+
+
+def set_y_minors(on: bool) -> None:
+    """y pivots formed in the y sweep each step from the minors recurrence
+    (default) or stored once per solve, for handles created afterwards."""
+    check(lib().hjm_set_y_minors(1 if on else 0))
+
+
+def get_y_minors() -> bool:
+    on = C.c_int32()
+    check(lib().hjm_get_y_minors(C.byref(on)))
     return bool(on.value)
 
 

@@ -36,9 +36,11 @@ def _need_gpu():
         pytest.skip("no GPU")
     old = hjm.get_line_tile()
     fused = hjm.get_r_fusion()
+    minors = hjm.get_y_minors()
     yield
     hjm.set_line_tile(*old)
     hjm.set_r_fusion(fused)
+    hjm.set_y_minors(minors)
 
 
 PLANS = []  # r method of every grid of the last gpu_grid call
@@ -264,6 +266,34 @@ def test_v_and_y_methods(shape, vs, yc):
     Uo, po = oracle_grid(s)
     assert_grid(Ug, Uo)
     assert_price(pg, po)
+
+
+@pytest.mark.parametrize("shape,tile", [((48, 48, 40), (16, 16, 8)), ((64, 29, 32), (16, 16, 16)),
+                                        ((64, 32, 128), (16, 16, 16)), ((32, 24, 96), (16, 16, 32)),
+                                        ((48, 24, 16), (16, 16, 16)), ((40, 20, 64), (8, 8, 8))],
+                         ids=["8x5seg", "16x2seg", "16x8seg", "32x3seg", "16x1seg", "8x8seg"])
+def test_y_pivots_from_minors_against_stored(shape, tile):
+    """The y sweep's reciprocal pivots formed in the kernel from the minors
+    recurrence (segment transfers composed across the line's segments) and
+    the stored ones of the set-up kernel: each solve against the oracle, and
+    the two grids within a few ulps of each other; 1 to 8 segments of 8, 16
+    and 32 rows."""
+    s = _sloped(shape, 12)
+    hjm.set_line_tile(*tile)
+    out = {}
+    for minors in (True, False):
+        hjm.set_y_minors(minors)
+        Ug, pg = gpu_grid(s)
+        assert PLANS[2], "y solve on reciprocal pivots expected"
+        out[minors] = (Ug, pg)
+    Uo, po = oracle_grid(s)
+    for minors, (Ug, pg) in out.items():
+        assert_grid(Ug, Uo)
+        assert_price(pg, po)
+    scale = np.abs(Uo).max()
+    diff = float(np.abs(out[True][0] - out[False][0]).max()) / scale
+    print(f"minors vs stored pivots: grid rel diff {diff:.2e}", flush=True)
+    assert diff <= 1e-13
 
 
 def test_config3_one_year_caplet_full_solve():
