@@ -1,26 +1,38 @@
-"""Autotuner for the line-solve tiles, per line shape.
+"""Autotuner for the line-solve tiles of a batch.
 
 A Douglas step runs one kernel per direction (the explicit predictor fused
 with the r sweep, then the v and y sweeps), and each kernel's speed depends
 on the rows per thread of its own line solve and on the shape of its lines:
 the line length n (the node count along its axis) and the number of lines
-(the product of the other two node counts).  The library times each kernel
-launch with HIP events, so timing every candidate value on every axis at
-once (the settings (8, 8, 8), (16, 16, 16), (32, 32, 32)) gives each
-kernel's time for each of its candidates on each grid shape; for every line
-shape (axis, n, lines) the candidate with the least time, weighted by the
-work (grid points times steps) of the solves that have that line shape,
-wins.  The choices go to the library as per-shape overrides
-(hjm_set_axis_tile), so that one batch runs each shape on its own best tiles.
+(the product of the other two node counts).
+
+Two stages:
+
+1. Per-kernel timing.  The library times each kernel launch with HIP events,
+   so timing every candidate value on every axis at once (the settings
+   (8, 8, 8), (16, 16, 16), (32, 32, 32)) on one grid of every distinct grid
+   shape gives each kernel's time for each candidate on each line shape,
+   weighted by the work (grid points times steps) of the solves with that
+   line shape.  From these come two proposals: per line shape its fastest
+   candidate, and per axis the candidate fastest summed over the axis's line
+   shapes (one value per axis keeps a batch's launch groups whole).
+2. End-to-end check.  A batch launches one kernel per launch group, and
+   solves whose rows differ fall into separate groups: more, smaller
+   launches per step, which the per-kernel times do not see.  So each
+   proposal, and the default (no overrides), prices the whole batch a few
+   times; the fastest wins and goes to the library as per-shape overrides
+   (hjm_set_axis_tile).
 
 Results are cached in a JSON file keyed by the device, the library build and
-each line shape, so a later process reuses them without timing again.
+the batch's workload (its line shapes with their work), so a later process
+reuses them without timing again.
 """
 from __future__ import annotations
 
 import hashlib
 import json
 import os
+import time
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -43,28 +55,49 @@ def line_shapes(shape: Tuple[int, int, int]) -> List[LineShape]:
 
 @dataclass
 class Tuning:
-    choice: Dict[LineShape, int]                          # rows per thread of every line shape
+    choice: Dict[LineShape, int]                          # overrides installed (empty: the default)
     us: Dict[LineShape, Dict[int, float]]                 # weighted kernel time per candidate
     default_rows: Tuple[int, int, int] = (16, 16, 16)
     cached: bool = False
     timed_grids: int = 0
+    per_shape: Dict[LineShape, int] = field(default_factory=dict)   # proposal: fastest per line shape
+    per_axis: Dict[LineShape, int] = field(default_factory=dict)    # proposal: one value per axis
+    batch_ms: Dict[str, float] = field(default_factory=dict)        # whole-batch time of each proposal
+    chosen: str = "default"
 
     def apply(self) -> None:
-        """Install the choices as the library's per-shape overrides."""
+        """Install the chosen overrides in the library."""
         for (axis, n, lines), rows in self.choice.items():
             hjm.set_axis_tile(axis, n, lines, rows)
 
     def summary(self) -> dict:
-        """Chosen rows per line shape ("r:96x9216" -> 16) and how many
-        shapes differ from the default."""
+        """The chosen proposal, its rows per line shape ("r:96x9216" -> 16),
+        how many shapes differ from the default, and every proposal's batch
+        time."""
         out = {f"{AXES[a]}:{n}x{lines}": rows for (a, n, lines), rows in sorted(self.choice.items())}
         differ = sum(1 for (a, _, _), rows in self.choice.items() if rows != self.default_rows[a])
-        return {"per_line_shape": out, "line_shapes": len(self.choice), "differ_from_default": differ}
+        return {"chosen": self.chosen, "per_line_shape": out, "line_shapes": len(self.per_shape),
+                "differ_from_default": differ, "batch_ms": {k: round(v, 3) for k, v in self.batch_ms.items()}}
 
 
 def choose(times: Dict[LineShape, Dict[int, float]]) -> Dict[LineShape, int]:
     """Each line shape's candidate with the least weighted time."""
     return {key: min(per, key=per.get) for key, per in times.items() if per}
+
+
+def choose_per_axis(times: Dict[LineShape, Dict[int, float]]) -> Dict[LineShape, int]:
+    """One candidate per axis, the least weighted time summed over the axis's
+    line shapes (candidates timed on every one of them), for every line shape
+    of that axis."""
+    best: Dict[int, int] = {}
+    for axis in range(3):
+        keys = [k for k in times if k[0] == axis]
+        common = set(CANDIDATES)
+        for k in keys:
+            common &= set(times[k])
+        if keys and common:
+            best[axis] = min(sorted(common), key=lambda c: sum(times[k][c] for k in keys))
+    return {k: best[k[0]] for k in times if k[0] in best}
 
 
 def _device_id() -> str:
@@ -81,11 +114,6 @@ def _lib_id() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _key_str(dev: str, lib: str, key: LineShape) -> str:
-    a, n, lines = key
-    return f"{dev}:{lib}:{AXES[a]}:{n}:{lines}"
-
-
 def shapes_by_work(specs: Sequence) -> Dict[Tuple[int, int, int], Tuple[object, float]]:
     """Each distinct grid shape of specs: a solve of that shape (the one with
     the most steps) and the shape's share of all point-steps."""
@@ -98,6 +126,13 @@ def shapes_by_work(specs: Sequence) -> Dict[Tuple[int, int, int], Tuple[object, 
             pick[sh] = s
     total = sum(work.values())
     return {sh: (pick[sh], work[sh] / total) for sh in work}
+
+
+def workload_key(specs: Sequence, tile: Tuple[int, int, int]) -> str:
+    """A digest of what the tuning depends on: every grid shape's work and
+    steps, and the global line tile the default runs on."""
+    sig = sorted(((sh, round(w, 12), spec.n_steps) for sh, (spec, w) in shapes_by_work(specs).items()))
+    return hashlib.sha256(json.dumps([sig, list(tile), len(specs)]).encode()).hexdigest()[:16]
 
 
 def time_shapes(shapes: Dict[tuple, Tuple[object, float]], steps: int) -> Dict[LineShape, Dict[int, float]]:
@@ -124,36 +159,79 @@ def time_shapes(shapes: Dict[tuple, Tuple[object, float]], steps: int) -> Dict[L
     return times
 
 
-def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bool = True) -> Tuning:
-    """Choose the rows per thread of every line shape of specs (timing what
-    the cache does not hold) and, if apply, install them as overrides; the
-    global line tile is left as it was."""
+def time_batch(specs: Sequence, overrides: Dict[LineShape, int], reps: int) -> float:
+    """Milliseconds per priced run of the whole batch (eager launches on a
+    stream of its own; one untimed run, then the median of reps) with the
+    given overrides installed; the overrides are cleared afterwards."""
+    import torch
+    hjm.clear_axis_tiles()
+    try:
+        for (axis, n, lines), rows in overrides.items():
+            hjm.set_axis_tile(axis, n, lines, rows)
+        b = hjm.Batch(specs, stream=torch.cuda.Stream())
+        try:
+            b.run()
+            b.prices()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                b.run()
+                b.prices()
+                ts.append(time.perf_counter() - t0)
+        finally:
+            b.close()
+    finally:
+        hjm.clear_axis_tiles()
+    ts.sort()
+    return 1e3 * ts[len(ts) // 2]
+
+
+def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bool = True,
+         batch_reps: int = 3) -> Tuning:
+    """Choose the line tiles of the batch specs (timing what the cache does
+    not hold) and, if apply, install them as per-shape overrides; the global
+    line tile is left as it was."""
     specs = list(specs)
     shapes = shapes_by_work(specs)
-    keys = sorted({k for sh in shapes for k in line_shapes(sh)})
-    dev, lib = _device_id(), _lib_id()
-    old_tile = hjm.get_line_tile()
+    old_tile = tuple(hjm.get_line_tile())
+    key = f"{_device_id()}:{_lib_id()}:{workload_key(specs, old_tile)}"
     stored = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
             stored = json.load(f)
-    if all(_key_str(dev, lib, k) in stored for k in keys):
-        t = Tuning({k: stored[_key_str(dev, lib, k)]["rows"] for k in keys},
-                   {k: {int(c): v for c, v in stored[_key_str(dev, lib, k)]["us"].items()} for k in keys},
-                   old_tile, cached=True)
+
+    def keys_of(d):
+        return {tuple(int(x) for x in k.split(",")): v for k, v in d.items()}
+
+    def str_keys(d):
+        return {",".join(map(str, k)): v for k, v in d.items()}
+
+    if key in stored:
+        e = stored[key]
+        t = Tuning(keys_of(e["choice"]), {k: {int(c): v for c, v in per.items()} for k, per in keys_of(e["us"]).items()},
+                   old_tile, cached=True, per_shape=keys_of(e["per_shape"]), per_axis=keys_of(e["per_axis"]),
+                   batch_ms=e["batch_ms"], chosen=e["chosen"])
     else:
         try:
             times = time_shapes(shapes, steps)
         finally:
             hjm.clear_axis_tiles()
             hjm.set_line_tile(*old_tile)
-        t = Tuning(choose(times), times, old_tile, timed_grids=len(shapes) * len(CANDIDATES))
+        proposals = {"default": {}, "per_axis": choose_per_axis(times), "per_shape": choose(times)}
+        batch_ms = {name: time_batch(specs, ov, batch_reps) for name, ov in proposals.items()}
+        chosen = min(batch_ms, key=batch_ms.get)
+        t = Tuning(proposals[chosen], times, old_tile, timed_grids=len(shapes) * len(CANDIDATES),
+                   per_shape=proposals["per_shape"], per_axis=proposals["per_axis"], batch_ms=batch_ms,
+                   chosen=chosen)
         if cache:
-            for k in keys:
-                stored[_key_str(dev, lib, k)] = {"rows": t.choice[k], "us": {str(c): v for c, v in t.us[k].items()}}
+            stored[key] = {"choice": str_keys(t.choice),
+                           "us": {",".join(map(str, k)): {str(c): v for c, v in per.items()} for k, per in t.us.items()},
+                           "per_shape": str_keys(t.per_shape), "per_axis": str_keys(t.per_axis),
+                           "batch_ms": t.batch_ms, "chosen": t.chosen}
             os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
             with open(cache, "w") as f:
                 json.dump(stored, f, indent=1)
     if apply:
+        hjm.clear_axis_tiles()
         t.apply()
     return t

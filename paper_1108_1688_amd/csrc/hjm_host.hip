@@ -1477,7 +1477,7 @@ hjm_status hjm_price_static(const hjm_axis ax[3], const hjm_model* model, const 
 enum { G_XR = 0, G_EXR, G_EXP, G_RS, G_V, G_VS, G_YU, G_YC, kGroupKinds };
 
 struct LaunchGroup {
-    int kind = 0, rows = 0;
+    int kind = 0, rows = 0;   // rows per thread, plus variant flags: 256 window or minors, 1024 x segments
     size_t off = 0;           // first task in the batch's task array
     std::vector<int2> tasks;
     std::vector<int> cnt;     // active task prefix per step
@@ -1607,9 +1607,9 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step, hipS
     case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, st);
     case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, st);
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, st);
-    case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
+    case G_VS: return launch_vs(g.rows & 0xff, b->d_desc, t, nt, g.aux, st);
     case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, st);
-    default: return launch_yc(g.rows & 0xff, b->d_desc, t, nt, g.aux, st, 0, (g.rows >> 8) != 0);
+    default: return launch_yc(g.rows & 0xff, b->d_desc, t, nt, g.aux, st, 0, ((g.rows >> 8) & 1) != 0);
     }
 }
 
@@ -1795,10 +1795,22 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
                 case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
                 case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
                 case G_V: if (!pl.vs_rows) { rows = pl.rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
-                case G_VS: if (pl.vs_rows) { rows = pl.vs_rows; tiles = pl.vs_tiles; aux = pl.vs_S; } break;
+                // the segmented sweeps run one wave per segment, in workgroups
+                // sized for the group's most segments: solves with fewer
+                // segments would leave waves idle for the workgroup's whole
+                // life, so each segment count is a group of its own (+1024 S)
+                case G_VS:
+                    if (pl.vs_rows) { rows = pl.vs_rows + 1024 * pl.vs_S; tiles = pl.vs_tiles; aux = pl.vs_S; }
+                    break;
                 case G_YU: if (!pl.yc_rows) { rows = pl.rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
-                // rows, plus 256 for pivots formed in the kernel (its own group)
-                default: if (pl.yc_rows) { rows = pl.yc_rows + (pl.y_minors ? 256 : 0); tiles = pl.yc_tiles; aux = pl.yc_S; } break;
+                // rows, plus 256 for pivots formed in the kernel, plus 1024 S
+                default:
+                    if (pl.yc_rows) {
+                        rows = pl.yc_rows + (pl.y_minors ? 256 : 0) + 1024 * pl.yc_S;
+                        tiles = pl.yc_tiles;
+                        aux = pl.yc_S;
+                    }
+                    break;
                 }
                 if (!tiles) continue;
                 LaunchGroup& g = group(lane, kind, rows);

@@ -19,6 +19,29 @@ def test_choose_takes_each_line_shapes_fastest_candidate():
     assert A.choose(times) == {(0, 96, 1536): 16, (1, 48, 3072): 32, (2, 32, 4608): 8}
 
 
+def test_choose_per_axis_sums_each_axis_over_its_line_shapes():
+    from paper_1108_1688_amd import autotune as A
+    times = {(0, 96, 1536): {8: 30.0, 16: 25.0, 32: 28.0},
+             (0, 64, 2048): {8: 10.0, 16: 16.0, 32: 12.0},   # r: 8 -> 40, 16 -> 41, 32 -> 40
+             (1, 48, 3072): {8: 20.0, 16: 22.0, 32: 18.0},
+             (2, 32, 4608): {8: 9.0, 16: 11.0, 32: 10.0}}
+    got = A.choose_per_axis(times)
+    assert got == {(0, 96, 1536): 8, (0, 64, 2048): 8, (1, 48, 3072): 32, (2, 32, 4608): 8}
+    # a candidate missing on one of the axis's shapes is not eligible for that axis
+    times[(2, 48, 100)] = {16: 1.0, 32: 1.0}
+    got = A.choose_per_axis(times)
+    assert got[(2, 32, 4608)] == 32 and got[(2, 48, 100)] == 32
+
+
+def test_workload_key_depends_on_shapes_steps_and_tile():
+    from paper_1108_1688_amd import autotune as A
+    specs = W.config4(16)
+    k = A.workload_key(specs, (16, 16, 16))
+    assert k == A.workload_key(list(specs), (16, 16, 16))
+    assert k != A.workload_key(specs, (8, 16, 16))
+    assert k != A.workload_key(specs[:-1], (16, 16, 16))
+
+
 def test_shapes_by_work_weights_sum_to_one():
     from paper_1108_1688_amd import autotune as A
     specs = W.config4(64)
@@ -67,19 +90,29 @@ def test_tuned_batch_matches_oracle_and_untuned(tmp_path):
         cache = str(tmp_path / "tune.json")
         t = A.tune(specs, steps=3, cache=cache)
         assert not t.cached and t.timed_grids == 3 * len(A.CANDIDATES)
-        assert len(t.choice) == 9
+        assert len(t.per_shape) == 9 and len(t.per_axis) == 9
+        assert set(t.batch_ms) == {"default", "per_axis", "per_shape"}
+        assert t.batch_ms[t.chosen] == min(t.batch_ms.values())
+        assert t.choice == {"default": {}, "per_axis": t.per_axis, "per_shape": t.per_shape}[t.chosen]
         assert tuple(hjm.get_line_tile()) == tuple(old)
-        for (axis, n, lines), rows in t.choice.items():
-            assert hjm.get_axis_tile(axis, n, lines) == rows
+        for (axis, n, lines), rows in t.per_shape.items():
+            assert hjm.get_axis_tile(axis, n, lines) == t.choice.get((axis, n, lines), 0)
         print(f"tuned: {t.summary()}")
         again = A.tune(specs, cache=cache)
-        assert again.cached and again.choice == t.choice
+        assert again.cached and again.choice == t.choice and again.chosen == t.chosen
         tuned = hjm.Batch(specs).run().prices()
+        # every proposal, installed, against the oracle and single grids
+        for ov in (t.per_shape, t.per_axis):
+            hjm.clear_axis_tiles()
+            for (axis, n, lines), rows in ov.items():
+                hjm.set_axis_tile(axis, n, lines, rows)
+            pb_all = hjm.Batch(specs).run().prices()
+            for sp, pb in zip(specs, pb_all):
+                g = hjm.Grid(sp)
+                g.step()
+                assert g.price() == pb
+                g.close()
         for sp, pb, pu in zip(specs, tuned, untuned):
-            g = hjm.Grid(sp)
-            g.step()
-            assert g.price() == pb
-            g.close()
             po, _ = O.price(to_oracle(sp), sp.r0, sp.v0)
             assert abs(pb - po) <= 1e-12 * abs(po)
             assert abs(pu - po) <= 1e-12 * abs(po)
