@@ -1702,7 +1702,7 @@ __device__ __forceinline__ void window_nodes(const SolveDesc& s, const ldouble* 
                                              const ExpColumn& q, const double (&ya)[J], const double (&yb)[J],
                                              double ulo, double uhi, int j0, double (&out)[J])
 {
-    const int nr = s.nr, nv = s.nv;
+    const int nr = s.nr;
     constexpr int CH = 4;
 #pragma unroll
     for (int m0 = 0; m0 < J; m0 += CH) {
@@ -1717,16 +1717,19 @@ __device__ __forceinline__ void window_nodes(const SolveDesc& s, const ldouble* 
         }
 #pragma unroll
         for (int mm = 0; mm < CH; ++mm) {
+            // every node of the tile, also those past nv (in-bounds reads of
+            // the clamped window rows; their results are never stored): no
+            // exit from the unrolled loop
             const int m = m0 + mm;
-            const int j = j0 + m;
-            if (j >= nv) break;  // wave-uniform
             // window rows m .. m + 2 hold v nodes j - 1 .. j + 1
             const ldouble* w0 = wcol + (size_t)(m + 1) * nr;
             const double lw0 = w0[-1], rw0 = w0[1];
             const double lwm = w0[-1 - nr], rwm = w0[1 - nr];
             const double lwp = w0[nr - 1], rwp = w0[nr + 1];
             const double* cw5 = col + mm;  // u(i, j - 2 .. j + 2)
-            const double ux = q.dx != 0 ? w0[q.dx] : cw5[2];
+            // the outflow extra entry (dx = 0 inside, where it reads the node
+            // itself under a zero weight): one read for every lane
+            const double ux = w0[q.dx];
             const double v = vtc[VT_V * J + m];
             const double olo = q.mlo + q.alo * v, odi = q.mdi + q.adi * v, oup = q.mup + q.aup * v;
             const double a1 = olo * lw0 + odi * cw5[2] + oup * rw0 + q.mex * ux;
@@ -1737,7 +1740,10 @@ __device__ __forceinline__ void window_nodes(const SolveDesc& s, const ldouble* 
             const double a3 = by * (q.wa * ya[m] + q.w2 * cw5[2] + q.wb * yb[m]);
             const double cross = (rwp - rwm) - (lwp - lwm);
             const double a0 = q.rx * vtc[VT_X * J + m] * cross;
-            const double val = q.dt * (((a1 + a2) + a3) + a0);
+            double val = q.dt * (((a1 + a2) + a3) + a0);
+            // formed on every lane and then selected: a branch around it for
+            // the Dirichlet lanes would copy the live arrays at every join
+            asm volatile("" : "+v"(val));
             out[m] = q.dir ? q.gval : val;
         }
     }
