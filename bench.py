@@ -48,14 +48,14 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "35bf7e94538d96303da2198a87b714b7a15025ff4a6d9f03f8c9ec8a49f42bec"
+    "sources_sha256": "a62003fc19f5d31aa1660d21e8d582aef63be9852c33820294746c4ec3cbfc5b"
                       ":161829d532aefc8a2b772d8867dda011d3a4a38de9c838c263ec446dcc49c327",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
     "exr_window": True,
     "y_minors": True,
-    "bytes_per_point": {"explicit+r": 18.430, "v": 15.978, "y+update": 24.071},
+    "bytes_per_point": {"explicit+r": 18.373, "v": 15.978, "y+update": 24.071},
 }
 
 def log(*a):
@@ -137,10 +137,11 @@ def calibration(hjm, W, torch, stream, n_solves: int, tune: bool):
     """Calibration-style throughput: n_solves independent caplet solves with
     uneven grids ({32,48,64,96} per axis, 50..200 steps, seeded parameters),
     priced one by one (plain single-solve ADI) and as one batch replayed from
-    a HIP graph (line tiles chosen by the autotuner on the batch's shapes)."""
+    a HIP graph (line tiles and stream lanes chosen by the autotuner on the
+    batch's shapes)."""
     from paper_1108_1688_amd import autotune
     specs = W.config4(n_solves)
-    old = hjm.get_line_tile(), hjm.get_explicit_chunk()
+    old = hjm.get_line_tile(), hjm.get_explicit_chunk(), hjm.get_batch_streams()
     out = {"workload": f"{n_solves} caplet solves, grids from {{32,48,64,96}}^3, 50-200 steps (seed 3)",
            "point_steps": int(sum(s.points * s.n_steps for s in specs))}
     try:
@@ -200,6 +201,7 @@ def calibration(hjm, W, torch, stream, n_solves: int, tune: bool):
         hjm.clear_axis_tiles()
         hjm.set_line_tile(*old[0])
         hjm.set_explicit_chunk(old[1])
+        hjm.set_batch_streams(old[2])
     return out
 
 

@@ -21,7 +21,9 @@ Two stages:
    launches per step, which the per-kernel times do not see.  So each
    proposal, and the default (no overrides), prices the whole batch a few
    times; the fastest wins and goes to the library as per-shape overrides
-   (hjm_set_axis_tile).
+   (hjm_set_axis_tile).  With those tiles the batch is then priced over
+   the candidate stream-lane counts (LANES), and the fastest count is kept
+   (hjm_set_batch_streams).
 
 Results are cached in a JSON file keyed by the device, the library build and
 the batch's workload (its line shapes with their work), so a later process
@@ -39,6 +41,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 from . import hjm
 
 CANDIDATES: Tuple[int, ...] = (8, 16, 32)
+LANES: Tuple[int, ...] = (2, 3, 4)
 AXES = ("r", "v", "y")
 # the pass of each axis's line solve in the per-pass timing (on grids whose
 # r lines are solved inside the explicit kernel, pass 0 holds both)
@@ -64,11 +67,15 @@ class Tuning:
     per_axis: Dict[LineShape, int] = field(default_factory=dict)    # proposal: one value per axis
     batch_ms: Dict[str, float] = field(default_factory=dict)        # whole-batch time of each proposal
     chosen: str = "default"
+    lanes: int = 0                                                  # stream lanes chosen (0: left as it was)
+    lanes_ms: Dict[int, float] = field(default_factory=dict)        # whole-batch time per lane count
 
     def apply(self) -> None:
-        """Install the chosen overrides in the library."""
+        """Install the chosen overrides (and lane count) in the library."""
         for (axis, n, lines), rows in self.choice.items():
             hjm.set_axis_tile(axis, n, lines, rows)
+        if self.lanes:
+            hjm.set_batch_streams(self.lanes)
 
     def summary(self) -> dict:
         """The chosen proposal, its rows per line shape ("r:96x9216" -> 16),
@@ -77,7 +84,8 @@ class Tuning:
         out = {f"{AXES[a]}:{n}x{lines}": rows for (a, n, lines), rows in sorted(self.choice.items())}
         differ = sum(1 for (a, _, _), rows in self.choice.items() if rows != self.default_rows[a])
         return {"chosen": self.chosen, "per_line_shape": out, "line_shapes": len(self.per_shape),
-                "differ_from_default": differ, "batch_ms": {k: round(v, 3) for k, v in self.batch_ms.items()}}
+                "differ_from_default": differ, "batch_ms": {k: round(v, 3) for k, v in self.batch_ms.items()},
+                "lanes": self.lanes, "lanes_ms": {str(k): round(v, 3) for k, v in self.lanes_ms.items()}}
 
 
 def choose(times: Dict[LineShape, Dict[int, float]]) -> Dict[LineShape, int]:
@@ -187,10 +195,11 @@ def time_batch(specs: Sequence, overrides: Dict[LineShape, int], reps: int) -> f
 
 
 def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bool = True,
-         batch_reps: int = 3) -> Tuning:
+         batch_reps: int = 3, lanes: bool = True) -> Tuning:
     """Choose the line tiles of the batch specs (timing what the cache does
-    not hold) and, if apply, install them as per-shape overrides; the global
-    line tile is left as it was."""
+    not hold) and, if lanes, the stream-lane count; if apply, install them
+    (per-shape overrides, hjm_set_batch_streams).  The global line tile is
+    left as it was; the lane count, if chosen, is process-wide."""
     specs = list(specs)
     shapes = shapes_by_work(specs)
     old_tile = tuple(hjm.get_line_tile())
@@ -210,7 +219,8 @@ def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bo
         e = stored[key]
         t = Tuning(keys_of(e["choice"]), {k: {int(c): v for c, v in per.items()} for k, per in keys_of(e["us"]).items()},
                    old_tile, cached=True, per_shape=keys_of(e["per_shape"]), per_axis=keys_of(e["per_axis"]),
-                   batch_ms=e["batch_ms"], chosen=e["chosen"])
+                   batch_ms=e["batch_ms"], chosen=e["chosen"], lanes=e["lanes"] if lanes else 0,
+                   lanes_ms={int(k): v for k, v in e["lanes_ms"].items()} if lanes else {})
     else:
         try:
             times = time_shapes(shapes, steps)
@@ -223,11 +233,23 @@ def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bo
         t = Tuning(proposals[chosen], times, old_tile, timed_grids=len(shapes) * len(CANDIDATES),
                    per_shape=proposals["per_shape"], per_axis=proposals["per_axis"], batch_ms=batch_ms,
                    chosen=chosen)
+        if lanes:
+            old_lanes = hjm.get_batch_streams()
+            try:
+                for n in LANES:
+                    hjm.set_batch_streams(n)
+                    t.lanes_ms[n] = batch_ms[chosen] if n == old_lanes else time_batch(specs, t.choice, batch_reps)
+            finally:
+                hjm.set_batch_streams(old_lanes)
+            t.lanes = min(t.lanes_ms, key=t.lanes_ms.get)
+        if cache and not lanes:
+            cache = None  # entries hold the lane choice: only full tunings are stored
         if cache:
             stored[key] = {"choice": str_keys(t.choice),
                            "us": {",".join(map(str, k)): {str(c): v for c, v in per.items()} for k, per in t.us.items()},
                            "per_shape": str_keys(t.per_shape), "per_axis": str_keys(t.per_axis),
-                           "batch_ms": t.batch_ms, "chosen": t.chosen}
+                           "batch_ms": t.batch_ms, "chosen": t.chosen, "lanes": t.lanes,
+                           "lanes_ms": {str(k): v for k, v in t.lanes_ms.items()}}
             os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
             with open(cache, "w") as f:
                 json.dump(stored, f, indent=1)

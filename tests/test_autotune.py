@@ -81,6 +81,7 @@ def test_tuned_batch_matches_oracle_and_untuned(tmp_path):
     from paper_1108_1688_amd import autotune as A
     from paper_1108_1688_amd import hjm
     old = hjm.get_line_tile()
+    old_lanes = hjm.get_batch_streams()
     base = W.config2()[1]
     specs = [W.with_shape(base, 64, 48, 32, 30), W.with_shape(base, 96, 32, 64, 24),
              W.with_shape(base, 32, 64, 48, 20)]
@@ -94,12 +95,14 @@ def test_tuned_batch_matches_oracle_and_untuned(tmp_path):
         assert set(t.batch_ms) == {"default", "per_axis", "per_shape"}
         assert t.batch_ms[t.chosen] == min(t.batch_ms.values())
         assert t.choice == {"default": {}, "per_axis": t.per_axis, "per_shape": t.per_shape}[t.chosen]
+        assert set(t.lanes_ms) == set(A.LANES) and t.lanes_ms[t.lanes] == min(t.lanes_ms.values())
+        assert hjm.get_batch_streams() == t.lanes
         assert tuple(hjm.get_line_tile()) == tuple(old)
         for (axis, n, lines), rows in t.per_shape.items():
             assert hjm.get_axis_tile(axis, n, lines) == t.choice.get((axis, n, lines), 0)
         print(f"tuned: {t.summary()}")
         again = A.tune(specs, cache=cache)
-        assert again.cached and again.choice == t.choice and again.chosen == t.chosen
+        assert again.cached and again.choice == t.choice and again.chosen == t.chosen and again.lanes == t.lanes
         tuned = hjm.Batch(specs).run().prices()
         # every proposal, installed, against the oracle and single grids
         for ov in (t.per_shape, t.per_axis):
@@ -119,3 +122,4 @@ def test_tuned_batch_matches_oracle_and_untuned(tmp_path):
     finally:
         hjm.clear_axis_tiles()
         hjm.set_line_tile(*old)
+        hjm.set_batch_streams(old_lanes)
