@@ -282,9 +282,26 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
                             void* d_workspace, size_t ws_bytes, void* hip_stream,
                             hjm_batch** out);
 
+/* The same with an ADI scheme per solve (schemes: n entries, section 5.1 and
+   the Craig-Sneyd family as for hjm_grid_create_scheme; null means Douglas
+   with theta = 1/2 for every solve, as hjm_batch_create).  A solve with a
+   correction scheme needs the kernels a grid of that scheme needs (else
+   HJM_EINVAL naming the solve, before any device work) and one more
+   nr*nv*ny array of workspace (hjm_batch_scheme_workspace_bytes).  Solves
+   share an operator only with the same theta and the same kind of pivots
+   (correction schemes store them).  Every price equals the single grid's of
+   the same scheme bit for bit. */
+hjm_status hjm_batch_scheme_workspace_bytes(int32_t n, const hjm_axis* ax, const int32_t* n_steps,
+                                            const hjm_scheme* schemes, size_t* bytes);
+hjm_status hjm_batch_create_scheme(int32_t n, const hjm_axis* ax, const hjm_model* model,
+                                   const hjm_payoff* payoff, const hjm_scheme* schemes,
+                                   const int32_t* n_steps, void* d_workspace, size_t ws_bytes,
+                                   void* hip_stream, hjm_batch** out);
+
 /* Enqueue a complete solve of every problem: terminal data at t = T, then
-   every Douglas step, where at step n one launch per pass covers all solves
-   with more than n steps.  The solves are dealt to hjm_get_batch_streams()
+   every step (each of its sweep sequences: one for Douglas, two for the
+   Craig-Sneyd family, 1 + q for Huang's correction), where at step n one
+   launch per pass and sequence covers all solves with more than n steps.  The solves are dealt to hjm_get_batch_streams()
    stream lanes (snake order by work), each launched on a stream the batch
    owns, forked from and joined back to the batch's stream with events, so
    that kernels of different lanes run concurrently; every result stays

@@ -1477,7 +1477,11 @@ hjm_status hjm_price_static(const hjm_axis ax[3], const hjm_model* model, const 
 enum { G_XR = 0, G_EXR, G_EXP, G_RS, G_V, G_VS, G_YU, G_YC, kGroupKinds };
 
 struct LaunchGroup {
-    int kind = 0, rows = 0;   // rows per thread, plus variant flags: 256 window or minors, 1024 x segments
+    int kind = 0, rows = 0;   // rows per thread (k_exp: v nodes per thread)
+    bool flag = false;        // k_exr: explicit phase from the LDS window; k_yc: pivots formed in the kernel
+    int segs = 0;             // k_vs, k_yc: segments per line (one group per count)
+    int seq = 0;              // sweep sequence of the step (0; 1.. the stage-2 sequences of a correction scheme)
+    int mode = 0;             // k_yc: what the sweep does with D3 (launch_yc's mode)
     size_t off = 0;           // first task in the batch's task array
     std::vector<int2> tasks;
     std::vector<int> cnt;     // active task prefix per step
@@ -1499,7 +1503,8 @@ struct hjm_batch {
     Readout* d_rq = nullptr;
     double* d_out = nullptr;
     int32_t* d_flags = nullptr;
-    std::vector<SolveDesc> descs;
+    std::vector<SolveDesc> descs;  // n stage-1 (Douglas) descriptors, then n stage-2 ones (correction schemes)
+    std::vector<hjm_scheme> schemes;
     std::vector<std::vector<double>> tables;
     std::vector<int> owner;  // the solve whose tables and y pivots each solve uses (itself, unless shared)
     int n_operators = 0;
@@ -1580,19 +1585,30 @@ void share_operator(SolveDesc& d, const SolveDesc& o)
     d.ypiv_skip = 1;
 }
 
-BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps)
+// Sweep sequences per Douglas step: 1 (Douglas), 2 (the Craig-Sneyd family),
+// 1 + q (Huang's correction with q subiterations).
+int sweep_sequences(const hjm_scheme& sc)
+{
+    return sc.kind == HJM_SCHEME_DOUGLAS ? 1 : (sc.kind == HJM_SCHEME_HUANG ? 1 + sc.af_iters : 2);
+}
+
+const hjm_scheme kDouglasHalf{HJM_SCHEME_DOUGLAS, 0, kTheta};
+
+// schemes: n entries, or null for Douglas with theta = 1/2 throughout.
+BatchLayout batch_layout(int n, const hjm_axis* ax, const int32_t* n_steps, const hjm_scheme* schemes)
 {
     Layout L;
     BatchLayout b;
     size_t nt = 0;
-    for (int s = 0; s < n; ++s) nt += task_bound(ax + 3 * s);
-    b.desc = L.take(sizeof(SolveDesc) * n);
+    for (int s = 0; s < n; ++s) nt += task_bound(ax + 3 * s) * sweep_sequences(schemes ? schemes[s] : kDouglasHalf);
+    b.desc = L.take(sizeof(SolveDesc) * 2 * n);
     b.tasks = L.take(sizeof(int2) * std::max<size_t>(nt, 1));
     b.rq = L.take(sizeof(Readout) * n);
     b.out = L.take(sizeof(double) * 3 * n);
     b.flags = L.take(sizeof(int32_t) * n);
     b.s.resize(n);
-    for (int s = 0; s < n; ++s) b.s[s] = layout_solve(L, ax + 3 * s, n_steps[s]);
+    for (int s = 0; s < n; ++s)
+        b.s[s] = layout_solve(L, ax + 3 * s, n_steps[s], schemes && schemes[s].kind != HJM_SCHEME_DOUGLAS);
     b.total = L.off;
     return b;
 }
@@ -1603,13 +1619,13 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step, hipS
     const int2* t = b->d_tasks + g.off;
     switch (g.kind) {
     case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, st);
-    case G_EXR: return launch_exr(g.rows & 0xff, b->d_desc, t, nt, step, g.lds, st, false, (g.rows >> 8) != 0);
-    case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, st);
+    case G_EXR: return launch_exr(g.rows, b->d_desc, t, nt, step, g.lds, st, g.seq > 0, g.flag);
+    case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, st, g.seq > 0);
     case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, st);
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, st);
-    case G_VS: return launch_vs(g.rows & 0xff, b->d_desc, t, nt, g.aux, st);
+    case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
     case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, st);
-    default: return launch_yc(g.rows & 0xff, b->d_desc, t, nt, g.aux, st, 0, ((g.rows >> 8) & 1) != 0);
+    default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, st, g.mode, g.flag);
     }
 }
 
@@ -1674,36 +1690,58 @@ hjm_status batch_enqueue(hjm_batch* b, bool timed)
 
 extern "C" {
 
-hjm_status hjm_batch_workspace_bytes(int32_t n, const hjm_axis* ax, const int32_t* n_steps, size_t* bytes)
+hjm_status hjm_batch_scheme_workspace_bytes(int32_t n, const hjm_axis* ax, const int32_t* n_steps,
+                                            const hjm_scheme* schemes, size_t* bytes)
 {
     if (n <= 0 || !ax || !n_steps || !bytes) return fail(HJM_EINVAL, "invalid batch arguments");
     for (int s = 0; s < n; ++s) {
         hjm_status st = validate_axes(ax + 3 * s);
         if (st) return fail(st, "solve %d: %s", s, g_last_error.c_str());
         if (n_steps[s] <= 0) return fail(HJM_EINVAL, "solve %d: n_steps must be > 0", s);
+        if (schemes && (st = validate_scheme(schemes + s))) return fail(st, "solve %d: %s", s, g_last_error.c_str());
     }
-    *bytes = batch_layout(n, ax, n_steps).total;
+    *bytes = batch_layout(n, ax, n_steps, schemes).total;
     return HJM_OK;
+}
+
+hjm_status hjm_batch_workspace_bytes(int32_t n, const hjm_axis* ax, const int32_t* n_steps, size_t* bytes)
+{
+    return hjm_batch_scheme_workspace_bytes(n, ax, n_steps, nullptr, bytes);
 }
 
 hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* model, const hjm_payoff* payoff,
                             const int32_t* n_steps, void* d_workspace, size_t ws_bytes, void* hip_stream,
                             hjm_batch** out)
 {
+    return hjm_batch_create_scheme(n, ax, model, payoff, nullptr, n_steps, d_workspace, ws_bytes, hip_stream, out);
+}
+
+hjm_status hjm_batch_create_scheme(int32_t n, const hjm_axis* ax, const hjm_model* model, const hjm_payoff* payoff,
+                                   const hjm_scheme* schemes, const int32_t* n_steps, void* d_workspace,
+                                   size_t ws_bytes, void* hip_stream, hjm_batch** out)
+{
     if (!out) return fail(HJM_EINVAL, "null output handle");
     *out = nullptr;
     if (n <= 0 || !ax || !model || !payoff || !n_steps) return fail(HJM_EINVAL, "invalid batch arguments");
+    std::vector<Plan> plans(n);
     for (int s = 0; s < n; ++s) {
         hjm_status st = validate_problem(ax + 3 * s, model + s, payoff + s, n_steps[s]);
+        if (!st && schemes) st = validate_scheme(schemes + s);
+        // the solve's kernel variants (a correction scheme needs the lane-split
+        // r solve and the y solve on reciprocal pivots)
+        if (!st) st = grid_plan(ax + 3 * s, model[s], payoff[s], schemes ? schemes[s] : kDouglasHalf, n_steps[s],
+                                &plans[s]);
         if (st) return fail(st, "solve %d: %s", s, g_last_error.c_str());
     }
     if (!d_workspace) return fail(HJM_EINVAL, "null workspace");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256) return fail(HJM_EINVAL, "workspace must be 256-byte aligned");
-    const BatchLayout bl = batch_layout(n, ax, n_steps);
+    const BatchLayout bl = batch_layout(n, ax, n_steps, schemes);
     if (ws_bytes < bl.total) return fail(HJM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, bl.total);
     hjm_batch* b = new (std::nothrow) hjm_batch;
     if (!b) return fail(HJM_EINVAL, "host allocation failed");
     b->n = n;
+    b->schemes.assign(n, kDouglasHalf);
+    if (schemes) b->schemes.assign(schemes, schemes + n);
     b->ax.assign(ax, ax + 3 * n);
     b->n_steps.assign(n_steps, n_steps + n);
     std::memcpy(b->rows, g_rows, sizeof b->rows);
@@ -1714,29 +1752,36 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
     b->d_rq = reinterpret_cast<Readout*>(b->base + bl.rq);
     b->d_out = reinterpret_cast<double*>(b->base + bl.out);
     b->d_flags = reinterpret_cast<int32_t*>(b->base + bl.flags);
-    b->descs.resize(n);
+    b->descs.resize(2 * n);
     b->tables.resize(n);
     b->owner.resize(n);
-    std::vector<Plan> plans(n);
     for (int s = 0; s < n; ++s) {
         const hjm_axis* a = ax + 3 * s;
+        const hjm_scheme& sc = b->schemes[s];
+        const bool corr = sc.kind != HJM_SCHEME_DOUGLAS;
+        // the correction schemes keep the stored y pivots (as on a grid)
+        if (corr) plans[s].y_minors = false;
         int own = s;
+        // one operator: the same tables (theta folded in) and the same pivot form
         for (int q = 0; g_batch_share && q < s && own == s; ++q)
-            if (b->owner[q] == q && same_operator(ax + 3 * q, model[q], payoff[q], n_steps[q], a, model[s], payoff[s],
-                                                  n_steps[s]))
+            if (b->owner[q] == q && b->schemes[q].theta == sc.theta &&
+                (b->schemes[q].kind != HJM_SCHEME_DOUGLAS) == corr &&
+                same_operator(ax + 3 * q, model[q], payoff[q], n_steps[q], a, model[s], payoff[s], n_steps[s]))
                 own = q;
         b->owner[s] = own;
         if (own == s) {
-            int rows[3];
-            plan_rows(a[0].n, a[1].n, a[2].n, rows);
-            plans[s] = make_plan(a[0].n, a[1].n, a[2].n, rows, r_spike_ok(a, model[s], payoff[s], n_steps[s]));
-            build_tables(a, model[s], payoff[s], n_steps[s], plans[s], b->tables[s]);
+            build_tables(a, model[s], payoff[s], n_steps[s], plans[s], b->tables[s], sc.theta);
             b->n_operators += 1;
         } else {
             plans[s] = plans[own];
         }
-        fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], plans[s], b->base, bl.s[s], b->d_flags + s);
+        fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], plans[s], b->base, bl.s[s], b->d_flags + s,
+                  sc.theta);
         if (own != s) share_operator(b->descs[s], b->descs[own]);
+        if (corr) {
+            b->descs[s].stage = 1;
+            scheme_stage2(b->descs[n + s], b->descs[s], sc, reinterpret_cast<double*>(b->base + bl.s[s].E));
+        }
         b->max_steps = std::max(b->max_steps, n_steps[s]);
         b->max_points = std::max<int64_t>(b->max_points, (int64_t)a[0].n * a[1].n * a[2].n);
         b->max_ylines = std::max<int64_t>(b->max_ylines, (int64_t)a[0].n * a[1].n);
@@ -1760,83 +1805,123 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
             lane_of[by_work[r]] = m < b->n_lanes ? m : 2 * b->n_lanes - 1 - m;
         }
     }
-    // (lane, kind, rows) -> group, created lane by lane in pass order
-    auto group = [&](int lane, int kind, int rows) -> LaunchGroup& {
+    // (lane, sequence, kind, variant) -> group, created lane by lane, and in
+    // a lane by sweep sequence and pass, the order in which a step launches
+    // them on the lane's stream
+    auto group = [&](int lane, int seq, int kind, int rows, bool flag, int segs, int mode) -> LaunchGroup& {
         for (LaunchGroup& g : b->groups)
-            if (g.lane == lane && g.kind == kind && g.rows == rows) return g;
+            if (g.lane == lane && g.seq == seq && g.kind == kind && g.rows == rows && g.flag == flag &&
+                g.segs == segs && g.mode == mode)
+                return g;
         b->groups.emplace_back();
-        b->groups.back().lane = lane;
-        b->groups.back().kind = kind;
-        b->groups.back().rows = rows;
-        b->groups.back().cnt.assign(b->max_steps, 0);
-        b->groups.back().pts.assign(b->max_steps, 0);
-        return b->groups.back();
+        LaunchGroup& g = b->groups.back();
+        g.lane = lane;
+        g.seq = seq;
+        g.kind = kind;
+        g.rows = rows;
+        g.flag = flag;
+        g.segs = segs;
+        g.mode = mode;
+        g.cnt.assign(b->max_steps, 0);
+        g.pts.assign(b->max_steps, 0);
+        return g;
     };
     for (int lane = 0; lane < b->n_lanes; ++lane) {
         std::vector<int> lane_order;
+        int lane_seqs = 1;
         for (int s : order)
-            if (lane_of[s] == lane) lane_order.push_back(s);
-        for (int kind = 0; kind < kGroupKinds; ++kind)
-            for (size_t oi = 0; oi < lane_order.size(); ++oi) {
-                const int s = lane_order[oi];
-                const Plan& pl = plans[s];
-                const int ns = n_steps[s];
-                int rows = 0, tiles = 0;
-                size_t lds = 0;
-                int aux = 0;
-                switch (kind) {
-                case G_XR:
-                    if (pl.r_mode == R_SPIKE || pl.r_mode == R_CHAIN) { rows = pl.rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; }
-                    break;
-                case G_EXR:
-                    // rows, plus 256 for the window variant (its own group)
-                    if (pl.r_mode == R_FUSED) { rows = pl.rs_rows + (pl.exr_win ? 256 : 0); tiles = pl.exr_tiles; lds = pl.exr_lds; }
-                    break;
-                case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
-                case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
-                case G_V: if (!pl.vs_rows) { rows = pl.rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
-                // the segmented sweeps run one wave per segment, in workgroups
-                // sized for the group's most segments: solves with fewer
-                // segments would leave waves idle for the workgroup's whole
-                // life, so each segment count is a group of its own (+1024 S)
-                case G_VS:
-                    if (pl.vs_rows) { rows = pl.vs_rows + 1024 * pl.vs_S; tiles = pl.vs_tiles; aux = pl.vs_S; }
-                    break;
-                case G_YU: if (!pl.yc_rows) { rows = pl.rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
-                // rows, plus 256 for pivots formed in the kernel, plus 1024 S
-                default:
-                    if (pl.yc_rows) {
-                        rows = pl.yc_rows + (pl.y_minors ? 256 : 0) + 1024 * pl.yc_S;
-                        tiles = pl.yc_tiles;
-                        aux = pl.yc_S;
-                    }
-                    break;
-                }
-                if (!tiles) continue;
-                LaunchGroup& g = group(lane, kind, rows);
-                if (kind != G_YC) {
-                    for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(s, t));
-                } else if (oi == 0 || b->owner[lane_order[oi - 1]] != b->owner[s]) {
-                    // the right-hand sides of one operator (adjacent in the
-                    // lane's order, same plan) share the y pivots: their tiles
-                    // go in 8 at a time, each block for every right-hand side
-                    // in turn, so that tasks t, t + 8, ... (dealt to one XCD)
-                    // read one tile's pivots from that XCD's cache
-                    std::vector<int> rhs{s};
-                    for (size_t oj = oi + 1; oj < lane_order.size() && b->owner[lane_order[oj]] == b->owner[s]; ++oj)
-                        rhs.push_back(lane_order[oj]);
-                    for (int tb = 0; tb < tiles; tb += 8)
-                        for (int r : rhs)
-                            for (int x = tb; x < std::min(tiles, tb + 8); ++x) g.tasks.push_back(make_int2(r, x));
-                }
-                const int64_t pts = (int64_t)ax[3 * s].n * ax[3 * s + 1].n * ax[3 * s + 2].n;
-                for (int step = 0; step < ns; ++step) {
-                    g.cnt[step] += tiles;
-                    g.pts[step] += pts;
-                }
-                g.lds = std::max(g.lds, lds);
-                g.aux = std::max(g.aux, aux);
+            if (lane_of[s] == lane) {
+                lane_order.push_back(s);
+                lane_seqs = std::max(lane_seqs, sweep_sequences(b->schemes[s]));
             }
+        for (int seq = 0; seq < lane_seqs; ++seq) {
+            // the lane's solves with this sweep sequence (a prefix of the
+            // order still holds: the order is by steps within every subset)
+            std::vector<int> seq_order;
+            for (int s : lane_order)
+                if (seq < sweep_sequences(b->schemes[s])) seq_order.push_back(s);
+            for (int kind = 0; kind < kGroupKinds; ++kind)
+                for (size_t oi = 0; oi < seq_order.size(); ++oi) {
+                    const int s = seq_order[oi];
+                    const Plan& pl = plans[s];
+                    const hjm_scheme& sc = b->schemes[s];
+                    const bool corr = sc.kind != HJM_SCHEME_DOUGLAS;
+                    const int nseq = sweep_sequences(sc);
+                    // the descriptor of this sequence: stage 1, or stage 2 (the
+                    // corrected start, the sweeps of E) at n + s
+                    const int di = seq == 0 ? s : n + s;
+                    const int ns = n_steps[s];
+                    int rows = 0, tiles = 0, segs = 0, mode = 0;
+                    bool flag = false;
+                    size_t lds = 0;
+                    int aux = 0;
+                    switch (kind) {
+                    case G_XR:
+                        if (pl.r_mode == R_SPIKE || pl.r_mode == R_CHAIN) { rows = pl.rows[0]; tiles = pl.r_tiles; lds = pl.r_lds; }
+                        break;
+                    case G_EXR:
+                        // the window form for the predictor only (the corrected
+                        // start keeps the per-lane loads)
+                        if (pl.r_mode == R_FUSED) {
+                            rows = pl.rs_rows;
+                            flag = pl.exr_win && seq == 0;
+                            tiles = pl.exr_tiles;
+                            lds = pl.exr_lds;
+                        }
+                        break;
+                    case G_EXP: if (pl.r_mode == R_SPLIT) { rows = pl.exp_J; tiles = pl.exp_tiles; } break;
+                    case G_RS: if (pl.r_mode == R_SPLIT) { rows = pl.rs_rows; tiles = pl.rs_tiles; aux = ax[3 * s].n; } break;
+                    case G_V: if (!pl.vs_rows) { rows = pl.rows[1]; tiles = pl.v_tiles; lds = pl.v_lds; } break;
+                    // the segmented sweeps run one wave per segment, in workgroups
+                    // sized for the group's most segments: solves with fewer
+                    // segments would leave waves idle for the workgroup's whole
+                    // life, so each segment count is a group of its own
+                    case G_VS:
+                        if (pl.vs_rows) { rows = pl.vs_rows; segs = pl.vs_S; tiles = pl.vs_tiles; aux = pl.vs_S; }
+                        break;
+                    case G_YU: if (!pl.yc_rows) { rows = pl.rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
+                    default:
+                        if (pl.yc_rows) {
+                            rows = pl.yc_rows;
+                            flag = pl.y_minors;
+                            segs = pl.yc_S;
+                            tiles = pl.yc_tiles;
+                            aux = pl.yc_S;
+                            // as on a grid: U += D3 (Douglas, the last CS / MCS
+                            // sequence), D3 stays in D (stage 1), U += D3 + E3 (HV,
+                            // Huang's last), D3 += E3 (Huang's intermediate ones)
+                            mode = !corr ? 0 : (seq == 0 ? 1 : (seq < nseq - 1 ? 3 : (sc.kind == HJM_SCHEME_HV ||
+                                                                                      sc.kind == HJM_SCHEME_HUANG ? 2 : 0)));
+                        }
+                        break;
+                    }
+                    if (!tiles) continue;
+                    LaunchGroup& g = group(lane, seq, kind, rows, flag, segs, mode);
+                    if (kind != G_YC) {
+                        for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(di, t));
+                    } else if (oi == 0 || b->owner[seq_order[oi - 1]] != b->owner[s]) {
+                        // the right-hand sides of one operator (adjacent in the
+                        // order, same plan and steps) read one table (and, stored,
+                        // one pivot array): their tiles go in 8 at a time, each
+                        // block for every right-hand side in turn, so that tasks
+                        // t, t + 8, ... (dealt to one XCD) meet in that XCD's cache
+                        std::vector<int> rhs{s};
+                        for (size_t oj = oi + 1; oj < seq_order.size() && b->owner[seq_order[oj]] == b->owner[s]; ++oj)
+                            rhs.push_back(seq_order[oj]);
+                        for (int tb = 0; tb < tiles; tb += 8)
+                            for (int r : rhs)
+                                for (int x = tb; x < std::min(tiles, tb + 8); ++x)
+                                    g.tasks.push_back(make_int2(seq == 0 ? r : n + r, x));
+                    }
+                    const int64_t pts = (int64_t)ax[3 * s].n * ax[3 * s + 1].n * ax[3 * s + 2].n;
+                    for (int step = 0; step < ns; ++step) {
+                        g.cnt[step] += tiles;
+                        g.pts[step] += pts;
+                    }
+                    g.lds = std::max(g.lds, lds);
+                    g.aux = std::max(g.aux, aux);
+                }
+        }
     }
     std::vector<int2> all;
     for (LaunchGroup& g : b->groups) {
@@ -1854,7 +1939,7 @@ hjm_status hjm_batch_create(int32_t n, const hjm_axis* ax, const hjm_model* mode
             if (!e && !(e = hipEventCreateWithFlags(&j, hipEventDisableTiming))) b->join_ev.push_back(j);
         }
     }
-    if (!e) e = hipMemcpyAsync(b->d_desc, b->descs.data(), sizeof(SolveDesc) * n, hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipMemcpyAsync(b->d_desc, b->descs.data(), sizeof(SolveDesc) * 2 * n, hipMemcpyHostToDevice, b->stream);
     if (!e && !all.empty())
         e = hipMemcpyAsync(b->d_tasks, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, b->stream);
     int64_t max_gd = 0;

@@ -90,6 +90,8 @@ def lib():
         "hjm_price_static": (st, [P(Axis), P(Model), P(Payoff), i32, d, d, vp, vp, P(d)]),
         "hjm_batch_workspace_bytes": (st, [i32, P(Axis), P(i32), P(sz)]),
         "hjm_batch_create": (st, [i32, P(Axis), P(Model), P(Payoff), P(i32), vp, sz, vp, P(vp)]),
+        "hjm_batch_scheme_workspace_bytes": (st, [i32, P(Axis), P(i32), P(Scheme), P(sz)]),
+        "hjm_batch_create_scheme": (st, [i32, P(Axis), P(Model), P(Payoff), P(Scheme), P(i32), vp, sz, vp, P(vp)]),
         "hjm_batch_run": (st, [vp, i32]),
         "hjm_batch_prices": (st, [vp, P(d), P(d), P(d)]),
         "hjm_batch_greeks": (st, [vp, P(d), P(d), P(d)]),
@@ -436,12 +438,12 @@ def price_static(spec, U, stream=None, r0: Optional[float] = None, v0: Optional[
 
 
 class Batch:
-    """Many independent solves advanced together (one launch per pass per step)."""
+    """Many independent solves advanced together (one launch per pass, sweep
+    sequence and step); each solve's ADI scheme comes from its spec, as for
+    Grid."""
 
     def __init__(self, specs: Sequence, stream=None, device: Optional[str] = None):
         torch = _torch()
-        if any(getattr(sp, "scheme", 0) != 0 or getattr(sp, "theta", 0.5) != 0.5 for sp in specs):
-            raise ValueError("batches run the Douglas scheme with theta = 1/2; price other schemes with Grid")
         L = lib()
         self.specs = list(specs)
         n = len(self.specs)
@@ -457,13 +459,14 @@ class Batch:
         self._models = (Model * n)(*self._model_refs)
         self._payoffs = (Payoff * n)(*[make_payoff(sp.payoff) for sp in self.specs])
         self._steps = (C.c_int32 * n)(*[sp.n_steps for sp in self.specs])
+        self._schemes = (Scheme * n)(*[make_scheme(sp) for sp in self.specs])
         nbytes = C.c_size_t()
-        check(L.hjm_batch_workspace_bytes(n, self._ax, self._steps, C.byref(nbytes)))
+        check(L.hjm_batch_scheme_workspace_bytes(n, self._ax, self._steps, self._schemes, C.byref(nbytes)))
         self.ws = _workspace(nbytes.value, self.device)
         h = C.c_void_p()
-        check(L.hjm_batch_create(n, self._ax, self._models, self._payoffs, self._steps,
-                                 C.c_void_p(self.ws.data_ptr()), nbytes.value, _stream_handle(self.stream),
-                                 C.byref(h)))
+        check(L.hjm_batch_create_scheme(n, self._ax, self._models, self._payoffs, self._schemes, self._steps,
+                                        C.c_void_p(self.ws.data_ptr()), nbytes.value, _stream_handle(self.stream),
+                                        C.byref(h)))
         self._h = h
 
     def run(self, graph: bool = False) -> "Batch":

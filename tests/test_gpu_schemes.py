@@ -128,3 +128,45 @@ def test_huang_one_subiteration_is_hv_on_gpu():
     Uh, ph, _ = _gpu(_spec((64, 24, 32), 6, W.HUANG, 0.5, af_iters=1))
     Uv, pv, _ = _gpu(_spec((64, 24, 32), 6, W.HV, 0.5))
     assert np.array_equal(Uh, Uv) and ph == pv
+
+
+@pytest.mark.parametrize("path", ["fused", "split"])
+def test_batch_of_mixed_schemes_equals_single_grids(path):
+    """A batch whose solves use different ADI schemes (each sweep sequence
+    its own launch groups, the stage-2 descriptors after the stage-1 ones,
+    uneven step counts so that the solves drop out at different steps):
+    every price equals its own grid's bit for bit, the graph replay equals
+    the eager run, and a CS and a Huang solve match the oracle's scheme."""
+    hjm.set_r_fusion(path == "fused")
+    specs = [_spec((64, 24, 32), 8, W.CS, 0.5), _spec((64, 24, 32), 6, W.MCS, THETA_MCS),
+             _spec((64, 24, 32), 7, W.HV, THETA_HV), _spec((64, 24, 32), 5, W.HUANG, 0.5, af_iters=2),
+             _spec((64, 24, 32), 8, W.DOUGLAS, 0.5), _spec((64, 24, 32), 4, W.DOUGLAS, 0.6),
+             _spec((32, 24, 48), 6, W.CS, 0.5, kind=W.FLOORLET), _spec((64, 24, 32), 8, W.CS, 0.5, kind=W.FLOORLET)]
+    print(f"[gpu] mixed-scheme batch of {len(specs)} ({path})", flush=True)
+    st = torch.cuda.Stream()
+    b = hjm.Batch(specs, stream=st)
+    eager = b.run().prices()
+    replay = b.run(graph=True).prices()
+    again = b.run(graph=True).prices()
+    n_ops = b.operators()
+    b.close()
+    assert np.array_equal(eager, replay) and np.array_equal(replay, again)
+    # the CS caplet and floorlet on one mesh share an operator, nothing else does
+    assert n_ops == len(specs) - 1
+    for sp, pb in zip(specs, eager):
+        _, pg, plan = _gpu(sp)
+        assert plan["r_method"] == path
+        assert pg == pb, (sp.scheme, sp.theta, pg, pb)
+    for sp, pb in ((specs[0], eager[0]), (specs[3], eager[3])):
+        p = to_oracle(sp)
+        po = O.readout(p, O.run(p, 0, sp.n_steps), sp.r0, sp.v0)
+        assert abs(pb - po) <= REL * abs(po), (sp.scheme, pb, po)
+
+
+def test_batch_scheme_rejected_where_unsupported():
+    """A batch with a correction scheme on a grid that needs the per-line
+    chained r solve is refused before any device work, naming the solve."""
+    specs = [_spec((64, 24, 32), 4, W.DOUGLAS, 0.5), _spec((40, 24, 32), 1, W.CS, 0.5)]
+    with pytest.raises(hjm.HjmError) as e:
+        hjm.Batch(specs)
+    assert e.value.status == hjm.EINVAL and "solve 1" in str(e.value)
