@@ -239,6 +239,29 @@ def schemes_leg(hjm, W, torch, stream, reps: int = 3):
         out[name] = {"theta": th, "ms_per_solve": round(el * 1e3, 3),
                      "point_steps_per_s": spec.points * spec.n_steps / el,
                      "price": p40, "price_160_steps": p160, "rel_diff_vs_160_steps": abs(p40 - p160) / abs(p160)}
+    # calibration batches with a second-order scheme: 128 of the uneven
+    # calibration solves as one batch, Douglas against Hundsdorfer-Verwer
+    specs = W.config4(128)
+    hv = [replace(sp, scheme=W.HV, theta=0.5 + math.sqrt(3.0) / 6.0) for sp in specs]
+    batch = {"workload": "128 calibration solves (grids from {32,48,64,96}^3, 50-200 steps), one batch, eager"}
+    prices = {}
+    for name, ss in (("douglas", specs), ("hv", hv)):
+        b = hjm.Batch(ss, stream=stream)
+        b.run()
+        b.prices()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run()
+            prices[name] = b.prices()
+            ts.append(time.perf_counter() - t0)
+        b.close()
+        el = sorted(ts)[len(ts) // 2]
+        batch[name] = {"ms_per_run": round(el * 1e3, 3), "solves_per_s": len(ss) / el}
+    d = np.abs(prices["hv"] - prices["douglas"]) / np.abs(prices["douglas"])
+    batch["hv_vs_douglas_rel_price_diff"] = {"median": float(np.median(d)), "max": float(d.max())}
+    out["calibration_batch"] = batch
     return out
 
 

@@ -25,9 +25,10 @@ Two stages:
    the candidate stream-lane counts (LANES), and the fastest count is kept
    (hjm_set_batch_streams).
 
-Results are cached in a JSON file keyed by the device, the library build and
-the batch's workload (its line shapes with their work), so a later process
-reuses them without timing again.
+Results are cached in a JSON file: the per-kernel times under (device,
+library build, axis, nodes per line, lines), reused by any later batch that
+has that line shape, and the batch-level choice under (device, build, the
+batch's workload), so a later process reuses them without timing again.
 """
 from __future__ import annotations
 
@@ -143,15 +144,20 @@ def workload_key(specs: Sequence, tile: Tuple[int, int, int]) -> str:
     return hashlib.sha256(json.dumps([sig, list(tile), len(specs)]).encode()).hexdigest()[:16]
 
 
-def time_shapes(shapes: Dict[tuple, Tuple[object, float]], steps: int) -> Dict[LineShape, Dict[int, float]]:
-    """Per line shape and candidate: the weighted per-launch microseconds of
-    that axis's kernel, from `steps` event-timed Douglas steps of one grid of
-    every shape under each candidate setting (after one untimed step)."""
-    times: Dict[LineShape, Dict[int, float]] = {}
+def time_shapes(shapes: Dict[tuple, Tuple[object, float]], steps: int,
+                known: Optional[Dict[LineShape, Dict[int, float]]] = None) -> Tuple[Dict[LineShape, Dict[int, float]], int]:
+    """Per line shape and candidate: the per-launch microseconds of that
+    axis's kernel, from `steps` event-timed Douglas steps of one grid of every
+    shape under each candidate setting (after one untimed step).  Line shapes
+    in `known` keep their times, and grid shapes whose three line shapes are
+    all known are not run.  Returns the times and the grids timed."""
+    raw: Dict[LineShape, Dict[int, float]] = {k: dict(v) for k, v in (known or {}).items()}
+    todo = {sh: v for sh, v in shapes.items() if not all(k in raw for k in line_shapes(sh))}
+    fresh: Dict[LineShape, Dict[int, List[float]]] = {}
     for rows in CANDIDATES:
         hjm.clear_axis_tiles()
         hjm.set_line_tile(rows, rows, rows)
-        for sh, (spec, weight) in shapes.items():
+        for sh, (spec, _) in todo.items():
             n = min(steps + 1, spec.n_steps)
             g = hjm.Grid(spec)
             g.step(1)
@@ -161,10 +167,24 @@ def time_shapes(shapes: Dict[tuple, Tuple[object, float]], steps: int) -> Dict[L
             ms, cnt = g.profile_read()
             g.close()
             for key in line_shapes(sh):
+                if key in raw:
+                    continue
                 us = sum(1e3 * ms[q] / cnt[q] for q in PASS_OF_AXIS[key[0]] if cnt[q])
-                times.setdefault(key, {})
-                times[key][rows] = times[key].get(rows, 0.0) + weight * us
-    return times
+                fresh.setdefault(key, {}).setdefault(rows, []).append(us)
+    # a line shape met in several grid shapes: the mean of its measurements
+    for key, per in fresh.items():
+        raw[key] = {rows: sum(v) / len(v) for rows, v in per.items()}
+    return raw, len(todo) * len(CANDIDATES)
+
+
+def weigh(raw: Dict[LineShape, Dict[int, float]], shapes: Dict[tuple, Tuple[object, float]]) -> Dict[LineShape, Dict[int, float]]:
+    """Each line shape's times weighted by the work share of the grid shapes
+    that have it."""
+    w: Dict[LineShape, float] = {}
+    for sh, (_, weight) in shapes.items():
+        for key in line_shapes(sh):
+            w[key] = w.get(key, 0.0) + weight
+    return {key: {rows: w[key] * us for rows, us in raw[key].items()} for key in w if key in raw}
 
 
 def time_batch(specs: Sequence, overrides: Dict[LineShape, int], reps: int) -> float:
@@ -203,11 +223,15 @@ def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bo
     specs = list(specs)
     shapes = shapes_by_work(specs)
     old_tile = tuple(hjm.get_line_tile())
-    key = f"{_device_id()}:{_lib_id()}:{workload_key(specs, old_tile)}"
+    dev, lib = _device_id(), _lib_id()
+    key = f"batch:{dev}:{lib}:{workload_key(specs, old_tile)}"
     stored = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
             stored = json.load(f)
+
+    def line_key(k: LineShape) -> str:
+        return f"line:{dev}:{lib}:{AXES[k[0]]}:{k[1]}:{k[2]}"
 
     def keys_of(d):
         return {tuple(int(x) for x in k.split(",")): v for k, v in d.items()}
@@ -215,22 +239,29 @@ def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bo
     def str_keys(d):
         return {",".join(map(str, k)): v for k, v in d.items()}
 
-    if key in stored:
+    if key in stored and (stored[key]["lanes"] or not lanes):
         e = stored[key]
-        t = Tuning(keys_of(e["choice"]), {k: {int(c): v for c, v in per.items()} for k, per in keys_of(e["us"]).items()},
-                   old_tile, cached=True, per_shape=keys_of(e["per_shape"]), per_axis=keys_of(e["per_axis"]),
+        raw = {k: {int(c): v for c, v in stored[line_key(k)]["us"].items()}
+               for sh in shapes for k in line_shapes(sh) if line_key(k) in stored}
+        t = Tuning(keys_of(e["choice"]), weigh(raw, shapes), old_tile, cached=True,
+                   per_shape=keys_of(e["per_shape"]), per_axis=keys_of(e["per_axis"]),
                    batch_ms=e["batch_ms"], chosen=e["chosen"], lanes=e["lanes"] if lanes else 0,
                    lanes_ms={int(k): v for k, v in e["lanes_ms"].items()} if lanes else {})
     else:
+        # per-kernel times: the cache's per line shape (device, build, axis,
+        # nodes, lines), the rest measured
+        known = {k: {int(c): v for c, v in stored[line_key(k)]["us"].items()}
+                 for sh in shapes for k in line_shapes(sh) if line_key(k) in stored}
         try:
-            times = time_shapes(shapes, steps)
+            raw, timed = time_shapes(shapes, steps, known)
         finally:
             hjm.clear_axis_tiles()
             hjm.set_line_tile(*old_tile)
+        times = weigh(raw, shapes)
         proposals = {"default": {}, "per_axis": choose_per_axis(times), "per_shape": choose(times)}
         batch_ms = {name: time_batch(specs, ov, batch_reps) for name, ov in proposals.items()}
         chosen = min(batch_ms, key=batch_ms.get)
-        t = Tuning(proposals[chosen], times, old_tile, timed_grids=len(shapes) * len(CANDIDATES),
+        t = Tuning(proposals[chosen], times, old_tile, timed_grids=timed,
                    per_shape=proposals["per_shape"], per_axis=proposals["per_axis"], batch_ms=batch_ms,
                    chosen=chosen)
         if lanes:
@@ -242,14 +273,12 @@ def tune(specs: Sequence, steps: int = 4, cache: Optional[str] = None, apply: bo
             finally:
                 hjm.set_batch_streams(old_lanes)
             t.lanes = min(t.lanes_ms, key=t.lanes_ms.get)
-        if cache and not lanes:
-            cache = None  # entries hold the lane choice: only full tunings are stored
         if cache:
-            stored[key] = {"choice": str_keys(t.choice),
-                           "us": {",".join(map(str, k)): {str(c): v for c, v in per.items()} for k, per in t.us.items()},
-                           "per_shape": str_keys(t.per_shape), "per_axis": str_keys(t.per_axis),
-                           "batch_ms": t.batch_ms, "chosen": t.chosen, "lanes": t.lanes,
-                           "lanes_ms": {str(k): v for k, v in t.lanes_ms.items()}}
+            for k, per in raw.items():
+                stored[line_key(k)] = {"us": {str(c): v for c, v in per.items()}}
+            stored[key] = {"choice": str_keys(t.choice), "per_shape": str_keys(t.per_shape),
+                           "per_axis": str_keys(t.per_axis), "batch_ms": t.batch_ms, "chosen": t.chosen,
+                           "lanes": t.lanes, "lanes_ms": {str(k): v for k, v in t.lanes_ms.items()}}
             os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
             with open(cache, "w") as f:
                 json.dump(stored, f, indent=1)

@@ -33,6 +33,18 @@ def test_choose_per_axis_sums_each_axis_over_its_line_shapes():
     assert got[(2, 32, 4608)] == 32 and got[(2, 48, 100)] == 32
 
 
+def test_weigh_sums_the_work_of_every_grid_shape_with_the_line_shape():
+    from paper_1108_1688_amd import autotune as A
+    # the r lines of (32, 96, 64) and (32, 64, 96) are one line shape
+    shapes = {(32, 96, 64): (None, 0.25), (32, 64, 96): (None, 0.5), (48, 48, 48): (None, 0.25)}
+    raw = {k: {8: 1.0, 16: 2.0} for sh in shapes for k in A.line_shapes(sh)}
+    w = A.weigh(raw, shapes)
+    assert w[(0, 32, 6144)] == {8: 0.75, 16: 1.5}
+    assert w[(1, 96, 2048)] == {8: 0.25, 16: 0.5}
+    assert w[(2, 48, 2304)] == {8: 0.25, 16: 0.5}
+    assert len(w) == 8
+
+
 def test_workload_key_depends_on_shapes_steps_and_tile():
     from paper_1108_1688_amd import autotune as A
     specs = W.config4(16)
@@ -103,6 +115,14 @@ def test_tuned_batch_matches_oracle_and_untuned(tmp_path):
         print(f"tuned: {t.summary()}")
         again = A.tune(specs, cache=cache)
         assert again.cached and again.choice == t.choice and again.chosen == t.chosen and again.lanes == t.lanes
+        assert again.us == t.us
+        # per-kernel times are kept per line shape: a batch of two of these
+        # grid shapes times no grid at all (only its end-to-end choice)
+        import json
+        stored = json.load(open(cache))
+        assert sum(1 for k in stored if k.startswith("line:")) == 9
+        part = A.tune(specs[:2], cache=cache, apply=False)
+        assert not part.cached and part.timed_grids == 0 and len(part.per_shape) == 6
         tuned = hjm.Batch(specs).run().prices()
         # every proposal, installed, against the oracle and single grids
         for ov in (t.per_shape, t.per_axis):
