@@ -473,6 +473,21 @@ hjm_status hjm_get_exr_window(int32_t* on);
 hjm_status hjm_set_y_minors(int32_t on);
 hjm_status hjm_get_y_minors(int32_t* on);
 
+/* Whether Douglas solves created afterwards fold the v sweep (section 5.1's
+   second implicit sweep) into the other kernels where they can (on by
+   default): the fused explicit + r kernel keeps D1 in its tile and solves
+   the tile's 16 v rows as one segment of the segmented v sweep from zero; a
+   small kernel composes the segments of every v line (and recovers the two
+   face rows); the y sweep adds each segment's hand-over terms as it loads
+   D2.  One pass over the grid less per step (16 bytes per point).  Needs the
+   fused kernel's window form with at most 16 lanes per r line, the y sweep
+   on pivots formed in the kernel, nv a multiple of 16 with 2 to 16 segments
+   and bounded segment products (plan[5] then reports 16); otherwise, and
+   off, the v sweep runs on its own.  Equal to the unfolded sweep to
+   rounding, not bit for bit.  Process-wide. */
+hjm_status hjm_set_v_fold(int32_t on);
+hjm_status hjm_get_v_fold(int32_t* on);
+
 /* Stream lanes of batches created afterwards (1..8, default 3; HJM_EINVAL
    otherwise).  More lanes overlap more kernels at fewer solves per launch.
    Process-wide. */

@@ -299,6 +299,7 @@ struct Plan {
     int vs_rows, vs_S, vs_tiles;        // segmented v solve (0: chained k_v)
     int yc_rows, yc_S, yc_L, yc_tiles;  // y solve on reciprocal pivots (0: k_yu)
     bool y_minors;                      // those pivots formed in k_yc each step (else stored by k_ypiv)
+    bool v_fold;                        // the v sweep folded into k_exr / k_vfix / k_yc (vs_rows = kExrJ)
 };
 
 // Segmented v solve: nv = S * ROWS with S <= 4 waves; preferred rows first.
@@ -343,6 +344,7 @@ int g_exp_J = 8;      // v nodes per k_exp thread (4, 8 or 16)
 bool g_fuse_r = true;  // fuse the explicit predictor with the spike r solve where k_exr applies
 bool g_exr_window = true;  // the fused kernel's explicit phase reads its neighbours from an LDS window
 bool g_y_minors = true;    // k_yc forms the y pivots from the minors recurrence (no stored pivot array)
+bool g_v_fold = true;      // Douglas solves fold the v sweep into the other kernels where they can
 constexpr int kMaxBatchLanes = 8;
 int g_batch_lanes = 3;  // streams a batch spreads its solves over
 bool g_batch_share = true;  // solves of one operator share tables and y pivots
@@ -411,6 +413,7 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     p.yc_L = p.yc_rows ? 64 : 0;
     p.yc_tiles = p.yc_rows ? (nr * nv + p.yc_L - 1) / p.yc_L : 0;
     p.y_minors = p.yc_rows && g_y_minors;
+    p.v_fold = false;
     if (p.rs_rows) {
         p.r_mode = R_SPLIT;
         p.rs_S = nr / p.rs_rows;
@@ -702,24 +705,40 @@ void build_tables(const hjm_axis ax[3], const hjm_model& m, const hjm_payoff& p,
             vg[VG_AL * nv + j] = mid ? -vf[VF_A * nv + j] * vf[VF_INV * nv + j] : 0.0;
             vg[VG_CP * nv + j] = mid ? vf[VF_C * nv + j] : 0.0;
         }
-        const int R = plan.vs_rows;
-        double worst = 0.0;
-        for (int s0 = 0; R > 0 && s0 < nv; s0 += R) {
-            double g = 1.0, h = 1.0;
-            for (int j = s0; j < s0 + R; ++j) {
-                g *= vg[VG_AL * nv + j];
-                vg[VG_G * nv + j] = g;
-                worst = std::max(worst, std::fabs(g));
+        // per segment of R rows: the products G and H and, for the folded
+        // sweep, K (the backward sweep of G); the largest magnitude
+        auto segment_products = [&](int R) {
+            double worst = 0.0;
+            for (int s0 = 0; R > 0 && s0 < nv; s0 += R) {
+                double g = 1.0, h = 1.0, kb = 0.0;
+                for (int j = s0; j < s0 + R; ++j) {
+                    g *= vg[VG_AL * nv + j];
+                    vg[VG_G * nv + j] = g;
+                    worst = std::max(worst, std::fabs(g));
+                }
+                for (int j = s0 + R - 1; j >= s0; --j) {
+                    h *= -vg[VG_CP * nv + j];
+                    vg[VG_H * nv + j] = h;
+                    kb = vg[VG_G * nv + j] - vg[VG_CP * nv + j] * kb;
+                    vg[VG_K * nv + j] = kb;
+                    worst = std::max(worst, std::max(std::fabs(h), std::fabs(kb)));
+                }
             }
-            for (int j = s0 + R - 1; j >= s0; --j) {
-                h *= -vg[VG_CP * nv + j];
-                vg[VG_H * nv + j] = h;
-                worst = std::max(worst, std::fabs(h));
-            }
+            return worst;
+        };
+        // the segment corrections add G d'_in and H x_in (K d'_in folded):
+        // keep them from amplifying (they are products of |AL|, |CP| < 1 on
+        // dominant rows); a folded sweep that fails falls back to k_vs's
+        // segments, and those to the chained sweep
+        double worst = segment_products(plan.vs_rows);
+        if (plan.v_fold && !(worst <= 1.0)) {
+            plan.v_fold = false;
+            plan.vs_rows = vs_rows_for(nv, plan.rows[1]);
+            plan.vs_S = plan.vs_rows ? nv / plan.vs_rows : 0;
+            plan.vs_tiles = plan.vs_rows ? (nr * ny + 63) / 64 : 0;
+            worst = segment_products(plan.vs_rows);
         }
-        // the segment corrections add G d'_in and H x_in: keep them from
-        // amplifying (they are products of |AL|, |CP| < 1 on dominant rows)
-        if (R > 0 && !(worst <= 1.0)) {
+        if (plan.vs_rows > 0 && !(worst <= 1.0)) {
             plan.vs_rows = plan.vs_S = plan.vs_tiles = 0;
         }
     }
@@ -956,7 +975,21 @@ hjm_status grid_plan(const hjm_axis ax[3], const hjm_model& model, const hjm_pay
                     "the correction schemes run on the lane-split r solve and the stored-pivot y solve: nr = S*ROWS "
                     "(S a power of two, rows within the spike bound) and ny = S*ROWS are needed (plan: r method %d, "
                     "y rows %d)", plan.r_mode, plan.yc_rows);
-    *out = plan;
+    Plan p = plan;
+    // the v sweep folded into the fused kernel (its tile's 16 v rows are one
+    // segment), k_vfix and k_yc: Douglas, the window form with the scanned
+    // reduced system (no reduced-system scratch in the tile), the y sweep on
+    // pivots formed in the kernel (its hand-over values use the pivot array),
+    // whole segments; the table gate may still turn it off
+    const int nr = ax[0].n, nv = ax[1].n, ny = ax[2].n;
+    if (!corr && g_v_fold && p.r_mode == R_FUSED && p.exr_win && p.rs_S <= 16 && p.yc_rows && p.y_minors &&
+        nv % kExrJ == 0 && nv / kExrJ >= 2 && nv / kExrJ <= kMaxFoldSegs) {
+        p.v_fold = true;
+        p.vs_rows = kExrJ;
+        p.vs_S = nv / kExrJ;
+        p.vs_tiles = (int)(((int64_t)nr * ny + kBlock - 1) / kBlock);
+    }
+    *out = p;
     return HJM_OK;
 }
 
@@ -1153,6 +1186,19 @@ hjm_status hjm_get_exr_window(int32_t* on)
     return HJM_OK;
 }
 
+hjm_status hjm_set_v_fold(int32_t on)
+{
+    g_v_fold = on != 0;
+    return HJM_OK;
+}
+
+hjm_status hjm_get_v_fold(int32_t* on)
+{
+    if (!on) return fail(HJM_EINVAL, "null argument");
+    *on = g_v_fold ? 1 : 0;
+    return HJM_OK;
+}
+
 hjm_status hjm_set_y_minors(int32_t on)
 {
     g_y_minors = on != 0;
@@ -1314,14 +1360,16 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
             }
             if (pass == 0 && split) e = launch_exp(p.exp_J, dd, nullptr, p.exp_tiles, n, g->stream, st2);
             else if (pass == 0 && p.r_mode == R_FUSED)
-                e = launch_exr(p.rs_rows, dd, nullptr, p.exr_tiles, n, p.exr_lds, g->stream, st2, p.exr_win);
+                e = launch_exr(p.rs_rows, dd, nullptr, p.exr_tiles, n, p.exr_lds, g->stream, st2, p.exr_win, p.v_fold);
             else if (pass == 0) e = launch_xr(g->rows[0], dd, nullptr, p.r_tiles, n, p.r_lds, g->stream);
             else if (pass == 1) e = launch_rs(p.rs_rows, dd, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
+            else if (pass == 2 && p.v_fold) e = launch_vfix(dd, nullptr, p.vs_tiles, g->stream);
             else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, dd, nullptr, p.vs_tiles, p.vs_S, g->stream);
             else if (pass == 2) e = launch_v(g->rows[1], dd, nullptr, p.v_tiles, p.v_lds, g->stream);
             else if (p.yc_rows)
                 e = launch_yc(p.yc_rows, dd, nullptr, p.yc_tiles, p.yc_S, g->stream,
-                              !g->corr ? 0 : (!st2 ? 1 : (!last_seq ? 3 : (g->desc2.hv ? 2 : 0))), p.y_minors);
+                              !g->corr ? 0 : (!st2 ? 1 : (!last_seq ? 3 : (g->desc2.hv ? 2 : 0))), p.y_minors,
+                              p.v_fold);
             else e = launch_yu(g->rows[2], dd, nullptr, p.y_tiles, p.y_lds, g->stream);
             if (e) return hip_fail(e, "hjm_adi_step");
             if (g->profile) {
@@ -1482,6 +1530,7 @@ struct LaunchGroup {
     int segs = 0;             // k_vs, k_yc: segments per line (one group per count)
     int seq = 0;              // sweep sequence of the step (0; 1.. the stage-2 sequences of a correction scheme)
     int mode = 0;             // k_yc: what the sweep does with D3 (launch_yc's mode)
+    bool fold = false;        // the folded v sweep (k_exr, k_vfix in place of k_vs, k_yc)
     size_t off = 0;           // first task in the batch's task array
     std::vector<int2> tasks;
     std::vector<int> cnt;     // active task prefix per step
@@ -1547,8 +1596,9 @@ struct BatchLayout {
 size_t task_bound(const hjm_axis* a)
 {
     const Plan pb = plan_bound(a[0].n, a[1].n, a[2].n);
+    // (plus the folded v sweep's k_vfix tasks, one per kBlock v lines)
     return (size_t)std::max(std::max(pb.r_tiles, pb.exp_tiles), pb.exr_tiles) + pb.rs_tiles +
-           std::max(pb.v_tiles, pb.vs_tiles) +
+           std::max(pb.v_tiles, pb.vs_tiles) + ((size_t)a[0].n * a[2].n + kBlock - 1) / kBlock +
            std::max(pb.y_tiles, pb.yc_tiles) + (size_t)pb.exp_tiles;
 }
 
@@ -1619,13 +1669,13 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step, hipS
     const int2* t = b->d_tasks + g.off;
     switch (g.kind) {
     case G_XR: return launch_xr(g.rows, b->d_desc, t, nt, step, g.lds, st);
-    case G_EXR: return launch_exr(g.rows, b->d_desc, t, nt, step, g.lds, st, g.seq > 0, g.flag);
+    case G_EXR: return launch_exr(g.rows, b->d_desc, t, nt, step, g.lds, st, g.seq > 0, g.flag, g.fold);
     case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, st, g.seq > 0);
     case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, st);
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, st);
-    case G_VS: return launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
+    case G_VS: return g.fold ? launch_vfix(b->d_desc, t, nt, st) : launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
     case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, st);
-    default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, st, g.mode, g.flag);
+    default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, st, g.mode, g.flag, g.fold);
     }
 }
 
@@ -1808,10 +1858,10 @@ hjm_status hjm_batch_create_scheme(int32_t n, const hjm_axis* ax, const hjm_mode
     // (lane, sequence, kind, variant) -> group, created lane by lane, and in
     // a lane by sweep sequence and pass, the order in which a step launches
     // them on the lane's stream
-    auto group = [&](int lane, int seq, int kind, int rows, bool flag, int segs, int mode) -> LaunchGroup& {
+    auto group = [&](int lane, int seq, int kind, int rows, bool flag, int segs, int mode, bool fold) -> LaunchGroup& {
         for (LaunchGroup& g : b->groups)
             if (g.lane == lane && g.seq == seq && g.kind == kind && g.rows == rows && g.flag == flag &&
-                g.segs == segs && g.mode == mode)
+                g.segs == segs && g.mode == mode && g.fold == fold)
                 return g;
         b->groups.emplace_back();
         LaunchGroup& g = b->groups.back();
@@ -1822,6 +1872,7 @@ hjm_status hjm_batch_create_scheme(int32_t n, const hjm_axis* ax, const hjm_mode
         g.flag = flag;
         g.segs = segs;
         g.mode = mode;
+        g.fold = fold;
         g.cnt.assign(b->max_steps, 0);
         g.pts.assign(b->max_steps, 0);
         return g;
@@ -1877,6 +1928,7 @@ hjm_status hjm_batch_create_scheme(int32_t n, const hjm_axis* ax, const hjm_mode
                     // segments would leave waves idle for the workgroup's whole
                     // life, so each segment count is a group of its own
                     case G_VS:
+                        // (folded: k_vfix, vs_tiles tasks of kBlock v lines)
                         if (pl.vs_rows) { rows = pl.vs_rows; segs = pl.vs_S; tiles = pl.vs_tiles; aux = pl.vs_S; }
                         break;
                     case G_YU: if (!pl.yc_rows) { rows = pl.rows[2]; tiles = pl.y_tiles; lds = pl.y_lds; } break;
@@ -1896,7 +1948,8 @@ hjm_status hjm_batch_create_scheme(int32_t n, const hjm_axis* ax, const hjm_mode
                         break;
                     }
                     if (!tiles) continue;
-                    LaunchGroup& g = group(lane, seq, kind, rows, flag, segs, mode);
+                    LaunchGroup& g = group(lane, seq, kind, rows, flag, segs, mode, pl.v_fold && (kind == G_EXR ||
+                                                                                       kind == G_VS || kind == G_YC));
                     if (kind != G_YC) {
                         for (int t = 0; t < tiles; ++t) g.tasks.push_back(make_int2(di, t));
                     } else if (oi == 0 || b->owner[seq_order[oi - 1]] != b->owner[s]) {

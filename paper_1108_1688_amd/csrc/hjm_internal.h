@@ -132,7 +132,13 @@ enum { RF_P = 0, RF_Q, RF_ALO, RF_ADI, RF_AUP, RF_B, kRF };
 // the backward x_j = d'_j - CP_j x_{j+1}.  Each segment runs both from zero
 // and adds G_j d'_in (G_j: product of AL from the segment start to j) and
 // H_j x_in (H_j: product of -CP from j to the segment end).
-enum { VG_INV = 0, VG_AL, VG_CP, VG_G, VG_H, kVG };
+// K_j, for the v sweep folded into the fused kernel: the backward sweep of G
+// within the segment (K_end = G_end, K_j = G_j - CP_j K_{j+1}), so that the
+// final value is x0_j + K_j d'_in + H_j x_in with x0 the segment's own
+// solution from zero.
+enum { VG_INV = 0, VG_AL, VG_CP, VG_G, VG_H, VG_K, kVG };
+// most v segments (of kExrJ rows) a folded v sweep hands over
+constexpr int kMaxFoldSegs = 16;
 
 // Dirichlet increments of step n: r_min face (ny values, by k), r_max face
 // (ny), y_max face (nr, by i); zero where the face is not Dirichlet.
@@ -186,11 +192,16 @@ void exr_lds(int nr, int rows, size_t* bytes, int* tab);
 // window: the explicit phase reads its neighbours from an LDS window of its
 // tile (else each thread loads its own).  The predictor only: the corrected
 // start keeps the per-lane loads.
+// fold: the v sweep folded in (window form, Douglas only): D1 stays in the
+// tile and the tile's v segment is solved from zero (k_vfix and k_yc finish it)
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
-                      hipStream_t st, bool stage2 = false, bool window = false);
+                      hipStream_t st, bool stage2 = false, bool window = false, bool fold = false);
 // rows per thread available to k_rs
 bool rs_rows_supported(int rows);
 hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);
+// the folded v sweep's segment hand-over and face rows: one thread per v line
+// (i, k), tasks of kBlock lines
+hipError_t launch_vfix(const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st);
 // Dirichlet increments of every step into each solve's gd table; max_entries
 // = the largest (2 ny + nr) n_steps of the solves
 hipError_t launch_gd(const SolveDesc* d_desc, int n_solves, int64_t max_entries, hipStream_t st);
@@ -201,7 +212,7 @@ hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines,
 // reciprocal pivots are formed in the kernel from the minors recurrence, else
 // read from the array k_ypiv wrote
 hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st,
-                     int mode = 0, bool minors = false);
+                     int mode = 0, bool minors = false, bool fold = false);
 // k_yc holds 4 ROWS-long arrays per thread: workgroups of at most 128 / ROWS
 // waves keep them in registers
 constexpr int yc_max_segments(int rows) { return 128 / rows; }

@@ -1842,7 +1842,7 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
 // is its first 8 kBlock doubles, inside its kBlock / S lines; the tile is
 // sized to whole passes).  Every thread calls it, after a barrier that
 // follows the tile's writes.
-template <int ROWS>
+template <int ROWS, bool FOLD = false>
 __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, const ldouble* tab, const ldouble* face,
                                            int P, int k0, int j0, int step)
 {
@@ -1877,7 +1877,17 @@ __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, co
             const double c = phi + gp(s.yt)[YT_Y * ny + k];
             ok = spike_r_lane<ROWS>(s, tab + seg * TP, face, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
         }
-        if (active) {
+        if constexpr (FOLD) {
+            // D1 back into the lane's own rows of the tile (no reduced-system
+            // scratch in LDS for S <= 16, so no other lane reads them), for
+            // the tile's v sweep
+            ldouble* dst = tile + (size_t)min(ln, L - 1) * LP + seg * SP;
+            if (active) {
+#pragma unroll
+                for (int mm = 0; mm < ROWS; ++mm) dst[mm] = d[mm];
+            }
+            if (active && !ok) raise_flag(s);
+        } else if (active) {
             gdouble* line = gp(s.D) + ((size_t)k * nv + j) * nr + (size_t)seg * ROWS;
 #pragma unroll
             for (int mm = 0; mm < ROWS; ++mm) line[mm] = d[mm];
@@ -1886,6 +1896,70 @@ __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, co
         // the next pass reads only its own lines' rows, which this pass's
         // scratch does not reach: no barrier needed here
     }
+}
+
+// The v sweep folded into the fused kernel (Douglas, the v lines cut into
+// segments of kExrJ = 16 rows, one per tile): the segmented solve of k_vs
+// (hjm_internal.h, VG_*) run on the tile's segment from zero in both
+// directions, by thread (i, plane), on D1 read back from the tile.  It
+// stores the segment's local solution x0 (the face rows' own D1 at j = 0
+// and nv - 1, which k_vfix recovers), the forward end value d'_end and the
+// backward first value x0_first; k_vfix composes the segments of each
+// (i, k) line and k_yc adds K_j d'_in + H_j x_in as it loads D2, K = the
+// backward sweep of G.  Lines on Dirichlet faces keep D1 (end values 0).
+template <int ROWS>
+__device__ __forceinline__ void fold_v_tile(const SolveDesc& s, const ldouble* tile, int P, int k0, int j0)
+{
+    constexpr int J = kExrJ;
+    constexpr int SP = ROWS + 1;
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int LP = s.rs_S * SP;  // the tile's line pitch
+    const int t = (int)threadIdx.x;
+    const int kk = t / nr;
+    const int i = t - kk * nr;
+    const int k = k0 + kk;
+    if (kk >= P || k >= ny) return;
+    const int g = i / ROWS;
+    const ldouble* col = tile + (size_t)kk * J * LP + g * SP + (i - g * ROWS);
+    const int Sv = s.vs_S;
+    const int sv = j0 / J;
+    const bool first = sv == 0, last = sv == Sv - 1;
+    const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir) || (k == ny - 1 && s.y_hi_dir);
+    kcdouble* vg = kp(s.vg) + j0;
+    kcdouble* fs = kp(s.vf) + kVF * nv;
+    double d[J];
+#pragma unroll
+    for (int m = 0; m < J; ++m) d[m] = col[(size_t)m * LP];
+    double lend = 0.0, x0f = 0.0;
+    if (!line_dir) {
+        const double d0 = d[0], dl = d[J - 1];
+        if (first) d[1] = d[1] - fs[VS_F1] * d0;
+        if (last) d[J - 2] = d[J - 2] - fs[VS_F2] * dl;
+        double l = 0.0;
+#pragma unroll
+        for (int m = 0; m < J; ++m) {
+            l = vg[VG_INV * nv + m] * d[m] + vg[VG_AL * nv + m] * l;
+            d[m] = l;
+        }
+        lend = d[J - 1];
+        double x = 0.0;
+#pragma unroll
+        for (int m = J - 1; m >= 0; --m) {
+            x = d[m] - vg[VG_CP * nv + m] * x;
+            d[m] = x;
+        }
+        x0f = d[0];
+        if (first) d[0] = d0;
+        if (last) d[J - 1] = dl;
+    }
+    gdouble* line = gp(s.D) + ((size_t)k * nv + j0) * nr + i;
+#pragma unroll
+    for (int m = 0; m < J; ++m) line[(size_t)m * nr] = d[m];
+    const size_t A = (size_t)nr * ny * Sv;
+    const size_t e = ((size_t)k * Sv + sv) * nr + i;
+    gdouble* ends = gp(s.yinv);
+    ends[e] = lend;
+    ends[A + e] = x0f;
 }
 
 // Explicit predictor (or, STAGE2, the corrected start of the Craig-Sneyd
@@ -1906,7 +1980,7 @@ __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, co
 template <bool STAGE2>
 constexpr int kExrChunk = STAGE2 ? 4 : 8;
 
-template <int ROWS, bool STAGE2, bool WIN = false>
+template <int ROWS, bool STAGE2, bool WIN = false, bool FOLD = false>
 __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks,
                                                 int step)
 {
@@ -1973,7 +2047,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
         }
     }
     __syncthreads();
-    if constexpr (WIN && !STAGE2) {
+    if constexpr (WIN && !STAGE2 && FOLD) {
+        // D1 stays in the tile; after every line is solved, the tile's v sweep
+        solve_tile<ROWS, true>(s, tile, tab, face, P, k0, j0, step);
+        __syncthreads();
+        fold_v_tile<ROWS>(s, tile, P, k0, j0);
+    } else if constexpr (WIN && !STAGE2) {
         solve_tile<ROWS>(s, tile, tab, face, P, k0, j0, step);
     } else {
         // the same passes as solve_tile, written out here: inlined as one
@@ -2087,6 +2166,74 @@ __global__ __launch_bounds__(kBlock) void k_vs(const SolveDesc* __restrict__ des
     }
 }
 
+// D2 of a folded v sweep: the segment's local solution plus the hand-over
+// terms (one expression, so that k_vfix and k_yc form the same value).
+__device__ __forceinline__ double fold_v_value(double x0, double K, double din, double H, double xin)
+{
+    return fma(H, xin, fma(K, din, x0));
+}
+
+// The segment hand-over of the folded v sweep (fold_v_tile), one thread per
+// v line (i, k): the recurrences of k_vs across segments, d'_in(s) =
+// d'_end(s - 1) + G_last(s - 1) d'_in(s - 1) from d'_in(0) = 0, and x_in(s) =
+// x_first(s + 1) + H_first(s + 1) x_in(s + 1) from x_in(Sv - 1) = 0, where
+// the first value of segment s + 1's backward sweep is x0_first + K_first
+// d'_in; then rows 0 and nv - 1 (outflow faces) from their own rows and the
+// final values of rows 1, 2 and nv - 3, nv - 2, as k_vs forms them.  The
+// hand-over values go to the solve's y-pivot array, which the folded solve
+// does not otherwise use: [d'_end | x0_first | d'_in | x_in], each
+// [k][segment][i].  Lines on Dirichlet faces keep D1 (zero hand-over).
+__global__ __launch_bounds__(kBlock) void k_vfix(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
+{
+    const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+    const SolveDesc& s = descs[tk.x];
+    const int nr = s.nr, nv = s.nv, ny = s.ny;
+    const int q = tk.y * kBlock + (int)threadIdx.x;
+    if (q >= nr * ny) return;
+    const int k = q / nr;
+    const int i = q - k * nr;
+    constexpr int J = kExrJ;
+    const int Sv = s.vs_S;  // 2 .. kMaxFoldSegs, checked on the host
+    const size_t A = (size_t)nr * ny * Sv;
+    const size_t e0 = (size_t)k * Sv * nr + i;
+    gdouble* ends = gp(s.yinv);
+    const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir) || (k == ny - 1 && s.y_hi_dir);
+    gcdouble* vg = gp(s.vg);
+    double din[kMaxFoldSegs], xin[kMaxFoldSegs];
+    din[0] = 0.0;
+#pragma unroll
+    for (int sv = 1; sv < kMaxFoldSegs; ++sv) {
+        if (sv >= Sv) break;  // uniform: one solve per workgroup
+        din[sv] = ends[e0 + (size_t)(sv - 1) * nr] + vg[VG_G * nv + sv * J - 1] * din[sv - 1];
+    }
+    double x = 0.0;
+#pragma unroll
+    for (int sv = kMaxFoldSegs - 1; sv >= 0; --sv) {
+        if (sv >= Sv) continue;
+        xin[sv] = x;
+        if (sv > 0) {
+            const double bf = fma(vg[VG_K * nv + sv * J], din[sv], ends[A + e0 + (size_t)sv * nr]);
+            x = bf + vg[VG_H * nv + sv * J] * x;
+        }
+    }
+#pragma unroll
+    for (int sv = 0; sv < kMaxFoldSegs; ++sv) {
+        if (sv >= Sv) break;
+        ends[2 * A + e0 + (size_t)sv * nr] = line_dir ? 0.0 : din[sv];
+        ends[3 * A + e0 + (size_t)sv * nr] = line_dir ? 0.0 : xin[sv];
+    }
+    if (line_dir) return;
+    gdouble* D = gp(s.D) + (size_t)k * nv * nr + i;
+    gcdouble* fs = gp(s.vf) + kVF * nv;
+    auto fin = [&](int j, int sv) {
+        return fold_v_value(D[(size_t)j * nr], vg[VG_K * nv + j], din[sv], vg[VG_H * nv + j], xin[sv]);
+    };
+    const double x1 = fin(1, 0), x2 = fin(2, 0);
+    const double xa = fin(nv - 3, Sv - 1), xb = fin(nv - 2, Sv - 1);
+    D[0] = (D[0] - fs[VS_C0] * x1 - fs[VS_E0] * x2) / fs[VS_B0];
+    D[(size_t)(nv - 1) * nr] = (D[(size_t)(nv - 1) * nr] - fs[VS_EL] * xa - fs[VS_AL] * xb) / fs[VS_BL];
+}
+
 // Reciprocal pivots 1 / den_k of every y line (i, j) of (I - theta dt A3),
 // which do not change from step to step: the Thomas forward recurrence
 // den_k = B_k - A_k c'_{k-1}, c'_k = C_k / den_k in row order (the quotient
@@ -2163,7 +2310,7 @@ __device__ __forceinline__ int pow2_exponent(double x)
 // terms: as accurate as the pivots of the division recurrence.  Both carried
 // values are rescaled by a power of two every 8 rows (exact), so the minors
 // never overflow.
-template <int ROWS, int MODE, bool MINORS>
+template <int ROWS, int MODE, bool MINORS, bool FOLD = false>
 __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
     extern __shared__ double lds_raw[];
@@ -2199,6 +2346,19 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
     for (int mm = 0; mm < ROWS; ++mm) {
         d[mm] = D[off + (size_t)mm * sy];
         if constexpr (!MINORS) iv[mm] = gp(s.yinv)[off + (size_t)mm * sy];
+    }
+    if constexpr (FOLD) {
+        // the folded v sweep's hand-over terms (k_vfix), as D2 is loaded
+        const int Sv = s.vs_S;
+        const int sv = j / kExrJ;
+        const size_t A = (size_t)nr * ny * Sv;
+        gcdouble* ho = gp(s.yinv) + 2 * A + (size_t)sv * nr + i;
+        const double Kj = gp(s.vg)[VG_K * nv + j], Hj = gp(s.vg)[VG_H * nv + j];
+#pragma unroll
+        for (int mm = 0; mm < ROWS; ++mm) {
+            const size_t e = (size_t)(sg * ROWS + mm) * Sv * nr;
+            d[mm] = fold_v_value(d[mm], Kj, ho[e], Hj, ho[A + e]);
+        }
     }
     // C inv goes to LDS (it is needed only by the backward chain), [row][lane]
     ldouble* cpl = lds + 128 + (size_t)sg * ROWS * 64 + l;
@@ -2481,7 +2641,8 @@ hipError_t allow_yc()
         (e = allow_lds(k_yc<ROWS, 2, false>)) || (e = allow_lds(k_yc<ROWS, 3, false>)))
         return e;
     if ((e = allow_lds(k_yc<ROWS, 0, true>)) || (e = allow_lds(k_yc<ROWS, 1, true>)) ||
-        (e = allow_lds(k_yc<ROWS, 2, true>)) || (e = allow_lds(k_yc<ROWS, 3, true>)))
+        (e = allow_lds(k_yc<ROWS, 2, true>)) || (e = allow_lds(k_yc<ROWS, 3, true>)) ||
+        (e = allow_lds(k_yc<ROWS, 0, true, true>)))
         return e;
     return hipSuccess;
 }
@@ -2519,6 +2680,8 @@ hipError_t init_kernel_attributes()
             (e = allow_lds(k_rs<16>)) || (e = allow_lds(k_exr<8, false>)) || (e = allow_lds(k_exr<12, false>)) ||
             (e = allow_lds(k_exr<16, false>)) || (e = allow_lds(k_exr<8, false, true>)) ||
             (e = allow_lds(k_exr<12, false, true>)) || (e = allow_lds(k_exr<16, false, true>)) ||
+            (e = allow_lds(k_exr<8, false, true, true>)) || (e = allow_lds(k_exr<12, false, true, true>)) ||
+            (e = allow_lds(k_exr<16, false, true, true>)) ||
             (e = allow_lds(k_exr<8, true>)) ||
             (e = allow_lds(k_exr<12, true>)) || (e = allow_lds(k_exr<16, true>)) || (e = allow_lds(k_vs<8>)) || (e = allow_lds(k_vs<16>)) ||
             (e = allow_lds(k_vs<32>)) || (e = allow_yc<8>()) || (e = allow_yc<16>()) || (e = allow_yc<32>()))
@@ -2635,9 +2798,19 @@ void exr_lds(int nr, int rows, size_t* bytes, int* tab)
 }
 
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
-                      hipStream_t st, bool stage2, bool window)
+                      hipStream_t st, bool stage2, bool window, bool fold)
 {
     if (n_tasks <= 0) return hipSuccess;
+    if (fold && (!window || stage2)) return hipErrorInvalidValue;
+    if (fold) {
+        switch (rows) {
+        case 8: HJM_LAUNCH((k_exr<8, false, true, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        case 12: HJM_LAUNCH((k_exr<12, false, true, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        case 16: HJM_LAUNCH((k_exr<16, false, true, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (window && !stage2) {
         switch (rows) {
         case 8: HJM_LAUNCH((k_exr<8, false, true>), dim3(n_tasks), dim3(kBlock), lds, st, d_desc, tasks, step); break;
@@ -2677,6 +2850,13 @@ hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     return hipGetLastError();
 }
 
+hipError_t launch_vfix(const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    HJM_LAUNCH(k_vfix, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks);
+    return hipGetLastError();
+}
+
 hipError_t launch_gd(const SolveDesc* d_desc, int n_solves, int64_t max_entries, hipStream_t st)
 {
     const int64_t blocks = (max_entries + kBlock - 1) / kBlock;
@@ -2694,12 +2874,18 @@ hipError_t launch_ypiv(const SolveDesc* d_desc, int n_solves, int64_t max_lines,
 }
 
 hipError_t launch_yc(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st,
-                     int mode, bool minors)
+                     int mode, bool minors, bool fold)
 {
     if (n_tasks <= 0) return hipSuccess;
     if (S_max < 1 || S_max > yc_max_segments(rows)) return hipErrorInvalidValue;
     // the exchange slots (2 per lane) and C inv of every row of the lines
     const size_t lds = (size_t)(2 + (size_t)S_max * rows) * 64 * 8;
+    if (fold) {
+        // the folded v sweep: Douglas (mode 0) on pivots formed in the kernel
+        if (mode != 0 || !minors) return hipErrorInvalidValue;
+        HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, 0, true, true>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks))
+        return hipGetLastError();
+    }
     switch (mode) {
 #define HJM_YC(M)                                                                                                       \
     if (minors) HJM_DISPATCH_ROWS(rows, HJM_LAUNCH((k_yc<R, M, true>), dim3(n_tasks), dim3(64 * S_max), lds, st, d_desc, tasks)) \

@@ -112,6 +112,8 @@ def lib():
         "hjm_get_exr_window": (st, [P(i32)]),
         "hjm_set_y_minors": (st, [i32]),
         "hjm_get_y_minors": (st, [P(i32)]),
+        "hjm_set_v_fold": (st, [i32]),
+        "hjm_get_v_fold": (st, [P(i32)]),
         "hjm_set_batch_streams": (st, [i32]),
         "hjm_get_batch_streams": (st, [P(i32)]),
         "hjm_set_batch_share": (st, [i32]),
@@ -249,6 +251,18 @@ def set_y_minors(on: bool) -> None:
 def get_y_minors() -> bool:
     on = C.c_int32()
     check(lib().hjm_get_y_minors(C.byref(on)))
+    return bool(on.value)
+
+
+def set_v_fold(on: bool) -> None:
+    """Douglas solves created afterwards fold the v sweep into the other
+    kernels where they can (default), or run it on its own."""
+    check(lib().hjm_set_v_fold(1 if on else 0))
+
+
+def get_v_fold() -> bool:
+    on = C.c_int32()
+    check(lib().hjm_get_v_fold(C.byref(on)))
     return bool(on.value)
 
 

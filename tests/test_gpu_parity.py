@@ -37,10 +37,12 @@ def _need_gpu():
     old = hjm.get_line_tile()
     fused = hjm.get_r_fusion()
     minors = hjm.get_y_minors()
+    fold = hjm.get_v_fold()
     yield
     hjm.set_line_tile(*old)
     hjm.set_r_fusion(fused)
     hjm.set_y_minors(minors)
+    hjm.set_v_fold(fold)
 
 
 PLANS = []  # r method of every grid of the last gpu_grid call
@@ -293,6 +295,37 @@ def test_y_pivots_from_minors_against_stored(shape, tile):
     scale = np.abs(Uo).max()
     diff = float(np.abs(out[True][0] - out[False][0]).max()) / scale
     print(f"minors vs stored pivots: grid rel diff {diff:.2e}", flush=True)
+    assert diff <= 1e-13
+
+
+@pytest.mark.parametrize("shape,gaussian", [((64, 32, 32), False), ((128, 48, 64), False), ((256, 64, 48), False),
+                                            ((96, 128, 32), False), ((64, 48, 32), True)],
+                         ids=["r4lanes-v2seg", "r8lanes-v3seg", "r16lanes-v4seg", "rows12-v8seg", "dirichlet-r"])
+def test_v_sweep_folded_against_unfolded(shape, gaussian):
+    """The v sweep folded into the fused kernel (each tile's 16 v rows one
+    segment, solved from zero there), the segment hand-over kernel and the
+    y sweep's loads, against the v sweep on its own: each solve against the
+    oracle, and the two grids within a few ulps of each other; 2 to 8 v
+    segments, 4 to 16 lanes per r line, Dirichlet r faces (lines that keep
+    D1)."""
+    s = _sloped(shape, 9 if shape[0] <= 64 else 80, gaussian=gaussian)
+    out = {}
+    for fold in (True, False):
+        hjm.set_v_fold(fold)
+        g = hjm.Grid(s)
+        plan = g.plan()
+        g.close()
+        assert plan["r_method"] == "fused" and plan["yc_rows"] > 0
+        if fold:
+            assert plan["vs_rows"] == 16, plan
+        Ug, pg = gpu_grid(s)
+        out[fold] = (Ug, pg)
+    Uo, po = oracle_grid(s)
+    for fold, (Ug, pg) in out.items():
+        assert_grid(Ug, Uo)
+        assert_price(pg, po)
+    diff = float(np.abs(out[True][0] - out[False][0]).max()) / np.abs(Uo).max()
+    print(f"folded vs unfolded v sweep: grid rel diff {diff:.2e}", flush=True)
     assert diff <= 1e-13
 
 
