@@ -35,6 +35,21 @@ PASS_NAMES = ["explicit", "r", "v", "y+update"]
 # algorithmic minimum of a whole Douglas step: read U twice (explicit, update)
 # plus D through the v and y sweeps, D0 never leaving the chip: 56 B per point
 STEP_BYTES = 56.0
+
+
+def folded_pass_bytes(nv: int):
+    """Algorithmic bytes per point of each pass when the v sweep is folded
+    into the other kernels (nv / 16 segments of 16 v rows): explicit+r reads U
+    and writes the local v solution D plus two end values per v line and
+    segment; the v pass (k_vfix) reads those end values and writes two
+    hand-over values per line and segment, and reads rows 0, 1, 2, nv-3,
+    nv-2, nv-1 of each v line to write rows 0 and nv-1; y+update reads D, U
+    and the hand-over values, writes U.  Returns (per pass, per step)."""
+    sv = nv // 16
+    ends = 2 * 8 * sv / nv
+    vfix = (4 * sv + 6 + 2) * 8 / nv
+    per = {"explicit+r": 16.0 + ends, "v": vfix, "y+update": 24.0 + ends}
+    return per, sum(per.values())
 # Douglas steps whose kernel launches are timed: the first 10 of the batch (or of
 # each grid in --mode grids).  Every step of a solve does the same work.  The
 # timed steps run one launch at a time (no stream-lane overlap) and their
@@ -48,14 +63,15 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "a62003fc19f5d31aa1660d21e8d582aef63be9852c33820294746c4ec3cbfc5b"
-                      ":161829d532aefc8a2b772d8867dda011d3a4a38de9c838c263ec446dcc49c327",
+    "sources_sha256": "e53a6ae4deffaaea2a8db83b07f5742b175f8c9a564a8178ded4a5eeb64b47cf"
+                      ":e3a5d1e644fd88343949c5e030d4f1dd2337042b1536dd464052f97866538d19",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
     "exr_window": True,
     "y_minors": True,
-    "bytes_per_point": {"explicit+r": 18.373, "v": 15.978, "y+update": 24.071},
+    "v_fold": True,
+    "bytes_per_point": {"explicit+r": 18.861, "v": 2.403, "y+update": 26.079},
 }
 
 def log(*a):
@@ -560,6 +576,8 @@ def main():
                     help="batch mode: time the launches of the first N Douglas steps (0: all)")
     ap.add_argument("--streams", type=int, default=None,
                     help="stream lanes the batch spreads its solves over (library default 3)")
+    ap.add_argument("--no-fold", action="store_true",
+                    help="run the v sweep on its own instead of folding it into the other kernels")
     ap.add_argument("--no-fusion", action="store_true",
                     help="keep the explicit predictor and the r sweep as two kernels")
     ap.add_argument("--mode", choices=("batch", "grids"), default="batch",
@@ -579,6 +597,8 @@ def main():
         hjm.set_line_tile(*[int(x) for x in args.tile.split(",")])
     if args.exp_chunk:
         hjm.set_explicit_chunk(args.exp_chunk)
+    if args.no_fold:
+        hjm.set_v_fold(False)
     if args.no_fusion:
         hjm.set_r_fusion(False)
     if args.streams:
@@ -655,12 +675,21 @@ def main():
     names = list(PASS_NAMES)
     if pass_n[1] == 0:
         names[0] = "explicit+r"
+    # the v sweep folded into the other kernels (the workload's grids all
+    # take the same plan): its pass is the segment hand-over kernel
+    probe = hjm.Grid(specs[0], stream=stream)
+    folded = probe.plan()["vs_rows"] == 16 and hjm.get_v_fold()
+    probe.close()
+    pass_bytes, step_bytes = dict(PASS_BYTES), STEP_BYTES
+    if folded:
+        per, step_bytes = folded_pass_bytes(specs[0].axes[1].n)
+        pass_bytes.update(per)
     passes = {}
     for q, name in enumerate(names):
         if pass_n[q] == 0:
             continue
         avg_ms = pass_ms[q] / max(pass_n[q], 1)
-        gbs = PASS_BYTES[name] * pass_pts[q] / (pass_ms[q] * 1e-3) / 1e9 if pass_n[q] else 0.0
+        gbs = pass_bytes[name] * pass_pts[q] / (pass_ms[q] * 1e-3) / 1e9 if pass_n[q] else 0.0
         passes[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": pass_n[q],
                         "points_per_launch": pass_pts[q] // max(pass_n[q], 1), "GB/s": round(gbs, 1),
                         "share": round(pass_ms[q] / max(sum(pass_ms), 1e-12), 3)}
@@ -669,7 +698,8 @@ def main():
                   and hjm.get_explicit_chunk() == MEASURED_TRAFFIC["explicit_chunk"]
                   and hjm.get_r_fusion() == MEASURED_TRAFFIC["r_fusion"]
                   and hjm.get_exr_window() == MEASURED_TRAFFIC["exr_window"]
-                  and hjm.get_y_minors() == MEASURED_TRAFFIC["y_minors"])
+                  and hjm.get_y_minors() == MEASURED_TRAFFIC["y_minors"]
+                  and hjm.get_v_fold() == MEASURED_TRAFFIC["v_fold"])
     for name in passes:
         b = MEASURED_TRAFFIC["bytes_per_point"].get(name)
         ok = traffic_ok and b is not None
@@ -681,12 +711,14 @@ def main():
     dom = max(range(npass), key=lambda q: pass_ms[q])
     dname = names[dom]
     achieved = passes[dname]["GB/s"]
-    step_gbs = STEP_BYTES * pass_pts[0] / (sum(pass_ms) * 1e-3) / 1e9
+    step_gbs = step_bytes * pass_pts[0] / (sum(pass_ms) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": passes[dname]["traffic_bytes"],
                 "traffic_unit": "HBM bytes per launch (measured bytes per point x points per launch)",
-                "bytes_per_point": PASS_BYTES[dname], "points_per_launch": passes[dname]["points_per_launch"],
-                "douglas_step_GBs": round(step_gbs, 1),
+                "bytes_per_point": round(pass_bytes[dname], 4), "points_per_launch": passes[dname]["points_per_launch"],
+                "douglas_step_GBs": round(step_gbs, 1), "douglas_step_bytes_per_point": round(step_bytes, 4),
+                "v_sweep": ("folded: solved per 16-row segment inside the explicit + r kernel, the segments composed "
+                            "by k_vfix (the 'v' pass) and finished as k_yc loads D2") if folded else "k_vs",
                 "stream_copy_GBs": round(copy_gbs, 1),
                 "stream_copy_note": "torch device-to-device copy of 1 GiB, read + write bytes, HIP events",
                 "passes": passes}
@@ -704,6 +736,8 @@ def main():
                       "mode": args.mode,
                       "grid": [256, 128, 128], "douglas_steps": total_steps, "line_tile": list(hjm.get_line_tile()),
                       "explicit_chunk": hjm.get_explicit_chunk(), "r_fusion": hjm.get_r_fusion(),
+                      "exr_window": hjm.get_exr_window(), "y_minors": hjm.get_y_minors(),
+                      "v_fold": hjm.get_v_fold(),
                       "stream_lanes": hjm.get_batch_streams() if args.mode == "batch" else 1,
                       "parallelism": "single GPU"},
            "roofline": roofline}
