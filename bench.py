@@ -678,7 +678,7 @@ def main():
     # the v sweep folded into the other kernels (the workload's grids all
     # take the same plan): its pass is the segment hand-over kernel
     probe = hjm.Grid(specs[0], stream=stream)
-    folded = probe.plan()["vs_rows"] == 16 and hjm.get_v_fold()
+    folded = probe.plan()["v_fold"]
     probe.close()
     pass_bytes, step_bytes = dict(PASS_BYTES), STEP_BYTES
     if folded:

@@ -217,11 +217,14 @@ hjm_status hjm_grid_destroy(hjm_grid* g);
    rows per thread of the r, v and y solves, plan[5] = rows per segment of the
    segmented v solve (0: the chained v solve), plan[6] = rows per segment of
    the y solve on stored pivots (0: the per-step elimination), plan[7] = the
-   ADI scheme (HJM_SCHEME_*).  The
+   ADI scheme (HJM_SCHEME_*), plan[8] = 1 where the y sweep forms its pivots
+   from the minors recurrence (0: stored by the pivot kernel), plan[9] = 1
+   where the v sweep is folded into the explicit + r and y kernels (16-row
+   segments joined by the hand-over kernel; 0: a v kernel of its own).  The
    spike variants are chosen only where the r rows keep (|A| + |C|) / B
    bounded (section 5, tridiagonal systems), so every variant matches the
    sequential elimination to rounding. */
-hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[8]);
+hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[10]);
 
 /* Per-pass timing.  While enabled, each kernel launch of hjm_adi_step is
    bracketed by HIP events recorded on the grid's stream.  Passes, in order:
@@ -499,12 +502,16 @@ hjm_status hjm_get_batch_streams(int32_t* n);
    the same axes, model (discrete curve included), expiry, payment date and
    steps discretise one operator: several right-hand sides of one system
    (the strikes of one caplet, a caplet and its floorlet).  With sharing on
-   they use the first such solve's coefficient tables and y-line pivots: the
-   host builds and uploads the tables once per operator, the pivot kernel
-   runs once per operator, and the y sweeps of the right-hand sides read one
-   pivot array, their line tiles interleaved so that the reads meet in cache.
-   Each solve keeps its own grid, terminal and Dirichlet data; every result
-   is bit-identical to the unshared batch.  Process-wide. */
+   they use the first such solve's coefficient tables: the host builds and
+   uploads the tables once per operator, and the y sweeps of the right-hand
+   sides are interleaved by line tile so that their table reads meet in
+   cache.  Where the y pivots are stored (hjm_set_y_minors(0), and the
+   correction schemes) the right-hand sides also share one pivot array,
+   which the pivot kernel writes once per operator; where they are formed in
+   the sweep each solve keeps its pivot array, which then holds the folded v
+   sweep's hand-over values of its own right-hand side.  Each solve keeps its
+   own grid, terminal and Dirichlet data; every result is bit-identical to
+   the unshared batch.  Process-wide. */
 hjm_status hjm_set_batch_share(int32_t on);
 hjm_status hjm_get_batch_share(int32_t* on);
 

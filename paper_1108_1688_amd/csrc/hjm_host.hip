@@ -1434,10 +1434,10 @@ hjm_status hjm_grid_destroy(hjm_grid* g)
     return HJM_OK;
 }
 
-hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[8])
+hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[10])
 {
     if (!g || !plan) return fail(HJM_EINVAL, "null argument");
-    for (int q = 0; q < 8; ++q) plan[q] = 0;
+    for (int q = 0; q < 10; ++q) plan[q] = 0;
     plan[0] = g->plan.r_mode;
     plan[1] = g->plan.rs_rows;
     plan[2] = g->rows[0];
@@ -1446,6 +1446,8 @@ hjm_status hjm_grid_plan(const hjm_grid* g, int32_t plan[8])
     plan[5] = g->plan.vs_rows;
     plan[6] = g->plan.yc_rows;
     plan[7] = g->scheme.kind;
+    plan[8] = g->plan.y_minors ? 1 : 0;
+    plan[9] = g->plan.v_fold ? 1 : 0;
     return HJM_OK;
 }
 
@@ -1625,14 +1627,19 @@ bool same_operator(const hjm_axis* a, const hjm_model& m, const hjm_payoff& p, i
     return p.expiry == r.expiry && pm == rm;
 }
 
-// A solve that shares another's operator reads that solve's tables and y
-// pivots; its own grid, Dirichlet increments and flag stay its own.
-void share_operator(SolveDesc& d, const SolveDesc& o)
+// A solve that shares another's operator reads that solve's tables and, if
+// the pivots are stored (stored_pivots), its y pivots; its own grid,
+// Dirichlet increments and flag stay its own.  With the pivots formed in the
+// sweep the pivot array stays the solve's own: the folded v sweep keeps its
+// per-solve hand-over values there.
+void share_operator(SolveDesc& d, const SolveDesc& o, bool stored_pivots)
 {
     d.rt = o.rt; d.vt = o.vt; d.yt = o.yt; d.vf = o.vf;
     d.st = o.st; d.rf = o.rf; d.vg = o.vg;
-    d.yinv = o.yinv;
-    d.ypiv_skip = 1;
+    if (stored_pivots) {
+        d.yinv = o.yinv;
+        d.ypiv_skip = 1;
+    }
 }
 
 // Sweep sequences per Douglas step: 1 (Douglas), 2 (the Craig-Sneyd family),
@@ -1827,7 +1834,7 @@ hjm_status hjm_batch_create_scheme(int32_t n, const hjm_axis* ax, const hjm_mode
         }
         fill_desc(b->descs[s], a, model[s], payoff[s], n_steps[s], plans[s], b->base, bl.s[s], b->d_flags + s,
                   sc.theta);
-        if (own != s) share_operator(b->descs[s], b->descs[own]);
+        if (own != s) share_operator(b->descs[s], b->descs[own], !plans[s].y_minors);
         if (corr) {
             b->descs[s].stage = 1;
             scheme_stage2(b->descs[n + s], b->descs[s], sc, reinterpret_cast<double*>(b->base + bl.s[s].E));

@@ -391,11 +391,14 @@ class Grid:
         """How this grid is solved: r method ('spike', 'chain', 'split' or
         'fused'), rows per lane of the split or fused r solve, line-tile rows, rows per segment
         of the segmented v solve and of the stored-pivot y solve (0 where the
-        chained per-line solves are used instead)."""
-        out = (C.c_int32 * 8)()
+        chained per-line solves are used instead), whether the y sweep forms
+        its pivots from the minors recurrence and whether the v sweep is
+        folded into the other kernels."""
+        out = (C.c_int32 * 10)()
         check(lib().hjm_grid_plan(self._h, out))
         return {"r_method": R_METHODS[out[0]], "rs_rows": out[1], "line_tile": (out[2], out[3], out[4]),
-                "vs_rows": out[5], "yc_rows": out[6], "scheme": SCHEMES[out[7]]}
+                "vs_rows": out[5], "yc_rows": out[6], "scheme": SCHEMES[out[7]],
+                "y_minors": bool(out[8]), "v_fold": bool(out[9])}
 
     def profile(self, enable: bool = True) -> None:
         """Bracket every pass launch with HIP events on the grid's stream."""

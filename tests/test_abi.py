@@ -114,7 +114,7 @@ def test_null_handles(L):
     assert L.hjm_adi_step(None, 1) == hjm.EINVAL
     assert L.hjm_price(None, 0.03, 1.0, C.byref(C.c_double())) == hjm.EINVAL
     assert L.hjm_batch_run(None, 0) == hjm.EINVAL
-    assert L.hjm_grid_plan(None, (C.c_int32 * 8)()) == hjm.EINVAL
+    assert L.hjm_grid_plan(None, (C.c_int32 * 10)()) == hjm.EINVAL
     assert L.hjm_grid_profile_read(None, (C.c_double * hjm.N_PASSES)(), (C.c_int64 * hjm.N_PASSES)()) == hjm.EINVAL
     assert L.hjm_grid_destroy(None) == hjm.OK
     b = hjm.MlpBaseline(0.15, 0.9, 0.25, 0.5, 1.0)

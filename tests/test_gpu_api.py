@@ -178,27 +178,33 @@ def test_batch_stream_lanes_bitwise(lanes):
         assert p == hjm.Grid(sp).step().price()
 
 
-def _rhs_specs():
+def _rhs_specs(nv=24):
     """Right-hand sides of one operator (config 2's three strikes and an ATM
-    floorlet on one 48x24x32 mesh, 30 steps), a solve on another model, and
-    two strikes on the discrete curve: three operators."""
+    floorlet on one 48 x nv x 32 mesh, 30 steps), a solve on another model, and
+    two strikes on the discrete curve: three operators.  nv = 24: the v sweep
+    on its own; nv = 32: folded into the other kernels (two 16-row segments),
+    whose hand-over values each right-hand side keeps for itself."""
     from dataclasses import replace
-    base = W.with_shape(W.config2()[1], 48, 24, 32, 30)
+    base = W.with_shape(W.config2()[1], 48, nv, 32, 30)
     k = base.payoff.strike
     same = [replace(base, payoff=replace(base.payoff, strike=k + dk)) for dk in (-0.01, 0.0, 0.01)]
     same.append(replace(base, payoff=replace(base.payoff, kind=W.FLOORLET)))
     other = replace(base, model=replace(base.model, epsilon=base.model.epsilon * 0.5))
-    disc = W.with_shape(W.config_discrete()[0], 48, 24, 32, 30)
+    disc = W.with_shape(W.config_discrete()[0], 48, nv, 32, 30)
     disc2 = replace(disc, payoff=replace(disc.payoff, strike=disc.payoff.strike + 0.005))
     return [same[0], other, same[1], disc, same[2], disc2, same[3]]
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
-def test_shared_operator_batch_bitwise(lanes):
-    """Solves of one operator share tables and y pivots (one pivot kernel per
-    operator, y tiles interleaved across the right-hand sides): prices equal
-    the single grids' and the unshared batch's bit for bit."""
-    specs = _rhs_specs()
+@pytest.mark.parametrize("lanes,nv", [(1, 24), (2, 24), (1, 32), (3, 32)])
+def test_shared_operator_batch_bitwise(lanes, nv):
+    """Solves of one operator share tables (and stored y pivots; y tiles
+    interleaved across the right-hand sides): prices equal the single grids'
+    and the unshared batch's bit for bit, with the v sweep on its own and
+    folded."""
+    specs = _rhs_specs(nv)
+    g = hjm.Grid(specs[0])
+    assert g.plan()["v_fold"] == (nv == 32)
+    g.close()
     old_l, old_s = hjm.get_batch_streams(), hjm.get_batch_share()
     try:
         hjm.set_batch_streams(lanes)

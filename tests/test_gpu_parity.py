@@ -45,7 +45,7 @@ def _need_gpu():
     hjm.set_v_fold(fold)
 
 
-PLANS = []  # r method of every grid of the last gpu_grid call
+PLANS = []  # r method, v segmented, y on pivots, y pivots from minors: the last gpu_grid call
 
 
 def gpu_grid(spec, steps=None, price=True):
@@ -53,7 +53,7 @@ def gpu_grid(spec, steps=None, price=True):
     g = hjm.Grid(spec)
     plan = g.plan()
     print(f"[gpu] plan {plan}", flush=True)
-    PLANS[:] = [plan["r_method"], plan["vs_rows"] > 0, plan["yc_rows"] > 0]
+    PLANS[:] = [plan["r_method"], plan["vs_rows"] > 0, plan["yc_rows"] > 0, plan["y_minors"]]
     g.step(steps)
     p = g.price() if (price and g.steps_taken == spec.n_steps) else None
     U = g.solution().cpu().numpy().copy()
@@ -177,7 +177,7 @@ def test_config3_full_size_first_steps_elementwise():
     configuration): three Douglas steps compared on every node."""
     s = W.config3()[-1]
     Ug, _ = gpu_grid(s, steps=3, price=False)
-    assert PLANS == ["fused", True, True]
+    assert PLANS == ["fused", True, True, True]
     Uo, _ = oracle_grid(s, steps=3)
     assert_grid(Ug, Uo)
 
@@ -264,7 +264,7 @@ def test_v_and_y_methods(shape, vs, yc):
     the per-step elimination elsewhere."""
     s = _sloped(shape, 15)
     Ug, pg = gpu_grid(s)
-    assert PLANS[1:] == [vs, yc]
+    assert PLANS[1:3] == [vs, yc]
     Uo, po = oracle_grid(s)
     assert_grid(Ug, Uo)
     assert_price(pg, po)
@@ -287,6 +287,7 @@ def test_y_pivots_from_minors_against_stored(shape, tile):
         hjm.set_y_minors(minors)
         Ug, pg = gpu_grid(s)
         assert PLANS[2], "y solve on reciprocal pivots expected"
+        assert PLANS[3] == minors
         out[minors] = (Ug, pg)
     Uo, po = oracle_grid(s)
     for minors, (Ug, pg) in out.items():
@@ -316,6 +317,7 @@ def test_v_sweep_folded_against_unfolded(shape, gaussian):
         plan = g.plan()
         g.close()
         assert plan["r_method"] == "fused" and plan["yc_rows"] > 0
+        assert plan["v_fold"] == fold and plan["y_minors"], plan
         if fold:
             assert plan["vs_rows"] == 16, plan
         Ug, pg = gpu_grid(s)
@@ -350,7 +352,7 @@ def test_config3_long_solves_against_oracle(which):
     s = W.config3()[which]
     assert s.n_steps == 40 * (which + 1) and s.shape == (128, 128, 256)
     Ug, pg = gpu_grid(s)
-    assert PLANS == ["fused", True, True]
+    assert PLANS == ["fused", True, True, True]
     Uo, po = oracle_grid(s)
     err = assert_grid(Ug, Uo)
     perr = assert_price(pg, po)
