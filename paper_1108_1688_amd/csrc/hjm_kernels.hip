@@ -975,19 +975,20 @@ __device__ __forceinline__ double from_lane_above(double x)
 
 // The value of the lane OFF below (row_shr) or above (row_shl) inside the
 // calling lane's row of 16 lanes, one DPP move per 32-bit half; a lane whose
-// source lies outside its row keeps its own value (the callers select).
+// source lies outside its row reads 0 (bound_ctrl; the callers select, so no
+// copy of the lane's own value is needed first).
 template <int OFF>
 __device__ __forceinline__ double row_below(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x110 + OFF, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x110 + OFF, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x110 + OFF, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x110 + OFF, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 template <int OFF>
 __device__ __forceinline__ double row_above(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), 0x100 + OFF, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), 0x100 + OFF, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x100 + OFF, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x100 + OFF, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -1694,9 +1695,10 @@ struct ExpColumn {
 // every lane reads the same address, a broadcast) and the y neighbours ya,
 // yb (planes k + oa, k + ob): the arithmetic of explicit_nodes, so the same
 // values.  Nothing here waits on a scalar load: the v-table values come
-// from LDS, whose reads return in order.  The nodes go in chunks of CH, each
-// reading its window rows (the column itself too) only when it starts, so
-// the registers hold one chunk's neighbours, not the whole window.
+// from LDS, whose reads return in order.  Each window row is read once
+// (its centre and its two neighbours) and kept in registers while the
+// stencils of the next nodes need it; the scheduler is fenced every CH
+// nodes, so that the registers hold a few rows, not the whole window.
 template <int J>
 __device__ __forceinline__ void window_nodes(const SolveDesc& s, const ldouble* wcol, const ldouble* vtc,
                                              const ExpColumn& q, const double (&ya)[J], const double (&yb)[J],
@@ -1704,48 +1706,42 @@ __device__ __forceinline__ void window_nodes(const SolveDesc& s, const ldouble* 
 {
     const int nr = s.nr;
     constexpr int CH = 4;
+    // window row w holds v node j0 - 1 + w (w = 0 .. J + 1), node m's centre
+    // is row m + 1.  Rolled through registers: c0 .. c3 = u(i, j - 2 ..
+    // j + 1), lm, rm and l0, r0 = u(i -+ 1) at j - 1 and j; node m reads row
+    // m + 2's neighbours and row m + 3's centre (past the window: uhi).
+    double c0 = ulo, c1 = wcol[0], c2 = wcol[nr], c3 = wcol[2 * nr];
+    double lm = wcol[-1], rm = wcol[1], l0 = wcol[nr - 1], r0 = wcol[nr + 1];
 #pragma unroll
-    for (int m0 = 0; m0 < J; m0 += CH) {
-        __builtin_amdgcn_sched_barrier(0);
-        // u(i, j0 + m0 - 2 .. j0 + m0 + CH + 1): window rows m0 - 1 .. m0 + CH,
-        // the two beyond the window from registers
-        double col[CH + 4];
-#pragma unroll
-        for (int c = 0; c < CH + 4; ++c) {
-            const int r = m0 - 1 + c;
-            col[c] = r < 0 ? ulo : (r > J + 1 ? uhi : wcol[(size_t)r * nr]);
-        }
-#pragma unroll
-        for (int mm = 0; mm < CH; ++mm) {
-            // every node of the tile, also those past nv (in-bounds reads of
-            // the clamped window rows; their results are never stored): no
-            // exit from the unrolled loop
-            const int m = m0 + mm;
-            // window rows m .. m + 2 hold v nodes j - 1 .. j + 1
-            const ldouble* w0 = wcol + (size_t)(m + 1) * nr;
-            const double lw0 = w0[-1], rw0 = w0[1];
-            const double lwm = w0[-1 - nr], rwm = w0[1 - nr];
-            const double lwp = w0[nr - 1], rwp = w0[nr + 1];
-            const double* cw5 = col + mm;  // u(i, j - 2 .. j + 2)
-            // the outflow extra entry (dx = 0 inside, where it reads the node
-            // itself under a zero weight): one read for every lane
-            const double ux = w0[q.dx];
-            const double v = vtc[VT_V * J + m];
-            const double olo = q.mlo + q.alo * v, odi = q.mdi + q.adi * v, oup = q.mup + q.aup * v;
-            const double a1 = olo * lw0 + odi * cw5[2] + oup * rw0 + q.mex * ux;
-            const double a2 = vtc[VT_O0 * J + m] * cw5[0] + vtc[VT_O1 * J + m] * cw5[1] +
-                              vtc[VT_O2 * J + m] * cw5[2] + vtc[VT_O3 * J + m] * cw5[3] +
-                              vtc[VT_O4 * J + m] * cw5[4];
-            const double by = q.ryk * v - q.kyk;
-            const double a3 = by * (q.wa * ya[m] + q.w2 * cw5[2] + q.wb * yb[m]);
-            const double cross = (rwp - rwm) - (lwp - lwm);
-            const double a0 = q.rx * vtc[VT_X * J + m] * cross;
-            double val = q.dt * (((a1 + a2) + a3) + a0);
-            // formed on every lane and then selected: a branch around it for
-            // the Dirichlet lanes would copy the live arrays at every join
-            asm volatile("" : "+v"(val));
-            out[m] = q.dir ? q.gval : val;
-        }
+    for (int m = 0; m < J; ++m) {
+        if (m % CH == 0) __builtin_amdgcn_sched_barrier(0);
+        // every node of the tile, also those past nv (in-bounds reads of the
+        // clamped window rows; their results are never stored): no exit from
+        // the unrolled loop
+        const ldouble* w0 = wcol + (size_t)(m + 1) * nr;
+        const double lwp = w0[nr - 1], rwp = w0[nr + 1];
+        const double c4 = m + 3 > J + 1 ? uhi : wcol[(size_t)(m + 3) * nr];
+        const double cw5[5] = {c0, c1, c2, c3, c4};  // u(i, j - 2 .. j + 2)
+        // the outflow extra entry (dx = 0 inside, where it reads the node
+        // itself under a zero weight): one read for every lane
+        const double ux = w0[q.dx];
+        const double v = vtc[VT_V * J + m];
+        const double olo = q.mlo + q.alo * v, odi = q.mdi + q.adi * v, oup = q.mup + q.aup * v;
+        const double a1 = olo * l0 + odi * cw5[2] + oup * r0 + q.mex * ux;
+        const double a2 = vtc[VT_O0 * J + m] * cw5[0] + vtc[VT_O1 * J + m] * cw5[1] +
+                          vtc[VT_O2 * J + m] * cw5[2] + vtc[VT_O3 * J + m] * cw5[3] +
+                          vtc[VT_O4 * J + m] * cw5[4];
+        const double by = q.ryk * v - q.kyk;
+        const double a3 = by * (q.wa * ya[m] + q.w2 * cw5[2] + q.wb * yb[m]);
+        const double cross = (rwp - rm) - (lwp - lm);
+        const double a0 = q.rx * vtc[VT_X * J + m] * cross;
+        double val = q.dt * (((a1 + a2) + a3) + a0);
+        // formed on every lane and then selected: a branch around it for
+        // the Dirichlet lanes would copy the live arrays at every join
+        asm volatile("" : "+v"(val));
+        out[m] = q.dir ? q.gval : val;
+        c0 = c1; c1 = c2; c2 = c3; c3 = c4;
+        lm = l0; rm = r0; l0 = lwp; r0 = rwp;
     }
 }
 
