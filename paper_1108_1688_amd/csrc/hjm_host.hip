@@ -1363,7 +1363,7 @@ hjm_status hjm_adi_step(hjm_grid* g, int32_t k)
                 e = launch_exr(p.rs_rows, dd, nullptr, p.exr_tiles, n, p.exr_lds, g->stream, st2, p.exr_win, p.v_fold);
             else if (pass == 0) e = launch_xr(g->rows[0], dd, nullptr, p.r_tiles, n, p.r_lds, g->stream);
             else if (pass == 1) e = launch_rs(p.rs_rows, dd, nullptr, p.rs_tiles, n, g->ax[0].n, g->stream);
-            else if (pass == 2 && p.v_fold) e = launch_vfix(dd, nullptr, p.vs_tiles, g->stream);
+            else if (pass == 2 && p.v_fold) e = launch_vfix(dd, nullptr, p.vs_tiles, p.vs_S, g->stream);
             else if (pass == 2 && p.vs_rows) e = launch_vs(p.vs_rows, dd, nullptr, p.vs_tiles, p.vs_S, g->stream);
             else if (pass == 2) e = launch_v(g->rows[1], dd, nullptr, p.v_tiles, p.v_lds, g->stream);
             else if (p.yc_rows)
@@ -1680,7 +1680,7 @@ hipError_t launch_group(const hjm_batch* b, const LaunchGroup& g, int step, hipS
     case G_EXP: return launch_exp(g.rows, b->d_desc, t, nt, step, st, g.seq > 0);
     case G_RS: return launch_rs(g.rows, b->d_desc, t, nt, step, g.aux, st);
     case G_V: return launch_v(g.rows, b->d_desc, t, nt, g.lds, st);
-    case G_VS: return g.fold ? launch_vfix(b->d_desc, t, nt, st) : launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
+    case G_VS: return g.fold ? launch_vfix(b->d_desc, t, nt, g.segs, st) : launch_vs(g.rows, b->d_desc, t, nt, g.aux, st);
     case G_YU: return launch_yu(g.rows, b->d_desc, t, nt, g.lds, st);
     default: return launch_yc(g.rows, b->d_desc, t, nt, g.aux, st, g.mode, g.flag, g.fold);
     }

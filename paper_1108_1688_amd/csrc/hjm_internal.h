@@ -201,7 +201,8 @@ bool rs_rows_supported(int rows);
 hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int S_max, hipStream_t st);
 // the folded v sweep's segment hand-over and face rows: one thread per v line
 // (i, k), tasks of kBlock lines
-hipError_t launch_vfix(const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st);
+// segs: the v segments of every solve of the launch (2 .. kMaxFoldSegs)
+hipError_t launch_vfix(const SolveDesc* d_desc, const int2* tasks, int n_tasks, int segs, hipStream_t st);
 // Dirichlet increments of every step into each solve's gd table; max_entries
 // = the largest (2 ny + nr) n_steps of the solves
 hipError_t launch_gd(const SolveDesc* d_desc, int n_solves, int64_t max_entries, hipStream_t st);

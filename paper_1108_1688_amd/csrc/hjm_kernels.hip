@@ -2170,15 +2170,18 @@ __device__ __forceinline__ double fold_v_value(double x0, double K, double din, 
 }
 
 // The segment hand-over of the folded v sweep (fold_v_tile), one thread per
-// v line (i, k): the recurrences of k_vs across segments, d'_in(s) =
-// d'_end(s - 1) + G_last(s - 1) d'_in(s - 1) from d'_in(0) = 0, and x_in(s) =
-// x_first(s + 1) + H_first(s + 1) x_in(s + 1) from x_in(Sv - 1) = 0, where
-// the first value of segment s + 1's backward sweep is x0_first + K_first
-// d'_in; then rows 0 and nv - 1 (outflow faces) from their own rows and the
-// final values of rows 1, 2 and nv - 3, nv - 2, as k_vs forms them.  The
-// hand-over values go to the solve's y-pivot array, which the folded solve
-// does not otherwise use: [d'_end | x0_first | d'_in | x_in], each
-// [k][segment][i].  Lines on Dirichlet faces keep D1 (zero hand-over).
+// v line (i, k), SV = vs_S segments (every solve of the launch has SV): the
+// recurrences of k_vs across segments, d'_in(s) = d'_end(s - 1) + G_last(s -
+// 1) d'_in(s - 1) from d'_in(0) = 0, and x_in(s) = x_first(s + 1) +
+// H_first(s + 1) x_in(s + 1) from x_in(SV - 1) = 0, where the first value of
+// segment s + 1's backward sweep is x0_first + K_first d'_in; then rows 0 and
+// nv - 1 (outflow faces) from their own rows and the final values of rows 1,
+// 2 and nv - 3, nv - 2, as k_vs forms them.  The hand-over values go to the
+// solve's y-pivot array, which the folded solve does not otherwise use:
+// [d'_end | x0_first | d'_in | x_in], each [k][segment][i].  Lines on
+// Dirichlet faces keep D1 (zero hand-over).  Every load is issued before the
+// recurrences (one memory round trip, not one per segment).
+template <int SV>
 __global__ __launch_bounds__(kBlock) void k_vfix(const SolveDesc* __restrict__ descs, const int2* __restrict__ tasks)
 {
     const int2 tk = tasks ? tasks[blockIdx.x] : make_int2(0, (int)blockIdx.x);
@@ -2189,45 +2192,48 @@ __global__ __launch_bounds__(kBlock) void k_vfix(const SolveDesc* __restrict__ d
     const int k = q / nr;
     const int i = q - k * nr;
     constexpr int J = kExrJ;
-    const int Sv = s.vs_S;  // 2 .. kMaxFoldSegs, checked on the host
-    const size_t A = (size_t)nr * ny * Sv;
-    const size_t e0 = (size_t)k * Sv * nr + i;
+    const size_t A = (size_t)nr * ny * SV;
+    const size_t e0 = (size_t)k * SV * nr + i;
     gdouble* ends = gp(s.yinv);
+    gdouble* D = gp(s.D) + (size_t)k * nv * nr + i;
     const bool line_dir = (i == 0 && s.r_lo_dir) || (i == nr - 1 && s.r_hi_dir) || (k == ny - 1 && s.y_hi_dir);
     gcdouble* vg = gp(s.vg);
-    double din[kMaxFoldSegs], xin[kMaxFoldSegs];
+    // the end values of segments 0 .. SV - 2 and the first values of
+    // segments 1 .. SV - 1, and the local solutions of the rows the face rows
+    // read
+    double lend[SV], x0f[SV];
+#pragma unroll
+    for (int sv = 0; sv < SV; ++sv) {
+        lend[sv] = sv < SV - 1 ? ends[e0 + (size_t)sv * nr] : 0.0;
+        x0f[sv] = sv > 0 ? ends[A + e0 + (size_t)sv * nr] : 0.0;
+    }
+    const double u0 = D[0], u1 = D[nr], u2 = D[(size_t)2 * nr];
+    const double ua = D[(size_t)(nv - 3) * nr], ub = D[(size_t)(nv - 2) * nr], ul = D[(size_t)(nv - 1) * nr];
+    double din[SV], xin[SV];
     din[0] = 0.0;
 #pragma unroll
-    for (int sv = 1; sv < kMaxFoldSegs; ++sv) {
-        if (sv >= Sv) break;  // uniform: one solve per workgroup
-        din[sv] = ends[e0 + (size_t)(sv - 1) * nr] + vg[VG_G * nv + sv * J - 1] * din[sv - 1];
-    }
+    for (int sv = 1; sv < SV; ++sv) din[sv] = lend[sv - 1] + vg[VG_G * nv + sv * J - 1] * din[sv - 1];
     double x = 0.0;
 #pragma unroll
-    for (int sv = kMaxFoldSegs - 1; sv >= 0; --sv) {
-        if (sv >= Sv) continue;
+    for (int sv = SV - 1; sv >= 0; --sv) {
         xin[sv] = x;
         if (sv > 0) {
-            const double bf = fma(vg[VG_K * nv + sv * J], din[sv], ends[A + e0 + (size_t)sv * nr]);
+            const double bf = fma(vg[VG_K * nv + sv * J], din[sv], x0f[sv]);
             x = bf + vg[VG_H * nv + sv * J] * x;
         }
     }
 #pragma unroll
-    for (int sv = 0; sv < kMaxFoldSegs; ++sv) {
-        if (sv >= Sv) break;
+    for (int sv = 0; sv < SV; ++sv) {
         ends[2 * A + e0 + (size_t)sv * nr] = line_dir ? 0.0 : din[sv];
         ends[3 * A + e0 + (size_t)sv * nr] = line_dir ? 0.0 : xin[sv];
     }
     if (line_dir) return;
-    gdouble* D = gp(s.D) + (size_t)k * nv * nr + i;
     gcdouble* fs = gp(s.vf) + kVF * nv;
-    auto fin = [&](int j, int sv) {
-        return fold_v_value(D[(size_t)j * nr], vg[VG_K * nv + j], din[sv], vg[VG_H * nv + j], xin[sv]);
-    };
-    const double x1 = fin(1, 0), x2 = fin(2, 0);
-    const double xa = fin(nv - 3, Sv - 1), xb = fin(nv - 2, Sv - 1);
-    D[0] = (D[0] - fs[VS_C0] * x1 - fs[VS_E0] * x2) / fs[VS_B0];
-    D[(size_t)(nv - 1) * nr] = (D[(size_t)(nv - 1) * nr] - fs[VS_EL] * xa - fs[VS_AL] * xb) / fs[VS_BL];
+    auto fin = [&](double u, int j, int sv) { return fold_v_value(u, vg[VG_K * nv + j], din[sv], vg[VG_H * nv + j], xin[sv]); };
+    const double x1 = fin(u1, 1, 0), x2 = fin(u2, 2, 0);
+    const double xa = fin(ua, nv - 3, SV - 1), xb = fin(ub, nv - 2, SV - 1);
+    D[0] = (u0 - fs[VS_C0] * x1 - fs[VS_E0] * x2) / fs[VS_B0];
+    D[(size_t)(nv - 1) * nr] = (ul - fs[VS_EL] * xa - fs[VS_AL] * xb) / fs[VS_BL];
 }
 
 // Reciprocal pivots 1 / den_k of every y line (i, j) of (I - theta dt A3),
@@ -2846,10 +2852,16 @@ hipError_t launch_vs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
     return hipGetLastError();
 }
 
-hipError_t launch_vfix(const SolveDesc* d_desc, const int2* tasks, int n_tasks, hipStream_t st)
+hipError_t launch_vfix(const SolveDesc* d_desc, const int2* tasks, int n_tasks, int segs, hipStream_t st)
 {
     if (n_tasks <= 0) return hipSuccess;
-    HJM_LAUNCH(k_vfix, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks);
+    switch (segs) {
+#define HJM_VFIX(SV) case SV: HJM_LAUNCH(k_vfix<SV>, dim3(n_tasks), dim3(kBlock), 0, st, d_desc, tasks); break;
+    HJM_VFIX(2) HJM_VFIX(3) HJM_VFIX(4) HJM_VFIX(5) HJM_VFIX(6) HJM_VFIX(7) HJM_VFIX(8) HJM_VFIX(9)
+    HJM_VFIX(10) HJM_VFIX(11) HJM_VFIX(12) HJM_VFIX(13) HJM_VFIX(14) HJM_VFIX(15) HJM_VFIX(16)
+#undef HJM_VFIX
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
