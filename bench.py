@@ -63,15 +63,15 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "e029dab4a9d8fae3b4ae09e2a368396a10a3e4c8f1276a4ca6b6455a2151b8b5"
-                      ":e3a5d1e644fd88343949c5e030d4f1dd2337042b1536dd464052f97866538d19",
+    "sources_sha256": "018e1d713b93ad7b9c40c1bd7879cf2e17da56d35f996996763a8a8ebb41f541"
+                      ":c4177e9e6f5845c61413ac1afa83bcb6bfbd7a16faea0119cd43db7ee5a319b3",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
     "exr_window": True,
     "y_minors": True,
     "v_fold": True,
-    "bytes_per_point": {"explicit+r": 18.936, "v": 2.403, "y+update": 26.076},
+    "bytes_per_point": {"explicit+r": 18.933, "v": 2.395, "y+update": 26.076},
 }
 
 def log(*a):
