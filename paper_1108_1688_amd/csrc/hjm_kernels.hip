@@ -1358,13 +1358,32 @@ __global__ __launch_bounds__(kBlock) void k_exp(const SolveDesc* __restrict__ de
 constexpr int kFaceRows[] = {RT_P, RT_Q, RT_MLO, RT_ALO, RT_MDI, RT_ADI, RT_RR, RT_MUP, RT_AUP, RT_MEX};
 constexpr int kFaceN = 10;
 constexpr int kFace = 2 * kFaceN;
-__device__ __forceinline__ void stage_face(const SolveDesc& s, ldouble* face)
+// the rows above, four bits each (an immediate: no load of the index table)
+constexpr uint64_t face_rows_packed()
+{
+    uint64_t p = 0;
+    for (int c = 0; c < kFaceN; ++c) p |= (uint64_t)kFaceRows[c] << (4 * c);
+    return p;
+}
+static_assert(RT_EHI < 16, "table rows fit four bits");
+// Thread t < kFace's entry of the face rows (load_face) and its store into
+// LDS (store_face), apart so that callers can issue the load early.
+__device__ __forceinline__ double load_face(const SolveDesc& s)
 {
     const int t = (int)threadIdx.x;
-    if (t < kFace) {
-        const int w = t / kFaceN;
-        face[t] = gp(s.rt)[(size_t)kFaceRows[t - w * kFaceN] * s.nr + (w ? s.nr - 1 : 0)];
-    }
+    if (t >= kFace) return 0.0;
+    const int w = t / kFaceN;
+    const int row = (int)((face_rows_packed() >> (4 * (t - w * kFaceN))) & 15u);
+    return gp(s.rt)[(size_t)row * s.nr + (w ? s.nr - 1 : 0)];
+}
+__device__ __forceinline__ void store_face(ldouble* face, double x)
+{
+    const int t = (int)threadIdx.x;
+    if (t < kFace) face[t] = x;
+}
+__device__ __forceinline__ void stage_face(const SolveDesc& s, ldouble* face)
+{
+    store_face(face, load_face(s));
 }
 
 // Face row w (0: row 0, 1: row nr - 1) of (I - theta dt A1) on a line with
@@ -1671,16 +1690,21 @@ struct ExpColumn {
         ryk = rt[RT_Y * nr + i] * yt[YT_I * ny + k];
         kyk = yt[YT_K * ny + k];
         rx = rt[RT_X * nr + i];
-        wa = yt[YT_W1 * ny + k];
-        wb = yt[YT_W3 * ny + k];
-        if (k == 0) { wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
-        else if (k == ny - 1) { wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
+        // the y weights of plane k's two neighbours (one-sided on the y
+        // faces) and the Dirichlet increment: the entries are chosen first
+        // and then loaded, every load unconditional, so that none of them
+        // waits for the others (or for the grid loads before them)
+        const int wra = k == 0 ? YT_W3 : (k == ny - 1 ? YT_W0 : YT_W1);
+        const int wrb = k == 0 ? YT_W4 : (k == ny - 1 ? YT_W1 : YT_W3);
+        wa = yt[wra * ny + k];
+        wb = yt[wrb * ny + k];
         w2 = yt[YT_W2 * ny + k];
         yhd = s.y_hi_dir && k == ny - 1;
         gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
         const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
         dir = rlo || rhi || yhd;
-        gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
+        const double g = gdn[yhd ? 2 * ny + i : (rlo ? k : (rhi ? ny + k : 0))];
+        gval = dir ? g : 0.0;
         dt = s.dt;
         dx = i == 0 ? 2 : (i == nr - 1 ? -2 : 0);
     }
@@ -1807,9 +1831,6 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
             yb[m] = U(vob, pob + row(j0 + m));
         }
     }
-    // the caller's staging (its loads queue behind the grid's, so that one
-    // memory round trip covers both)
-    stage();
     // the tile's v-table values (kVT rows of J; v nodes past nv repeat the
     // last one, whose results are not stored) by vector loads, into LDS
     double vv = 0.0;
@@ -1818,6 +1839,9 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
         vv = gp(s.vt)[(size_t)r * nv + min(j0 + (t - r * J), nv - 1)];
     }
     const ExpColumn q(s, i, k, step);
+    // the caller's staging (its loads queue behind the grid's and the
+    // column constants')
+    stage();
     ldouble* wcol = win + (size_t)kk * WL * nr + i;
     window_guards(win, P, WL, nr);
     if (t < kVT * J) vtc[t] = vv;
@@ -1999,11 +2023,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
     const int t = threadIdx.x;
     ldouble* tile = lds;
     ldouble* tab = lds + s.exr_tab;  // after the tile, rounded up to whole passes
-    auto stage_table = [&]() {};
-    stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
     // after the row table and the window variant's v-table cache
     ldouble* face = tab + (size_t)S * (kRF * ROWS + 1) + (size_t)kVT * kExrJ;
-    stage_face(s, face);
+    // the row table and the face rows into LDS first (staged after the grid
+    // loads, their waits held up the explicit phase: measured slower)
+    auto stage_table = [&]() {};
+    const double fv = load_face(s);  // issued with the row table's loads
+    stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
+    store_face(face, fv);
     if constexpr (WIN && !STAGE2) {
         // explicit phase from the LDS window (it shares the LDS of the tile,
         // which is written once every thread has finished reading it)
