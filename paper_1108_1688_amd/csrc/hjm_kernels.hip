@@ -1159,15 +1159,16 @@ __device__ __forceinline__ void explicit_nodes(const SolveDesc& s, int i, int k,
     const double ryk = rt[RT_Y * nr + i] * yt[YT_I * ny + k];
     const double kyk = yt[YT_K * ny + k];
     const double rx = rt[RT_X * nr + i];
-    double wa = yt[YT_W1 * ny + k], wb = yt[YT_W3 * ny + k];
-    if (k == 0) { wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
-    else if (k == ny - 1) { wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
+    // (entries chosen first, then loaded unconditionally: no load in a
+    // branch, which would wait for every load before it)
+    const double wa = yt[(k == 0 ? YT_W3 : (k == ny - 1 ? YT_W0 : YT_W1)) * ny + k];
+    const double wb = yt[(k == 0 ? YT_W4 : (k == ny - 1 ? YT_W1 : YT_W3)) * ny + k];
     const double w2 = yt[YT_W2 * ny + k];
     // Dirichlet nodes: the increment does not depend on j
     gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
     const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
     const bool dir = rlo || rhi || yhd;
-    const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
+    const double gval = dir ? gdn[yhd ? 2 * ny + i : (rlo ? k : (rhi ? ny + k : 0))] : 0.0;
     const double dt = s.dt;
 #pragma unroll
     for (int m = 0; m < J; ++m) {
@@ -1276,9 +1277,10 @@ __device__ __forceinline__ void corrected_start(const SolveDesc& s, int i, int k
     const double ryk = rt[RT_Y * nr + i] * yt[YT_I * ny + k];
     const double kyk = yt[YT_K * ny + k];
     const double rx = rt[RT_X * nr + i];
-    double wa = yt[YT_W1 * ny + k], wb = yt[YT_W3 * ny + k];
-    if (k == 0) { wa = yt[YT_W3 * ny + k]; wb = yt[YT_W4 * ny + k]; }
-    else if (k == ny - 1) { wa = yt[YT_W0 * ny + k]; wb = yt[YT_W1 * ny + k]; }
+    // (entries chosen first, then loaded unconditionally: no load in a
+    // branch, which would wait for every load before it)
+    const double wa = yt[(k == 0 ? YT_W3 : (k == ny - 1 ? YT_W0 : YT_W1)) * ny + k];
+    const double wb = yt[(k == 0 ? YT_W4 : (k == ny - 1 ? YT_W1 : YT_W3)) * ny + k];
     const double w2 = yt[YT_W2 * ny + k];
     // (A1 + A2 + A3) and A0 of the loaded field at node j0 + m
     auto stencil = [&](int m, double& a123, double& a0) {
@@ -1299,7 +1301,7 @@ __device__ __forceinline__ void corrected_start(const SolveDesc& s, int i, int k
     gcdouble* gdn = gp(s.gd) + (size_t)step * (2 * ny + nr);
     const bool rlo = i == 0 && s.r_lo_dir, rhi = i == nr - 1 && s.r_hi_dir;
     const bool dir = rlo || rhi || yhd;
-    const double gval = yhd ? gdn[2 * ny + i] : (rlo ? gdn[k] : (rhi ? gdn[ny + k] : 0.0));
+    const double gval = dir ? gdn[yhd ? 2 * ny + i : (rlo ? k : (rhi ? ny + k : 0))] : 0.0;
     const double dt = s.dt;
     {
         double su[J], s0[J];
