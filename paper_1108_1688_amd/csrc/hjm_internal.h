@@ -21,6 +21,7 @@ enum { R_SPIKE = 0,   // fused k_xr; segments eliminated in parallel, reduced sy
 constexpr int kExpCols = 256;  // r-y columns per k_exp workgroup (one thread each)
 constexpr int kExrJ = 16;      // v nodes per k_exr tile (computed 8 at a time)
 constexpr int kExrMaxNr = kBlock;  // k_exr: one thread per r node of a plane
+constexpr int kExrMaxP = kBlock / 8;  // k_exr: planes per tile (nr >= 8)
 
 // Per-solve descriptor, resident in device memory (read-only in kernels).
 struct SolveDesc {

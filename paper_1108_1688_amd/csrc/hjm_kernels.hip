@@ -1672,6 +1672,7 @@ struct GridBuf {
 // explicit_nodes forms them).
 struct ExpColumn {
     double mlo, alo, mdi, adi, mup, aup, mex, ryk, kyk, rx, wa, wb, w2, gval, dt;
+    double cy;  // c = f_t + kappa f + y of plane k (the r rows' shift)
     bool dir, yhd;
     int dx;  // outflow r face rows reach two nodes in (+2 at r_min, -2 at r_max)
     __device__ __forceinline__ ExpColumn(const SolveDesc& s, int i, int k, int step)
@@ -1681,6 +1682,7 @@ struct ExpColumn {
         gcdouble* yt = gp(s.yt);
         gcdouble* stn = gp(s.st) + kStepStride * step;
         const double c = stn[ST_PHI] + yt[YT_Y * ny + k];
+        cy = c;
         const double e = rt[RT_P * nr + i] * c + rt[RT_Q * nr + i];
         mlo = rt[RT_MLO * nr + i] * e;
         alo = rt[RT_ALO * nr + i];
@@ -1795,8 +1797,8 @@ __device__ __forceinline__ void window_guards(ldouble* win, int P, int WR, int n
 // once the grid loads are issued (the caller's own staging into LDS).  Every
 // thread of the workgroup calls it (one barrier inside).
 template <int J, bool UK, class Stage>
-__device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win, ldouble* vtc, int P, int k0, int j0,
-                                                int step, double (&out)[J], const Stage& stage)
+__device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win, ldouble* vtc, ldouble* cpl, int P,
+                                                int k0, int j0, int step, double (&out)[J], const Stage& stage)
 {
     constexpr int WR = J + 4;   // the column's v nodes j0 - 2 .. j0 + J + 1
     constexpr int WL = J + 2;   // the window's rows: v nodes j0 - 1 .. j0 + J
@@ -1847,6 +1849,7 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
     ldouble* wcol = win + (size_t)kk * WL * nr + i;
     window_guards(win, P, WL, nr);
     if (t < kVT * J) vtc[t] = vv;
+    if (i == 0 && kk < P) cpl[kk] = q.cy;  // each plane's c, for the r solve
     if (act) {
 #pragma unroll
         for (int m = 0; m < WL; ++m) wcol[(size_t)m * nr] = cw[m + 1];
@@ -1866,7 +1869,7 @@ __device__ __forceinline__ void explicit_window(const SolveDesc& s, ldouble* win
 // follows the tile's writes.
 template <int ROWS, bool FOLD = false>
 __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, const ldouble* tab, const ldouble* face,
-                                           int P, int k0, int j0, int step)
+                                           const ldouble* vtc, const ldouble* cpl, int P, int k0, int j0, int step)
 {
     const int nr = s.nr, nv = s.nv, ny = s.ny;
     const int S = s.rs_S;
@@ -1875,7 +1878,6 @@ __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, co
     constexpr int TP = kRF * ROWS + 1;
     const int LP = S * SP;
     const int t = (int)threadIdx.x;
-    const double phi = gp(s.st)[kStepStride * step + ST_PHI];
     const int L = P * kExrJ;
     for (int base = 0; base < L * S; base += kBlock) {  // uniform trip count
         const int u = base + t;
@@ -1895,8 +1897,10 @@ __device__ __forceinline__ void solve_tile(const SolveDesc& s, ldouble* tile, co
         const bool ydir = s.y_hi_dir && k == ny - 1;
         bool ok = true;
         if (!ydir) {
-            const double v = gp(s.vt)[VT_V * nv + j];
-            const double c = phi + gp(s.yt)[YT_Y * ny + k];
+            // the line's v and c from the explicit phase's LDS copies (the
+            // v-table cache, one c per plane): no memory round trip here
+            const double v = vtc[VT_V * kExrJ + jj];
+            const double c = cpl[min(kk, P - 1)];
             ok = spike_r_lane<ROWS>(s, tab + seg * TP, face, tile + (size_t)base * SP + t * 8, seg, S, v, c, d);
         }
         if constexpr (FOLD) {
@@ -2033,16 +2037,17 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
     const double fv = load_face(s);  // issued with the row table's loads
     stage_rf<ROWS, (kRF * kExrMaxNr + kBlock - 1) / kBlock>(s, tab);
     store_face(face, fv);
+    // the v-table cache after the row table, the planes' c after the face rows
+    ldouble* vtc = tab + (size_t)S * (kRF * ROWS + 1);
+    ldouble* cpl = face + kFace;
     if constexpr (WIN && !STAGE2) {
         // explicit phase from the LDS window (it shares the LDS of the tile,
         // which is written once every thread has finished reading it)
         double out[kExrJ];
-        // the v-table cache after the row table
-        ldouble* vtc = tab + (size_t)S * (kRF * ROWS + 1);
         if (nr % 64 == 0)
-            explicit_window<kExrJ, true>(s, tile + 2, vtc, P, k0, j0, step, out, stage_table);
+            explicit_window<kExrJ, true>(s, tile + 2, vtc, cpl, P, k0, j0, step, out, stage_table);
         else
-            explicit_window<kExrJ, false>(s, tile + 2, vtc, P, k0, j0, step, out, stage_table);
+            explicit_window<kExrJ, false>(s, tile + 2, vtc, cpl, P, k0, j0, step, out, stage_table);
         const int kk = t / nr;
         const int i = t - kk * nr;
         __syncthreads();
@@ -2074,11 +2079,11 @@ __global__ __launch_bounds__(kBlock, 3) void k_exr(const SolveDesc* __restrict__
     __syncthreads();
     if constexpr (WIN && !STAGE2 && FOLD) {
         // D1 stays in the tile; after every line is solved, the tile's v sweep
-        solve_tile<ROWS, true>(s, tile, tab, face, P, k0, j0, step);
+        solve_tile<ROWS, true>(s, tile, tab, face, vtc, cpl, P, k0, j0, step);
         __syncthreads();
         fold_v_tile<ROWS>(s, tile, P, k0, j0);
     } else if constexpr (WIN && !STAGE2) {
-        solve_tile<ROWS>(s, tile, tab, face, P, k0, j0, step);
+        solve_tile<ROWS>(s, tile, tab, face, vtc, cpl, P, k0, j0, step);
     } else {
         // the same passes as solve_tile, written out here: inlined as one
         // function the per-lane-load variants keep fewer registers spilled
@@ -2823,9 +2828,9 @@ void exr_lds(int nr, int rows, size_t* bytes, int* tab)
     // guard doubles each side), which the tile overwrites after it
     const int tile = std::max(passes * kBlock * (rows + 1), P * (kExrJ + 2) * nr + 4);
     *tab = tile;
-    // the row table, the window variant's v-table cache (kVT x kExrJ) and the
-    // face rows' table entries
-    *bytes = ((size_t)tile + (size_t)S * (kRF * rows + 1) + (size_t)kVT * kExrJ + (size_t)kFace) * 8;
+    // the row table, the window variant's v-table cache (kVT x kExrJ), the
+    // face rows' table entries and the window variant's c of each plane
+    *bytes = ((size_t)tile + (size_t)S * (kRF * rows + 1) + (size_t)kVT * kExrJ + (size_t)kFace + kExrMaxP) * 8;
 }
 
 hipError_t launch_exr(int rows, const SolveDesc* d_desc, const int2* tasks, int n_tasks, int step, size_t lds,
