@@ -1679,8 +1679,10 @@ struct ExpColumn {
     {
         const int nr = s.nr, ny = s.ny;
         gcdouble* rt = gp(s.rt);
-        gcdouble* yt = gp(s.yt);
-        gcdouble* stn = gp(s.st) + kStepStride * step;
+        // the plane's entries through the constant space: scalar loads where
+        // k is the same on every lane
+        kcdouble* yt = kp(s.yt);
+        kcdouble* stn = kp(s.st) + kStepStride * step;
         const double c = stn[ST_PHI] + yt[YT_Y * ny + k];
         cy = c;
         const double e = rt[RT_P * nr + i] * c + rt[RT_Q * nr + i];
