@@ -63,15 +63,15 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "018e1d713b93ad7b9c40c1bd7879cf2e17da56d35f996996763a8a8ebb41f541"
-                      ":c4177e9e6f5845c61413ac1afa83bcb6bfbd7a16faea0119cd43db7ee5a319b3",
+    "sources_sha256": "19058ed0ef19ad349a9d182fbbba91ce6dca193989065b03dff2b9cbd5b575f5"
+                      ":6b29000f401025673b7e581e71494315298077a408893aa170981f277e9961cb",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
     "exr_window": True,
     "y_minors": True,
     "v_fold": True,
-    "bytes_per_point": {"explicit+r": 18.933, "v": 2.395, "y+update": 26.076},
+    "bytes_per_point": {"explicit+r": 18.253, "v": 2.395, "y+update": 26.079},
 }
 
 def log(*a):
