@@ -32,13 +32,13 @@ OUT_SCALE = 0.1     # network units with the baseline: 10 ln(price / B)
 PLAIN_SCALE = 1e-3  # network units without it: prices in units of 1e-3
 # the baseline's model constants: lambda, gamma, theta_v (section 3.3 values of
 # the solves), curve decay and tenor of the training rows
-BASELINE = (W.LAMBDA, W.GAMMA, W.THETA_V, W.SURROGATE_F_DECAY, W.SURROGATE_TENOR)
+GAUSS_ARGS = (W.LAMBDA, W.GAMMA, W.THETA_V, W.SURROGATE_F_DECAY, W.SURROGATE_TENOR)
 # rows priced at or below this are left out of the training (log target): the
 # relative error is stated above it, and the deep out-of-the-money rows below
 # it stretch the log-ratio's range (to 97 from 29), which the BF16
 # activations' rounding then turns into error on every row
 FIT_PRICE_FLOOR = 1e-4
-SOFTEN = 0          # terminal data of the solves the network learns from and is judged against
+SOFTEN = 0          # terminal data of the solves the network learns from and is checked against
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -99,7 +99,7 @@ def make_mlp(max_batch: int = 65536, stream=None, baseline: bool = True) -> hjm.
     if not baseline:
         return hjm.Mlp(W.SURROGATE_BOX_LO, W.SURROGATE_BOX_HI, PLAIN_SCALE, 0.0, max_batch=max_batch, stream=stream)
     m = hjm.Mlp(W.SURROGATE_BOX_LO, W.SURROGATE_BOX_HI, OUT_SCALE, 0.0, max_batch=max_batch, stream=stream)
-    m.set_baseline(*BASELINE)
+    m.set_baseline(*GAUSS_ARGS)
     return m
 
 

@@ -97,7 +97,7 @@ def test_baseline_output_and_targets_match_oracle():
     y = y.cpu().numpy().astype(np.float64)
     yo, _ = M.forward(p.astype(np.float64), x, LO, HI, emulate=True)
     y32, _ = M.forward(p.astype(np.float64), x, LO, HI, emulate="emulate32")
-    B = M.caplet_baseline(x64, *S.BASELINE)
+    B = M.caplet_baseline(x64, *S.GAUSS_ARGS)
     assert np.all(B > 0) and np.all(np.isfinite(y)) and np.all(y > 0)
     yb = np.log(y / B) / S.OUT_SCALE  # the GPU's network output, recovered
     scale = np.abs(yo).mean()
@@ -109,7 +109,7 @@ def test_baseline_output_and_targets_match_oracle():
     price = B * np.exp(np.random.default_rng(9).uniform(-1.0, 2.0, len(x)))
     price[:3] = (0.0, -1e-6, 1.0)
     t = m.targets(_dev(x), torch.from_numpy(price).cuda()).cpu().numpy().astype(np.float64)
-    to = M.baseline_target(x64[3:], price[3:], S.OUT_SCALE, 0.0, S.BASELINE)
+    to = M.baseline_target(x64[3:], price[3:], S.OUT_SCALE, 0.0, S.GAUSS_ARGS)
     assert np.isnan(t[0]) and np.isnan(t[1])
     np.testing.assert_allclose(t[3:], to, rtol=1e-6, atol=1e-5)
     np.testing.assert_allclose(np.exp(-S.OUT_SCALE * t[2]), B[2], rtol=1e-6)
