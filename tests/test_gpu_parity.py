@@ -299,17 +299,22 @@ def test_y_pivots_from_minors_against_stored(shape, tile):
     assert diff <= 1e-13
 
 
-@pytest.mark.parametrize("shape,gaussian", [((64, 32, 32), False), ((128, 48, 64), False), ((256, 64, 48), False),
-                                            ((96, 128, 32), False), ((64, 48, 32), True)],
-                         ids=["r4lanes-v2seg", "r8lanes-v3seg", "r16lanes-v4seg", "rows12-v8seg", "dirichlet-r"])
-def test_v_sweep_folded_against_unfolded(shape, gaussian):
+@pytest.mark.parametrize("shape,gaussian,steps", [((64, 32, 32), False, 9), ((128, 48, 64), False, 80),
+                                                  ((256, 64, 48), False, 80), ((96, 128, 32), False, 80),
+                                                  ((64, 48, 32), True, 9), ((64, 80, 32), False, 160),
+                                                  ((64, 256, 16), False, 160)],
+                         ids=["r4lanes-v2seg", "r8lanes-v3seg", "r16lanes-v4seg", "rows12-v8seg", "dirichlet-r",
+                              "v5seg", "v16seg"])
+def test_v_sweep_folded_against_unfolded(shape, gaussian, steps):
     """The v sweep folded into the fused kernel (each tile's 16 v rows one
     segment, solved from zero there), the segment hand-over kernel and the
     y sweep's loads, against the v sweep on its own: each solve against the
-    oracle, and the two grids within a few ulps of each other; 2 to 8 v
-    segments, 4 to 16 lanes per r line, Dirichlet r faces (lines that keep
-    D1)."""
-    s = _sloped(shape, 9 if shape[0] <= 64 else 80, gaussian=gaussian)
+    oracle, and the two grids within a few ulps of each other; 2 to 16 v
+    segments (the hand-over kernel is built per count), 4 to 16 lanes per r
+    line, Dirichlet r faces (lines that keep D1)."""
+    # (the fold's segment products stay bounded on these meshes at these
+    # steps; finer v meshes need shorter steps)
+    s = _sloped(shape, steps, gaussian=gaussian)
     out = {}
     for fold in (True, False):
         hjm.set_v_fold(fold)
