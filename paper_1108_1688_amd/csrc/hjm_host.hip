@@ -426,7 +426,7 @@ Plan make_plan(int nr, int nv, int ny, const int rows[3], bool r_spike = true)
     // the window variant addresses the grid as one buffer of < 4 GiB
     p.exr_win = g_exr_window && (uint64_t)nr * nv * ny * 8 < (1ull << 32);
     if (p.rs_rows >= 8 && nr <= kExrMaxNr && kBlock / nr <= kExrMaxP) {
-        p.exr_P = kBlock / nr;
+        p.exr_P = exr_planes(nr, p.rs_rows);
         p.exr_tiles = ((ny + p.exr_P - 1) / p.exr_P) * ((nv + kExrJ - 1) / kExrJ);
         exr_lds(nr, p.rs_rows, &p.exr_lds, &p.exr_tab);
         if (g_fuse_r) p.r_mode = R_FUSED;

@@ -37,7 +37,7 @@ struct SolveDesc {
     int32_t exp_J, exp_cb, exp_tiles, rs_S;
     int32_t rs_log2S, rs_L, rs_tiles, exr_P;
     // fused path (R_FUSED): k_exr tiles = ceil(ny / exr_P) plane blocks x
-    // ceil(nv / kExrJ) v blocks, exr_P = kBlock / nr planes per tile; the
+    // ceil(nv / kExrJ) v blocks, exr_P = exr_planes(nr, rows) planes per tile; the
     // row table sits exr_tab doubles into the dynamic LDS, after the tile
     // segmented v solve (k_vs, vs_S > 0): vs_S segments of nv / vs_S rows, one
     // wave of 64 consecutive i per segment; chained y solve on stored pivots
@@ -190,6 +190,18 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
 // (rows >= 8: a pass's scratch, 8 doubles per lane, fits in its rows); the
 // same for both explicit phases
 void exr_lds(int nr, int rows, size_t* bytes, int* tab);
+// Whole y planes per fused tile: as many as the workgroup's threads cover
+// (one per r node), but no more than one pass of the r solve's lanes holds
+// (kExrJ lines of S lanes per plane): a partly filled second pass would idle
+// most of its lanes (nr = 48: five planes need 1.25 passes, four need one).
+inline int exr_planes(int nr, int rows)
+{
+    const int S = nr / rows;
+    const int by_threads = kBlock / nr;
+    const int by_pass = kBlock / (kExrJ * S);
+    const int p = by_threads < by_pass ? by_threads : by_pass;
+    return p > 1 ? p : 1;
+}
 // window: the explicit phase reads its neighbours from an LDS window of its
 // tile (else each thread loads its own).  The predictor only: the corrected
 // start keeps the per-lane loads.

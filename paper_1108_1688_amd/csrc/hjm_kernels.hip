@@ -1993,7 +1993,7 @@ __device__ __forceinline__ void fold_v_tile(const SolveDesc& s, const ldouble* t
 // Explicit predictor (or, STAGE2, the corrected start of the Craig-Sneyd
 // family) and r sweep in one kernel (nr <= 256, nr = S * ROWS as for k_rs,
 // ROWS >= 8): the workgroup computes D0 on kExrJ consecutive v nodes of
-// exr_P = 256 / nr whole y planes (thread = (i, plane)) into an LDS tile,
+// exr_P = exr_planes(nr, ROWS) whole y planes (thread = (i, plane)) into an LDS tile,
 // then solves the tile's exr_P * kExrJ r lines with the spike method, S lanes
 // per line, and writes D1.  D0 never goes to memory: 16 bytes per point less
 // than the split pair.  Tile layout: line (plane kk, node jj) at
@@ -2822,7 +2822,7 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
 void exr_lds(int nr, int rows, size_t* bytes, int* tab)
 {
     const int S = nr / rows;
-    const int P = kBlock / nr;
+    const int P = exr_planes(nr, rows);
     const int lanes = P * kExrJ * S;
     const int passes = (lanes + kBlock - 1) / kBlock;
     // whole passes: the last pass's scratch stays inside; at least the
