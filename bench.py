@@ -63,15 +63,15 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "19058ed0ef19ad349a9d182fbbba91ce6dca193989065b03dff2b9cbd5b575f5"
-                      ":6b29000f401025673b7e581e71494315298077a408893aa170981f277e9961cb",
+    "sources_sha256": "666a81bfc19e6a006aceba2a66395c8a820fe8fb83b1b09cd1c94ca48bf5f274"
+                      ":4a34fe34a0cc0b9affdebde45aa08b5c465364e6eb241829ee7b264c51153190",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,
     "exr_window": True,
     "y_minors": True,
     "v_fold": True,
-    "bytes_per_point": {"explicit+r": 18.253, "v": 2.395, "y+update": 26.079},
+    "bytes_per_point": {"explicit+r": 18.263, "v": 2.394, "y+update": 26.077},
 }
 
 def log(*a):
