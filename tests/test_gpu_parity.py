@@ -208,9 +208,11 @@ def test_each_r_method(method):
                                         ((192, 20, 10), 16), ((16, 33, 7), 16)],
                          ids=lambda x: "x".join(map(str, x)) if isinstance(x, tuple) else f"rows{x}")
 def test_fused_explicit_r_tiles(shape, tile):
-    """The fused explicit + r kernel over its tilings: 256 / nr whole y planes
-    per workgroup (1 to 16), one or two passes of spike lanes (16 v nodes x
-    planes x nr / rows lanes), several planes per wavefront (nr = 16, 32),
+    """The fused explicit + r kernel over its tilings: up to 256 / nr whole y
+    planes per workgroup (1 to 16; fewer where the planes' spike lanes, 16 v
+    nodes x planes x nr / rows, would need a second pass: nr = 32 at 8 rows
+    takes 4), two passes where one plane needs them (nr = 256 at 8 rows),
+    several planes per wavefront (nr = 16, 32),
     ragged plane and v blocks (ny, nv not multiples of the tile), and nr = 192
     (12 rows per lane, a quarter of the threads idle in the explicit phase).
     Fine r meshes take 80 steps: with 9 the rows exceed the spike bound and
