@@ -64,7 +64,7 @@ PROFILED_STEPS = 10
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
     "sources_sha256": "666a81bfc19e6a006aceba2a66395c8a820fe8fb83b1b09cd1c94ca48bf5f274"
-                      ":4a34fe34a0cc0b9affdebde45aa08b5c465364e6eb241829ee7b264c51153190",
+                      ":3a478981e3360b16e9c5a3b856690dcadc5db9005e46a8c07b2d0e96a8c7cb94",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
     "r_fusion": True,

@@ -191,15 +191,15 @@ hipError_t launch_rs(int rows, const SolveDesc* d_desc, const int2* tasks, int n
 // same for both explicit phases
 void exr_lds(int nr, int rows, size_t* bytes, int* tab);
 // Whole y planes per fused tile: as many as the workgroup's threads cover
-// (one per r node), but no more than one pass of the r solve's lanes holds
-// (kExrJ lines of S lanes per plane): a partly filled second pass would idle
-// most of its lanes (nr = 48: five planes need 1.25 passes, four need one).
+// (one per r node), fewer where the r solve's lanes (kExrJ lines of S lanes
+// per plane) would leave its last pass part-full, most of that pass's lanes
+// idle (nr = 48: five planes need 1.25 passes, four need one; nr = 32 at 8
+// rows keeps eight planes in two full passes).
 inline int exr_planes(int nr, int rows)
 {
-    const int S = nr / rows;
-    const int by_threads = kBlock / nr;
-    const int by_pass = kBlock / (kExrJ * S);
-    const int p = by_threads < by_pass ? by_threads : by_pass;
+    const int per_plane = kExrJ * (nr / rows);
+    int p = kBlock / nr;
+    while (p > 1 && p * per_plane > kBlock && (p * per_plane) % kBlock != 0) --p;
     return p > 1 ? p : 1;
 }
 // window: the explicit phase reads its neighbours from an LDS window of its
