@@ -1,7 +1,7 @@
 // hjm_run: price a list of solves through the C ABI from a plain-text spec,
 // without Python (for profilers and for callers that embed the library).
 //
-//   hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y] [--batch]
+//   hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y] [--batch [--graph]]
 //   hjm_run --copy MIB
 //
 // SPEC holds one solve per line ('#' starts a comment), 37 numbers:
@@ -14,7 +14,9 @@
 // --steps K only the first K steps of each solve run and no price is read.
 // With --batch the list is priced as one batch (hjm_batch_*: at every Douglas
 // step one launch per kernel covers all solves still running); --steps does
-// not apply there.
+// not apply there.  With --graph each pass runs the batch twice from a HIP
+// graph (captured on the first run, replayed on the second) before reading
+// the prices.
 // Prints the prices of the last repeat and the throughput in grid-point
 // Douglas steps per second.  Exit status 0 on success, 1 on a bad spec or
 // argument, 2 on a library or HIP error.
@@ -82,7 +84,7 @@ int lib_fail(const char* what, hjm_status st) {
 }
 
 int usage() {
-    std::fprintf(stderr, "usage: hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y] [--batch]\n"
+    std::fprintf(stderr, "usage: hjm_run SPEC [--repeat N] [--warmup W] [--steps K] [--tile R,V,Y] [--batch [--graph]]\n"
                          "       hjm_run --copy MIB\n");
     return 1;
 }
@@ -121,7 +123,7 @@ int run_copy(int mib) {
     return 0;
 }
 
-int run_batch(const std::vector<Solve>& solves, hipStream_t stream, int repeat, int warmup) {
+int run_batch(const std::vector<Solve>& solves, hipStream_t stream, int repeat, int warmup, bool graph) {
     const int32_t n = int32_t(solves.size());
     std::vector<hjm_axis> ax(3 * solves.size());
     std::vector<hjm_model> model(solves.size());
@@ -154,7 +156,8 @@ int run_batch(const std::vector<Solve>& solves, hipStream_t stream, int repeat, 
         hjm_batch* b = nullptr;
         st = hjm_batch_create(n, ax.data(), model.data(), payoff.data(), steps.data(), ws, bytes, stream, &b);
         if (st != HJM_OK) return lib_fail("batch create", st);
-        st = hjm_batch_run(b, 0);
+        st = hjm_batch_run(b, graph ? 1 : 0);
+        if (graph && st == HJM_OK) st = hjm_batch_run(b, 1);
         if (st == HJM_OK) st = hjm_batch_prices(b, r0.data(), v0.data(), prices.data());
         hjm_batch_destroy(b);
         if (st != HJM_OK) return lib_fail("batch run", st);
@@ -163,7 +166,7 @@ int run_batch(const std::vector<Solve>& solves, hipStream_t stream, int repeat, 
                     it < warmup ? " (warmup)" : "", 1e3 * el);
         std::fflush(stdout);
         if (it >= warmup) {
-            point_steps += per_pass;
+            point_steps += per_pass * (graph ? 2 : 1);
             seconds += el;
         }
     }
@@ -182,10 +185,14 @@ int main(int argc, char** argv) {
     if (argc < 2) return usage();
     if (!std::strcmp(argv[1], "--copy")) return argc == 3 ? run_copy(std::atoi(argv[2])) : usage();
     int repeat = 1, warmup = 0, steps_cap = 0;
-    bool batch = false;
+    bool batch = false, graph = false;
     for (int a = 2; a < argc; ++a) {
         if (!std::strcmp(argv[a], "--batch")) {
             batch = true;
+            continue;
+        }
+        if (!std::strcmp(argv[a], "--graph")) {
+            graph = true;
             continue;
         }
         if (a + 1 >= argc) return usage();
@@ -204,7 +211,7 @@ int main(int argc, char** argv) {
             return usage();
         }
     }
-    if (repeat < 1 || warmup < 0 || steps_cap < 0 || (batch && steps_cap > 0)) return usage();
+    if (repeat < 1 || warmup < 0 || steps_cap < 0 || (batch && steps_cap > 0) || (graph && !batch)) return usage();
 
     std::ifstream file(argv[1]);
     if (!file) {
@@ -235,7 +242,7 @@ int main(int argc, char** argv) {
         return 2;
     }
     if (batch) {
-        int rc = run_batch(solves, stream, repeat, warmup);
+        int rc = run_batch(solves, stream, repeat, warmup, graph);
         (void)hipStreamDestroy(stream);
         return rc;
     }

@@ -251,3 +251,18 @@ def test_discrete_curve_validation(L):
     st = L.hjm_grid_create_scheme(hjm.make_axes(s.axes), C.byref(m), C.byref(hjm.make_payoff(s.payoff)),
                                   C.byref(hjm.make_scheme(s)), s.n_steps, C.c_void_p(256), 1 << 40, None, C.byref(h))
     assert st == hjm.EINVAL and "null" in L.hjm_last_error().decode()
+
+
+def test_hjm_run_argument_errors(tmp_path):
+    """The command-line driver refuses bad arguments with its usage (exit 1)
+    before it touches the device: no spec, an unknown option, and --graph
+    without --batch (graph replay is a batch feature)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1108_1688_amd", "hjm_run")
+    if not os.path.exists(exe):
+        pytest.skip("hjm_run not built")
+    spec = tmp_path / "one.spec"
+    spec.write_text(W.spec_line(W.config1()[0]) + "\n")
+    for args in ([], [str(spec), "--bogus"], [str(spec), "--graph"], [str(spec), "--batch", "--steps", "3"]):
+        res = subprocess.run([exe, *args], capture_output=True, text=True, timeout=60)
+        assert res.returncode == 1 and "usage: hjm_run" in res.stderr, (args, res.returncode, res.stderr)
