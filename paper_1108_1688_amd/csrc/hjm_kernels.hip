@@ -1980,9 +1980,12 @@ __device__ __forceinline__ void fold_v_tile(const SolveDesc& s, const ldouble* t
         if (first) d[0] = d0;
         if (last) d[J - 1] = dl;
     }
+    // non-temporal: the y sweep reads D1 back two launches later, after
+    // the hand-over kernel, so streaming it past the caches keeps them for
+    // the window's halo reads (measured faster for both kernels)
     gdouble* line = gp(s.D) + ((size_t)k * nv + j0) * nr + i;
 #pragma unroll
-    for (int m = 0; m < J; ++m) line[(size_t)m * nr] = d[m];
+    for (int m = 0; m < J; ++m) __builtin_nontemporal_store(d[m], &line[(size_t)m * nr]);
     const size_t A = (size_t)nr * ny * Sv;
     const size_t e = ((size_t)k * Sv + sv) * nr + i;
     gdouble* ends = gp(s.yinv);
@@ -2002,7 +2005,7 @@ __device__ __forceinline__ void fold_v_tile(const SolveDesc& s, const ldouble* t
 // lines' part of the tile as the reduced-system scratch once every lane has
 // read its rows (pass p's scratch is its first 8 kBlock doubles, inside its
 // kBlock / S lines; the tile is sized to whole passes).  Three waves per SIMD
-// (at most 168 VGPRs; a few spill) measured faster than two without spills.
+// (at most 168 VGPRs, no spills) measured faster than two.
 // v nodes per explicit chunk of k_exr: 8; 4 for the corrected start, which
 // holds the stencil of U while it loads the windows of D3
 template <bool STAGE2>
