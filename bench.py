@@ -63,7 +63,7 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "666a81bfc19e6a006aceba2a66395c8a820fe8fb83b1b09cd1c94ca48bf5f274"
+    "sources_sha256": "934ed06f7451b19fc2a2085f36284ed2ef8841d50326c9d41865c2f9d411aa75"
                       ":3a478981e3360b16e9c5a3b856690dcadc5db9005e46a8c07b2d0e96a8c7cb94",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,
@@ -71,7 +71,7 @@ MEASURED_TRAFFIC = {
     "exr_window": True,
     "y_minors": True,
     "v_fold": True,
-    "bytes_per_point": {"explicit+r": 18.263, "v": 2.394, "y+update": 26.077},
+    "bytes_per_point": {"explicit+r": 18.081, "v": 2.394, "y+update": 26.077},
 }
 
 def log(*a):
