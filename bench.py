@@ -63,7 +63,7 @@ PROFILED_STEPS = 10
 # valid only for the kernel sources and settings they were taken on: reported
 # as null otherwise.  A launch's traffic = bytes per point x its grid points.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "934ed06f7451b19fc2a2085f36284ed2ef8841d50326c9d41865c2f9d411aa75"
+    "sources_sha256": "f4cb9e9c801bd8cdfb7f2d6c2216ecbf2acdd65af456bf79d42ce9dadc348c5d"
                       ":3a478981e3360b16e9c5a3b856690dcadc5db9005e46a8c07b2d0e96a8c7cb94",
     "line_tile": (16, 16, 16),
     "explicit_chunk": 8,

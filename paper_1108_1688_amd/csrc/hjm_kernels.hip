@@ -2383,9 +2383,11 @@ __global__ __launch_bounds__(64 * yc_max_segments(ROWS)) void k_yc(const SolveDe
     // the end, so that the chains hold just d and -A inv in registers and two
     // workgroups fit on a compute unit.
     double d[ROWS], al[ROWS], iv[ROWS];
+    // D2 is read once (non-temporal: the next step rewrites it), which
+    // leaves the caches to the hand-over values the segment's rows share
 #pragma unroll
     for (int mm = 0; mm < ROWS; ++mm) {
-        d[mm] = D[off + (size_t)mm * sy];
+        d[mm] = __builtin_nontemporal_load(&D[off + (size_t)mm * sy]);
         if constexpr (!MINORS) iv[mm] = gp(s.yinv)[off + (size_t)mm * sy];
     }
     if constexpr (FOLD) {
